@@ -1,0 +1,311 @@
+"""Powersort CPU oracle: TEST INFRASTRUCTURE ONLY.
+
+Thin ctypes/numpy wrapper over ``liboracle.so`` (plain C, ``oracle.c``).
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package; the product path never does.
+
+Every function follows the paper "Virtual-Memory Powersort":
+Algorithm 1 (Abstract Powersort), the Power theorem of Section 2, Pingpong
+Powersort (Section 3), StandardMerge (Algorithm 2), and the minrun rule of
+Section 5.  The learned-partition helpers are the fp64 reference of the
+project's CDF model (a monotone integer feature, one hidden ReLU layer, an
+integer knot table, and a stable counting sort by bucket id).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+PINGPONG, PINGPONG_LASTPOP, CPYTHON = 0, 1, 2
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "n", "runs", "merges", "merge_cost", "max_stack", "cmp_run", "cmp_ins",
+        "cmp_merge", "mov_ins", "mov_push", "mov_merge")] + [("entropy", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    src = os.path.join(_HERE, "oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        i64, i32, u64, vp, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double
+        lib.orc_minrun.restype = i32
+        lib.orc_minrun.argtypes = [i64]
+        lib.orc_power_def.restype = i32
+        lib.orc_power_def.argtypes = [i64, i64, i64, i64]
+        lib.orc_power_closed.restype = i32
+        lib.orc_power_closed.argtypes = [i64, i64, i64, i64]
+        lib.orc_extract_runs.restype = i64
+        lib.orc_extract_runs.argtypes = [vp, i64, i32, vp]
+        lib.orc_run_powers.restype = None
+        lib.orc_run_powers.argtypes = [vp, i64, i64, vp]
+        lib.orc_powersort.restype = ctypes.c_int
+        lib.orc_powersort.argtypes = [vp, vp, i64, i32, ctypes.c_int, ctypes.POINTER(Stats), vp, i64]
+        lib.orc_segmented_powersort.restype = ctypes.c_int
+        lib.orc_segmented_powersort.argtypes = [vp, vp, vp, i64, ctypes.c_int]
+        lib.orc_standard_merge.restype = None
+        lib.orc_standard_merge.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp]
+        lib.orc_tree_nodes.restype = None
+        lib.orc_tree_nodes.argtypes = [vp, i64, i64, vp, vp]
+        lib.orc_plan.restype = i64
+        lib.orc_plan.argtypes = [vp, i64, i64, vp, i64, vp, vp, vp, vp, vp]
+        lib.orc_mix64.restype = u64
+        lib.orc_mix64.argtypes = [u64, u64]
+        lib.orc_sample_positions.restype = None
+        lib.orc_sample_positions.argtypes = [i64, i64, u64, vp]
+        lib.orc_feature.restype = u64
+        lib.orc_feature.argtypes = [u64, i32, i32]
+        lib.orc_mlp_forward.restype = dbl
+        lib.orc_mlp_forward.argtypes = [vp, vp, vp, dbl, i32, dbl]
+        lib.orc_mlp_grad.restype = dbl
+        lib.orc_mlp_grad.argtypes = [vp, vp, vp, dbl, i32, vp, vp, i64, vp, vp, vp, vp]
+        lib.orc_cdf_table.restype = None
+        lib.orc_cdf_table.argtypes = [vp, vp, vp, dbl, i32, i32, vp]
+        lib.orc_bucket_of.restype = ctypes.c_uint32
+        lib.orc_bucket_of.argtypes = [u64, i32, i32, u64, u64, vp, i32, ctypes.c_uint32]
+        lib.orc_cdf_init.restype = None
+        lib.orc_cdf_init.argtypes = [vp, i64, i32, vp, vp, vp, vp]
+        lib.orc_cdf_loss.restype = dbl
+        lib.orc_cdf_loss.argtypes = [vp, vp, vp, dbl, i32, vp, i64, i64]
+        lib.orc_cdf_train.restype = dbl
+        lib.orc_cdf_train.argtypes = [vp, i64, i32, i32, i32, dbl, vp]
+        lib.orc_partition.restype = None
+        lib.orc_partition.argtypes = [vp, vp, i64, i32, i32, u64, u64, vp, i32, ctypes.c_uint32,
+                                      vp, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _keys64(keys) -> np.ndarray:
+    keys = np.asarray(keys)
+    if keys.dtype in (np.uint32, np.int32):
+        return keys.view(np.uint32).astype(np.uint64)
+    return np.ascontiguousarray(keys.view(np.uint64) if keys.dtype == np.int64 else keys.astype(np.uint64))
+
+
+def minrun(n: int) -> int:
+    return int(_L().orc_minrun(n))
+
+
+def power_def(n, i, j, k) -> int:
+    return int(_L().orc_power_def(n, i, j, k))
+
+
+def power_closed(n, i, j, k) -> int:
+    return int(_L().orc_power_closed(n, i, j, k))
+
+
+def extract_runs(keys, ell: int | None = None) -> np.ndarray:
+    """Run bounds (r+1 int64) of the sequential ExtractRun chain."""
+    x = _keys64(keys)
+    n = x.size
+    if ell is None:
+        ell = minrun(n)
+    bounds = np.zeros(n + 2, dtype=np.int64)
+    r = _L().orc_extract_runs(_p(x), n, ell, _p(bounds))
+    return bounds[: r + 1].copy()
+
+
+def run_powers(bounds: np.ndarray, n: int) -> np.ndarray:
+    bounds = np.ascontiguousarray(bounds, dtype=np.int64)
+    r = bounds.size - 1
+    out = np.zeros(max(r - 1, 1), dtype=np.uint8)
+    _L().orc_run_powers(_p(bounds), r, n, _p(out))
+    return out[: max(r - 1, 0)].copy()
+
+
+def powersort(keys, vals=None, variant: int = PINGPONG, ell: int = 0, log_merges: bool = False):
+    """Algorithm 1 on a copy of keys (and vals). Returns (keys, vals, stats, merge_log)."""
+    orig = np.asarray(keys)
+    x = _keys64(orig).copy()
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    n = x.size
+    st = Stats()
+    cap = n if log_merges else 0
+    log = np.zeros(3 * max(cap, 1), dtype=np.int64)
+    rc = _L().orc_powersort(_p(x), _p(v), n, ell, variant, ctypes.byref(st),
+                            _p(log) if log_merges else None, cap)
+    if rc != 0:
+        raise RuntimeError("oracle powersort failed")
+    out = x.astype(orig.dtype) if orig.dtype in (np.uint32, np.int32) else x.view(orig.dtype) if orig.dtype == np.int64 else x
+    merges = log[: 3 * st.merges].reshape(-1, 3).copy() if log_merges else None
+    return out, v, st.as_dict(), merges
+
+
+def segmented_powersort(keys, offsets, vals=None, variant: int = PINGPONG):
+    orig = np.asarray(keys)
+    x = _keys64(orig).copy()
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    rc = _L().orc_segmented_powersort(_p(x), _p(v), _p(off), off.size - 1, variant)
+    if rc != 0:
+        raise RuntimeError("oracle segmented powersort failed")
+    out = x.astype(orig.dtype) if orig.dtype in (np.uint32, np.int32) else x
+    return out, v
+
+
+def standard_merge(a, b, va=None, vb=None):
+    A, B = _keys64(a), _keys64(b)
+    out = np.zeros(A.size + B.size, dtype=np.uint64)
+    vout = None
+    if va is not None:
+        va = np.ascontiguousarray(va, dtype=np.uint32)
+        vb = np.ascontiguousarray(vb, dtype=np.uint32)
+        vout = np.zeros(out.size, dtype=np.uint32)
+    _L().orc_standard_merge(_p(A), _p(va), A.size, _p(B), _p(vb), B.size, _p(out), _p(vout))
+    return out, vout
+
+
+def tree_nodes(bounds, n, powers) -> np.ndarray:
+    bounds = np.ascontiguousarray(bounds, dtype=np.int64)
+    powers = np.ascontiguousarray(powers, dtype=np.uint8)
+    r = bounds.size - 1
+    nodes = np.zeros(4 * max(r - 1, 1), dtype=np.int64)
+    _L().orc_tree_nodes(_p(bounds), r, n, _p(powers), _p(nodes))
+    return nodes[: 4 * max(r - 1, 0)].reshape(-1, 4).copy()
+
+
+def plan(bounds, n, powers, T):
+    """Pingpong placement: (node_buf, node_depth, segs[(start,end,buf)], M, M_hbm)."""
+    bounds = np.ascontiguousarray(bounds, dtype=np.int64)
+    powers = np.ascontiguousarray(powers, dtype=np.uint8)
+    r = bounds.size - 1
+    nb = max(r - 1, 0)
+    node_buf = np.zeros(max(nb, 1), dtype=np.int8)
+    node_depth = np.zeros(max(nb, 1), dtype=np.int32)
+    segs = np.zeros(3 * (nb + 1), dtype=np.int64)
+    mt = ctypes.c_int64(0)
+    mh = ctypes.c_int64(0)
+    ns = _L().orc_plan(_p(bounds), r, n, _p(powers), T, _p(node_buf), _p(node_depth), _p(segs),
+                       ctypes.byref(mt), ctypes.byref(mh))
+    return node_buf[:nb].copy(), node_depth[:nb].copy(), segs[: 3 * ns].reshape(-1, 3).copy(), mt.value, mh.value
+
+
+# ---- learned CDF partitioner reference (fp64) ----
+
+def mix64(seed: int, counter: int) -> int:
+    return int(_L().orc_mix64(seed & (2**64 - 1), counter))
+
+
+def sample_positions(n: int, m: int, seed: int) -> np.ndarray:
+    out = np.zeros(m, dtype=np.int64)
+    _L().orc_sample_positions(n, m, seed & (2**64 - 1), _p(out))
+    return out
+
+
+def feature(key: int, key_bits: int, fbits: int) -> int:
+    return int(_L().orc_feature(key, key_bits, fbits))
+
+
+def features(keys, key_bits: int, fbits: int) -> np.ndarray:
+    return np.array([feature(int(k), key_bits, fbits) for k in np.asarray(keys).ravel()], dtype=np.uint64)
+
+
+def mlp_forward(params: dict, u: float) -> float:
+    w1, b1, w2 = (np.ascontiguousarray(params[k], dtype=np.float64) for k in ("w1", "b1", "w2"))
+    return float(_L().orc_mlp_forward(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, u))
+
+
+def mlp_grad(params: dict, u, y):
+    """(loss, grads dict) of the minibatch MSE, fp64."""
+    w1, b1, w2 = (np.ascontiguousarray(params[k], dtype=np.float64) for k in ("w1", "b1", "w2"))
+    H = w1.size
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = {k: np.zeros(H, dtype=np.float64) for k in ("w1", "b1", "w2")}
+    gb2 = ctypes.c_double(0.0)
+    loss = _L().orc_mlp_grad(_p(w1), _p(b1), _p(w2), float(params["b2"]), H, _p(u), _p(y), u.size,
+                             _p(g["w1"]), _p(g["b1"]), _p(g["w2"]), ctypes.byref(gb2))
+    g["b2"] = gb2.value
+    return float(loss), g
+
+
+def cdf_table(params: dict, K: int) -> np.ndarray:
+    w1, b1, w2 = (np.ascontiguousarray(params[k], dtype=np.float64) for k in ("w1", "b1", "w2"))
+    table = np.zeros(K + 1, dtype=np.uint64)
+    _L().orc_cdf_table(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, K, _p(table))
+    return table
+
+
+def bucket_of(key: int, key_bits: int, fbits: int, z_lo: int, z_hi: int, table: np.ndarray, B: int) -> int:
+    table = np.ascontiguousarray(table, dtype=np.uint64)
+    return int(_L().orc_bucket_of(key, key_bits, fbits, z_lo, z_hi, _p(table), table.size - 1, B))
+
+
+def partition(keys, key_bits: int, fbits: int, z_lo: int, z_hi: int, table, B: int, vals=None):
+    """Stable counting sort by bucket id: (keys_out, vals_out, offsets[B+1])."""
+    orig = np.asarray(keys)
+    x = _keys64(orig)
+    table = np.ascontiguousarray(table, dtype=np.uint64)
+    n = x.size
+    ko = np.zeros(n, dtype=np.uint64)
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32)
+    vo = None if v is None else np.zeros(n, dtype=np.uint32)
+    off = np.zeros(B + 1, dtype=np.int64)
+    _L().orc_partition(_p(x), _p(v), n, key_bits, fbits, z_lo, z_hi, _p(table), table.size - 1, B,
+                       _p(ko), _p(vo), _p(off))
+    if orig.dtype in (np.uint32, np.int32):
+        ko = ko.astype(np.uint32)
+    return ko, vo, off
+
+
+def _unpack(p, H):
+    return {"w1": p[:H].copy(), "b1": p[H:2 * H].copy(), "w2": p[2 * H:3 * H].copy(), "b2": float(p[3 * H])}
+
+
+def normalised_features(sorted_keys, key_bits: int, fbits: int):
+    """(u in [0,1], z_lo, z_hi) of a sorted sample, fp64."""
+    z = features(sorted_keys, key_bits, fbits).astype(np.float64)
+    z_lo, z_hi = int(features(sorted_keys[:1], key_bits, fbits)[0]), int(features(sorted_keys[-1:], key_bits, fbits)[0])
+    rng_ = z_hi - z_lo
+    u = (z - z_lo) / rng_ if rng_ > 0 else np.zeros_like(z)
+    return u, z_lo, z_hi
+
+
+def cdf_init(u, H: int) -> dict:
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.zeros(3 * H + 1, dtype=np.float64)
+    b2 = ctypes.c_double(0.0)
+    _L().orc_cdf_init(_p(u), u.size, H, _p(p), p[H:].ctypes.data, p[2 * H:].ctypes.data, ctypes.byref(b2))
+    p[3 * H] = b2.value
+    return _unpack(p, H)
+
+
+def cdf_loss(params: dict, u, stride: int = 64) -> float:
+    w1, b1, w2 = (np.ascontiguousarray(params[k], dtype=np.float64) for k in ("w1", "b1", "w2"))
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    return float(_L().orc_cdf_loss(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, _p(u), u.size, stride))
+
+
+def cdf_train(u, H: int, steps: int, nb: int, lr: float):
+    """fp64 reference training: quantile init + Adam; returns (params, loss)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    p = np.zeros(3 * H + 1, dtype=np.float64)
+    loss = _L().orc_cdf_train(_p(u), u.size, H, steps, nb, lr, _p(p))
+    return _unpack(p, H), float(loss)

@@ -1,0 +1,302 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Nothing here compares the oracle with itself: every check is a hand-derived
+value (tests/golden, derived from the paper's definitions), a closed form, an
+invariant stated by the paper's theorem or analysis, a library special case
+(Python's stable sort), or brute force on tiny inputs.
+"""
+import itertools
+import math
+import random
+
+import numpy as np
+import pytest
+
+from conftest import read_golden
+
+import workloads
+
+
+# ---------------------------------------------------------------- minrun --
+def test_minrun_golden(orc):
+    for ((n, l),) in read_golden("minrun.txt"):
+        assert orc.minrun(n) == l, n
+
+
+def test_minrun_closed_form(orc):
+    # Nested ceilings collapse: ceil(ceil(n/2)/2) = ceil(n/4), so the rule
+    # returns ceil(n / 2^k) for the least k with ceil(n / 2^k) < 64.
+    rng = random.Random(5)
+    for n in list(range(1, 3000)) + [rng.randrange(1, 2**40) for _ in range(3000)]:
+        k = 0
+        while -(-n // (1 << k)) >= 64:
+            k += 1
+        assert orc.minrun(n) == -(-n // (1 << k))
+
+
+# ----------------------------------------------------------------- power --
+def test_power_golden(orc):
+    for (n,), bounds, powers, (M,) in read_golden("powers.txt"):
+        b = np.array(bounds, dtype=np.int64)
+        got = orc.run_powers(b, n)
+        assert got.tolist() == powers
+        nodes = orc.tree_nodes(b, n, got)
+        assert int((nodes[:, 2] - nodes[:, 0]).sum()) == M
+
+
+def test_power_ruler_sequence(orc):
+    # Equal runs of length l with n = l * 2^K form a perfect binary tree:
+    # the boundary after run t has power K - (trailing zeros of t+1).
+    for K in range(1, 9):
+        for l in (1, 3, 32):
+            n = l << K
+            bounds = np.arange(0, n + 1, l, dtype=np.int64)
+            got = orc.run_powers(bounds, n)
+            want = [K - ((t + 1) & -(t + 1)).bit_length() + 1 for t in range(bounds.size - 2)]
+            assert got.tolist() == want
+
+
+def test_power_closed_form_matches_definition(orc):
+    for n in range(2, 41):
+        for i in range(0, n):
+            for j in range(i + 1, n):
+                for k in range(j + 1, n + 1):
+                    assert orc.power_def(n, i, j, k) == orc.power_closed(n, i, j, k)
+    rng = random.Random(11)
+    for _ in range(20000):
+        n = rng.randrange(3, 2**32 + 1)
+        i, j, k = sorted(rng.sample(range(0, min(n, 2**62) + 1), 3)) if n < 1000 else sorted(
+            [rng.randrange(0, n - 1), rng.randrange(0, n - 1), rng.randrange(0, n + 1)])
+        if not (i < j < k <= n):
+            continue
+        assert orc.power_def(n, i, j, k) == orc.power_closed(n, i, j, k)
+
+
+def test_power_tree_invariants(orc):
+    # Derived from the theorem: adjacent boundaries never share a power, two
+    # equal powers are separated by a smaller one, max power <= ceil(log2 n).
+    rng = np.random.default_rng(3)
+    for trial in range(60):
+        n = int(rng.integers(2, 5000))
+        cuts = np.unique(np.concatenate([[0, n], rng.integers(1, n, size=int(rng.integers(1, n)))]))
+        P = orc.run_powers(cuts.astype(np.int64), n)
+        if P.size == 0:
+            continue
+        assert int(P.max()) <= math.ceil(math.log2(n))
+        assert np.all(P[1:] != P[:-1])
+        last = {}
+        for t, p in enumerate(P.tolist()):
+            if p in last:
+                assert P[last[p] + 1:t].min() < p
+            last[p] = t
+
+
+# ------------------------------------------------------------ ExtractRun --
+def test_extract_runs_golden(orc):
+    for (ell,), keys, bounds in read_golden("extract_runs.txt"):
+        assert orc.extract_runs(np.array(keys, dtype=np.uint64), ell).tolist() == bounds
+
+
+def _check_runs_characterisation(x, bounds, ell):
+    n = x.size
+    assert bounds[0] == 0 and bounds[-1] == n
+    for s, e in zip(bounds[:-1], bounds[1:]):
+        nat = s + 1
+        while nat < n and x[nat - 1] <= x[nat]:
+            nat += 1
+        if nat - s >= ell:
+            assert e == nat
+        else:
+            assert e == min(n, s + ell)
+
+
+def test_extract_runs_characterisation(orc):
+    rng = np.random.default_rng(9)
+    for trial in range(40):
+        n = int(rng.integers(1, 3000))
+        x = workloads.presorted(n, int(rng.integers(1 << 30)), mean_run=int(rng.choice([2, 20, 80, 400])),
+                                swap_frac=0.0)
+        for ell in (1, 4, 32, orc.minrun(n)):
+            _check_runs_characterisation(x, orc.extract_runs(x, ell), ell)
+
+
+# ------------------------------------------------------------ full sorts --
+def _stable_positions(keys):
+    return sorted(range(len(keys)), key=lambda i: (keys[i], i))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_bruteforce_permutations(orc, variant):
+    for n in range(0, 8):
+        for perm in itertools.permutations(range(n)):
+            keys = np.array(perm, dtype=np.uint64)
+            out, v, st, _ = orc.powersort(keys, np.arange(n, dtype=np.uint32), variant=variant, ell=2)
+            assert out.tolist() == sorted(perm)
+            assert v.tolist() == _stable_positions(list(perm))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_bruteforce_words_stability(orc, variant):
+    # every word over {0,1,2} of length <= 9, minrun forced to 2 so merges happen
+    for n in range(1, 10):
+        for w in itertools.product(range(3), repeat=n):
+            keys = np.array(w, dtype=np.uint64)
+            out, v, _, _ = orc.powersort(keys, np.arange(n, dtype=np.uint32), variant=variant, ell=2)
+            assert v.tolist() == _stable_positions(list(w))
+
+
+def test_stability_golden(orc):
+    for keys, pos in read_golden("stability.txt"):
+        _, v, _, _ = orc.powersort(np.array(keys, dtype=np.uint64), np.arange(len(keys), dtype=np.uint32), ell=2)
+        assert v.tolist() == pos
+
+
+@pytest.mark.parametrize("maker", ["uniform32", "presorted", "mixture", "lognormal", "dup16", "paper"])
+def test_matches_library_stable_sort(orc, maker):
+    rng = np.random.default_rng(21)
+    for trial in range(4):
+        n = int(rng.integers(1, 40000))
+        seed = int(rng.integers(1 << 30))
+        x = {"uniform32": lambda: workloads.uniform(n, 32, seed),
+             "presorted": lambda: workloads.presorted(n, seed, mean_run=256),
+             "mixture": lambda: workloads.mixture(n, seed),
+             "lognormal": lambda: workloads.lognormal(n, seed),
+             "dup16": lambda: workloads.dup16(n, seed),
+             "paper": lambda: workloads.paper_workload(seed, 100, n=n)}[maker]()
+        want = np.argsort(x, kind="stable").astype(np.uint32)
+        for variant in (0, 1, 2):
+            out, v, _, _ = orc.powersort(x, np.arange(n, dtype=np.uint32), variant=variant)
+            assert np.array_equal(v, want)
+            assert np.array_equal(out, x[want])
+
+
+# ------------------------------------------------------------ invariants --
+def test_theorem_bounds_and_counters(orc):
+    rng = np.random.default_rng(4)
+    for trial in range(30):
+        n = int(rng.integers(2, 60000))
+        x = workloads.presorted(n, int(rng.integers(1 << 30)), mean_run=int(rng.choice([4, 64, 1000, 20000])))
+        _, _, pp, log_pp = orc.powersort(x, variant=0, log_merges=True)
+        _, _, lp, log_lp = orc.powersort(x, variant=1, log_merges=True)
+        _, _, cp, log_cp = orc.powersort(x, variant=2, log_merges=True)
+        for st in (pp, lp, cp):
+            # Theorem (Section 2): stack height and merge cost bounds
+            assert st["max_stack"] <= math.ceil(math.log2(n)) + 1
+            assert st["merge_cost"] <= n * (st["entropy"] + 2) + 1e-6
+            # run detection compares each adjacent pair at most once
+            assert st["cmp_run"] <= n - 1
+            assert st["cmp_merge"] <= st["merge_cost"] - st["merges"]
+        # same merges, same merge cost in every buffer scheme
+        assert np.array_equal(log_pp, log_lp) and np.array_equal(log_pp, log_cp)
+        # Pingpong (Section 3): with the right-to-left last pop, pushes copy
+        # only freshly extracted runs, so at most n copies and M + n moves
+        # outside insertion sort.  Without it a merged run is copied again on
+        # push; merges alone still write at most M elements.
+        assert lp["mov_push"] <= n
+        assert lp["mov_push"] + lp["mov_merge"] <= lp["merge_cost"] + n
+        assert pp["mov_merge"] <= pp["merge_cost"]
+        assert lp["mov_push"] + lp["mov_merge"] <= pp["mov_push"] + pp["mov_merge"]
+        # CPython style: copy the smaller run, merge back: <= 1.5 M moves
+        assert cp["mov_merge"] <= 1.5 * cp["merge_cost"]
+
+
+def test_merge_cost_closed_form_perfect_tree(orc):
+    # n = 2^16 uniform keys: every run is forced to l = 32 (a natural run of
+    # 32 has probability ~1/32!), 2^11 runs in a perfect tree, M = 11 n.
+    x = workloads.uniform(1 << 16, 32, 1)
+    _, _, st, _ = orc.powersort(x)
+    assert st["runs"] == 2048
+    assert st["merge_cost"] == 11 * (1 << 16) == 720896
+
+
+def test_sorted_and_constant_inputs(orc):
+    for x in (np.arange(5000, dtype=np.uint64), np.full(5000, 7, dtype=np.uint64)):
+        out, _, st, _ = orc.powersort(x)
+        assert st["runs"] == 1 and st["merge_cost"] == 0 and st["cmp_run"] == x.size - 1
+        assert st["mov_push"] + st["mov_merge"] + st["mov_ins"] == 0
+        assert np.array_equal(out, x)
+
+
+def test_merge_log_equals_tree_form(orc):
+    rng = np.random.default_rng(12)
+    for trial in range(40):
+        n = int(rng.integers(2, 30000))
+        x = workloads.presorted(n, int(rng.integers(1 << 30)), mean_run=int(rng.choice([8, 100, 3000])))
+        _, _, st, log = orc.powersort(x, log_merges=True)
+        b = orc.extract_runs(x)
+        P = orc.run_powers(b, n)
+        nodes = orc.tree_nodes(b, n, P)
+        assert sorted(map(tuple, log.tolist())) == sorted(map(tuple, nodes[:, :3].tolist()))
+        assert st["runs"] == b.size - 1
+
+
+def test_standard_merge(orc):
+    rng = np.random.default_rng(2)
+    for trial in range(100):
+        na, nb = int(rng.integers(0, 300)), int(rng.integers(0, 300))
+        a = np.sort(rng.integers(0, 20, size=na).astype(np.uint64))
+        b = np.sort(rng.integers(0, 20, size=nb).astype(np.uint64))
+        va = np.arange(na, dtype=np.uint32)
+        vb = np.arange(na, na + nb, dtype=np.uint32)
+        out, vout = orc.standard_merge(a, b, va, vb)
+        cat = np.concatenate([a, b])
+        want = np.argsort(cat, kind="stable")
+        assert np.array_equal(out, cat[want]) and np.array_equal(vout, want.astype(np.uint32))
+
+
+# ------------------------------------------------------------------ plan --
+def _execute_plan(x, bounds, powers, T, node_buf, segs, nodes):
+    """Run the planned schedule with two numpy buffers, tracking which buffer
+    holds valid data for every position; merges are stable sorts of the
+    concatenation of two sorted runs (a library special case)."""
+    n = x.size
+    A, B = x.copy(), np.zeros_like(x)
+    bufs = [A, B]
+    where = np.zeros(n, dtype=np.int8)          # everything starts in A
+    for s, e, b in segs:
+        seg = np.sort(A[s:e], kind="stable")
+        bufs[b][s:e] = seg
+        where[s:e] = b
+    order = np.argsort(-nodes[:, 3], kind="stable")
+    for t in order:
+        L, mid, R, p = nodes[t]
+        if R - L <= T:
+            continue
+        src = 1 - node_buf[t]
+        assert np.all(where[L:R] == src), "children not in the opposite buffer"
+        cat = bufs[src][L:R]
+        assert np.all(np.diff(cat[: mid - L].astype(np.float64)) >= 0)
+        bufs[node_buf[t]][L:R] = np.sort(cat, kind="stable")
+        where[L:R] = node_buf[t]
+    assert np.all(where == 0), "result not in the input buffer"
+    return A
+
+
+def test_plan_executes_to_sorted_result(orc):
+    rng = np.random.default_rng(8)
+    for trial in range(40):
+        n = int(rng.integers(1, 50000))
+        x = workloads.presorted(n, int(rng.integers(1 << 30)), mean_run=int(rng.choice([2, 50, 2000])))
+        b = orc.extract_runs(x)
+        P = orc.run_powers(b, n)
+        nodes = orc.tree_nodes(b, n, P)
+        for T in (64, 512, 4096):
+            node_buf, depth, segs, M, Mh = orc.plan(b, n, P, T)
+            assert segs[0, 0] == 0 and segs[-1, 1] == n and np.all(segs[1:, 0] == segs[:-1, 1])
+            for s, e, _ in segs:
+                assert e - s <= T or np.count_nonzero((b > s) & (b < e)) == 0
+            got = _execute_plan(x, b, P, T, node_buf, segs, nodes)
+            assert np.array_equal(got, np.sort(x))
+            assert M == int((nodes[:, 2] - nodes[:, 0]).sum())
+            assert Mh == int(sum(R - L for L, _, R, _ in nodes if R - L > T))
+
+
+def test_plan_depth_perfect_tree(orc):
+    # perfect tree: depth = power - 1, so the buffer is (power - 1) mod 2
+    n = 32 << 8
+    b = np.arange(0, n + 1, 32, dtype=np.int64)
+    P = orc.run_powers(b, n)
+    node_buf, depth, segs, M, Mh = orc.plan(b, n, P, 1024)
+    assert np.array_equal(depth, P.astype(np.int32) - 1)
+    assert M == 8 * n and Mh == 3 * n
+    assert segs.shape[0] == n // 1024 and np.all(segs[:, 2] == 1)

@@ -1,0 +1,143 @@
+"""Pins of the oracle's learned-partition reference (fp64).
+
+Hand-derived feature values, finite differences for the backward pass, a
+closed form for the identity model's buckets, the published SplitMix64
+outputs, and numpy's stable argsort as the partition's library special case.
+"""
+import numpy as np
+import pytest
+
+import workloads
+
+
+def test_splitmix64_published_vectors(orc):
+    # first outputs of splitmix64.c (Vigna, public domain) for seed 1234567
+    want = [6457827717110365317, 3203168211198807973, 9817491932198370423,
+            4593380528125082431, 16408922859458223821]
+    assert [orc.mix64(1234567, i) for i in range(5)] == want
+    pos = orc.sample_positions(1000, 5, 1234567)
+    assert pos.tolist() == [w % 1000 for w in want]
+
+
+def test_feature_hand_values(orc):
+    F = 4
+    cases = {0: 0, 1: 16, 2: 32, 3: 40, 22: 86, 91: 118, 2**63: 64 << 4, 2**64 - 1: (64 << 4) | 15}
+    for k, z in cases.items():
+        assert orc.feature(k, 64, F) == z, k
+    assert orc.feature(2**32 - 1, 32, F) == (32 << 4) | 15
+    assert orc.feature(2**32 + 5, 32, F) == orc.feature(5, 32, F)  # high bits ignored
+
+
+def test_feature_monotone(orc):
+    keys = np.sort(workloads.mixture(3000, 4))
+    z = orc.features(keys, 64, 20)
+    assert np.all(np.diff(z.astype(np.float64)) >= 0)
+
+
+def _rand_params(rng, H):
+    return {"w1": rng.normal(1, 0.5, H), "b1": rng.normal(-0.5, 0.3, H), "w2": rng.normal(0, 1, H),
+            "b2": float(rng.normal())}
+
+
+def test_forward_hand_value(orc):
+    p = {"w1": np.array([1.0, 2.0]), "b1": np.array([0.0, -1.0]), "w2": np.array([0.5, -0.25]), "b2": 0.1}
+    # u = 0.75: 0.1 + 0.5*relu(0.75) - 0.25*relu(0.5) = 0.1 + 0.375 - 0.125
+    assert orc.mlp_forward(p, 0.75) == pytest.approx(0.35, abs=1e-15)
+    # u = 0.25: second unit inactive
+    assert orc.mlp_forward(p, 0.25) == pytest.approx(0.225, abs=1e-15)
+
+
+def test_gradient_matches_finite_differences(orc):
+    rng = np.random.default_rng(1)
+    for H in (1, 4, 32):
+        p = _rand_params(rng, H)
+        u = rng.random(257)
+        y = rng.random(257)
+        loss, g = orc.mlp_grad(p, u, y)
+        eps = 1e-6
+        for name in ("w1", "b1", "w2", "b2"):
+            for idx in (range(H) if name != "b2" else [None]):
+                hi = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+                lo = {k: (v.copy() if isinstance(v, np.ndarray) else v) for k, v in p.items()}
+                if idx is None:
+                    hi[name] += eps; lo[name] -= eps
+                    gi = g[name]
+                else:
+                    hi[name][idx] += eps; lo[name][idx] -= eps
+                    gi = g[name][idx]
+                fd = (orc.mlp_grad(hi, u, y)[0] - orc.mlp_grad(lo, u, y)[0]) / (2 * eps)
+                assert gi == pytest.approx(fd, rel=1e-4, abs=1e-7), (H, name, idx)
+
+
+def test_identity_table_and_buckets_closed_form(orc):
+    # f(u) = u gives knots floor(s/K * 2^32) (last one saturates at 2^32-1) and,
+    # for K and B powers of two, bucket = floor(d B / range) by nested floors.
+    K, B = 64, 256
+    ident = {"w1": np.array([1.0]), "b1": np.array([0.0]), "w2": np.array([1.0]), "b2": 0.0}
+    t = orc.cdf_table(ident, K)
+    assert t[:K].tolist() == [(s << 32) // K for s in range(K)]
+    assert t[K] == 2**32 - 1
+    z_lo, z_hi = 1000, 1000 + 12345
+    rng = np.random.default_rng(0)
+    for d in list(range(0, 200)) + rng.integers(0, 12345, 500).tolist():
+        seg = d * K // 12345
+        if seg >= K - 1:
+            continue
+        # a key whose feature is z_lo + d: with fbits = 40 and bitlen 41 the
+        # feature of key k is (41 << 40) | (k - 2^40); pick z_lo accordingly
+        key = (1 << 40) + d
+        zl = orc.feature(1 << 40, 64, 40)
+        assert orc.bucket_of(key, 64, 40, zl, zl + 12345, t, B) == d * B // 12345
+    del z_lo, z_hi
+
+
+def test_table_monotone_and_buckets_monotone(orc):
+    rng = np.random.default_rng(7)
+    for trial in range(10):
+        p = _rand_params(rng, 8)
+        t = orc.cdf_table(p, 128)
+        assert np.all(np.diff(t.astype(np.float64)) >= 0)
+        keys = np.sort(workloads.lognormal(2000, trial))
+        z = orc.features(keys, 64, 20)
+        b = [orc.bucket_of(int(k), 64, 20, int(z[10]), int(z[-10]), t, 1000) for k in keys]
+        assert all(x <= y for x, y in zip(b, b[1:]))
+        assert max(b) < 1000
+
+
+def test_partition_is_stable_counting_sort(orc):
+    rng = np.random.default_rng(3)
+    for trial in range(5):
+        n = int(rng.integers(1, 5000))
+        keys = workloads.lognormal(n, trial)
+        vals = np.arange(n, dtype=np.uint32)
+        p = _rand_params(rng, 4)
+        t = orc.cdf_table(p, 64)
+        zs = orc.features(np.sort(keys), 64, 20)
+        z_lo, z_hi, B = int(zs[0]), int(zs[-1]), 97
+        ko, vo, off = orc.partition(keys, 64, 20, z_lo, z_hi, t, B, vals=vals)
+        ids = np.array([orc.bucket_of(int(k), 64, 20, z_lo, z_hi, t, B) for k in keys])
+        order = np.argsort(ids, kind="stable")
+        assert np.array_equal(vo, order.astype(np.uint32)) and np.array_equal(ko, keys[order])
+        assert np.array_equal(off, np.concatenate([[0], np.cumsum(np.bincount(ids, minlength=B))]))
+
+
+def test_quantile_init_interpolates_ecdf(orc):
+    keys = np.sort(workloads.lognormal(1 << 14, 5))
+    u, z_lo, z_hi = orc.normalised_features(keys, 64, 20)
+    H = 16
+    p = orc.cdf_init(u, H)
+    m = u.size
+    for h in range(H):
+        qi = h * (m - 1) // (H - 1)
+        if h == 0 or u[qi] > u[(h - 1) * (m - 1) // (H - 1)]:
+            assert orc.mlp_forward(p, float(u[qi])) == pytest.approx((qi + 0.5) / m, abs=1e-9)
+    assert orc.mlp_forward(p, -1.0) == pytest.approx(0.5 / m)
+
+
+def test_training_does_not_increase_loss(orc):
+    keys = np.sort(workloads.lognormal(1 << 14, 6))
+    u, _, _ = orc.normalised_features(keys, 64, 20)
+    p0 = orc.cdf_init(u, 32)
+    l0 = orc.cdf_loss(p0, u)
+    p1, l1 = orc.cdf_train(u, 32, 64, 1024, 1e-4)
+    assert l1 <= l0

@@ -1,0 +1,247 @@
+"""Python binding of libvmps.so: stable run-adaptive sorting on MI355X.
+
+Argument marshalling only.  Every step of the sort runs in the HIP kernels
+of ``libvmps.so``; PyTorch provides device memory and the current stream.
+Importing works without a GPU, but calling any entry point requires the
+built library and a HIP device: there is no CPU fallback.
+
+Tensors may be torch.int32/uint32 (keys compared as unsigned 32-bit) or
+torch.int64/uint64 (unsigned 64-bit), contiguous, on the current device.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "VmpsError", "load_library", "library_path", "minrun", "max_runs", "sort_", "argsort_", "merge",
+    "extract_runs", "run_powers", "sort_schedule", "segmented_sort_", "sort_workspace_size",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libvmps.so")
+_lib = None
+
+OK, INVALID_ARG, WORKSPACE_TOO_SMALL, UNSUPPORTED, DEVICE = range(5)
+U32, U64 = 0, 1
+VALUES_IOTA = 1
+
+
+class VmpsError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__(f"{where}: {status_string(status)} ({status})")
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libvmps.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with paper_2605_27147_amd/build.py")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i64, i32, u32, sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "vmps_status_string": (ctypes.c_char_p, [st]),
+        "vmps_minrun": (i32, [i64]),
+        "vmps_max_runs": (i64, [i64, i32]),
+        "vmps_sort_workspace_size": (st, [i64, st, st, ctypes.POINTER(sz)]),
+        "vmps_sort": (st, [vp, vp, i64, st, u32, vp, sz, vp]),
+        "vmps_merge_workspace_size": (st, [i64, i64, st, ctypes.POINTER(sz)]),
+        "vmps_merge": (st, [vp, vp, i64, vp, vp, i64, vp, vp, st, vp, sz, vp]),
+        "vmps_extract_runs": (st, [vp, i64, st, i32, vp, vp, vp, sz, vp]),
+        "vmps_run_powers": (st, [vp, vp, i64, i64, vp, vp]),
+        "vmps_sort_schedule": (st, [vp, i64, st, st, vp, vp, vp, vp, vp, vp, vp, vp, vp,
+                                    ctypes.POINTER(i32), vp, sz, vp]),
+        "vmps_segmented_sort_workspace_size": (st, [i64, i64, st, st, ctypes.POINTER(sz)]),
+        "vmps_segmented_sort": (st, [vp, vp, vp, i64, i64, st, vp, sz, vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(s: int) -> str:
+    try:
+        return load_library().vmps_status_string(s).decode()
+    except ImportError:
+        return {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported",
+                4: "device error"}.get(s, "unknown status")
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        raise VmpsError(status, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype in (torch.int32, getattr(torch, "uint32", torch.int32)):
+        return U32
+    if t.dtype in (torch.int64, getattr(torch, "uint64", torch.int64)):
+        return U64
+    raise TypeError(f"keys must be 32- or 64-bit integers, got {t.dtype}")
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None:
+            if not t.is_cuda:
+                raise ValueError("tensors must live on the GPU")
+            if not t.is_contiguous():
+                raise ValueError("tensors must be contiguous")
+
+
+def _workspace(nbytes: int, device):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def minrun(n: int) -> int:
+    return int(load_library().vmps_minrun(n))
+
+
+def max_runs(n: int, minrun_: int = 0) -> int:
+    return int(load_library().vmps_max_runs(n, minrun_))
+
+
+def sort_workspace_size(n: int, dtype_code: int, has_values: bool) -> int:
+    out = ctypes.c_size_t(0)
+    _check(load_library().vmps_sort_workspace_size(n, dtype_code, int(bool(has_values)), ctypes.byref(out)),
+           "vmps_sort_workspace_size")
+    return out.value
+
+
+def sort_(keys, values=None, *, iota: bool = False, workspace=None):
+    """Stable in-place sort of keys (and values).  iota=True fills `values`
+    with the stable permutation instead of reading it."""
+    lib = load_library()
+    _require_cuda(keys, values)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    ws_bytes = sort_workspace_size(n, kt, values is not None)
+    ws = workspace if workspace is not None else _workspace(ws_bytes, keys.device)
+    flags = VALUES_IOTA if iota else 0
+    _check(lib.vmps_sort(_ptr(keys), _ptr(values), n, kt, flags, _ptr(ws), ws.numel(), _stream(keys.device)),
+           "vmps_sort")
+    return keys
+
+
+def argsort_(keys, indices):
+    """Sort keys in place and write the stable permutation into indices (int32)."""
+    return sort_(keys, indices, iota=True)
+
+
+def merge(a, b, va=None, vb=None, out=None, vout=None):
+    torch = _torch()
+    lib = load_library()
+    _require_cuda(a, b, va, vb)
+    kt = _dtype_code(a)
+    if _dtype_code(b) != kt:
+        raise TypeError("a and b must have the same key type")
+    na, nb = a.numel(), b.numel()
+    if out is None:
+        out = torch.empty(na + nb, dtype=a.dtype, device=a.device)
+    if va is not None and vout is None:
+        vout = torch.empty(na + nb, dtype=va.dtype, device=a.device)
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_merge_workspace_size(na, nb, kt, ctypes.byref(need)), "vmps_merge_workspace_size")
+    ws = _workspace(need.value, a.device)
+    _check(lib.vmps_merge(_ptr(a), _ptr(va), na, _ptr(b), _ptr(vb), nb, _ptr(out), _ptr(vout), kt, _ptr(ws),
+                          ws.numel(), _stream(a.device)), "vmps_merge")
+    return out, vout
+
+
+def extract_runs(keys, minrun_: int = 0):
+    """(run_bounds int32 tensor of r+1 bounds, r) — synchronises to read r."""
+    torch = _torch()
+    lib = load_library()
+    _require_cuda(keys)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    cap = max_runs(n, minrun_)
+    bounds = torch.empty(cap + 1, dtype=torch.int32, device=keys.device)
+    nr = torch.zeros(1, dtype=torch.int64, device=keys.device)
+    ws = _workspace(sort_workspace_size(n, kt, False), keys.device)
+    _check(lib.vmps_extract_runs(_ptr(keys), n, kt, minrun_, _ptr(bounds), _ptr(nr), _ptr(ws), ws.numel(),
+                                 _stream(keys.device)), "vmps_extract_runs")
+    r = int(nr.item())
+    return bounds[: r + 1], r
+
+
+def run_powers(bounds, r: int, n: int):
+    torch = _torch()
+    lib = load_library()
+    _require_cuda(bounds)
+    nr = torch.tensor([r], dtype=torch.int64, device=bounds.device)
+    powers = torch.zeros(max(r - 1, 1), dtype=torch.uint8, device=bounds.device)
+    _check(lib.vmps_run_powers(_ptr(bounds), _ptr(nr), n, max(r, 0), _ptr(powers), _stream(bounds.device)),
+           "vmps_run_powers")
+    return powers[: max(r - 1, 0)]
+
+
+def sort_schedule(keys, has_values: bool = False):
+    """The merge schedule vmps_sort would run: dict of host numpy arrays."""
+    torch = _torch()
+    lib = load_library()
+    _require_cuda(keys)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    cap = max_runs(n, 0) + 1
+    dev = keys.device
+    u32 = lambda: torch.zeros(cap, dtype=torch.int32, device=dev)
+    u8 = lambda: torch.zeros(cap, dtype=torch.uint8, device=dev)
+    nl, nm, nr_, nlev, nbuf, ss, se, sb = u32(), u32(), u32(), u8(), u8(), u32(), u32(), u8()
+    counts = torch.zeros(4, dtype=torch.int64, device=dev)
+    tile = ctypes.c_int32(0)
+    ws = _workspace(sort_workspace_size(n, kt, has_values), dev)
+    _check(lib.vmps_sort_schedule(_ptr(keys), n, kt, int(bool(has_values)), _ptr(nl), _ptr(nm), _ptr(nr_),
+                                  _ptr(nlev), _ptr(nbuf), _ptr(ss), _ptr(se), _ptr(sb), _ptr(counts),
+                                  ctypes.byref(tile), _ptr(ws), ws.numel(), _stream(dev)), "vmps_sort_schedule")
+    c = counts.cpu().tolist()
+    h, ns = int(c[1]), int(c[2])
+    return {
+        "runs": int(c[0]), "merge_cost": int(c[3]), "tile": tile.value,
+        "node_l": nl[:h].cpu().numpy(), "node_m": nm[:h].cpu().numpy(), "node_r": nr_[:h].cpu().numpy(),
+        "node_level": nlev[:h].cpu().numpy(), "node_buf": nbuf[:h].cpu().numpy(),
+        "seg_start": ss[:ns].cpu().numpy(), "seg_end": se[:ns].cpu().numpy(), "seg_buf": sb[:ns].cpu().numpy(),
+    }
+
+
+def segmented_sort_(keys, offsets, values=None):
+    """Independent stable sorts of keys[offsets[s]:offsets[s+1]] (offsets: int64 on the GPU)."""
+    lib = load_library()
+    _require_cuda(keys, values, offsets)
+    kt = _dtype_code(keys)
+    total = keys.numel()
+    nseg = offsets.numel() - 1
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_segmented_sort_workspace_size(total, max(nseg, 0), kt, int(values is not None),
+                                                  ctypes.byref(need)), "vmps_segmented_sort_workspace_size")
+    ws = _workspace(need.value, keys.device)
+    _check(lib.vmps_segmented_sort(_ptr(keys), _ptr(values), _ptr(offsets), nseg, total, kt, _ptr(ws),
+                                   ws.numel(), _stream(keys.device)), "vmps_segmented_sort")
+    return keys

@@ -1,0 +1,342 @@
+// C ABI of libvmps.so: argument checks, workspace carving, launch order.
+#include <string.h>
+
+#include "vmps_internal.hpp"
+
+using namespace vmps;
+
+namespace {
+
+inline int key_bits_of(vmps_dtype kt) { return kt == VMPS_U64 ? 64 : 32; }
+inline size_t key_bytes(vmps_dtype kt) { return kt == VMPS_U64 ? 8 : 4; }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + bbytes && y < x + abytes;
+}
+
+inline vmps_status dev_status(hipError_t e) { return e == hipSuccess ? VMPS_OK : VMPS_ERR_DEVICE; }
+
+// Workspace layout of a sort: [B keys][B values][plan]
+struct SortLayout {
+    size_t keys_b, vals_b, plan, total;
+};
+
+SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values)
+{
+    const int kb = key_bits_of(kt);
+    SortLayout L;
+    L.keys_b = 0;
+    L.vals_b = align256(key_bytes(kt) * n);
+    L.plan = L.vals_b + (has_values ? align256(4 * n) : 0);
+    const uint32_t T = tilesort_capacity(kb, has_values);
+    const uint32_t TO = merge_tile_out(kb, has_values);
+    L.total = L.plan + plan_workspace_bytes(n, k, T, TO);
+    return L;
+}
+
+__global__ void k_single_segment(uint32_t* inst_start, uint32_t n, Seg* segs, uint32_t* counters)
+{
+    inst_start[0] = 0;
+    inst_start[1] = n;
+    Seg s;
+    s.start = 0; s.end = n; s.inst = 0; s.dst = 0;
+    segs[0] = s;
+    for (int c = 0; c < CNT_COUNT; ++c) counters[c] = 0;
+    counters[CNT_NSEG] = 1;
+}
+
+__global__ void k_write_zero_u32(uint32_t* p) { *p = 0; }
+__global__ void k_write_zero_i64(int64_t* p) { *p = 0; }
+
+__global__ void k_powers(const uint32_t* __restrict__ bounds, const int64_t* __restrict__ num_runs, uint64_t n,
+                         uint8_t* __restrict__ powers, uint64_t cap)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t r = *num_runs;
+    if (r < 2 || t + 1 >= (uint64_t)r || t >= cap) return;
+    const uint64_t i = bounds[t], j = bounds[t + 1], k = bounds[t + 2];
+    const uint64_t A = ((i + j) << 31) / n, B = ((j + k) << 31) / n;
+    powers[t] = (uint8_t)(__clz((uint32_t)(A ^ B)) + 1);
+}
+
+__global__ void k_export_runs(const uint32_t* __restrict__ run_start, const uint32_t* counters,
+                              uint32_t* __restrict__ out, int64_t* num_runs, uint64_t cap)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nr = counters[CNT_NRUNS];
+    if (t == 0) *num_runs = nr;
+    if (t <= nr && t <= cap) out[t] = run_start[t];
+}
+
+__global__ void k_export_schedule(Plan P, uint32_t* node_l, uint32_t* node_m, uint32_t* node_r,
+                                  uint8_t* node_level, uint8_t* node_buf, uint32_t* seg_start, uint32_t* seg_end,
+                                  uint8_t* seg_buf, int64_t* counts)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t h = P.counters[CNT_NHBM], ns = P.counters[CNT_NSEG];
+    if (x == 0) {
+        counts[0] = P.counters[CNT_NRUNS];
+        counts[1] = h;
+        counts[2] = ns;
+        counts[3] = (int64_t)P.stats[0];
+    }
+    if (x < h) {
+        const uint32_t t = P.hbm_list[x];
+        node_l[x] = P.bnd_lpos[t];
+        node_m[x] = P.run_start[t + 1];
+        node_r[x] = P.bnd_rpos[t];
+        node_level[x] = P.power[t];
+        node_buf[x] = (uint8_t)(P.hbm_depth[x] & 1u);
+    }
+    if (x < ns) {
+        seg_start[x] = P.segs[x].start;
+        seg_end[x] = P.segs[x].end;
+        seg_buf[x] = (uint8_t)P.segs[x].dst;
+    }
+}
+
+template <typename F>
+vmps_status guarded(F f)
+{
+    hipError_t e = f();
+    if (e != hipSuccess) return VMPS_ERR_DEVICE;
+    return dev_status(hipGetLastError());
+}
+
+vmps_status check_keys(const void* keys, int64_t n, vmps_dtype kt)
+{
+    if (n < 0 || (uint64_t)n >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    if (n > 0 && !keys) return VMPS_ERR_INVALID_ARG;
+    if (keys && ((uintptr_t)keys % key_bytes(kt))) return VMPS_ERR_INVALID_ARG;
+    return VMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* vmps_status_string(vmps_status s)
+{
+    switch (s) {
+    case VMPS_OK: return "ok";
+    case VMPS_ERR_INVALID_ARG: return "invalid argument";
+    case VMPS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case VMPS_ERR_UNSUPPORTED: return "unsupported";
+    case VMPS_ERR_DEVICE: return "device error";
+    }
+    return "unknown status";
+}
+
+int32_t vmps_minrun(int64_t n) { return n <= 0 ? 0 : (int32_t)minrun_of((uint64_t)n); }
+
+int64_t vmps_max_runs(int64_t n, int32_t minrun)
+{
+    if (n <= 0) return 0;
+    (void)minrun;  // runs are at least 16 long except the last one
+    return (int64_t)((uint64_t)n / 16 + 3);
+}
+
+vmps_status vmps_sort_workspace_size(int64_t n, vmps_dtype kt, int has_values, size_t* bytes)
+{
+    if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    *bytes = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0).total;
+    return VMPS_OK;
+}
+
+vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
+                      size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (flags & ~VMPS_VALUES_IOTA) return VMPS_ERR_INVALID_ARG;
+    if ((flags & VMPS_VALUES_IOTA) && !values && n > 0) return VMPS_ERR_INVALID_ARG;
+    if (values && ((uintptr_t)values & 3)) return VMPS_ERR_INVALID_ARG;
+    if (values && n > 0 && ranges_overlap(keys, key_bytes(kt) * n, values, 4 * (size_t)n)) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 1) {
+        if (n == 1 && (flags & VMPS_VALUES_IOTA))
+            return guarded([&] { k_write_zero_u32<<<1, 1, 0, s>>>(values); return hipGetLastError(); });
+        return VMPS_OK;
+    }
+    const int has_values = values ? 1 : 0;
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values);
+    if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    const int kb = key_bits_of(kt);
+    const int vmode = values ? ((flags & VMPS_VALUES_IOTA) ? 2 : 1) : 0;
+    uint8_t* w = (uint8_t*)ws;
+    void* keysB = w + L.keys_b;
+    uint32_t* valsB = has_values ? (uint32_t*)(w + L.vals_b) : nullptr;
+    Plan P;
+    const uint32_t T = tilesort_capacity(kb, has_values);
+    plan_carve(P, w + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values));
+    P.big_min = T;
+    return guarded([&]() -> hipError_t {
+        if ((uint64_t)n <= T) {
+            k_single_segment<<<1, 1, 0, s>>>(P.inst_start, (uint32_t)n, P.segs, P.counters);
+            return tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s);
+        }
+        VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
+        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
+    });
+}
+
+vmps_status vmps_merge_workspace_size(int64_t na, int64_t nb, vmps_dtype kt, size_t* bytes)
+{
+    if (!bytes || na < 0 || nb < 0 || (uint64_t)(na + nb) >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    *bytes = align256(4 * (ceil_div((uint64_t)(na + nb), 4096) + 2));
+    return VMPS_OK;
+}
+
+vmps_status vmps_merge(const void* a, const uint32_t* va, int64_t na, const void* b, const uint32_t* vb, int64_t nb,
+                       void* out, uint32_t* vout, vmps_dtype kt, void* ws, size_t ws_bytes, void* stream)
+{
+    if (na < 0 || nb < 0 || (uint64_t)(na + nb) >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    vmps_status st = check_keys(a, na, kt);
+    if (st == VMPS_OK) st = check_keys(b, nb, kt);
+    if (st == VMPS_OK) st = check_keys(out, na + nb, kt);
+    if (st != VMPS_OK) return st;
+    const bool vals = va || vb || vout;
+    if (vals && ((na > 0 && !va) || (nb > 0 && !vb) || (na + nb > 0 && !vout))) return VMPS_ERR_INVALID_ARG;
+    const size_t kbytes = key_bytes(kt);
+    if (na + nb > 0) {
+        if (na > 0 && ranges_overlap(out, kbytes * (na + nb), a, kbytes * na)) return VMPS_ERR_INVALID_ARG;
+        if (nb > 0 && ranges_overlap(out, kbytes * (na + nb), b, kbytes * nb)) return VMPS_ERR_INVALID_ARG;
+    }
+    size_t need = 0;
+    vmps_merge_workspace_size(na, nb, kt, &need);
+    if (na + nb == 0) return VMPS_OK;
+    if (!ws || ws_bytes < need) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        return merge_two_enqueue(a, vals ? va : nullptr, (uint32_t)na, b, vals ? vb : nullptr, (uint32_t)nb, out,
+                                 vals ? vout : nullptr, key_bits_of(kt), (uint32_t*)ws, s);
+    });
+}
+
+vmps_status vmps_extract_runs(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun, uint32_t* run_bounds,
+                              int64_t* num_runs, void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (!run_bounds || !num_runs) return VMPS_ERR_INVALID_ARG;
+    const uint32_t ell = minrun > 0 ? (uint32_t)minrun : (n > 0 ? minrun_of((uint64_t)n) : 1u);
+    if (minrun > 0 && (int64_t)ell < (n < 16 ? n : 16)) return VMPS_ERR_INVALID_ARG;
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, 0);
+    if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n == 0) {
+        return guarded([&] {
+            k_write_zero_u32<<<1, 1, 0, s>>>(run_bounds);
+            k_write_zero_i64<<<1, 1, 0, s>>>(num_runs);
+            return hipGetLastError();
+        });
+    }
+    const int kb = key_bits_of(kt);
+    Plan P;
+    plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, tilesort_capacity(kb, 0), merge_tile_out(kb, 0));
+    P.big_min = 0;
+    return guarded([&]() -> hipError_t {
+        VMPS_HIP(plan_enqueue(P, keys, kb, minrun > 0 ? (uint32_t)minrun : 0u, s));
+        const uint64_t cap = (uint64_t)vmps_max_runs(n, minrun);
+        k_export_runs<<<(unsigned)ceil_div(cap + 1, 256), 256, 0, s>>>(P.run_start, P.counters, run_bounds,
+                                                                       num_runs, cap);
+        return hipGetLastError();
+    });
+}
+
+vmps_status vmps_run_powers(const uint32_t* run_bounds, const int64_t* num_runs, int64_t n, int64_t max_runs,
+                            uint8_t* powers, void* stream)
+{
+    if (!run_bounds || !num_runs || !powers || n < 1 || (uint64_t)n >= (1ull << 32) || max_runs < 0)
+        return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (max_runs < 2) return VMPS_OK;
+    return guarded([&] {
+        k_powers<<<(unsigned)ceil_div((uint64_t)max_runs, 256), 256, 0, s>>>(run_bounds, num_runs, (uint64_t)n,
+                                                                            powers, (uint64_t)max_runs);
+        return hipGetLastError();
+    });
+}
+
+vmps_status vmps_sort_schedule(const void* keys, int64_t n, vmps_dtype kt, int has_values, uint32_t* node_l,
+                               uint32_t* node_m, uint32_t* node_r, uint8_t* node_level, uint8_t* node_buf,
+                               uint32_t* seg_start, uint32_t* seg_end, uint8_t* seg_buf, int64_t* counts,
+                               int32_t* tile, void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (n < 1 || !node_l || !node_m || !node_r || !node_level || !node_buf || !seg_start || !seg_end || !seg_buf ||
+        !counts || !tile)
+        return VMPS_ERR_INVALID_ARG;
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0);
+    if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    const int kb = key_bits_of(kt);
+    const uint32_t T = tilesort_capacity(kb, has_values ? 1 : 0);
+    *tile = (int32_t)T;
+    Plan P;
+    plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values ? 1 : 0));
+    P.big_min = 0;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&]() -> hipError_t {
+        VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        const uint64_t cap = (uint64_t)vmps_max_runs(n, 0) + 1;
+        k_export_schedule<<<(unsigned)ceil_div(cap, 256), 256, 0, s>>>(P, node_l, node_m, node_r, node_level,
+                                                                       node_buf, seg_start, seg_end, seg_buf,
+                                                                       counts);
+        return hipGetLastError();
+    });
+}
+
+vmps_status vmps_segmented_sort_workspace_size(int64_t total, int64_t nseg, vmps_dtype kt, int has_values,
+                                               size_t* bytes)
+{
+    if (!bytes || total < 0 || (uint64_t)total >= (1ull << 32) || nseg < 0 || (uint64_t)nseg >= (1ull << 31))
+        return VMPS_ERR_INVALID_ARG;
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    *bytes = sort_layout((uint64_t)total, (uint64_t)(nseg > 0 ? nseg : 1), kt, has_values ? 1 : 0).total;
+    return VMPS_OK;
+}
+
+vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg_offsets, int64_t nseg,
+                                int64_t total, vmps_dtype kt, void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys, total, kt);
+    if (st != VMPS_OK) return st;
+    if (nseg < 0 || (uint64_t)nseg >= (1ull << 31) || !seg_offsets) return VMPS_ERR_INVALID_ARG;
+    if ((uintptr_t)seg_offsets & 7) return VMPS_ERR_INVALID_ARG;
+    if (values && ((uintptr_t)values & 3)) return VMPS_ERR_INVALID_ARG;
+    if (values && total > 0 && ranges_overlap(keys, key_bytes(kt) * total, values, 4 * (size_t)total))
+        return VMPS_ERR_INVALID_ARG;
+    if (nseg == 0 || total <= 1) return VMPS_OK;
+    const int has_values = values ? 1 : 0;
+    const SortLayout L = sort_layout((uint64_t)total, (uint64_t)nseg, kt, has_values);
+    if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    const int kb = key_bits_of(kt);
+    uint8_t* w = (uint8_t*)ws;
+    void* keysB = w + L.keys_b;
+    uint32_t* valsB = has_values ? (uint32_t*)(w + L.vals_b) : nullptr;
+    Plan P;
+    const uint32_t T = tilesort_capacity(kb, has_values);
+    plan_carve(P, w + L.plan, (uint64_t)total, (uint64_t)nseg, T, merge_tile_out(kb, has_values));
+    P.inst_off64 = seg_offsets;
+    P.big_min = T;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&]() -> hipError_t {
+        VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
+        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
+    });
+}
+
+}  // extern "C"

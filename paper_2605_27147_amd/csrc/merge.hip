@@ -1,0 +1,266 @@
+// Merges longer than an LDS tile, one tree level (one power) per launch.
+//
+// Every merge [L,Mid) + [Mid,R) of the level is cut into output tiles of
+// T_out elements aligned to multiples of T_out in the array; the cut points
+// of the two inputs come from a merge-path binary search (the output prefix
+// of length d holds the first i elements of the left run and the first d-i
+// of the right run).  This plays the role of PageMerge in Algorithm 2: a
+// merge into a bounded output page whose trip count is fixed, so the inner
+// loop needs no output bound check.  Ties go to the left run (StandardMerge).
+#include "vmps_internal.hpp"
+
+namespace vmps {
+
+// Number of elements of a among the first d outputs of the stable merge.
+template <typename K>
+__device__ inline uint32_t merge_path(const K* __restrict__ a, uint32_t na, const K* __restrict__ b,
+                                      uint32_t nb, uint32_t d)
+{
+    uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a[mid] <= b[d - 1 - mid]) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// Merge a[i0,i1) and b[j0,j1) into out[0, (i1-i0)+(j1-j0)) through LDS.
+template <typename K, bool VAL, int NT, int KI>
+__device__ inline void merge_tile(const K* __restrict__ a, const uint32_t* __restrict__ va, uint32_t i0,
+                                  uint32_t i1, const K* __restrict__ b, const uint32_t* __restrict__ vb,
+                                  uint32_t j0, uint32_t j1, K* __restrict__ out, uint32_t* __restrict__ vout,
+                                  K* S, uint32_t* SV, K* SO, uint32_t* SOV)
+{
+    const uint32_t na = i1 - i0, nb = j1 - j0, nt = na + nb;
+    for (uint32_t i = threadIdx.x; i < na; i += NT) {
+        S[i] = a[i0 + i];
+        if (VAL) SV[i] = va[i0 + i];
+    }
+    for (uint32_t i = threadIdx.x; i < nb; i += NT) {
+        S[na + i] = b[j0 + i];
+        if (VAL) SV[na + i] = vb[j0 + i];
+    }
+    __syncthreads();
+    const uint32_t d = threadIdx.x * KI;
+    if (d < nt) {
+        const K* A = S;
+        const K* B = S + na;
+        uint32_t ia = merge_path<K>(A, na, B, nb, d);
+        uint32_t jb = d - ia;
+        const uint32_t stop = min(nt, d + KI);
+        for (uint32_t o = d; o < stop; ++o) {
+            const bool takeA = ia < na && (jb >= nb || A[ia] <= B[jb]);
+            if (takeA) {
+                SO[o] = A[ia];
+                if (VAL) SOV[o] = SV[ia];
+                ++ia;
+            } else {
+                SO[o] = B[jb];
+                if (VAL) SOV[o] = SV[na + jb];
+                ++jb;
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < nt; i += NT) {
+        out[i] = SO[i];
+        if (VAL) vout[i] = SOV[i];
+    }
+    __syncthreads();
+}
+
+struct LevelArgs {
+    const uint32_t* table;
+    const uint32_t* hbm_list;
+    const uint32_t* lpos;
+    const uint32_t* rpos;
+    const uint32_t* run_start;
+    const uint32_t* depth;
+    const uint32_t* counters;
+    uint32_t* splits;
+    uint32_t n_tiles_out;
+    uint32_t T_out;
+    uint32_t level;
+};
+
+template <typename K>
+__global__ void k_level_partition(LevelArgs A, const K* __restrict__ keysA, const K* __restrict__ keysB)
+{
+    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t tile = (uint32_t)(x >> 1), slot = (uint32_t)(x & 1);
+    if (tile >= A.n_tiles_out) return;
+    const uint32_t q = A.table[((uint64_t)A.level * A.n_tiles_out + tile) * 2 + slot];
+    if (q == NONE) return;
+    const uint32_t t = A.hbm_list[q];
+    const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+    const K* src = (A.depth[q] & 1u) ? keysA : keysB;  // node writes to depth parity, reads the other
+    const uint64_t t0 = (uint64_t)tile * A.T_out;
+    const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
+    const uint32_t o1 = (uint32_t)(R < t0 + A.T_out ? R : t0 + A.T_out);
+    const uint32_t i0 = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o0 - L);
+    const uint32_t i1 = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o1 - L);
+    A.splits[(uint64_t)tile * 4 + slot * 2 + 0] = i0;
+    A.splits[(uint64_t)tile * 4 + slot * 2 + 1] = i1;
+}
+
+template <typename K, bool VAL, int NT, int KI>
+__global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__ keysA, K* __restrict__ keysB,
+                                                    uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB)
+{
+    constexpr uint32_t TO = NT * KI;
+    extern __shared__ __align__(16) uint8_t smem[];
+    K* S = (K*)smem;
+    K* SO = S + TO;
+    uint32_t* SV = (uint32_t*)(SO + TO);
+    uint32_t* SOV = SV + (VAL ? TO : 0);
+    for (uint32_t tile = blockIdx.x; tile < A.n_tiles_out; tile += gridDim.x) {
+        for (uint32_t slot = 0; slot < 2; ++slot) {
+            const uint32_t q = A.table[((uint64_t)A.level * A.n_tiles_out + tile) * 2 + slot];
+            if (q == NONE) continue;
+            const uint32_t t = A.hbm_list[q];
+            const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+            const bool dstB = (A.depth[q] & 1u) != 0;
+            K* src = dstB ? keysA : keysB;
+            K* dst = dstB ? keysB : keysA;
+            uint32_t* vsrc = dstB ? valsA : valsB;
+            uint32_t* vdst = dstB ? valsB : valsA;
+            const uint64_t t0 = (uint64_t)tile * TO;
+            const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
+            const uint32_t i0 = A.splits[(uint64_t)tile * 4 + slot * 2 + 0];
+            const uint32_t i1 = A.splits[(uint64_t)tile * 4 + slot * 2 + 1];
+            const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
+            const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
+            merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid,
+                                       VAL ? vsrc + Mid : nullptr, j0, j1, dst + o0,
+                                       VAL ? vdst + o0 : nullptr, S, SV, SO, SOV);
+        }
+    }
+}
+
+template <typename K, bool VAL, int NT, int KI>
+static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
+                                hipStream_t s)
+{
+    constexpr uint32_t TO = NT * KI;
+    constexpr size_t lds = 2 * sizeof(K) * TO + (VAL ? 2 * sizeof(uint32_t) * TO : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+        VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        attr_set = true;
+    }
+    LevelArgs A;
+    A.table = P.level_table;
+    A.hbm_list = P.hbm_list;
+    A.lpos = P.bnd_lpos;
+    A.rpos = P.bnd_rpos;
+    A.run_start = P.run_start;
+    A.depth = P.hbm_depth;
+    A.counters = P.counters;
+    A.splits = P.splits;
+    A.n_tiles_out = P.n_tiles_out;
+    A.T_out = TO;
+    uint32_t top = 1;
+    while (top < 32 && (1ull << top) < P.n) ++top;  // powers never exceed ceil(log2 n)
+    const unsigned pgrid = (unsigned)ceil_div((uint64_t)P.n_tiles_out * 2, 256);
+    const unsigned mgrid = P.n_tiles_out < 2048 ? P.n_tiles_out : 2048;
+    for (int lvl = (int)top; lvl >= 1; --lvl) {
+        A.level = (uint32_t)lvl;
+        k_level_partition<K><<<pgrid, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
+        k_level_merge<K, VAL, NT, KI><<<mgrid, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+    }
+    return hipGetLastError();
+}
+
+uint32_t merge_tile_out(int key_bits, int has_values)
+{
+    if (key_bits == 64 && has_values) return 256 * 8;
+    return 256 * 16;
+}
+
+hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
+                                int key_bits, int has_values, hipStream_t s)
+{
+    if (key_bits == 32) {
+        if (has_values) return launch_levels<uint32_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+        return launch_levels<uint32_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+    }
+    if (has_values) return launch_levels<uint64_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+    return launch_levels<uint64_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+}
+
+// ------------------------------------------------- merge of two arrays --
+template <typename K>
+__global__ void k_merge2_partition(const K* __restrict__ a, uint32_t na, const K* __restrict__ b, uint32_t nb,
+                                   uint32_t TO, uint32_t ntiles, uint32_t* __restrict__ splits)
+{
+    const uint32_t tile = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tile > ntiles) return;
+    const uint64_t d = (uint64_t)tile * TO;
+    const uint32_t dd = (uint32_t)(d < (uint64_t)na + nb ? d : (uint64_t)na + nb);
+    splits[tile] = merge_path<K>(a, na, b, nb, dd);
+}
+
+template <typename K, bool VAL, int NT, int KI>
+__global__ __launch_bounds__(NT) void k_merge2(const K* __restrict__ a, const uint32_t* __restrict__ va, uint32_t na,
+                                               const K* __restrict__ b, const uint32_t* __restrict__ vb,
+                                               uint32_t nb, K* __restrict__ out, uint32_t* __restrict__ vout,
+                                               uint32_t ntiles, const uint32_t* __restrict__ splits)
+{
+    constexpr uint32_t TO = NT * KI;
+    extern __shared__ __align__(16) uint8_t smem[];
+    K* S = (K*)smem;
+    K* SO = S + TO;
+    uint32_t* SV = (uint32_t*)(SO + TO);
+    uint32_t* SOV = SV + (VAL ? TO : 0);
+    const uint64_t ntot = (uint64_t)na + nb;
+    for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint64_t o0 = (uint64_t)tile * TO;
+        const uint64_t o1 = o0 + TO < ntot ? o0 + TO : ntot;
+        const uint32_t i0 = splits[tile], i1 = splits[tile + 1];
+        const uint32_t j0 = (uint32_t)(o0 - i0), j1 = (uint32_t)(o1 - i1);
+        merge_tile<K, VAL, NT, KI>(a, va, i0, i1, b, vb, j0, j1, out + o0, VAL ? vout + o0 : nullptr, S, SV, SO,
+                                   SOV);
+    }
+}
+
+template <typename K, bool VAL>
+static hipError_t merge2_t(const K* a, const uint32_t* va, uint32_t na, const K* b, const uint32_t* vb,
+                           uint32_t nb, K* out, uint32_t* vout, uint32_t* splits, hipStream_t s)
+{
+    constexpr int NT = 256, KI = 16;
+    constexpr uint32_t TO = NT * KI;
+    constexpr size_t lds = 2 * sizeof(K) * TO + (VAL ? 2 * sizeof(uint32_t) * TO : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+        VMPS_HIP(hipFuncSetAttribute((const void*)k_merge2<K, VAL, NT, KI>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds));
+        attr_set = true;
+    }
+    const uint64_t ntot = (uint64_t)na + nb;
+    const uint32_t ntiles = (uint32_t)ceil_div(ntot, TO);
+    k_merge2_partition<K><<<(unsigned)ceil_div(ntiles + 1, 256), 256, 0, s>>>(a, na, b, nb, TO, ntiles, splits);
+    const unsigned grid = ntiles < 4096 ? ntiles : 4096;
+    k_merge2<K, VAL, NT, KI><<<grid, NT, lds, s>>>(a, va, na, b, vb, nb, out, vout, ntiles, splits);
+    return hipGetLastError();
+}
+
+hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, const void* b, const uint32_t* vb,
+                             uint32_t nb, void* out, uint32_t* vout, int key_bits, uint32_t* splits,
+                             hipStream_t s)
+{
+    if ((uint64_t)na + nb == 0) return hipSuccess;
+    const bool vals = vout != nullptr;  // va or vb may be null when its run is empty
+    if (key_bits == 32) {
+        if (vals) return merge2_t<uint32_t, true>((const uint32_t*)a, va, na, (const uint32_t*)b, vb, nb,
+                                                (uint32_t*)out, vout, splits, s);
+        return merge2_t<uint32_t, false>((const uint32_t*)a, va, na, (const uint32_t*)b, vb, nb, (uint32_t*)out,
+                                         vout, splits, s);
+    }
+    if (vals) return merge2_t<uint64_t, true>((const uint64_t*)a, va, na, (const uint64_t*)b, vb, nb,
+                                            (uint64_t*)out, vout, splits, s);
+    return merge2_t<uint64_t, false>((const uint64_t*)a, va, na, (const uint64_t*)b, vb, nb, (uint64_t*)out, vout,
+                                     splits, s);
+}
+
+}  // namespace vmps

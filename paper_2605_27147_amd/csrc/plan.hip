@@ -1,0 +1,818 @@
+// Merge-schedule planner: runs, powers, tree, Pingpong placement.
+//
+// Input: keys[0,n) split into k independent Powersort instances.  Instances
+// no longer than the LDS tile T are left whole to the tile sorter; the rest
+// are planned here, entirely on the device (no host round trip):
+//
+//  1. descent bitmap: bit p set iff keys[p-1] > keys[p] or p starts an
+//     instance (boundaries of maximal non-decreasing runs, ExtractRun of
+//     Sections 2 and 3);
+//  2. long natural runs: runs of at least minrun elements (Section 5);
+//  3. run starts: ExtractRun from s returns max(s + l, natural end) capped
+//     at the instance end.  Between long natural runs the starts step by l;
+//     inside a long run [u,e) the chain jumps to e iff it lands at a point
+//     s with e - s >= l.  The state carried along is the last jump target,
+//     so each long run acts as a map on phases mod l; the maps are composed
+//     block by block and applied with a scan;
+//  4. powers (theorem of Section 2) in closed form from the 32-bit
+//     expansions Q of the run midpoints;
+//  5. tree: the merge of Algorithm 1 at boundary t spans [L,R) where L, R are
+//     the nearest boundaries of smaller power.  The nearest smaller boundary
+//     on the left is the one whose midpoint interval holds (c-1)/2^p, with
+//     c/2^p the witness of t (and (c+1)/2^p on the right), so it is found by
+//     a galloping search over Q;
+//  6. Pingpong placement (Section 3 as a tree): the root writes the input
+//     buffer A and every node writes the buffer opposite its parent; node
+//     depths of the merges longer than T come from pointer jumping;
+//  7. LDS segments: the pieces between consecutive long merges, each with
+//     the buffer its subtree must be written to; and a table of output tiles
+//     per level for the HBM merges.
+#include "vmps_internal.hpp"
+
+namespace vmps {
+
+// ------------------------------------------------------------------ util --
+__device__ inline uint32_t inst_of(const uint32_t* inst_start, uint32_t k, uint32_t p)
+{
+    // largest i < k with inst_start[i] <= p
+    uint32_t lo = 0, hi = k;  // answer in [lo, hi)
+    while (hi - lo > 1) {
+        uint32_t m = (lo + hi) >> 1;
+        if (inst_start[m] <= p) lo = m; else hi = m;
+    }
+    return lo;
+}
+
+__device__ inline uint32_t inst_ell(const uint32_t* inst_start, uint32_t i, uint32_t ovr)
+{
+    return ovr ? ovr : minrun_of(inst_start[i + 1] - inst_start[i]);
+}
+
+// --------------------------------------------------------- instances --
+// Offsets are validated; a bad table (not starting at 0, decreasing, or not
+// ending at n) turns into one instance [0,n) marked "not to be sorted",
+// which the tile sorter leaves untouched.
+__global__ void k_inst_prep(const int64_t* __restrict__ off64, uint32_t k, uint32_t n, uint32_t big_min,
+                            uint32_t* inst_start, uint32_t* inst_big, uint32_t* inst_rfinal,
+                            uint32_t* inst_run_lo, uint32_t* inst_run_hi, uint32_t* counters)
+{
+    __shared__ int bad;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    // one workgroup validates the whole table
+    if (off64) {
+        for (uint32_t i = threadIdx.x; i <= k; i += blockDim.x) {
+            int64_t v = off64[i];
+            if (v < 0 || v > (int64_t)n) bad = 1;
+            if (i == 0 && v != 0) bad = 1;
+            if (i == k && v != (int64_t)n) bad = 1;
+            if (i < k && off64[i + 1] < v) bad = 1;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i <= k; i += blockDim.x) {
+        uint32_t s;
+        if (bad) s = (i == 0) ? 0 : n;
+        else s = off64 ? (uint32_t)off64[i] : (i == 0 ? 0 : n);
+        inst_start[i] = s;
+        if (i < k) {
+            uint32_t e = bad ? (i == 0 ? n : n) : (off64 ? (uint32_t)off64[i + 1] : n);
+            inst_big[i] = (!bad && e - s > big_min) ? 1u : 0u;
+            inst_rfinal[i] = 0;
+            inst_run_lo[i] = NONE;
+            inst_run_hi[i] = NONE;
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int c = 0; c < CNT_COUNT; ++c) counters[c] = 0;
+        counters[CNT_BAD] = bad;
+    }
+}
+
+// ------------------------------------------------------------ bitmap --
+template <typename K>
+__global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint32_t n,
+                                                const uint32_t* __restrict__ inst_start,
+                                                const uint32_t* __restrict__ inst_big, uint32_t k,
+                                                uint64_t* __restrict__ bitmap,
+                                                uint32_t* __restrict__ tile_first)
+{
+    __shared__ uint32_t s_first[4];
+    const uint32_t tile = blockIdx.x;
+    const uint64_t base = (uint64_t)tile * BITMAP_TILE;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t ii = 0;
+    if (k > 1 && base < n) ii = inst_of(inst_start, k, (uint32_t)base);
+    uint32_t first = NONE;
+    for (int w = wave; w < (int)(BITMAP_TILE / 64); w += 4) {
+        const uint64_t wpos = base + (uint64_t)w * 64;
+        const uint64_t p = wpos + lane;
+        bool bit = true;
+        if (wpos < n)
+            while (ii + 1 < k && inst_start[ii + 1] <= wpos) ++ii;  // uniform across the wave
+        if (p < n) {
+            uint32_t my = ii;
+            while (my + 1 < k && inst_start[my + 1] <= p) ++my;
+            if (p != inst_start[my] && inst_big[my]) bit = keys[p - 1] > keys[p];
+        }
+        const uint64_t word = __ballot(bit);
+        if (lane == 0) bitmap[(uint64_t)tile * 64 + w] = word;
+        if (word && first == NONE) first = (uint32_t)(wpos + ffs64(word));
+    }
+    if (lane == 0) s_first[wave] = first;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t m = s_first[0];
+        for (int w = 1; w < 4; ++w) m = min(m, s_first[w]);
+        tile_first[tile] = m;
+    }
+}
+
+// tile_next[t] = first set bit in tiles after t (one workgroup)
+__global__ __launch_bounds__(1024) void k_suffix_min(const uint32_t* __restrict__ first,
+                                                     uint32_t* __restrict__ next, uint32_t ntile)
+{
+    __shared__ uint32_t part[1024];
+    const uint32_t chunk = (ntile + 1023) / 1024;
+    const uint32_t a = threadIdx.x * chunk, b = min(ntile, a + chunk);
+    uint32_t m = NONE;
+    for (uint32_t t = a; t < b; ++t) m = min(m, first[t]);
+    part[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = NONE;
+        for (int c = 1023; c >= 0; --c) { uint32_t v = part[c]; part[c] = run; run = min(run, v); }
+    }
+    __syncthreads();
+    uint32_t run = part[threadIdx.x];
+    for (uint32_t t = b; t > a; --t) { next[t - 1] = run; run = min(run, first[t - 1]); }
+}
+
+// Long natural runs: count (EMIT=false) or write (EMIT=true).  One wave
+// per bitmap tile, one lane per 64-bit word.
+template <bool EMIT>
+__global__ __launch_bounds__(64) void k_long_runs(const uint64_t* __restrict__ bitmap, uint32_t n,
+                                                  const uint32_t* __restrict__ tile_next,
+                                                  const uint32_t* __restrict__ inst_start,
+                                                  const uint32_t* __restrict__ inst_big, uint32_t k,
+                                                  uint32_t ell_ovr, uint32_t cand_min, uint32_t lr_cap,
+                                                  uint32_t* __restrict__ tile_cnt,
+                                                  const uint32_t* __restrict__ tile_off,
+                                                  uint32_t* __restrict__ lr_u, uint32_t* __restrict__ lr_e,
+                                                  uint32_t* __restrict__ lr_inst)
+{
+    const uint32_t tile = blockIdx.x;
+    const int lane = threadIdx.x;
+    const uint64_t w = (uint64_t)tile * 64 + lane;
+    const uint64_t word = bitmap[w];
+    const uint64_t p0 = w * 64;
+    // a word holds at most 4 starts of runs of length >= 16
+    uint32_t cnt = 0;
+    uint32_t ru[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0};
+    uint64_t bits = word;
+    while (bits) {
+        const int b = ffs64(bits);
+        bits &= bits - 1;
+        const uint64_t u = p0 + b;
+        if (u >= n) break;
+        const uint64_t above = (b == 63) ? 0ull : ((word >> (b + 1)) << (b + 1));
+        uint64_t next;
+        if (above) {
+            next = p0 + ffs64(above);
+        } else {
+            next = NONE;
+            for (uint64_t ww = w + 1; ww < (uint64_t)(tile + 1) * 64; ++ww) {
+                const uint64_t x = bitmap[ww];
+                if (x) { next = ww * 64 + ffs64(x); break; }
+            }
+            if (next == NONE) next = tile_next[tile];
+        }
+        if (next > n) next = n;
+        if (next - u < cand_min) continue;
+        const uint32_t inst = k > 1 ? inst_of(inst_start, k, (uint32_t)u) : 0;
+        if (!inst_big[inst]) continue;
+        if (next - u < inst_ell(inst_start, inst, ell_ovr)) continue;
+        if (cnt < 4) { ru[cnt] = (uint32_t)u; re[cnt] = (uint32_t)next; ri[cnt] = inst; }
+        ++cnt;
+    }
+    const uint32_t inc = wave_incl_scan(cnt);
+    if (!EMIT) {
+        if (lane == 63) tile_cnt[tile] = inc;
+    } else {
+        uint32_t o = tile_off[tile] + inc - cnt;
+        for (uint32_t c = 0; c < cnt && c < 4 && o + c < lr_cap; ++c) {
+            lr_u[o + c] = ru[c];
+            lr_e[o + c] = re[c];
+            lr_inst[o + c] = ri[c];
+        }
+    }
+}
+
+// ------------------------------------------------------------- chain --
+// Smallest x >= u with x == r (mod l), written from u's residue.
+__device__ inline uint32_t chain_land(uint32_t u, uint32_t ph, uint32_t ell)
+{
+    return u + (ph + ell - u % ell) % ell;
+}
+
+// Map of a block of long runs: lane phi follows the chain entering the
+// block at phase phi; afterwards it holds the last jump target (known) or
+// is still the identity.
+__global__ __launch_bounds__(64) void k_chain_blocks(const uint32_t* __restrict__ lr_u,
+                                                     const uint32_t* __restrict__ lr_e,
+                                                     const uint32_t* __restrict__ lr_inst,
+                                                     const uint32_t* __restrict__ inst_start,
+                                                     uint32_t ell_ovr, const uint32_t* counters,
+                                                     uint32_t* __restrict__ chain_val,
+                                                     uint64_t* __restrict__ chain_known)
+{
+    const uint32_t nl = counters[CNT_NLONG];
+    const uint32_t b = blockIdx.x;
+    const uint32_t j0 = b * CHAIN_BLOCK;
+    if (j0 >= nl) return;
+    const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
+    const uint32_t lane = threadIdx.x;
+    uint32_t prev = j0 ? lr_inst[j0 - 1] : NONE;
+    bool known = false;
+    uint32_t r = 0, ell = 1, ib = 0;
+    if (prev != NONE) { ell = inst_ell(inst_start, prev, ell_ovr); ib = inst_start[prev]; }
+    for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t inst = lr_inst[j];
+        if (inst != prev) {
+            known = true; r = 0; prev = inst;
+            ell = inst_ell(inst_start, inst, ell_ovr);
+            ib = inst_start[inst];
+        }
+        const uint32_t u = lr_u[j] - ib, e = lr_e[j] - ib;
+        const uint32_t ph = known ? r % ell : lane % ell;
+        const uint32_t sf = chain_land(u, ph, ell);
+        if (e - sf >= ell) { known = true; r = e; }
+    }
+    chain_val[(uint64_t)b * 64 + lane] = r;
+    const uint64_t m = __ballot(known);
+    if (lane == 0) chain_known[b] = m;
+}
+
+// Sequential composition over blocks: incoming chain state of every block.
+__global__ void k_chain_scan(const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
+                             uint32_t ell_ovr, const uint32_t* counters,
+                             const uint32_t* __restrict__ chain_val,
+                             const uint64_t* __restrict__ chain_known, uint32_t* __restrict__ chain_rin)
+{
+    if (threadIdx.x != 0) return;
+    const uint32_t nl = counters[CNT_NLONG];
+    const uint32_t nb = (uint32_t)ceil_div(nl, CHAIN_BLOCK);
+    uint32_t r = 0, prev_last = NONE;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint32_t j0 = b * CHAIN_BLOCK;
+        const uint32_t first = lr_inst[j0];
+        if (first != prev_last) r = 0;
+        chain_rin[b] = r;
+        const uint32_t ph = r % inst_ell(inst_start, first, ell_ovr);
+        if ((chain_known[b] >> ph) & 1ull) r = chain_val[(uint64_t)b * 64 + ph];
+        prev_last = lr_inst[min(nl, j0 + CHAIN_BLOCK) - 1];
+    }
+}
+
+// Apply: walk each block with its real incoming state, recording for every
+// long run where the chain jumps (run count of the progression it closes).
+__global__ __launch_bounds__(64) void k_chain_apply(const uint32_t* __restrict__ lr_u,
+                                                    const uint32_t* __restrict__ lr_e,
+                                                    const uint32_t* __restrict__ lr_inst,
+                                                    const uint32_t* __restrict__ inst_start,
+                                                    uint32_t ell_ovr, const uint32_t* counters,
+                                                    const uint32_t* __restrict__ chain_rin,
+                                                    uint32_t* __restrict__ lr_cnt,
+                                                    uint32_t* __restrict__ lr_base,
+                                                    uint32_t* __restrict__ inst_rfinal)
+{
+    __shared__ uint32_t su[CHAIN_BLOCK], se[CHAIN_BLOCK], si[CHAIN_BLOCK];
+    const uint32_t nl = counters[CNT_NLONG];
+    const uint32_t b = blockIdx.x;
+    const uint32_t j0 = b * CHAIN_BLOCK;
+    if (j0 >= nl) return;
+    const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
+    for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
+        su[j - j0] = lr_u[j]; se[j - j0] = lr_e[j]; si[j - j0] = lr_inst[j];
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    uint32_t prev = j0 ? lr_inst[j0 - 1] : NONE;
+    uint32_t r = chain_rin[b], ell = 1, ib = 0;
+    if (prev != NONE) { ell = inst_ell(inst_start, prev, ell_ovr); ib = inst_start[prev]; }
+    const uint32_t next_inst = j1 < nl ? lr_inst[j1] : NONE;
+    for (uint32_t j = j0; j < j1; ++j) {
+        const uint32_t inst = si[j - j0];
+        if (inst != prev) {
+            r = 0; prev = inst;
+            ell = inst_ell(inst_start, inst, ell_ovr);
+            ib = inst_start[inst];
+        }
+        const uint32_t u = su[j - j0] - ib, e = se[j - j0] - ib;
+        const uint32_t sf = chain_land(u, r % ell, ell);
+        if (e - sf >= ell) {
+            lr_cnt[j] = (sf - r) / ell + 1;
+            lr_base[j] = r;
+            r = e;
+        } else {
+            lr_cnt[j] = 0;
+            lr_base[j] = 0;
+        }
+        const uint32_t nxt = (j + 1 < j1) ? si[j + 1 - j0] : next_inst;
+        if (nxt != inst) inst_rfinal[inst] = r;
+    }
+}
+
+// ----------------------------------------------------------- entries --
+// Progressions of run starts: one per jumping long run (closing at it) and
+// one tail per planned instance, laid out in position order.
+__global__ void k_entries_lr(const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ lr_cnt,
+                             const uint32_t* __restrict__ lr_base,
+                             const uint32_t* __restrict__ inst_bigrank, const uint32_t* counters,
+                             uint32_t* __restrict__ ent_cnt, uint32_t* __restrict__ ent_base,
+                             uint32_t* __restrict__ ent_inst)
+{
+    const uint32_t nl = counters[CNT_NLONG];
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nl) return;
+    const uint32_t inst = lr_inst[j];
+    const uint32_t idx = j + inst_bigrank[inst];
+    ent_cnt[idx] = lr_cnt[j];
+    ent_base[idx] = lr_base[j];
+    ent_inst[idx] = inst;
+}
+
+__global__ void k_entries_tail(const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
+                               const uint32_t* __restrict__ inst_big,
+                               const uint32_t* __restrict__ inst_bigrank,
+                               const uint32_t* __restrict__ inst_rfinal, uint32_t k, uint32_t ell_ovr,
+                               uint32_t* counters, uint32_t* __restrict__ ent_cnt,
+                               uint32_t* __restrict__ ent_base, uint32_t* __restrict__ ent_inst)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nl = counters[CNT_NLONG];
+    if (i == 0) counters[CNT_NENT] = nl + counters[CNT_NBIG];
+    if (i >= k || !inst_big[i]) return;
+    // number of long runs in instances <= i
+    uint32_t lo = 0, hi = nl;
+    while (lo < hi) {
+        uint32_t m = (lo + hi) >> 1;
+        if (lr_inst[m] <= i) lo = m + 1; else hi = m;
+    }
+    const uint32_t idx = lo + inst_bigrank[i];
+    const uint32_t len = inst_start[i + 1] - inst_start[i];
+    const uint32_t ell = inst_ell(inst_start, i, ell_ovr);
+    const uint32_t rf = inst_rfinal[i];
+    ent_cnt[idx] = rf < len ? (uint32_t)ceil_div(len - rf, ell) : 0u;
+    ent_base[idx] = rf;
+    ent_inst[idx] = i;
+}
+
+// -------------------------------------------------------------- runs --
+__global__ void k_runs_emit(const uint32_t* __restrict__ ent_off, const uint32_t* __restrict__ ent_base,
+                            const uint32_t* __restrict__ ent_inst, const uint32_t* __restrict__ inst_start,
+                            uint32_t n, uint32_t ell_ovr, const uint32_t* counters,
+                            uint32_t* __restrict__ run_start, uint32_t* __restrict__ run_inst)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nr = counters[CNT_NRUNS], ne = counters[CNT_NENT];
+    if (t == nr) run_start[t] = n;
+    if (t >= nr || ne == 0) return;
+    // largest entry e with ent_off[e] <= t (it has a non-zero count)
+    uint32_t lo = 0, hi = ne;
+    while (hi - lo > 1) {
+        uint32_t m = (lo + hi) >> 1;
+        if (ent_off[m] <= t) lo = m; else hi = m;
+    }
+    const uint32_t inst = ent_inst[lo];
+    const uint32_t ell = inst_ell(inst_start, inst, ell_ovr);
+    run_start[t] = inst_start[inst] + ent_base[lo] + (t - ent_off[lo]) * ell;
+    run_inst[t] = inst;
+}
+
+// Q[t] = floor(2^31 (s_t + e_t) / len): the first 32 bits of the binary
+// expansion of the run midpoint over the instance length.
+__global__ void k_run_q(const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_inst,
+                        const uint32_t* __restrict__ inst_start, const uint32_t* counters,
+                        uint32_t* __restrict__ run_q, uint32_t* __restrict__ inst_run_lo,
+                        uint32_t* __restrict__ inst_run_hi)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nr = counters[CNT_NRUNS];
+    if (t >= nr) return;
+    const uint32_t inst = run_inst[t];
+    const uint32_t ib = inst_start[inst], il = inst_start[inst + 1] - ib;
+    const bool last = (t + 1 == nr) || run_inst[t + 1] != inst;
+    const uint64_t s = run_start[t] - ib;
+    const uint64_t e = last ? il : run_start[t + 1] - ib;
+    run_q[t] = (uint32_t)(((s + e) << 31) / il);
+    if (t == 0 || run_inst[t - 1] != inst) inst_run_lo[inst] = t;
+    if (last) inst_run_hi[inst] = t;
+}
+
+// Power, witness, and the node [L,R) of every boundary.
+__global__ void k_boundaries(const uint32_t* __restrict__ run_start, const uint32_t* __restrict__ run_inst,
+                             const uint32_t* __restrict__ run_q, const uint32_t* __restrict__ inst_start,
+                             const uint32_t* __restrict__ inst_run_lo,
+                             const uint32_t* __restrict__ inst_run_hi, uint32_t T,
+                             uint32_t* counters, uint8_t* __restrict__ power,
+                             uint32_t* __restrict__ bnd_l, uint32_t* __restrict__ bnd_r,
+                             uint32_t* __restrict__ bnd_lpos, uint32_t* __restrict__ bnd_rpos,
+                             uint32_t* __restrict__ hbm_flag, unsigned long long* stats)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t nr = counters[CNT_NRUNS];
+    uint64_t cost = 0, cost_hbm = 0;
+    uint32_t p = 0;
+    if (t < nr) {
+        const uint32_t inst = run_inst[t];
+        const uint32_t lo = inst_run_lo[inst], hi = inst_run_hi[inst];
+        if (t == hi || lo == NONE || hi == NONE || t < lo || t > hi) {
+            power[t] = 0;
+            hbm_flag[t] = 0;
+            bnd_l[t] = NONE; bnd_r[t] = NONE;
+        } else {
+            const uint32_t ib = inst_start[inst], ie = inst_start[inst + 1];
+            const uint32_t qt = run_q[t], qn = run_q[t + 1];
+            p = __clz(qt ^ qn) + 1;
+            const uint32_t sh = 32 - p;
+            const uint64_t c = (uint64_t)qn >> sh;
+            const uint64_t V = (c - 1) << sh, W = (c + 1) << sh;
+            // left: largest u in [lo, t) with Q[u] < V
+            int64_t b = t, a, d = 1;
+            for (;;) {
+                a = (int64_t)b - d;
+                if (a < (int64_t)lo) { a = (int64_t)lo - 1; break; }
+                if (run_q[a] < V) break;
+                b = a; d <<= 1;
+            }
+            while (b - a > 1) {
+                int64_t m = (a + b) >> 1;
+                if (run_q[m] < V) a = m; else b = m;
+            }
+            const uint32_t uL = a < (int64_t)lo ? NONE : (uint32_t)a;
+            // right: largest u in (t, hi] with Q[u] < W
+            a = (int64_t)t + 1; d = 1;
+            for (;;) {
+                b = a + d;
+                if (b > (int64_t)hi) { b = (int64_t)hi + 1; break; }
+                if (run_q[b] >= W) break;
+                a = b; d <<= 1;
+            }
+            while (b - a > 1) {
+                int64_t m = (a + b) >> 1;
+                if (run_q[m] < W) a = m; else b = m;
+            }
+            const uint32_t uR = (a == (int64_t)hi) ? NONE : (uint32_t)a;
+            const uint32_t L = uL == NONE ? ib : run_start[uL + 1];
+            const uint32_t R = uR == NONE ? ie : run_start[uR + 1];
+            power[t] = (uint8_t)p;
+            bnd_l[t] = uL; bnd_r[t] = uR;
+            bnd_lpos[t] = L; bnd_rpos[t] = R;
+            hbm_flag[t] = (R - L > T) ? 1u : 0u;
+            cost = R - L;
+            if (R - L > T) cost_hbm = R - L;
+        }
+    }
+    // per-wave sums, one atomic each
+    for (int d = 32; d >= 1; d >>= 1) {
+        cost += __shfl_down(cost, d, 64);
+        cost_hbm += __shfl_down(cost_hbm, d, 64);
+        p = max(p, (uint32_t)__shfl_down((int)p, d, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (cost) atomicAdd(&stats[0], (unsigned long long)cost);
+        if (cost_hbm) atomicAdd(&stats[1], (unsigned long long)cost_hbm);
+        if (p) atomicMax(&counters[CNT_MAXPOW], p);
+    }
+}
+
+// --------------------------------------------------------- HBM nodes --
+__global__ void k_hbm_emit(const uint32_t* __restrict__ hbm_flag, const uint32_t* __restrict__ hbm_rank,
+                           const uint32_t* counters, uint32_t* __restrict__ hbm_list,
+                           uint32_t* __restrict__ hbm_idx)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= counters[CNT_NRUNS]) return;
+    if (hbm_flag[t]) {
+        hbm_list[hbm_rank[t]] = t;
+        hbm_idx[t] = hbm_rank[t];
+    }
+}
+
+// parent of an HBM node: the nearer-in-tree of its two smaller-power
+// neighbours, i.e. the one with the larger power.
+__global__ void k_depth_init(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ hbm_idx,
+                             const uint32_t* __restrict__ bnd_l, const uint32_t* __restrict__ bnd_r,
+                             const uint8_t* __restrict__ power, const uint32_t* __restrict__ hbm_flag,
+                             const uint32_t* counters, uint32_t* __restrict__ par, uint32_t* __restrict__ val)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= counters[CNT_NHBM]) return;
+    const uint32_t t = hbm_list[q];
+    const uint32_t l = bnd_l[t], r = bnd_r[t];
+    uint32_t parent;
+    if (l == NONE) parent = r;
+    else if (r == NONE) parent = l;
+    else parent = power[l] > power[r] ? l : r;
+    const bool ok = parent != NONE && hbm_flag[parent];
+    par[q] = ok ? hbm_idx[parent] : q;
+    val[q] = ok ? 1u : 0u;
+}
+
+__global__ void k_depth_jump(const uint32_t* __restrict__ par_in, const uint32_t* __restrict__ val_in,
+                             const uint32_t* counters, uint32_t* __restrict__ par_out,
+                             uint32_t* __restrict__ val_out)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= counters[CNT_NHBM]) return;
+    const uint32_t p = par_in[q];
+    val_out[q] = val_in[q] + val_in[p];
+    par_out[q] = par_in[p];
+}
+
+// ------------------------------------------------------ LDS segments --
+__device__ inline uint32_t seg_dst(uint32_t depth_parent) { return (depth_parent + 1) & 1u; }
+
+__global__ void k_segs_hbm(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ run_start,
+                           const uint32_t* __restrict__ run_inst, const uint8_t* __restrict__ power,
+                           const uint32_t* __restrict__ depth, const uint32_t* __restrict__ inst_start,
+                           const uint32_t* counters, Seg* __restrict__ segs)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= counters[CNT_NHBM]) return;
+    const uint32_t t = hbm_list[q];
+    const uint32_t inst = run_inst[t];
+    uint32_t a = inst_start[inst], par = q;
+    if (q > 0) {
+        const uint32_t tp = hbm_list[q - 1];
+        if (run_inst[tp] == inst) {
+            a = run_start[tp + 1];
+            if (power[tp] > power[t]) par = q - 1;
+        }
+    }
+    Seg s;
+    s.start = a; s.end = run_start[t + 1]; s.inst = inst; s.dst = seg_dst(depth[par]);
+    segs[q] = s;
+}
+
+__global__ void k_segs_inst(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ run_start,
+                            const uint32_t* __restrict__ run_inst, const uint32_t* __restrict__ depth,
+                            const uint32_t* __restrict__ inst_start, const uint32_t* __restrict__ inst_big,
+                            const uint32_t* __restrict__ inst_bigrank, uint32_t k, uint32_t* counters,
+                            Seg* __restrict__ segs)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t h = counters[CNT_NHBM], nbig = counters[CNT_NBIG];
+    if (i == 0) counters[CNT_NSEG] = h + k;
+    if (i >= k) return;
+    const uint32_t ib = inst_start[i], ie = inst_start[i + 1];
+    Seg s;
+    s.end = ie; s.inst = i;
+    if (inst_big[i]) {
+        // last HBM node with position < ie
+        uint32_t lo = 0, hi = h;  // count of nodes with pos < ie
+        while (lo < hi) {
+            uint32_t m = (lo + hi) >> 1;
+            if (run_start[hbm_list[m] + 1] < ie) lo = m + 1; else hi = m;
+        }
+        if (lo > 0 && run_inst[hbm_list[lo - 1]] == i) {
+            s.start = run_start[hbm_list[lo - 1] + 1];
+            s.dst = seg_dst(depth[lo - 1]);
+        } else {
+            s.start = ib; s.dst = 0;
+        }
+        segs[h + inst_bigrank[i]] = s;
+    } else {
+        s.start = ib; s.dst = 0;
+        segs[h + nbig + (i - inst_bigrank[i])] = s;
+    }
+}
+
+// ------------------------------------------------------- level table --
+__global__ void k_level_count(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ bnd_lpos,
+                              const uint32_t* __restrict__ bnd_rpos, uint32_t T_out,
+                              const uint32_t* counters, uint32_t* __restrict__ tiles)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= counters[CNT_NHBM]) return;
+    const uint32_t t = hbm_list[q];
+    const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
+    tiles[q] = (R - 1) / T_out - L / T_out + 1;
+}
+
+__global__ void k_level_fill(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ bnd_lpos,
+                             const uint8_t* __restrict__ power, const uint32_t* __restrict__ tile_off,
+                             uint32_t T_out, uint32_t n_tiles_out, const uint32_t* counters,
+                             uint32_t* __restrict__ table)
+{
+    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t h = counters[CNT_NHBM];
+    if (x >= counters[CNT_NPAIRS]) return;
+    uint32_t lo = 0, hi = h;
+    while (hi - lo > 1) {
+        uint32_t m = (lo + hi) >> 1;
+        if (tile_off[m] <= x) lo = m; else hi = m;
+    }
+    const uint32_t t = hbm_list[lo];
+    const uint32_t L = bnd_lpos[t];
+    const uint32_t tt = L / T_out + (x - tile_off[lo]);
+    const uint32_t slot = (L <= (uint64_t)tt * T_out) ? 0u : 1u;
+    if (tt >= n_tiles_out || power[t] >= MAX_LEVEL) return;
+    table[((uint64_t)power[t] * n_tiles_out + tt) * 2 + slot] = lo;
+}
+
+// ------------------------------------------------------------- host --
+namespace {
+struct Carver {
+    uint8_t* base;
+    size_t off;
+    template <typename T>
+    T* take(uint64_t count)
+    {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += sizeof(T) * (size_t)(count ? count : 1);
+        return p;
+    }
+};
+
+inline unsigned grid_for(uint64_t threads, unsigned block) { return (unsigned)ceil_div(threads ? threads : 1, block); }
+}  // namespace
+
+size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out)
+{
+    Carver c{(uint8_t*)ws, 0};
+    P.n = (uint32_t)n;
+    P.k = (uint32_t)k;
+    P.T = T;
+    P.big_min = T;
+    P.T_out = T_out;
+    P.n_tiles_out = (uint32_t)ceil_div(n ? n : 1, T_out);
+    // runs are at least 16 long (explicit minrun >= 16, rule >= 32) except
+    // the last of each instance
+    P.lr_cap = (uint32_t)(n / 16 + 2);
+    P.run_cap = (uint32_t)(n / 16 + k + 2);
+    P.ent_cap = P.lr_cap + (uint32_t)k + 1;
+    P.seg_cap = P.run_cap + (uint32_t)k + 1;
+    P.chain_blocks = (uint32_t)ceil_div(P.lr_cap, CHAIN_BLOCK);
+    P.bm_tiles = (uint32_t)ceil_div(n / 64 + 2, 64);
+    P.bm_words = P.bm_tiles * 64;
+    P.inst_start = c.take<uint32_t>(k + 1);
+    P.inst_big = c.take<uint32_t>(k);
+    P.inst_bigrank = c.take<uint32_t>(k);
+    P.inst_rfinal = c.take<uint32_t>(k);
+    P.inst_run_lo = c.take<uint32_t>(k);
+    P.inst_run_hi = c.take<uint32_t>(k);
+    P.bitmap = c.take<uint64_t>(P.bm_words);
+    P.tile_first = c.take<uint32_t>(P.bm_tiles);
+    P.tile_next = c.take<uint32_t>(P.bm_tiles);
+    P.tile_cnt = c.take<uint32_t>(P.bm_tiles);
+    P.tile_off = c.take<uint32_t>(P.bm_tiles);
+    P.lr_u = c.take<uint32_t>(P.lr_cap);
+    P.lr_e = c.take<uint32_t>(P.lr_cap);
+    P.lr_inst = c.take<uint32_t>(P.lr_cap);
+    P.lr_cnt = c.take<uint32_t>(P.lr_cap);
+    P.lr_base = c.take<uint32_t>(P.lr_cap);
+    P.chain_val = c.take<uint32_t>((uint64_t)P.chain_blocks * 64);
+    P.chain_known = c.take<uint64_t>(P.chain_blocks);
+    P.chain_rin = c.take<uint32_t>(P.chain_blocks);
+    P.ent_cnt = c.take<uint32_t>(P.ent_cap);
+    P.ent_base = c.take<uint32_t>(P.ent_cap);
+    P.ent_inst = c.take<uint32_t>(P.ent_cap);
+    P.ent_off = c.take<uint32_t>(P.ent_cap);
+    P.run_start = c.take<uint32_t>(P.run_cap + 1);
+    P.run_inst = c.take<uint32_t>(P.run_cap);
+    P.run_q = c.take<uint32_t>(P.run_cap);
+    P.power = c.take<uint8_t>(P.run_cap);
+    P.bnd_l = c.take<uint32_t>(P.run_cap);
+    P.bnd_r = c.take<uint32_t>(P.run_cap);
+    P.bnd_lpos = c.take<uint32_t>(P.run_cap);
+    P.bnd_rpos = c.take<uint32_t>(P.run_cap);
+    P.hbm_flag = c.take<uint32_t>(P.run_cap);
+    P.hbm_rank = c.take<uint32_t>(P.run_cap);
+    P.hbm_idx = c.take<uint32_t>(P.run_cap);
+    P.hbm_list = c.take<uint32_t>(P.run_cap);
+    P.hbm_par[0] = c.take<uint32_t>(P.run_cap);
+    P.hbm_par[1] = c.take<uint32_t>(P.run_cap);
+    P.hbm_val[0] = c.take<uint32_t>(P.run_cap);
+    P.hbm_val[1] = c.take<uint32_t>(P.run_cap);
+    P.hbm_tiles = c.take<uint32_t>(P.run_cap + 1);
+    P.hbm_tile_off = c.take<uint32_t>(P.run_cap + 1);
+    P.segs = c.take<Seg>(P.seg_cap);
+    P.level_table = c.take<uint32_t>((uint64_t)MAX_LEVEL * P.n_tiles_out * 2);
+    P.splits = c.take<uint32_t>((uint64_t)P.n_tiles_out * 4);
+    P.counters = c.take<uint32_t>(CNT_COUNT);
+    P.stats = c.take<unsigned long long>(8);
+    uint64_t cap = P.bm_tiles;
+    if (P.run_cap + 1 > cap) cap = P.run_cap + 1;
+    if (P.ent_cap > cap) cap = P.ent_cap;
+    if (k > cap) cap = k;
+    P.scan_tmp_words = scan_tmp_words(cap);
+    P.scan_tmp = c.take<uint32_t>(P.scan_tmp_words);
+    P.hbm_depth = nullptr;
+    P.inst_off64 = nullptr;
+    return c.off + 256;
+}
+
+size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out)
+{
+    Plan P;
+    return plan_carve(P, nullptr, n, k, T, T_out);
+}
+
+// Counts are clamped to the capacities the arrays were carved for, so a
+// wrong count can only give a wrong schedule, never an access out of range.
+__global__ void k_clamp(uint32_t* counters, int which, uint32_t cap)
+{
+    if (threadIdx.x == 0 && counters[which] > cap) {
+        counters[which] = cap;
+        counters[CNT_BAD] |= 2u;
+    }
+}
+
+__global__ void k_zero_stats(unsigned long long* stats)
+{
+    if (threadIdx.x < 8) stats[threadIdx.x] = 0;
+}
+
+template <typename K>
+static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipStream_t s)
+{
+    const uint32_t n = P.n, k = P.k;
+    uint32_t* C = P.counters;
+    k_inst_prep<<<1, 1024, 0, s>>>(P.inst_off64, k, n, P.big_min, P.inst_start, P.inst_big, P.inst_rfinal,
+                                   P.inst_run_lo, P.inst_run_hi, C);
+    k_zero_stats<<<1, 64, 0, s>>>(P.stats);
+    VMPS_HIP(scan_exclusive_u32(P.inst_big, P.inst_bigrank, k, nullptr, C + CNT_NBIG, P.scan_tmp, s));
+    // 1. bitmap
+    k_bitmap<K><<<P.bm_tiles, 256, 0, s>>>(keys, n, P.inst_start, P.inst_big, k, P.bitmap, P.tile_first);
+    k_suffix_min<<<1, 1024, 0, s>>>(P.tile_first, P.tile_next, P.bm_tiles);
+    // 2. long natural runs
+    const uint32_t cand_min = (k == 1) ? (ell_ovr ? ell_ovr : minrun_of(n)) : 32u;
+    k_long_runs<false><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, P.inst_start, P.inst_big, k, ell_ovr,
+                                                 cand_min, P.lr_cap, P.tile_cnt, nullptr, nullptr, nullptr, nullptr);
+    VMPS_HIP(scan_exclusive_u32(P.tile_cnt, P.tile_off, P.bm_tiles, nullptr, C + CNT_NLONG, P.scan_tmp, s));
+    k_clamp<<<1, 64, 0, s>>>(C, CNT_NLONG, P.lr_cap);
+    k_long_runs<true><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, P.inst_start, P.inst_big, k, ell_ovr,
+                                                cand_min, P.lr_cap, nullptr, P.tile_off, P.lr_u, P.lr_e, P.lr_inst);
+    // 3. chain of run starts
+    k_chain_blocks<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C,
+                                                 P.chain_val, P.chain_known);
+    k_chain_scan<<<1, 64, 0, s>>>(P.lr_inst, P.inst_start, ell_ovr, C, P.chain_val, P.chain_known, P.chain_rin);
+    k_chain_apply<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C, P.chain_rin,
+                                                P.lr_cnt, P.lr_base, P.inst_rfinal);
+    k_entries_lr<<<grid_for(P.lr_cap, 256), 256, 0, s>>>(P.lr_inst, P.lr_cnt, P.lr_base, P.inst_bigrank, C,
+                                                         P.ent_cnt, P.ent_base, P.ent_inst);
+    k_entries_tail<<<grid_for(k, 256), 256, 0, s>>>(P.lr_inst, P.inst_start, P.inst_big, P.inst_bigrank,
+                                                    P.inst_rfinal, k, ell_ovr, C, P.ent_cnt, P.ent_base,
+                                                    P.ent_inst);
+    VMPS_HIP(scan_exclusive_u32(P.ent_cnt, P.ent_off, P.ent_cap, C + CNT_NENT, C + CNT_NRUNS, P.scan_tmp, s));
+    k_clamp<<<1, 64, 0, s>>>(C, CNT_NRUNS, P.run_cap);
+    k_runs_emit<<<grid_for(P.run_cap + 1, 256), 256, 0, s>>>(P.ent_off, P.ent_base, P.ent_inst, P.inst_start, n,
+                                                             ell_ovr, C, P.run_start, P.run_inst);
+    // 4-5. powers and tree
+    k_run_q<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.run_start, P.run_inst, P.inst_start, C, P.run_q,
+                                                     P.inst_run_lo, P.inst_run_hi);
+    k_boundaries<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.run_start, P.run_inst, P.run_q, P.inst_start,
+                                                          P.inst_run_lo, P.inst_run_hi, P.T, C, P.power,
+                                                          P.bnd_l, P.bnd_r, P.bnd_lpos, P.bnd_rpos,
+                                                          P.hbm_flag, P.stats);
+    // 6. nodes longer than T and their depths
+    VMPS_HIP(scan_exclusive_u32(P.hbm_flag, P.hbm_rank, P.run_cap, C + CNT_NRUNS, C + CNT_NHBM, P.scan_tmp, s));
+    k_hbm_emit<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.hbm_list, P.hbm_idx);
+    k_depth_init<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.hbm_idx, P.bnd_l, P.bnd_r, P.power,
+                                                          P.hbm_flag, C,
+                                                          P.hbm_par[0], P.hbm_val[0]);
+    int cur = 0;
+    for (int round = 0; round < 6; ++round) {
+        k_depth_jump<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_par[cur], P.hbm_val[cur], C,
+                                                              P.hbm_par[cur ^ 1], P.hbm_val[cur ^ 1]);
+        cur ^= 1;
+    }
+    P.hbm_depth = P.hbm_val[cur];
+    // 7. LDS segments and the level table
+    k_segs_hbm<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
+                                                        P.hbm_depth, P.inst_start, C, P.segs);
+    k_segs_inst<<<grid_for(k, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.hbm_depth,
+                                                 P.inst_start, P.inst_big, P.inst_bigrank, k, C, P.segs);
+    k_level_count<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.T_out, C,
+                                                           P.hbm_tiles);
+    VMPS_HIP(scan_exclusive_u32(P.hbm_tiles, P.hbm_tile_off, P.run_cap, C + CNT_NHBM, C + CNT_NPAIRS,
+                                P.scan_tmp, s));
+    k_clamp<<<1, 64, 0, s>>>(C, CNT_NPAIRS, (uint32_t)((uint64_t)MAX_LEVEL * P.n_tiles_out + P.run_cap));
+    VMPS_HIP(fill_u32(P.level_table, NONE, (uint64_t)MAX_LEVEL * P.n_tiles_out * 2, s));
+    // pairs are at most MAX_LEVEL tiles per position plus one per node
+    const uint64_t pair_cap = (uint64_t)MAX_LEVEL * P.n_tiles_out + P.run_cap;
+    k_level_fill<<<grid_for(pair_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
+                                                         P.T_out, P.n_tiles_out, C, P.level_table);
+    return hipGetLastError();
+}
+
+hipError_t plan_enqueue(Plan& P, const void* keys, int key_bits, uint32_t ell_override, hipStream_t s)
+{
+    if (key_bits == 32) return plan_enqueue_t<uint32_t>(P, (const uint32_t*)keys, ell_override, s);
+    return plan_enqueue_t<uint64_t>(P, (const uint64_t*)keys, ell_override, s);
+}
+
+}  // namespace vmps

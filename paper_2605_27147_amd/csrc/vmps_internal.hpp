@@ -1,0 +1,195 @@
+// Internal declarations of the vmps HIP library (gfx950 / MI355X).
+//
+// The library sorts unsigned keys stably with Powersort's merge policy
+// ("Virtual-Memory Powersort", Algorithm 1 and the Power theorem of Section 2,
+// Pingpong buffers of Section 3), re-scheduled for a GPU:
+//   * runs and powers are computed for all positions at once,
+//   * the merge tree is executed level by level (a level = one power),
+//   * subtrees no longer than an LDS tile are sorted inside one workgroup,
+//   * longer merges are split into fixed-size output tiles by merge path.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/vmps.h"
+
+namespace vmps {
+
+constexpr uint32_t NONE = 0xFFFFFFFFu;
+constexpr int WAVE = 64;
+constexpr int MAX_LEVEL = 33;          // powers are 1..32 for n <= 2^32
+constexpr uint32_t BITMAP_TILE = 4096; // positions per run-scan workgroup
+constexpr uint32_t CHAIN_BLOCK = 2048; // long runs per chain-scan block
+
+// ------------------------------------------------------------ helpers --
+__host__ __device__ inline uint32_t minrun_of(uint64_t n)
+{
+    // minrun rule of Section 5: halve (rounding up) until below 64
+    uint64_t l = n;
+    while (l >= 64) l = (l + 1) >> 1;
+    return (uint32_t)l;
+}
+
+__host__ __device__ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
+
+// Inclusive scan across the 64 lanes of a wave.
+__device__ inline uint32_t wave_incl_scan(uint32_t v)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, WAVE);
+        if (lane >= d) v += t;
+    }
+    return v;
+}
+
+// Exclusive scan over the workgroup; *total gets the workgroup sum.
+// lds must hold blockDim/64 + 1 words.
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t* lds, uint32_t* total)
+{
+    const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
+    const int nw = blockDim.x / WAVE;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == WAVE - 1) lds[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < nw; ++w) { uint32_t t = lds[w]; lds[w] = acc; acc += t; }
+        lds[nw] = acc;
+    }
+    __syncthreads();
+    uint32_t res = lds[wave] + inc - v;
+    if (total) *total = lds[nw];
+    __syncthreads();
+    return res;
+}
+
+// Position of the first set bit (0-based) of a non-zero word.
+__device__ inline int ffs64(uint64_t w) { return __ffsll((unsigned long long)w) - 1; }
+
+// One LDS-sort unit: a subtree of at most T elements (or a single sorted run
+// longer than T), its Powersort instance, and the buffer it must end up in.
+struct Seg {
+    uint32_t start;  // global position
+    uint32_t end;
+    uint32_t inst;   // instance index
+    uint32_t dst;    // 0 = keys (A), 1 = workspace copy (B)
+};
+
+// Device pointers of the planner, carved from the caller's workspace.
+struct Plan {
+    uint32_t n, k;                 // total length, number of instances
+    uint32_t T;                    // LDS tile length (elements)
+    uint32_t big_min;              // instances longer than this are planned here
+    uint32_t T_out;                // merge output tile length
+    uint32_t n_tiles_out;          // ceil(n / T_out)
+    uint32_t lr_cap, run_cap, ent_cap, seg_cap, chain_blocks, bm_tiles, bm_words;
+    // instances
+    const int64_t* inst_off64;     // caller offsets (k+1), may be null for k = 1
+    uint32_t* inst_start;          // k+1
+    uint32_t* inst_big;            // k (0/1), scanned into inst_bigrank
+    uint32_t* inst_bigrank;        // k
+    uint32_t* inst_rfinal;         // k
+    uint32_t* inst_run_lo;         // k
+    uint32_t* inst_run_hi;         // k
+    // run detection
+    uint64_t* bitmap;              // bm_words
+    uint32_t* tile_first;          // bm_tiles
+    uint32_t* tile_next;           // bm_tiles
+    uint32_t* tile_cnt;            // bm_tiles
+    uint32_t* tile_off;            // bm_tiles
+    uint32_t* lr_u;                // lr_cap
+    uint32_t* lr_e;
+    uint32_t* lr_inst;
+    uint32_t* lr_cnt;
+    uint32_t* lr_base;
+    uint32_t* chain_val;           // chain_blocks * 64
+    uint64_t* chain_known;         // chain_blocks
+    uint32_t* chain_rin;           // chain_blocks
+    uint32_t* ent_cnt;             // ent_cap
+    uint32_t* ent_base;
+    uint32_t* ent_inst;
+    uint32_t* ent_off;
+    // runs and boundaries
+    uint32_t* run_start;           // run_cap + 1
+    uint32_t* run_inst;            // run_cap
+    uint32_t* run_q;               // run_cap
+    uint8_t*  power;               // run_cap (boundary t between runs t, t+1)
+    uint32_t* bnd_l;               // run_cap: left neighbour boundary (run index) or NONE
+    uint32_t* bnd_r;               // run_cap
+    uint32_t* bnd_lpos;            // run_cap: node start L
+    uint32_t* bnd_rpos;            // run_cap: node end R
+    uint32_t* hbm_flag;            // run_cap
+    uint32_t* hbm_rank;            // run_cap
+    uint32_t* hbm_idx;             // run_cap: boundary -> HBM list index
+    uint32_t* hbm_list;            // run_cap
+    uint32_t* hbm_par[2];          // run_cap each
+    uint32_t* hbm_val[2];
+    uint32_t* hbm_depth;           // points at the final hbm_val buffer
+    uint32_t* hbm_tiles;           // run_cap + 1 : output tiles per HBM node, scanned
+    uint32_t* hbm_tile_off;
+    // LDS segments
+    Seg* segs;                     // seg_cap
+    // merge levels
+    uint32_t* level_table;         // MAX_LEVEL * n_tiles_out * 2
+    uint32_t* splits;              // n_tiles_out * 4
+    // counters (device scalars)
+    uint32_t* counters;            // see CNT_* below
+    // scan scratch
+    uint32_t* scan_tmp;            // scan_tmp_words
+    uint64_t scan_tmp_words;
+    // statistics
+    unsigned long long* stats;     // [0] M, [1] M_hbm, [2] levels
+};
+
+enum {
+    CNT_NBIG = 0, CNT_NLONG, CNT_NENT, CNT_NRUNS, CNT_NHBM, CNT_NSEG, CNT_NPAIRS,
+    CNT_MAXPOW, CNT_BAD, CNT_COUNT = 16
+};
+
+// ------------------------------------------------------------ host API --
+size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
+// Carve Plan arrays from ws; returns bytes used.
+size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
+
+// Enqueue run detection + powers + tree + placement for the instances.
+// key_bits: 32 or 64. ell_override: 0 = minrun rule.
+hipError_t plan_enqueue(Plan& P, const void* keys, int key_bits, uint32_t ell_override,
+                        hipStream_t s);
+
+// Device-wide exclusive scan of count u32 values (count read from device if
+// count_dev != null, else count_host). total (device, nullable) gets the sum.
+hipError_t scan_exclusive_u32(const uint32_t* in, uint32_t* out, uint64_t count_host,
+                              const uint32_t* count_dev, uint32_t* total, uint32_t* tmp,
+                              hipStream_t s);
+uint64_t scan_tmp_words(uint64_t count);
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t count, hipStream_t s);
+
+// LDS Powersort over the segment list (k_tilesort).
+hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
+                            uint32_t* valsB, int key_bits, int vmode, uint32_t ell_override,
+                            hipStream_t s);
+uint32_t tilesort_capacity(int key_bits, int has_values);
+size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
+
+// HBM merge levels.
+hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
+                                uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
+uint32_t merge_tile_out(int key_bits, int has_values);
+
+// Standalone stable merge of two sorted arrays.
+hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, const void* b,
+                             const uint32_t* vb, uint32_t nb, void* out, uint32_t* vout,
+                             int key_bits, uint32_t* splits, hipStream_t s);
+
+}  // namespace vmps
+
+#define VMPS_HIP(x)                                  \
+    do {                                             \
+        hipError_t e__ = (x);                        \
+        if (e__ != hipSuccess) return e__;           \
+    } while (0)

@@ -1,0 +1,46 @@
+"""The C-ABI library loads on the CPU and exports every symbol the header declares."""
+import ctypes
+import os
+import re
+
+from conftest import ROOT
+
+
+def _declared():
+    names = set()
+    for hdr in os.listdir(os.path.join(ROOT, "include")):
+        if hdr.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", hdr)).read()
+            names |= set(re.findall(r"\b(vmps_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+def test_header_declares_entry_points():
+    names = _declared()
+    for must in ("vmps_sort", "vmps_merge", "vmps_extract_runs", "vmps_run_powers", "vmps_segmented_sort",
+                 "vmps_minrun", "vmps_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2605_27147_amd as vm
+    lib = vm.load_library()
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_side_entry_points_without_gpu():
+    import paper_2605_27147_amd as vm
+    lib = vm.load_library()
+    assert [lib.vmps_minrun(n) for n in (0, 10, 64, 65, 1 << 28)] == [0, 10, 32, 33, 32]
+    sz = ctypes.c_size_t(0)
+    assert lib.vmps_sort_workspace_size(1 << 20, 1, 0, ctypes.byref(sz)) == 0 and sz.value > 8 << 20
+    assert lib.vmps_sort_workspace_size(-1, 1, 0, ctypes.byref(sz)) == vm.INVALID_ARG
+    assert lib.vmps_sort_workspace_size(1 << 32, 1, 0, ctypes.byref(sz)) == vm.INVALID_ARG
+    # argument errors are reported before any device work
+    assert lib.vmps_sort(None, None, 5, 0, 0, None, 0, None) == vm.INVALID_ARG
+    assert lib.vmps_sort(ctypes.c_void_p(16), None, 5, 0, 2, None, 0, None) == vm.INVALID_ARG
+    assert lib.vmps_sort(ctypes.c_void_p(16), None, 100, 0, 0, None, 0, None) == vm.WORKSPACE_TOO_SMALL
+    assert lib.vmps_sort(ctypes.c_void_p(18), None, 100, 1, 0, None, 0, None) == vm.INVALID_ARG  # misaligned
+    assert lib.vmps_sort(ctypes.c_void_p(16), ctypes.c_void_p(20), 100, 0, 0, None, 0, None) == vm.INVALID_ARG
+    assert lib.vmps_status_string(2).decode() == "workspace too small"

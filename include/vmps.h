@@ -90,8 +90,8 @@ vmps_status vmps_merge(const void* a, const uint32_t* va, int64_t na, const void
 /* Run decomposition of keys[0,n) (ExtractRun applied from the left until
  * the input is used up).  Each run is the maximal non-decreasing run from
  * its start, or minrun elements if that run is shorter (the last run may be
- * shorter still).  minrun <= 0 selects vmps_minrun(n); otherwise minrun must
- * be >= 32 when n >= 64 (smaller values only for n < 64).
+ * shorter still).  minrun <= 0 selects vmps_minrun(n); an explicit minrun
+ * must be >= min(16, n) (INVALID_ARG otherwise).
  *   run_bounds : device, capacity vmps_max_runs(n, minrun)+1 u32; receives
  *                r+1 bounds (0 = b[0] < ... < b[r] = n).
  *   num_runs   : device int64 receiving r.
@@ -137,12 +137,34 @@ vmps_status vmps_segmented_sort_workspace_size(int64_t total, int64_t nseg, vmps
 /* Independent stable sorts of keys[off[s], off[s+1]) for s < nseg, each a
  * Powersort instance of its own length (its own minrun and powers).
  *   seg_offsets : device int64[nseg+1], non-decreasing, off[0] = 0,
- *                 off[nseg] = total (checked on the device: a bad table
- *                 leaves keys unchanged and sets *status_dev).
+ *                 off[nseg] = total.  The table is checked on the device:
+ *                 a bad table sorts nothing and leaves keys unchanged.
  *   values      : NULL or total payloads. */
 vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg_offsets,
                                 int64_t nseg, int64_t total, vmps_dtype kt, void* ws,
                                 size_t ws_bytes, void* stream);
+
+/* ---- launch timing (instrumentation) ----
+ * When enabled, the library brackets its hot launches with HIP events on
+ * the caller's stream.  vmps_trace_collect() waits for those events and
+ * returns, per kind, the summed milliseconds and the number of bracketed
+ * launches since the previous collect, then forgets them.  Host-side state
+ * shared by all calls of the process (not for concurrent use). */
+typedef enum {
+    VMPS_TRACE_PLAN = 0,            /* whole planner (runs, powers, tree, placement) */
+    VMPS_TRACE_TILESORT = 1,        /* LDS Powersort of subtrees / buckets */
+    VMPS_TRACE_LEVEL_PARTITION = 2, /* merge-path splits of one tree level */
+    VMPS_TRACE_LEVEL_MERGE = 3,     /* merges of one tree level */
+    VMPS_TRACE_HISTOGRAM = 4,       /* learned partition: bucket histogram */
+    VMPS_TRACE_SCATTER = 5,         /* learned partition: stable scatter */
+    VMPS_TRACE_TRAIN = 6,           /* CDF model training + table */
+    VMPS_TRACE_SAMPLE = 7,          /* sample gather + sample sort */
+    VMPS_TRACE_KINDS = 8
+} vmps_trace_kind;
+
+vmps_status vmps_trace_enable(int on);
+/* ms, launches: host arrays of nkinds entries. */
+vmps_status vmps_trace_collect(double* ms, int64_t* launches, int32_t nkinds);
 
 #ifdef __cplusplus
 }

@@ -61,6 +61,8 @@ def load_library():
                                     ctypes.POINTER(i32), vp, sz, vp]),
         "vmps_segmented_sort_workspace_size": (st, [i64, i64, st, st, ctypes.POINTER(sz)]),
         "vmps_segmented_sort": (st, [vp, vp, vp, i64, i64, st, vp, sz, vp]),
+        "vmps_trace_enable": (st, [st]),
+        "vmps_trace_collect": (st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -229,6 +231,22 @@ def sort_schedule(keys, has_values: bool = False):
         "node_level": nlev[:h].cpu().numpy(), "node_buf": nbuf[:h].cpu().numpy(),
         "seg_start": ss[:ns].cpu().numpy(), "seg_end": se[:ns].cpu().numpy(), "seg_buf": sb[:ns].cpu().numpy(),
     }
+
+
+TRACE_KINDS = ["plan", "tilesort", "level_partition", "level_merge", "histogram", "scatter", "train", "sample"]
+
+
+def trace_enable(on: bool = True):
+    _check(load_library().vmps_trace_enable(int(bool(on))), "vmps_trace_enable")
+
+
+def trace_collect() -> dict:
+    """{kind: (milliseconds, launches)} since the previous collect (waits for the events)."""
+    k = len(TRACE_KINDS)
+    ms = (ctypes.c_double * k)()
+    cnt = (ctypes.c_int64 * k)()
+    _check(load_library().vmps_trace_collect(ms, cnt, k), "vmps_trace_collect")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(TRACE_KINDS)}
 
 
 def segmented_sort_(keys, offsets, values=None):

@@ -166,8 +166,14 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     const unsigned mgrid = P.n_tiles_out < 2048 ? P.n_tiles_out : 2048;
     for (int lvl = (int)top; lvl >= 1; --lvl) {
         A.level = (uint32_t)lvl;
-        k_level_partition<K><<<pgrid, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
-        k_level_merge<K, VAL, NT, KI><<<mgrid, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+        {
+            TraceScope tr(VMPS_TRACE_LEVEL_PARTITION, s);
+            k_level_partition<K><<<pgrid, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
+        }
+        {
+            TraceScope tr(VMPS_TRACE_LEVEL_MERGE, s);
+            k_level_merge<K, VAL, NT, KI><<<mgrid, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+        }
     }
     return hipGetLastError();
 }

@@ -811,6 +811,7 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
 
 hipError_t plan_enqueue(Plan& P, const void* keys, int key_bits, uint32_t ell_override, hipStream_t s)
 {
+    TraceScope tr(VMPS_TRACE_PLAN, s);
     if (key_bits == 32) return plan_enqueue_t<uint32_t>(P, (const uint32_t*)keys, ell_override, s);
     return plan_enqueue_t<uint64_t>(P, (const uint64_t*)keys, ell_override, s);
 }

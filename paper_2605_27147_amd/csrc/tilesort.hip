@@ -372,6 +372,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
+    TraceScope tr(VMPS_TRACE_TILESORT, s);
     k_tilesort<K, NT, TCAP, VMODE><<<grid, NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, nseg_dev,
                                                         nseg_host, P.inst_start, ell_ovr);
     return hipGetLastError();

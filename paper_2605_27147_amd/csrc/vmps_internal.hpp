@@ -150,6 +150,22 @@ enum {
     CNT_MAXPOW, CNT_BAD, CNT_COUNT = 16
 };
 
+// ------------------------------------------------------------ tracing --
+// Brackets the launches issued in its lifetime with HIP events when
+// vmps_trace_enable(1) is in effect (kinds: vmps_trace_kind).
+class TraceScope {
+public:
+    TraceScope(int kind, hipStream_t s);
+    ~TraceScope();
+    TraceScope(const TraceScope&) = delete;
+    TraceScope& operator=(const TraceScope&) = delete;
+
+private:
+    int kind_;
+    hipStream_t stream_;
+    void* a_;
+};
+
 // ------------------------------------------------------------ host API --
 size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
 // Carve Plan arrays from ws; returns bytes used.

@@ -81,10 +81,13 @@ def _L():
         lib.orc_mlp_forward.argtypes = [vp, vp, vp, dbl, i32, dbl]
         lib.orc_mlp_grad.restype = dbl
         lib.orc_mlp_grad.argtypes = [vp, vp, vp, dbl, i32, vp, vp, i64, vp, vp, vp, vp]
+        lib.orc_cdf_grid.restype = None
+        lib.orc_cdf_grid.argtypes = [u64, u64, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         lib.orc_cdf_table.restype = None
-        lib.orc_cdf_table.argtypes = [vp, vp, vp, dbl, i32, i32, vp]
+        lib.orc_cdf_table.argtypes = [vp, vp, vp, dbl, i32, u64, u64, i32, vp, ctypes.POINTER(i32),
+                                      ctypes.POINTER(i32)]
         lib.orc_bucket_of.restype = ctypes.c_uint32
-        lib.orc_bucket_of.argtypes = [u64, i32, i32, u64, u64, vp, i32, ctypes.c_uint32]
+        lib.orc_bucket_of.argtypes = [u64, i32, i32, u64, u64, vp, i32, i32, ctypes.c_uint32]
         lib.orc_cdf_init.restype = None
         lib.orc_cdf_init.argtypes = [vp, i64, i32, vp, vp, vp, vp]
         lib.orc_cdf_loss.restype = dbl
@@ -92,7 +95,7 @@ def _L():
         lib.orc_cdf_train.restype = dbl
         lib.orc_cdf_train.argtypes = [vp, i64, i32, i32, i32, dbl, vp]
         lib.orc_partition.restype = None
-        lib.orc_partition.argtypes = [vp, vp, i64, i32, i32, u64, u64, vp, i32, ctypes.c_uint32,
+        lib.orc_partition.argtypes = [vp, vp, i64, i32, i32, u64, u64, vp, i32, i32, ctypes.c_uint32,
                                       vp, vp, vp]
         _lib = lib
     return _lib
@@ -246,29 +249,44 @@ def mlp_grad(params: dict, u, y):
     return float(loss), g
 
 
-def cdf_table(params: dict, K: int) -> np.ndarray:
+class Table:
+    """Compiled CDF model: knot positions (Q32) every 2^shift feature units."""
+
+    def __init__(self, table, shift, knots, z_lo, z_hi):
+        self.table, self.shift, self.knots, self.z_lo, self.z_hi = table, shift, knots, z_lo, z_hi
+
+
+def cdf_grid(z_lo: int, z_hi: int, K: int):
+    sh, kn = ctypes.c_int32(0), ctypes.c_int32(0)
+    _L().orc_cdf_grid(z_lo, z_hi, K, ctypes.byref(sh), ctypes.byref(kn))
+    return sh.value, kn.value
+
+
+def cdf_table(params: dict, z_lo: int, z_hi: int, K: int) -> Table:
     w1, b1, w2 = (np.ascontiguousarray(params[k], dtype=np.float64) for k in ("w1", "b1", "w2"))
-    table = np.zeros(K + 1, dtype=np.uint64)
-    _L().orc_cdf_table(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, K, _p(table))
-    return table
+    table = np.zeros(K + 2, dtype=np.uint64)
+    sh, kn = ctypes.c_int32(0), ctypes.c_int32(0)
+    _L().orc_cdf_table(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, z_lo, z_hi, K, _p(table),
+                       ctypes.byref(sh), ctypes.byref(kn))
+    return Table(table[: kn.value + 1].copy(), sh.value, kn.value, z_lo, z_hi)
 
 
-def bucket_of(key: int, key_bits: int, fbits: int, z_lo: int, z_hi: int, table: np.ndarray, B: int) -> int:
-    table = np.ascontiguousarray(table, dtype=np.uint64)
-    return int(_L().orc_bucket_of(key, key_bits, fbits, z_lo, z_hi, _p(table), table.size - 1, B))
+def bucket_of(key: int, key_bits: int, fbits: int, tab: Table, B: int) -> int:
+    t = np.ascontiguousarray(tab.table, dtype=np.uint64)
+    return int(_L().orc_bucket_of(key, key_bits, fbits, tab.z_lo, tab.z_hi, _p(t), tab.shift, tab.knots, B))
 
 
-def partition(keys, key_bits: int, fbits: int, z_lo: int, z_hi: int, table, B: int, vals=None):
+def partition(keys, key_bits: int, fbits: int, tab: Table, B: int, vals=None):
     """Stable counting sort by bucket id: (keys_out, vals_out, offsets[B+1])."""
     orig = np.asarray(keys)
     x = _keys64(orig)
-    table = np.ascontiguousarray(table, dtype=np.uint64)
+    t = np.ascontiguousarray(tab.table, dtype=np.uint64)
     n = x.size
     ko = np.zeros(n, dtype=np.uint64)
     v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32)
     vo = None if v is None else np.zeros(n, dtype=np.uint32)
     off = np.zeros(B + 1, dtype=np.int64)
-    _L().orc_partition(_p(x), _p(v), n, key_bits, fbits, z_lo, z_hi, _p(table), table.size - 1, B,
+    _L().orc_partition(_p(x), _p(v), n, key_bits, fbits, tab.z_lo, tab.z_hi, _p(t), tab.shift, tab.knots, B,
                        _p(ko), _p(vo), _p(off))
     if orig.dtype in (np.uint32, np.int32):
         ko = ko.astype(np.uint32)

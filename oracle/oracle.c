@@ -475,13 +475,32 @@ double orc_mlp_grad(const double* w1, const double* b1, const double* w2, double
     return loss / (double)nb;
 }
 
-/* Compile the model into K+1 monotone fixed-point knots (Q32 of [0,1]). */
-void orc_cdf_table(const double* w1, const double* b1, const double* w2, double b2,
-                   int32_t H, int32_t K, uint64_t* table)
+/* Knot spacing of the table: segments of 2^shift feature units, the least
+ * power of two that covers [z_lo, z_hi] with at most K segments. */
+void orc_cdf_grid(uint64_t z_lo, uint64_t z_hi, int32_t K, int32_t* shift, int32_t* knots)
 {
+    uint64_t range = z_hi > z_lo ? z_hi - z_lo : 0;
+    int32_t sh = 0;
+    while (((range + (1ull << sh) - 1) >> sh) > (uint64_t)K) ++sh;
+    uint64_t kk = (range + (1ull << sh) - 1) >> sh;
+    *shift = sh;
+    *knots = kk > 0 ? (int32_t)kk : 1;
+}
+
+/* Compile the model into knots+1 monotone fixed-point positions (Q32 of
+ * [0,1]) at feature offsets s * 2^shift. */
+void orc_cdf_table(const double* w1, const double* b1, const double* w2, double b2,
+                   int32_t H, uint64_t z_lo, uint64_t z_hi, int32_t K, uint64_t* table,
+                   int32_t* shift_out, int32_t* knots_out)
+{
+    int32_t sh, kn;
+    orc_cdf_grid(z_lo, z_hi, K, &sh, &kn);
+    uint64_t range = z_hi > z_lo ? z_hi - z_lo : 0;
     uint64_t run_max = 0;
-    for (int32_t s = 0; s <= K; ++s) {
-        double v = orc_mlp_forward(w1, b1, w2, b2, H, (double)s / (double)K);
+    for (int32_t s = 0; s <= kn; ++s) {
+        double u = range ? (double)((uint64_t)s << sh) / (double)range : 0.0;
+        if (u > 1.0) u = 1.0;
+        double v = orc_mlp_forward(w1, b1, w2, b2, H, u);
         if (!(v > 0.0)) v = 0.0;
         if (v > 1.0) v = 1.0;
         double q = floor(v * 4294967296.0);
@@ -490,24 +509,26 @@ void orc_cdf_table(const double* w1, const double* b1, const double* w2, double 
         run_max = qi;
         table[s] = qi;
     }
+    *shift_out = sh;
+    *knots_out = kn;
 }
 
 /* Bucket of a key: linear interpolation between the table's knots in the
  * feature coordinate, all in integers, then scaled to B buckets. */
 uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo,
-                       uint64_t z_hi, const uint64_t* table, int32_t K, uint32_t B)
+                       uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots,
+                       uint32_t B)
 {
     uint64_t z = orc_feature(key, key_bits, fbits);
     uint64_t range = z_hi > z_lo ? z_hi - z_lo : 0;
+    uint64_t d = z <= z_lo ? 0 : (z - z_lo > range ? range : z - z_lo);
+    uint64_t seg = d >> shift;
     uint64_t pos;
-    if (range == 0) {
-        pos = table[0];
+    if (seg >= (uint64_t)knots) {
+        pos = table[knots];
     } else {
-        uint64_t d = z <= z_lo ? 0 : (z - z_lo > range ? range : z - z_lo);
-        uint64_t seg = d * (uint64_t)K / range;
-        uint64_t rem = d * (uint64_t)K - seg * range;
-        if (seg >= (uint64_t)K) pos = table[K];
-        else pos = table[seg] + (table[seg + 1] - table[seg]) * rem / range;
+        uint64_t rem = d & ((1ull << shift) - 1);
+        pos = table[seg] + (((table[seg + 1] - table[seg]) * rem) >> shift);
     }
     uint64_t b = (pos * (uint64_t)B) >> 32;
     return (uint32_t)(b >= B ? B - 1 : b);
@@ -516,13 +537,13 @@ uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z
 /* Stable counting sort by bucket id: the plain definition of the partition. */
 void orc_partition(const uint64_t* keys, const uint32_t* vals, int64_t n,
                    int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
-                   const uint64_t* table, int32_t K, uint32_t B,
+                   const uint64_t* table, int32_t shift, int32_t knots, uint32_t B,
                    uint64_t* keys_out, uint32_t* vals_out, int64_t* offsets)
 {
     uint32_t* id = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
     for (uint32_t b = 0; b <= B; ++b) offsets[b] = 0;
     for (int64_t i = 0; i < n; ++i) {
-        id[i] = orc_bucket_of(keys[i], key_bits, fbits, z_lo, z_hi, table, K, B);
+        id[i] = orc_bucket_of(keys[i], key_bits, fbits, z_lo, z_hi, table, shift, knots, B);
         offsets[id[i] + 1]++;
     }
     for (uint32_t b = 0; b < B; ++b) offsets[b + 1] += offsets[b];

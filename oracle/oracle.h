@@ -102,10 +102,13 @@ double   orc_mlp_forward(const double* w1, const double* b1, const double* w2, d
 double   orc_mlp_grad(const double* w1, const double* b1, const double* w2, double b2,
                       int32_t H, const double* u, const double* y, int64_t nb,
                       double* g_w1, double* g_b1, double* g_w2, double* g_b2);
+void     orc_cdf_grid(uint64_t z_lo, uint64_t z_hi, int32_t K, int32_t* shift, int32_t* knots);
 void     orc_cdf_table(const double* w1, const double* b1, const double* w2, double b2,
-                       int32_t H, int32_t K, uint64_t* table);
+                       int32_t H, uint64_t z_lo, uint64_t z_hi, int32_t K, uint64_t* table,
+                       int32_t* shift, int32_t* knots);
 uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo,
-                       uint64_t z_hi, const uint64_t* table, int32_t K, uint32_t B);
+                       uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots,
+                       uint32_t B);
 void     orc_cdf_init(const double* u, int64_t m, int32_t H, double* w1, double* b1,
                       double* w2, double* b2);
 void     orc_adam_update(double* p, const double* g, double* m1, double* m2, int32_t n,
@@ -116,7 +119,7 @@ double   orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int
                        double lr, double* params);
 void     orc_partition(const uint64_t* keys, const uint32_t* vals, int64_t n,
                        int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
-                       const uint64_t* table, int32_t K, uint32_t B,
+                       const uint64_t* table, int32_t shift, int32_t knots, uint32_t B,
                        uint64_t* keys_out, uint32_t* vals_out, int64_t* offsets);
 
 #ifdef __cplusplus

@@ -69,37 +69,47 @@ def test_gradient_matches_finite_differences(orc):
                 assert gi == pytest.approx(fd, rel=1e-4, abs=1e-7), (H, name, idx)
 
 
+def test_grid_is_least_power_of_two_cover(orc):
+    rng = np.random.default_rng(4)
+    for _ in range(500):
+        z_lo = int(rng.integers(0, 2**40))
+        rng_ = int(rng.integers(0, 2**31))
+        K = int(rng.choice([1, 7, 64, 4096]))
+        sh, kn = orc.cdf_grid(z_lo, z_lo + rng_, K)
+        assert 1 <= kn <= K
+        assert -(-rng_ // (1 << sh)) == (kn if rng_ else 0)
+        if sh > 0:
+            assert -(-rng_ // (1 << (sh - 1))) > K
+
+
 def test_identity_table_and_buckets_closed_form(orc):
-    # f(u) = u gives knots floor(s/K * 2^32) (last one saturates at 2^32-1) and,
-    # for K and B powers of two, bucket = floor(d B / range) by nested floors.
+    # f(u) = u over a range 2^20 with K = 64 knots: segments of 2^14, knots
+    # floor(s/64 * 2^32) (the last saturates at 2^32-1), and for B a power of
+    # two the bucket is floor(d B / 2^20) by nested floors.
     K, B = 64, 256
     ident = {"w1": np.array([1.0]), "b1": np.array([0.0]), "w2": np.array([1.0]), "b2": 0.0}
-    t = orc.cdf_table(ident, K)
-    assert t[:K].tolist() == [(s << 32) // K for s in range(K)]
-    assert t[K] == 2**32 - 1
-    z_lo, z_hi = 1000, 1000 + 12345
+    z_lo = orc.feature(1 << 40, 64, 40)
+    tab = orc.cdf_table(ident, z_lo, z_lo + (1 << 20), K)
+    assert (tab.shift, tab.knots) == (14, 64)
+    assert tab.table[:K].tolist() == [(s << 32) // K for s in range(K)]
+    assert tab.table[K] == 2**32 - 1
     rng = np.random.default_rng(0)
-    for d in list(range(0, 200)) + rng.integers(0, 12345, 500).tolist():
-        seg = d * K // 12345
-        if seg >= K - 1:
+    for d in list(range(0, 200)) + rng.integers(0, 1 << 20, 500).tolist():
+        if (d >> 14) >= K - 1:
             continue
-        # a key whose feature is z_lo + d: with fbits = 40 and bitlen 41 the
-        # feature of key k is (41 << 40) | (k - 2^40); pick z_lo accordingly
-        key = (1 << 40) + d
-        zl = orc.feature(1 << 40, 64, 40)
-        assert orc.bucket_of(key, 64, 40, zl, zl + 12345, t, B) == d * B // 12345
-    del z_lo, z_hi
+        key = (1 << 40) + d   # bit length 41, feature = (41 << 40) | (key - 2^40)
+        assert orc.bucket_of(key, 64, 40, tab, B) == d * B >> 20
 
 
 def test_table_monotone_and_buckets_monotone(orc):
     rng = np.random.default_rng(7)
     for trial in range(10):
         p = _rand_params(rng, 8)
-        t = orc.cdf_table(p, 128)
-        assert np.all(np.diff(t.astype(np.float64)) >= 0)
         keys = np.sort(workloads.lognormal(2000, trial))
         z = orc.features(keys, 64, 20)
-        b = [orc.bucket_of(int(k), 64, 20, int(z[10]), int(z[-10]), t, 1000) for k in keys]
+        tab = orc.cdf_table(p, int(z[10]), int(z[-10]), 128)
+        assert np.all(np.diff(tab.table.astype(np.float64)) >= 0)
+        b = [orc.bucket_of(int(k), 64, 20, tab, 1000) for k in keys]
         assert all(x <= y for x, y in zip(b, b[1:]))
         assert max(b) < 1000
 
@@ -111,11 +121,11 @@ def test_partition_is_stable_counting_sort(orc):
         keys = workloads.lognormal(n, trial)
         vals = np.arange(n, dtype=np.uint32)
         p = _rand_params(rng, 4)
-        t = orc.cdf_table(p, 64)
         zs = orc.features(np.sort(keys), 64, 20)
-        z_lo, z_hi, B = int(zs[0]), int(zs[-1]), 97
-        ko, vo, off = orc.partition(keys, 64, 20, z_lo, z_hi, t, B, vals=vals)
-        ids = np.array([orc.bucket_of(int(k), 64, 20, z_lo, z_hi, t, B) for k in keys])
+        tab = orc.cdf_table(p, int(zs[0]), int(zs[-1]), 64)
+        B = 97
+        ko, vo, off = orc.partition(keys, 64, 20, tab, B, vals=vals)
+        ids = np.array([orc.bucket_of(int(k), 64, 20, tab, B) for k in keys])
         order = np.argsort(ids, kind="stable")
         assert np.array_equal(vo, order.astype(np.uint32)) and np.array_equal(ko, keys[order])
         assert np.array_equal(off, np.concatenate([[0], np.cumsum(np.bincount(ids, minlength=B))]))

@@ -144,6 +144,112 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
                                 int64_t nseg, int64_t total, vmps_dtype kt, void* ws,
                                 size_t ws_bytes, void* stream);
 
+/* ---- learned CDF partitioning ----
+ * A small model of the keys' distribution routes every key to one of B
+ * buckets that are increasing key ranges; a stable scatter groups the keys
+ * by bucket and every bucket is then sorted by Powersort as an instance of
+ * its own (vmps_segmented_sort), so the result is exactly the stable sort
+ * whatever the model predicts: a poor model only makes buckets uneven, and
+ * buckets longer than the LDS tile go through the merge levels.
+ *
+ * Model: feature z(key) = (bit length << F) | the F bits below the leading
+ * one (integer, monotone); u = (z - z_lo) / (z_hi - z_lo) over the sorted
+ * sample; f(u) = b2 + sum_h w2[h] relu(w1[h] u + b1[h]) trained on the
+ * sample's empirical CDF (i + 1/2)/m with mean squared error and Adam,
+ * starting from hinges at sample quantiles; the model is then compiled into
+ * a monotone Q32 knot table every 2^shift feature units and a key's bucket
+ * is (table interpolation * B) >> 32, all in integers. */
+#define VMPS_CDF_MAX_HIDDEN 64
+#define VMPS_CDF_MAX_KNOTS 4096
+
+typedef struct {
+    int32_t num_buckets;  /* B: power of two in [2, 65536]; 0 = automatic */
+    int32_t hidden;       /* H in {16, 32, 64} */
+    int32_t steps;        /* Adam steps (>= 0) */
+    int32_t batch;        /* minibatch points per step, multiple of 64, >= 64 */
+    float lr;             /* Adam learning rate */
+    int32_t knots;        /* K: at most this many table segments (1..4096) */
+    int32_t feature_bits; /* F in [4, 24] */
+    int32_t reserved;
+    int64_t sample_size;  /* m: keys sampled at SplitMix64 positions (<= n) */
+    uint64_t seed;        /* SplitMix64 seed of the sample positions */
+} vmps_learned_config;
+
+/* The compiled model (lives in device memory; 33 KiB). */
+typedef struct {
+    uint64_t z_lo, z_hi;         /* feature range of the sorted sample */
+    int32_t key_bits, feature_bits, hidden;
+    int32_t knots;               /* table has knots+1 entries */
+    int32_t shift;               /* knot spacing 2^shift feature units */
+    int32_t trained;             /* 1 if Adam improved on the initial model */
+    float loss_init, loss_final; /* MSE on every 64th sample point */
+    float w1[VMPS_CDF_MAX_HIDDEN], b1[VMPS_CDF_MAX_HIDDEN], w2[VMPS_CDF_MAX_HIDDEN];
+    float b2, reserved;
+    uint64_t table[VMPS_CDF_MAX_KNOTS + 1];
+} vmps_cdf_model;
+
+typedef struct {
+    int64_t buckets, nonempty_buckets;
+    int64_t fallback_buckets, fallback_keys; /* buckets longer than the LDS tile */
+    int64_t max_bucket;
+    float loss_init, loss_final;
+} vmps_learned_stats;
+
+/* Defaults for n keys of type kt (host struct). */
+vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_config* cfg);
+
+vmps_status vmps_learned_workspace_size(int64_t n, vmps_dtype kt, int has_values,
+                                        const vmps_learned_config* cfg, size_t* bytes);
+
+/* Stable sort of keys[0,n) through the learned partition (sample, sort the
+ * sample with vmps_sort, train, compile, partition, sort every bucket).
+ * values as in vmps_sort (flags: VMPS_VALUES_IOTA).  model / stats: device,
+ * nullable, receive the compiled model and bucket statistics.  cfg: host.
+ * Inputs too small for the model (n < 4 * LDS tile or m < 1024) take the
+ * plain vmps_sort path. */
+vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtype kt,
+                              uint32_t flags, const vmps_learned_config* cfg,
+                              vmps_cdf_model* model, vmps_learned_stats* stats, void* ws,
+                              size_t ws_bytes, void* stream);
+
+/* Keys at the sample positions: out[i] = keys[SplitMix64(seed, i) mod n],
+ * i < m, where SplitMix64(seed, i) is output i (0-based) of the published
+ * SplitMix64 generator seeded with seed. */
+vmps_status vmps_sample(const void* keys, int64_t n, vmps_dtype kt, int64_t m, uint64_t seed,
+                        void* out, void* stream);
+
+/* Minibatch MSE gradient of the model (forward and backward kernels).
+ *   params : device float[3H+1] = w1[H] b1[H] w2[H] b2
+ *   u, y   : device float[nb] inputs and targets
+ *   grad   : device float[3H+1]; loss: device float[1] */
+vmps_status vmps_cdf_grad(const float* params, int32_t hidden, const float* u, const float* y,
+                          int32_t nb, float* grad, float* loss, void* stream);
+
+/* Train on a sorted sample and compile (model: device). */
+vmps_status vmps_cdf_train(const void* sorted_sample, int64_t m, vmps_dtype kt,
+                           const vmps_learned_config* cfg, vmps_cdf_model* model, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Compile given parameters (device float[3H+1]) for a feature range. */
+vmps_status vmps_cdf_compile(const float* params, int32_t hidden, uint64_t z_lo, uint64_t z_hi,
+                             int32_t key_bits, int32_t feature_bits, int32_t knots,
+                             vmps_cdf_model* model, void* stream);
+
+/* Bucket id of every key under a compiled model (ids: device u32[n]). */
+vmps_status vmps_bucket_ids(const void* keys, int64_t n, vmps_dtype kt, const vmps_cdf_model* model,
+                            int32_t num_buckets, uint32_t* ids, void* stream);
+
+vmps_status vmps_partition_workspace_size(int64_t n, vmps_dtype kt, int has_values,
+                                          int32_t num_buckets, size_t* bytes);
+
+/* Stable partition by bucket id (a stable counting sort by bucket): keys
+ * with smaller bucket ids first, input order inside a bucket.
+ * bucket_offsets: device int64[B+1].  keys_out must not overlap keys_in. */
+vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t n, vmps_dtype kt,
+                           const vmps_cdf_model* model, int32_t num_buckets, void* keys_out,
+                           uint32_t* vals_out, int64_t* bucket_offsets, void* ws, size_t ws_bytes,
+                           void* stream);
+
 /* ---- launch timing (instrumentation) ----
  * When enabled, the library brackets its hot launches with HIP events on
  * the caller's stream.  vmps_trace_collect() waits for those events and

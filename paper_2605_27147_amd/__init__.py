@@ -27,6 +27,32 @@ U32, U64 = 0, 1
 VALUES_IOTA = 1
 
 
+class LearnedConfig(ctypes.Structure):
+    _fields_ = [("num_buckets", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("knots", ctypes.c_int32),
+                ("feature_bits", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sample_size", ctypes.c_int64),
+                ("seed", ctypes.c_uint64)]
+
+
+CDF_MAX_HIDDEN, CDF_MAX_KNOTS = 64, 4096
+
+
+class CdfModel(ctypes.Structure):
+    _fields_ = [("z_lo", ctypes.c_uint64), ("z_hi", ctypes.c_uint64), ("key_bits", ctypes.c_int32),
+                ("feature_bits", ctypes.c_int32), ("hidden", ctypes.c_int32), ("knots", ctypes.c_int32),
+                ("shift", ctypes.c_int32), ("trained", ctypes.c_int32), ("loss_init", ctypes.c_float),
+                ("loss_final", ctypes.c_float), ("w1", ctypes.c_float * CDF_MAX_HIDDEN),
+                ("b1", ctypes.c_float * CDF_MAX_HIDDEN), ("w2", ctypes.c_float * CDF_MAX_HIDDEN),
+                ("b2", ctypes.c_float), ("reserved", ctypes.c_float),
+                ("table", ctypes.c_uint64 * (CDF_MAX_KNOTS + 1))]
+
+
+class LearnedStats(ctypes.Structure):
+    _fields_ = [("buckets", ctypes.c_int64), ("nonempty_buckets", ctypes.c_int64),
+                ("fallback_buckets", ctypes.c_int64), ("fallback_keys", ctypes.c_int64),
+                ("max_bucket", ctypes.c_int64), ("loss_init", ctypes.c_float), ("loss_final", ctypes.c_float)]
+
+
 class VmpsError(RuntimeError):
     def __init__(self, status: int, where: str):
         self.status = status
@@ -61,6 +87,16 @@ def load_library():
                                     ctypes.POINTER(i32), vp, sz, vp]),
         "vmps_segmented_sort_workspace_size": (st, [i64, i64, st, st, ctypes.POINTER(sz)]),
         "vmps_segmented_sort": (st, [vp, vp, vp, i64, i64, st, vp, sz, vp]),
+        "vmps_learned_default_config": (st, [i64, st, ctypes.POINTER(LearnedConfig)]),
+        "vmps_learned_workspace_size": (st, [i64, st, st, ctypes.POINTER(LearnedConfig), ctypes.POINTER(sz)]),
+        "vmps_sort_learned": (st, [vp, vp, i64, st, u32, ctypes.POINTER(LearnedConfig), vp, vp, vp, sz, vp]),
+        "vmps_sample": (st, [vp, i64, st, i64, ctypes.c_uint64, vp, vp]),
+        "vmps_cdf_grad": (st, [vp, i32, vp, vp, i32, vp, vp, vp]),
+        "vmps_cdf_train": (st, [vp, i64, st, ctypes.POINTER(LearnedConfig), vp, vp, sz, vp]),
+        "vmps_cdf_compile": (st, [vp, i32, ctypes.c_uint64, ctypes.c_uint64, i32, i32, i32, vp, vp]),
+        "vmps_bucket_ids": (st, [vp, i64, st, vp, i32, vp, vp]),
+        "vmps_partition_workspace_size": (st, [i64, st, st, i32, ctypes.POINTER(sz)]),
+        "vmps_partition": (st, [vp, vp, i64, st, vp, i32, vp, vp, vp, vp, sz, vp]),
         "vmps_trace_enable": (st, [st]),
         "vmps_trace_collect": (st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]),
     }
@@ -263,3 +299,125 @@ def segmented_sort_(keys, offsets, values=None):
     _check(lib.vmps_segmented_sort(_ptr(keys), _ptr(values), _ptr(offsets), nseg, total, kt, _ptr(ws),
                                    ws.numel(), _stream(keys.device)), "vmps_segmented_sort")
     return keys
+
+
+# ------------------------------------------------------------- learned --
+def learned_default_config(n: int, dtype_code: int) -> LearnedConfig:
+    cfg = LearnedConfig()
+    _check(load_library().vmps_learned_default_config(n, dtype_code, ctypes.byref(cfg)), "vmps_learned_default_config")
+    return cfg
+
+
+def _struct_from_tensor(t, cls):
+    raw = t.cpu().numpy().tobytes()
+    return cls.from_buffer_copy(raw[: ctypes.sizeof(cls)])
+
+
+def model_to_tensor(model: CdfModel, device="cuda"):
+    """Copy a host model struct into a device byte tensor."""
+    torch = _torch()
+    raw = bytes(model)
+    import numpy as np
+    return torch.from_numpy(np.frombuffer(raw, dtype=np.uint8).copy()).to(device)
+
+
+def model_from_tensor(t) -> CdfModel:
+    return _struct_from_tensor(t, CdfModel)
+
+
+def sort_learned_(keys, values=None, *, iota: bool = False, cfg: LearnedConfig | None = None, workspace=None,
+                  want_model: bool = False):
+    """Stable in-place sort through the learned partition.  Returns
+    (stats dict, model struct or None); synchronises to read them."""
+    torch = _torch()
+    lib = load_library()
+    _require_cuda(keys, values)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    if cfg is None:
+        cfg = learned_default_config(n, kt)
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_learned_workspace_size(n, kt, int(values is not None), ctypes.byref(cfg), ctypes.byref(need)),
+           "vmps_learned_workspace_size")
+    ws = workspace if workspace is not None else _workspace(need.value, keys.device)
+    model_t = torch.zeros(ctypes.sizeof(CdfModel), dtype=torch.uint8, device=keys.device) if want_model else None
+    stats_t = torch.zeros(ctypes.sizeof(LearnedStats), dtype=torch.uint8, device=keys.device)
+    _check(lib.vmps_sort_learned(_ptr(keys), _ptr(values), n, kt, VALUES_IOTA if iota else 0, ctypes.byref(cfg),
+                                 _ptr(model_t), _ptr(stats_t), _ptr(ws), ws.numel(), _stream(keys.device)),
+           "vmps_sort_learned")
+    st = _struct_from_tensor(stats_t, LearnedStats)
+    stats = {name: getattr(st, name) for name, _ in LearnedStats._fields_}
+    return stats, (model_from_tensor(model_t) if want_model else None)
+
+
+def learned_workspace_size(n: int, dtype_code: int, has_values: bool, cfg: LearnedConfig) -> int:
+    need = ctypes.c_size_t(0)
+    _check(load_library().vmps_learned_workspace_size(n, dtype_code, int(bool(has_values)), ctypes.byref(cfg),
+                                                      ctypes.byref(need)), "vmps_learned_workspace_size")
+    return need.value
+
+
+def sample(keys, m: int, seed: int):
+    torch = _torch()
+    _require_cuda(keys)
+    out = torch.empty(m, dtype=keys.dtype, device=keys.device)
+    _check(load_library().vmps_sample(_ptr(keys), keys.numel(), _dtype_code(keys), m, seed, _ptr(out),
+                                      _stream(keys.device)), "vmps_sample")
+    return out
+
+
+def cdf_grad(params, hidden: int, u, y):
+    """params, u, y: float32 device tensors. Returns (grad[3H+1], loss)."""
+    torch = _torch()
+    grad = torch.empty(3 * hidden + 1, dtype=torch.float32, device=params.device)
+    loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    _check(load_library().vmps_cdf_grad(_ptr(params), hidden, _ptr(u), _ptr(y), u.numel(), _ptr(grad), _ptr(loss),
+                                        _stream(params.device)), "vmps_cdf_grad")
+    return grad, loss
+
+
+def cdf_train(sorted_sample, cfg: LearnedConfig) -> CdfModel:
+    torch = _torch()
+    _require_cuda(sorted_sample)
+    m = sorted_sample.numel()
+    model_t = torch.zeros(ctypes.sizeof(CdfModel), dtype=torch.uint8, device=sorted_sample.device)
+    ws = _workspace(4 * m, sorted_sample.device)
+    _check(load_library().vmps_cdf_train(_ptr(sorted_sample), m, _dtype_code(sorted_sample), ctypes.byref(cfg),
+                                         _ptr(model_t), _ptr(ws), ws.numel(), _stream(sorted_sample.device)),
+           "vmps_cdf_train")
+    return model_from_tensor(model_t)
+
+
+def cdf_compile(params, hidden: int, z_lo: int, z_hi: int, key_bits: int, feature_bits: int, knots: int):
+    """Returns the compiled model as a device byte tensor."""
+    torch = _torch()
+    model_t = torch.zeros(ctypes.sizeof(CdfModel), dtype=torch.uint8, device=params.device)
+    _check(load_library().vmps_cdf_compile(_ptr(params), hidden, z_lo, z_hi, key_bits, feature_bits, knots,
+                                           _ptr(model_t), _stream(params.device)), "vmps_cdf_compile")
+    return model_t
+
+
+def bucket_ids(keys, model_t, num_buckets: int):
+    torch = _torch()
+    ids = torch.empty(keys.numel(), dtype=torch.int32, device=keys.device)
+    _check(load_library().vmps_bucket_ids(_ptr(keys), keys.numel(), _dtype_code(keys), _ptr(model_t), num_buckets,
+                                          _ptr(ids), _stream(keys.device)), "vmps_bucket_ids")
+    return ids
+
+
+def partition(keys, model_t, num_buckets: int, values=None):
+    """Stable partition by bucket: (keys_out, vals_out, offsets int64[B+1])."""
+    torch = _torch()
+    lib = load_library()
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_partition_workspace_size(n, kt, int(values is not None), num_buckets, ctypes.byref(need)),
+           "vmps_partition_workspace_size")
+    ws = _workspace(need.value, keys.device)
+    ko = torch.empty_like(keys)
+    vo = None if values is None else torch.empty_like(values)
+    off = torch.empty(num_buckets + 1, dtype=torch.int64, device=keys.device)
+    _check(lib.vmps_partition(_ptr(keys), _ptr(values), n, kt, _ptr(model_t), num_buckets, _ptr(ko), _ptr(vo),
+                              _ptr(off), _ptr(ws), ws.numel(), _stream(keys.device)), "vmps_partition")
+    return ko, vo, off

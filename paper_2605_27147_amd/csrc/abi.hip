@@ -340,3 +340,245 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ learned --
+namespace {
+bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+vmps_status check_config(const vmps_learned_config& c, int64_t n)
+{
+    if (c.num_buckets != 0 && (!pow2((uint64_t)c.num_buckets) || c.num_buckets < 2 || c.num_buckets > 65536))
+        return VMPS_ERR_INVALID_ARG;
+    if (c.hidden != 16 && c.hidden != 32 && c.hidden != 64) return VMPS_ERR_INVALID_ARG;
+    if (c.steps < 0 || c.batch < 64 || (c.batch % 64) || c.batch > (1 << 20)) return VMPS_ERR_INVALID_ARG;
+    if (!(c.lr >= 0.f) || c.knots < 1 || c.knots > VMPS_CDF_MAX_KNOTS) return VMPS_ERR_INVALID_ARG;
+    if (c.feature_bits < 4 || c.feature_bits > 24) return VMPS_ERR_INVALID_ARG;
+    if (c.sample_size < 2 || c.sample_size > n) return VMPS_ERR_INVALID_ARG;
+    return VMPS_OK;
+}
+
+uint32_t auto_buckets(uint64_t n, uint32_t T)
+{
+    // about half an LDS tile per bucket, so uneven buckets still fit the tile
+    uint64_t target = T / 2;
+    uint64_t b = 2;
+    while (b < 65536 && b * target < n) b <<= 1;
+    return (uint32_t)b;
+}
+
+struct LearnedLayout {
+    size_t keys_b, vals_b, sample, sample_ws, u, model, boff, arena, plan, total;
+    uint32_t B, T;
+    uint64_t m;
+};
+
+LearnedLayout learned_layout(uint64_t n, vmps_dtype kt, int has_values, const vmps_learned_config& c)
+{
+    const int kb = key_bits_of(kt);
+    LearnedLayout L;
+    L.T = tilesort_capacity(kb, has_values);
+    L.B = c.num_buckets ? (uint32_t)c.num_buckets : auto_buckets(n, L.T);
+    L.m = (uint64_t)c.sample_size;
+    size_t off = 0;
+    L.keys_b = off; off += align256(key_bytes(kt) * n);
+    L.vals_b = off; off += has_values ? align256(4 * n) : 0;
+    L.sample = off; off += align256(key_bytes(kt) * L.m);
+    L.sample_ws = off; off += align256(sort_layout(L.m, 1, kt, 0).total);
+    L.u = off; off += align256(4 * L.m);
+    L.model = off; off += align256(sizeof(vmps_cdf_model));
+    L.boff = off; off += align256(8 * ((uint64_t)L.B + 1));
+    L.arena = off; off += align256(4 * partition_arena_words(n, L.B));
+    L.plan = off;
+    off += plan_workspace_bytes(n, L.B, L.T, merge_tile_out(kb, has_values));
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+extern "C" {
+
+vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_config* cfg)
+{
+    if (!cfg || n < 0 || (kt != VMPS_U32 && kt != VMPS_U64)) return VMPS_ERR_INVALID_ARG;
+    memset(cfg, 0, sizeof *cfg);
+    cfg->num_buckets = 0;
+    cfg->hidden = 32;
+    cfg->steps = 64;
+    cfg->batch = 1024;
+    cfg->lr = 1e-4f;
+    cfg->knots = VMPS_CDF_MAX_KNOTS;
+    cfg->feature_bits = 20;
+    cfg->sample_size = n < (1 << 20) ? n : (1 << 20);
+    cfg->seed = 55;
+    return VMPS_OK;
+}
+
+vmps_status vmps_learned_workspace_size(int64_t n, vmps_dtype kt, int has_values, const vmps_learned_config* cfg,
+                                        size_t* bytes)
+{
+    if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32) || (kt != VMPS_U32 && kt != VMPS_U64))
+        return VMPS_ERR_INVALID_ARG;
+    vmps_learned_config c;
+    if (cfg) c = *cfg; else vmps_learned_default_config(n, kt, &c);
+    if (n < 2) { *bytes = 256; return VMPS_OK; }
+    if (check_config(c, n) != VMPS_OK) return VMPS_ERR_INVALID_ARG;
+    const size_t plain = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0).total;
+    const size_t lrn = learned_layout((uint64_t)n, kt, has_values ? 1 : 0, c).total;
+    *bytes = plain > lrn ? plain : lrn;
+    return VMPS_OK;
+}
+
+vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                              const vmps_learned_config* cfg, vmps_cdf_model* model, vmps_learned_stats* stats,
+                              void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (flags & ~VMPS_VALUES_IOTA) return VMPS_ERR_INVALID_ARG;
+    if ((flags & VMPS_VALUES_IOTA) && !values && n > 0) return VMPS_ERR_INVALID_ARG;
+    if (values && ((uintptr_t)values & 3)) return VMPS_ERR_INVALID_ARG;
+    if (values && n > 0 && ranges_overlap(keys, key_bytes(kt) * n, values, 4 * (size_t)n)) return VMPS_ERR_INVALID_ARG;
+    vmps_learned_config c;
+    if (cfg) c = *cfg; else vmps_learned_default_config(n, kt, &c);
+    const int has_values = values ? 1 : 0;
+    const int kb = key_bits_of(kt);
+    const uint32_t T = tilesort_capacity(kb, has_values);
+    if (n < 2) return vmps_sort(keys, values, n, kt, flags, ws, ws_bytes, stream);
+    if (check_config(c, n) != VMPS_OK) return VMPS_ERR_INVALID_ARG;
+    size_t need = 0;
+    vmps_learned_workspace_size(n, kt, has_values, &c, &need);
+    if (!ws || ws_bytes < need) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    if ((uint64_t)n < 4ull * T || c.sample_size < 1024) return vmps_sort(keys, values, n, kt, flags, ws, ws_bytes, stream);
+    const LearnedLayout L = learned_layout((uint64_t)n, kt, has_values, c);
+    uint8_t* w = (uint8_t*)ws;
+    void* keysB = w + L.keys_b;
+    uint32_t* valsB = has_values ? (uint32_t*)(w + L.vals_b) : nullptr;
+    vmps_cdf_model* M = (vmps_cdf_model*)(w + L.model);
+    int64_t* boff = (int64_t*)(w + L.boff);
+    hipStream_t s = (hipStream_t)stream;
+    const int vmode = values ? ((flags & VMPS_VALUES_IOTA) ? 2 : 1) : 0;
+    return guarded([&]() -> hipError_t {
+        {
+            TraceScope tr(VMPS_TRACE_SAMPLE, s);
+            VMPS_HIP(sample_enqueue(keys, (uint64_t)n, kb, L.m, c.seed, w + L.sample, s));
+            if (vmps_sort(w + L.sample, nullptr, (int64_t)L.m, kt, 0, w + L.sample_ws,
+                          sort_layout(L.m, 1, kt, 0).total, stream) != VMPS_OK)
+                return hipErrorLaunchFailure;
+        }
+        {
+            TraceScope tr(VMPS_TRACE_TRAIN, s);
+            VMPS_HIP(train_enqueue(w + L.sample, L.m, kb, c, (float*)(w + L.u), M, s));
+        }
+        VMPS_HIP(partition_enqueue(keys, values, keysB, valsB, keys, values, (uint32_t)n, kb, vmode, M, L.B, boff,
+                                   (uint32_t*)(w + L.arena), s));
+        Plan P;
+        plan_carve(P, w + L.plan, (uint64_t)n, L.B, T, merge_tile_out(kb, has_values));
+        P.inst_off64 = boff;
+        P.big_min = T;
+        VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
+        VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
+        if (stats) VMPS_HIP(learned_stats_enqueue(boff, L.B, T, M, stats, s));
+        if (model) VMPS_HIP(hipMemcpyAsync(model, M, sizeof(vmps_cdf_model), hipMemcpyDeviceToDevice, s));
+        return hipGetLastError();
+    });
+}
+
+vmps_status vmps_sample(const void* keys, int64_t n, vmps_dtype kt, int64_t m, uint64_t seed, void* out,
+                        void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (n < 1 || m < 0 || !out || ((uintptr_t)out % key_bytes(kt))) return VMPS_ERR_INVALID_ARG;
+    if (m == 0) return VMPS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] { return sample_enqueue(keys, (uint64_t)n, key_bits_of(kt), (uint64_t)m, seed, out, s); });
+}
+
+vmps_status vmps_cdf_grad(const float* params, int32_t hidden, const float* u, const float* y, int32_t nb,
+                          float* grad, float* loss, void* stream)
+{
+    if (!params || !u || !y || !grad || !loss || nb < 1) return VMPS_ERR_INVALID_ARG;
+    if (hidden != 16 && hidden != 32 && hidden != 64) return VMPS_ERR_INVALID_ARG;
+    if (nb % 64) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] { return grad_enqueue(params, hidden, u, y, nb, grad, loss, s); });
+}
+
+vmps_status vmps_cdf_train(const void* sorted_sample, int64_t m, vmps_dtype kt, const vmps_learned_config* cfg,
+                           vmps_cdf_model* model, void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(sorted_sample, m, kt);
+    if (st != VMPS_OK) return st;
+    if (!cfg || !model || m < 2) return VMPS_ERR_INVALID_ARG;
+    vmps_learned_config c = *cfg;
+    c.sample_size = m;
+    if (check_config(c, m) != VMPS_OK) return VMPS_ERR_INVALID_ARG;
+    if (!ws || ws_bytes < 4 * (size_t)m) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] { return train_enqueue(sorted_sample, (uint64_t)m, key_bits_of(kt), c, (float*)ws, model, s); });
+}
+
+vmps_status vmps_cdf_compile(const float* params, int32_t hidden, uint64_t z_lo, uint64_t z_hi, int32_t key_bits,
+                             int32_t feature_bits, int32_t knots, vmps_cdf_model* model, void* stream)
+{
+    if (!params || !model || (hidden != 16 && hidden != 32 && hidden != 64)) return VMPS_ERR_INVALID_ARG;
+    if (z_hi < z_lo || (key_bits != 32 && key_bits != 64) || feature_bits < 4 || feature_bits > 24) return VMPS_ERR_INVALID_ARG;
+    if (knots < 1 || knots > VMPS_CDF_MAX_KNOTS || z_hi - z_lo >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] { return compile_enqueue(params, hidden, z_lo, z_hi, key_bits, feature_bits, knots, model, s); });
+}
+
+vmps_status vmps_bucket_ids(const void* keys, int64_t n, vmps_dtype kt, const vmps_cdf_model* model,
+                            int32_t num_buckets, uint32_t* ids, void* stream)
+{
+    vmps_status st = check_keys(keys, n, kt);
+    if (st != VMPS_OK) return st;
+    if (!model || !ids || num_buckets < 1) return VMPS_ERR_INVALID_ARG;
+    if (n == 0) return VMPS_OK;
+    hipStream_t s = (hipStream_t)stream;
+    return guarded([&] {
+        return bucket_ids_enqueue(keys, (uint64_t)n, key_bits_of(kt), model, (uint32_t)num_buckets, ids, s);
+    });
+}
+
+vmps_status vmps_partition_workspace_size(int64_t n, vmps_dtype kt, int has_values, int32_t num_buckets,
+                                          size_t* bytes)
+{
+    if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32) || (kt != VMPS_U32 && kt != VMPS_U64)) return VMPS_ERR_INVALID_ARG;
+    if (!pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > 65536) return VMPS_ERR_INVALID_ARG;
+    *bytes = align256(key_bytes(kt) * (size_t)n) + (has_values ? align256(4 * (size_t)n) : 0) +
+             align256(4 * partition_arena_words((uint64_t)n, (uint32_t)num_buckets));
+    return VMPS_OK;
+}
+
+vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t n, vmps_dtype kt,
+                           const vmps_cdf_model* model, int32_t num_buckets, void* keys_out, uint32_t* vals_out,
+                           int64_t* bucket_offsets, void* ws, size_t ws_bytes, void* stream)
+{
+    vmps_status st = check_keys(keys_in, n, kt);
+    if (st == VMPS_OK) st = check_keys(keys_out, n, kt);
+    if (st != VMPS_OK) return st;
+    if (!model || !bucket_offsets || !pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > 65536)
+        return VMPS_ERR_INVALID_ARG;
+    if ((vals_in == nullptr) != (vals_out == nullptr)) return VMPS_ERR_INVALID_ARG;
+    if (n > 0 && ranges_overlap(keys_in, key_bytes(kt) * n, keys_out, key_bytes(kt) * n)) return VMPS_ERR_INVALID_ARG;
+    size_t need = 0;
+    vmps_partition_workspace_size(n, kt, vals_in != nullptr, num_buckets, &need);
+    if (!ws || ws_bytes < need) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    uint8_t* w = (uint8_t*)ws;
+    void* ktmp = w;
+    size_t off = align256(key_bytes(kt) * (size_t)n);
+    uint32_t* vtmp = vals_in ? (uint32_t*)(w + off) : nullptr;
+    off += vals_in ? align256(4 * (size_t)n) : 0;
+    uint32_t* arena = (uint32_t*)(w + off);
+    return guarded([&] {
+        return partition_enqueue(keys_in, vals_in, ktmp, vtmp, keys_out, vals_out, (uint32_t)n, key_bits_of(kt),
+                                 vals_in ? 1 : 0, model, (uint32_t)num_buckets, bucket_offsets, arena, s);
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,732 @@
+// Learned CDF partitioning in front of Powersort.
+//
+// sample -> sort the sample (the plain Powersort path) -> features ->
+// train (forward/backward/Adam in one workgroup) -> compile to an integer
+// knot table -> stable two-level scatter by bucket id -> Powersort of every
+// bucket as an instance of its own (the segmented path).  Buckets are
+// increasing key ranges and the scatter is stable, so the output is the
+// stable sort for any model; the model only decides how even the buckets
+// are, and buckets longer than the LDS tile fall back to the merge levels.
+#include <string.h>
+
+#include "vmps_internal.hpp"
+
+namespace vmps {
+
+constexpr uint32_t PART_TILE = 4096;  // keys per scatter workgroup
+constexpr int PART_NT = 256;
+constexpr int PART_KPT = PART_TILE / PART_NT;
+constexpr uint64_t BATCH_STRIDE = 0x9E3779B1ull;  // odd: visits every sample mod 2^k
+constexpr int LOSS_STRIDE = 64;
+constexpr float KNOT_GAP = 1e-6f;
+
+// ------------------------------------------------------------ helpers --
+// Output `counter` (0-based) of SplitMix64 seeded with `seed`.
+__device__ inline uint64_t splitmix64_at(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Monotone feature: bit length, then the fbits bits below the leading one.
+__device__ inline uint64_t feature_of(uint64_t key, int fbits)
+{
+    if (!key) return 0;
+    const int b = 64 - __clzll((long long)key);
+    const uint64_t rest = key & ((1ull << (b - 1)) - 1);
+    const uint64_t mant = (b - 1 >= fbits) ? (rest >> (b - 1 - fbits)) : (rest << (fbits - (b - 1)));
+    return ((uint64_t)b << fbits) | (mant & ((1ull << fbits) - 1));
+}
+
+struct ModelArgs {
+    uint64_t z_lo, range;
+    int fbits, shift, knots;
+    uint32_t B;
+    const uint64_t* table;
+};
+
+__device__ inline uint32_t bucket_of(uint64_t key, const ModelArgs& M)
+{
+    const uint64_t z = feature_of(key, M.fbits);
+    const uint64_t d = z <= M.z_lo ? 0 : (z - M.z_lo > M.range ? M.range : z - M.z_lo);
+    const uint64_t seg = d >> M.shift;
+    uint64_t pos;
+    if (seg >= (uint64_t)M.knots) {
+        pos = M.table[M.knots];
+    } else {
+        const uint64_t t0 = M.table[seg], t1 = M.table[seg + 1];
+        pos = t0 + (((t1 - t0) * (d & ((1ull << M.shift) - 1))) >> M.shift);
+    }
+    const uint64_t b = (pos * M.B) >> 32;
+    return (uint32_t)(b >= M.B ? M.B - 1 : b);
+}
+
+// Bucket arguments of a compiled model (uniform loads at kernel start).
+__device__ inline ModelArgs model_args(const vmps_cdf_model* model, uint32_t B)
+{
+    ModelArgs a;
+    a.z_lo = model->z_lo;
+    a.range = model->z_hi > model->z_lo ? model->z_hi - model->z_lo : 0;
+    // a caller-built model is clamped to the table it can hold
+    a.fbits = min(max(model->feature_bits, 1), 24);
+    a.shift = min(max(model->shift, 0), 62);
+    a.knots = min(max(model->knots, 1), VMPS_CDF_MAX_KNOTS);
+    a.B = B;
+    a.table = model->table;
+    return a;
+}
+
+// ------------------------------------------------------------ sample --
+template <typename K>
+__global__ void k_sample_gather(const K* __restrict__ keys, uint64_t n, uint64_t m, uint64_t seed,
+                                K* __restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    out[i] = keys[splitmix64_at(seed, i) % n];
+}
+
+template <typename K>
+__global__ void k_cdf_features(const K* __restrict__ s, uint64_t m, int key_bits, int fbits,
+                               float* __restrict__ u, vmps_cdf_model* model)
+{
+    const uint64_t z_lo = feature_of((uint64_t)s[0], fbits), z_hi = feature_of((uint64_t)s[m - 1], fbits);
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
+        model->z_lo = z_lo;
+        model->z_hi = z_hi;
+        model->key_bits = key_bits;
+        model->feature_bits = fbits;
+    }
+    if (i >= m) return;
+    const uint64_t range = z_hi - z_lo;
+    u[i] = range ? (float)(feature_of((uint64_t)s[i], fbits) - z_lo) / (float)range : 0.f;
+}
+
+// ------------------------------------------------------------- model --
+// Sum over the H lanes of a lane group (xor butterfly; H divides 64).
+template <int H>
+__device__ inline float group_sum(float v)
+{
+#pragma unroll
+    for (int off = 1; off < H; off <<= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+constexpr int TRAIN_NT = 1024;
+
+struct TrainLds {
+    float p[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    float g[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    float m1[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    float m2[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    float best[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    float pw1[TRAIN_NT], pb1[TRAIN_NT], pw2[TRAIN_NT];
+    float pb2[TRAIN_NT], pl[TRAIN_NT];
+    float q[VMPS_CDF_MAX_HIDDEN], y[VMPS_CDF_MAX_HIDDEN];
+    float loss;
+};
+
+// Gradient of the minibatch MSE (forward pass, then backpropagation through
+// the hidden ReLU layer).  Thread t owns hidden unit t % H of lane group
+// t / H; groups take the batch points in turn; partial sums are reduced in
+// a fixed order, so the result does not depend on timing.
+// point(j, u, y) yields minibatch point j.  Writes S.g and S.loss.
+template <int H, typename Point>
+__device__ void batch_grad(TrainLds& S, int nb, Point point)
+{
+    constexpr int G = TRAIN_NT / H;
+    const int t = threadIdx.x, h = t % H, grp = t / H;
+    const float w1 = S.p[h], b1 = S.p[H + h], w2 = S.p[2 * H + h], b2 = S.p[3 * H];
+    const float inv = 2.f / (float)nb;
+    float aw1 = 0.f, ab1 = 0.f, aw2 = 0.f, ab2 = 0.f, al = 0.f;
+    for (int j = grp; j < nb; j += G) {
+        float u, y;
+        point(j, u, y);
+        const float a = w1 * u + b1;
+        const float r = a > 0.f ? a : 0.f;
+        const float f = group_sum<H>(w2 * r) + b2;
+        const float e = f - y;
+        const float dfd = inv * e;
+        if (a > 0.f) {
+            aw2 += dfd * r;
+            aw1 += dfd * w2 * u;
+            ab1 += dfd * w2;
+        }
+        ab2 += dfd;
+        al += e * e;
+    }
+    S.pw1[t] = aw1; S.pb1[t] = ab1; S.pw2[t] = aw2;
+    if (h == 0) { S.pb2[grp] = ab2; S.pl[grp] = al; }
+    __syncthreads();
+    if (t < H) {
+        float s1 = 0.f, s2 = 0.f, s3 = 0.f;
+        for (int gg = 0; gg < G; ++gg) {
+            s1 += S.pw1[gg * H + t];
+            s2 += S.pb1[gg * H + t];
+            s3 += S.pw2[gg * H + t];
+        }
+        S.g[t] = s1; S.g[H + t] = s2; S.g[2 * H + t] = s3;
+    } else if (t == H) {
+        float s = 0.f, l = 0.f;
+        for (int gg = 0; gg < G; ++gg) { s += S.pb2[gg]; l += S.pl[gg]; }
+        S.g[3 * H] = s;
+        S.loss = l / (float)nb;
+    }
+    __syncthreads();
+}
+
+template <int H>
+__global__ __launch_bounds__(TRAIN_NT) void k_cdf_grad(const float* __restrict__ params, const float* __restrict__ u,
+                                                       const float* __restrict__ y, int nb, float* __restrict__ grad,
+                                                       float* __restrict__ loss)
+{
+    __shared__ TrainLds S;
+    const int t = threadIdx.x;
+    if (t < 3 * H + 1) S.p[t] = params[t];
+    __syncthreads();
+    batch_grad<H>(S, nb, [&](int j, float& uu, float& yy) { uu = u[j]; yy = y[j]; });
+    if (t < 3 * H + 1) grad[t] = S.g[t];
+    if (t == 0) *loss = S.loss;
+}
+
+template <int H>
+__device__ float model_eval(const float* p, float u)
+{
+    float f = p[3 * H];
+#pragma unroll 8
+    for (int h = 0; h < H; ++h) {
+        const float a = p[h] * u + p[H + h];
+        f += p[2 * H + h] * (a > 0.f ? a : 0.f);
+    }
+    return f;
+}
+
+// Mean squared error over every LOSS_STRIDE-th sample point (block-wide).
+template <int H>
+__device__ float strided_loss(TrainLds& S, const float* __restrict__ u, uint64_t m)
+{
+    const int t = threadIdx.x;
+    float acc = 0.f;
+    uint64_t cnt = (m + LOSS_STRIDE - 1) / LOSS_STRIDE;
+    for (uint64_t k = t; k < cnt; k += TRAIN_NT) {
+        const uint64_t i = k * LOSS_STRIDE;
+        const float e = model_eval<H>(S.p, u[i]) - ((float)i + 0.5f) / (float)m;
+        acc += e * e;
+    }
+    S.pl[t] = acc;
+    __syncthreads();
+    if (t == 0) {
+        float s = 0.f;
+        for (int k = 0; k < TRAIN_NT; ++k) s += S.pl[k];
+        S.loss = s / (float)cnt;
+    }
+    __syncthreads();
+    return S.loss;
+}
+
+// Compile the parameters in p into the model's knot table (block-wide).
+template <int H>
+__device__ void compile_table(const float* p, vmps_cdf_model* model, uint64_t z_lo, uint64_t z_hi, int K,
+                              uint32_t* scan_lds)
+{
+    const int t = threadIdx.x;
+    const uint64_t range = z_hi > z_lo ? z_hi - z_lo : 0;
+    int sh = 0;
+    while (((range + (1ull << sh) - 1) >> sh) > (uint64_t)K) ++sh;
+    uint64_t kk = (range + (1ull << sh) - 1) >> sh;
+    const int kn = kk > 0 ? (int)kk : 1;
+    // knots, then a running maximum (block scan of per-thread maxima)
+    constexpr int PER = (VMPS_CDF_MAX_KNOTS + 1 + TRAIN_NT - 1) / TRAIN_NT;
+    uint32_t v[PER];
+    uint32_t mx = 0;
+    for (int j = 0; j < PER; ++j) {
+        const int s = t * PER + j;
+        uint32_t q = 0;
+        if (s <= kn) {
+            float u = range ? (float)((uint64_t)s << sh) / (float)range : 0.f;
+            if (u > 1.f) u = 1.f;
+            float f = model_eval<H>(p, u);
+            if (!(f > 0.f)) f = 0.f;
+            if (f > 1.f) f = 1.f;
+            const float qf = floorf(f * 4294967296.0f);
+            q = qf >= 4294967295.0f ? 4294967295u : (uint32_t)qf;
+        }
+        mx = max(mx, q);
+        v[j] = mx;
+    }
+    scan_lds[t] = mx;
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < TRAIN_NT; ++k) { uint32_t x = scan_lds[k]; scan_lds[k] = run; run = max(run, x); }
+    }
+    __syncthreads();
+    const uint32_t before = scan_lds[t];
+    for (int j = 0; j < PER; ++j) {
+        const int s = t * PER + j;
+        if (s <= kn) model->table[s] = (uint64_t)max(before, v[j]);
+    }
+    if (t == 0) {
+        model->knots = kn;
+        model->shift = sh;
+        model->hidden = H;
+    }
+    if (t < H) {
+        model->w1[t] = p[t];
+        model->b1[t] = p[H + t];
+        model->w2[t] = p[2 * H + t];
+    }
+    if (t == 0) model->b2 = p[3 * H];
+    __syncthreads();
+}
+
+template <int H>
+__global__ __launch_bounds__(TRAIN_NT) void k_cdf_compile(const float* __restrict__ params, uint64_t z_lo,
+                                                          uint64_t z_hi, int key_bits, int fbits, int K,
+                                                          vmps_cdf_model* model)
+{
+    __shared__ float p[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    __shared__ uint32_t scan_lds[TRAIN_NT];
+    const int t = threadIdx.x;
+    if (t < 3 * H + 1) p[t] = params[t];
+    if (t == 0) {
+        model->z_lo = z_lo; model->z_hi = z_hi; model->key_bits = key_bits; model->feature_bits = fbits;
+        model->trained = 0; model->loss_init = 0.f; model->loss_final = 0.f;
+    }
+    __syncthreads();
+    compile_table<H>(p, model, z_lo, z_hi, K, scan_lds);
+}
+
+// Whole training in one workgroup: quantile initialisation, `steps` Adam
+// steps on strided minibatches, keep the better of initial and trained
+// model, compile.
+template <int H>
+__global__ __launch_bounds__(TRAIN_NT) void k_cdf_train(const float* __restrict__ u, uint64_t m, int steps,
+                                                        int nb, float lr, int K, vmps_cdf_model* model)
+{
+    __shared__ TrainLds S;
+    __shared__ uint32_t scan_lds[TRAIN_NT];
+    const int t = threadIdx.x;
+    constexpr int NP = 3 * H + 1;
+    // hinges at evenly spaced sample quantiles, interpolating (i + 1/2)/m
+    if (t < H) {
+        const uint64_t qi = (H > 1) ? ((uint64_t)t * (m - 1)) / (H - 1) : 0;
+        S.q[t] = u[qi];
+        S.y[t] = ((float)qi + 0.5f) / (float)m;
+    }
+    __syncthreads();
+    if (t == 0)
+        for (int h = 1; h < H; ++h)
+            if (S.q[h] <= S.q[h - 1]) S.q[h] = S.q[h - 1] + KNOT_GAP;
+    __syncthreads();
+    if (t < H) {
+        const float right = (t + 1 < H) ? (S.y[t + 1] - S.y[t]) / (S.q[t + 1] - S.q[t]) : 0.f;
+        const float left = (t > 0) ? (S.y[t] - S.y[t - 1]) / (S.q[t] - S.q[t - 1]) : 0.f;
+        S.p[t] = 1.f;
+        S.p[H + t] = -S.q[t];
+        S.p[2 * H + t] = right - left;
+    }
+    if (t == 0) S.p[3 * H] = S.y[0];
+    if (t < NP) { S.m1[t] = 0.f; S.m2[t] = 0.f; }
+    __syncthreads();
+    const float loss0 = strided_loss<H>(S, u, m);
+    if (t < NP) S.best[t] = S.p[t];
+    __syncthreads();
+    const float fm = (float)m;
+    for (int s = 0; s < steps; ++s) {
+        batch_grad<H>(S, nb, [&](int j, float& uu, float& yy) {
+            const uint64_t idx = (((uint64_t)s * (uint64_t)nb + (uint64_t)j) * BATCH_STRIDE) % m;
+            uu = u[idx];
+            yy = ((float)idx + 0.5f) / fm;
+        });
+        if (t < NP) {
+            // Adam (Kingma and Ba 2015) with bias correction
+            const float g = S.g[t];
+            const float m1 = 0.9f * S.m1[t] + 0.1f * g;
+            const float m2 = 0.999f * S.m2[t] + 0.001f * g * g;
+            S.m1[t] = m1; S.m2[t] = m2;
+            const float c1 = 1.f - powf(0.9f, (float)(s + 1));
+            const float c2 = 1.f - powf(0.999f, (float)(s + 1));
+            S.p[t] -= lr * (m1 / c1) / (sqrtf(m2 / c2) + 1e-8f);
+        }
+        __syncthreads();
+    }
+    const float loss1 = strided_loss<H>(S, u, m);
+    const bool keep = !(loss1 <= loss0);
+    if (keep && t < NP) S.p[t] = S.best[t];
+    __syncthreads();
+    if (t == 0) {
+        model->trained = keep ? 0 : 1;
+        model->loss_init = loss0;
+        model->loss_final = keep ? loss0 : loss1;
+    }
+    compile_table<H>(S.p, model, model->z_lo, model->z_hi, K, scan_lds);
+}
+
+// ------------------------------------------------------------ buckets --
+template <typename K>
+__global__ void k_bucket_ids(const K* __restrict__ keys, uint64_t n, const vmps_cdf_model* __restrict__ model,
+                             uint32_t B, uint32_t* __restrict__ ids)
+{
+    const ModelArgs M = model_args(model, B);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        ids[i] = bucket_of((uint64_t)keys[i], M);
+}
+
+// One level of the stable scatter: parents [pstart[c], pstart[c+1]) are cut
+// into tiles (tile prefix tbase); digit = (bucket >> shift) & mask.
+struct PartLevel {
+    const uint32_t* pstart;
+    const uint32_t* tbase;
+    uint32_t P, F, shift, mask;
+    uint32_t* counts;
+    const uint32_t* offs;
+};
+
+__device__ inline void part_tile(const PartLevel& L, uint32_t tile, uint32_t& c, uint32_t& tl, uint32_t& nt,
+                                 uint32_t& s0, uint32_t& s1)
+{
+    uint32_t lo = 0, hi = L.P;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (L.tbase[mid] <= tile) lo = mid; else hi = mid;
+    }
+    c = lo;
+    tl = tile - L.tbase[c];
+    nt = L.tbase[c + 1] - L.tbase[c];
+    s0 = L.pstart[c] + tl * PART_TILE;
+    s1 = min(L.pstart[c + 1], s0 + PART_TILE);
+}
+
+template <typename K>
+__global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ keys, PartLevel L,
+                                                       const vmps_cdf_model* __restrict__ model, uint32_t B)
+{
+    __shared__ uint32_t hist[256];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= L.tbase[L.P]) return;
+    const ModelArgs M = model_args(model, B);
+    uint32_t c, tl, nt, s0, s1;
+    part_tile(L, tile, c, tl, nt, s0, s1);
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t i = s0 + threadIdx.x; i < s1; i += PART_NT)
+        atomicAdd(&hist[(bucket_of((uint64_t)keys[i], M) >> L.shift) & L.mask], 1u);
+    __syncthreads();
+    if (threadIdx.x < L.F) L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)threadIdx.x * nt + tl] = hist[threadIdx.x];
+}
+
+// Stable scatter of one tile: ranks by (digit, input position) from
+// wave ballots, a local reorder by digit in LDS, then runs of equal digit
+// are written contiguously.  VMODE 2 generates the values (input index).
+template <typename K, int VMODE>
+__global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                          K* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                          PartLevel L, const vmps_cdf_model* __restrict__ model,
+                                                          uint32_t B)
+{
+    constexpr int NW = PART_NT / 64;
+    __shared__ K skey[PART_TILE];
+    __shared__ uint32_t sval[VMODE ? PART_TILE : 1];
+    __shared__ uint8_t sdig[PART_TILE];
+    __shared__ uint32_t cnt[256], loff[256], goff[256], wcnt[NW][256];
+    __shared__ uint32_t scan_lds[NW + 1];
+    const uint32_t tile = blockIdx.x;
+    if (tile >= L.tbase[L.P]) return;
+    const ModelArgs M = model_args(model, B);
+    uint32_t c, tl, nt, s0, s1;
+    part_tile(L, tile, c, tl, nt, s0, s1);
+    const uint32_t len = s1 - s0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    cnt[tid] = 0;
+    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    K kr[PART_KPT];
+    uint32_t vr[PART_KPT], rk[PART_KPT], dg[PART_KPT];
+    const uint64_t lt = (1ull << lane) - 1;
+#pragma unroll
+    for (int r = 0; r < PART_KPT; ++r) {
+        const uint32_t i = r * PART_NT + tid;
+        const bool valid = i < len;
+        K key = 0;
+        uint32_t d = 0;
+        if (valid) {
+            key = kin[s0 + i];
+            d = (bucket_of((uint64_t)key, M) >> L.shift) & L.mask;
+            if (VMODE == 1) vr[r] = vin[s0 + i];
+            if (VMODE == 2) vr[r] = s0 + i;
+        }
+        kr[r] = key;
+        uint64_t peers = __ballot(valid);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool bit = (d >> k) & 1u;
+            const uint64_t bk = __ballot(bit);
+            peers &= bit ? bk : ~bk;
+        }
+        const uint32_t rw = __popcll(peers & lt);
+        if (valid && rw == 0) wcnt[wave][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t base = cnt[d];
+            for (int w = 0; w < wave; ++w) base += wcnt[w][d];
+            rk[r] = base + rw;
+            dg[r] = d;
+        }
+        __syncthreads();
+        {
+            uint32_t tot = 0;
+            for (int w = 0; w < NW; ++w) { tot += wcnt[w][tid]; wcnt[w][tid] = 0; }
+            cnt[tid] += tot;
+        }
+        __syncthreads();
+    }
+    uint32_t total;
+    const uint32_t ex = block_excl_scan(cnt[tid], scan_lds, &total);
+    loff[tid] = ex;
+    if ((uint32_t)tid < L.F) goff[tid] = L.offs[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl];
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < PART_KPT; ++r) {
+        const uint32_t i = r * PART_NT + tid;
+        if (i < len) {
+            const uint32_t lp = loff[dg[r]] + rk[r];
+            skey[lp] = kr[r];
+            if (VMODE) sval[lp] = vr[r];
+            sdig[lp] = (uint8_t)dg[r];
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < len; i += PART_NT) {
+        const uint32_t d = sdig[i];
+        const uint32_t o = goff[d] + (i - loff[d]);
+        kout[o] = skey[i];
+        if (VMODE) vout[o] = sval[i];
+    }
+}
+
+// Level-1 parents: the whole array.
+__global__ void k_part_init(uint32_t n, uint32_t* pstart, uint32_t* tbase, uint32_t* count_out, uint32_t F)
+{
+    pstart[0] = 0;
+    pstart[1] = n;
+    tbase[0] = 0;
+    tbase[1] = (uint32_t)ceil_div(n, PART_TILE);
+    *count_out = tbase[1] * F;
+}
+
+// Level-2 parents: the level-1 digit ranges.
+__global__ __launch_bounds__(256) void k_part_level2(const uint32_t* __restrict__ offs1, uint32_t nt1, uint32_t F1,
+                                                     uint32_t n, uint32_t F2, uint32_t* __restrict__ pstart,
+                                                     uint32_t* __restrict__ tbase, uint32_t* count_out)
+{
+    __shared__ uint32_t lds[256 / WAVE + 1];
+    const uint32_t c = threadIdx.x;
+    uint32_t s = 0, e = 0;
+    if (c < F1) {
+        s = offs1[(uint64_t)c * nt1];
+        e = (c + 1 < F1) ? offs1[(uint64_t)(c + 1) * nt1] : n;
+        pstart[c] = s;
+    }
+    if (c == 0) pstart[F1] = n;
+    const uint32_t tiles = c < F1 ? (uint32_t)ceil_div(e - s, PART_TILE) : 0u;
+    uint32_t tot;
+    const uint32_t ex = block_excl_scan(tiles, lds, &tot);
+    if (c < F1) tbase[c] = ex;
+    if (c == 0) { tbase[F1] = tot; *count_out = tot * F2; }
+}
+
+__global__ void k_zero_offsets(int64_t* off, uint32_t B)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= B) off[b] = 0;
+}
+
+// Start of every bucket after both levels.
+__global__ void k_bucket_offsets(const uint32_t* __restrict__ pstart2, const uint32_t* __restrict__ tbase2,
+                                 const uint32_t* __restrict__ offs2, uint32_t F2, uint32_t lo_bits, uint32_t B,
+                                 uint32_t n, int64_t* __restrict__ off)
+{
+    const uint32_t b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > B) return;
+    if (b == B) { off[B] = n; return; }
+    const uint32_t c = b >> lo_bits, f = b & ((1u << lo_bits) - 1);
+    const uint32_t nt = tbase2[c + 1] - tbase2[c];
+    off[b] = nt ? offs2[(uint64_t)tbase2[c] * F2 + (uint64_t)f * nt] : pstart2[c];
+}
+
+__global__ __launch_bounds__(256) void k_learned_stats(const int64_t* __restrict__ off, uint32_t B, uint32_t T,
+                                                       const vmps_cdf_model* model, vmps_learned_stats* st)
+{
+    __shared__ unsigned long long s_ne, s_fb, s_fk, s_mx;
+    if (threadIdx.x == 0) { s_ne = 0; s_fb = 0; s_fk = 0; s_mx = 0; }
+    __syncthreads();
+    unsigned long long ne = 0, fb = 0, fk = 0, mx = 0;
+    for (uint32_t b = threadIdx.x; b < B; b += 256) {
+        const unsigned long long len = (unsigned long long)(off[b + 1] - off[b]);
+        ne += len > 0;
+        if (len > T) { fb += 1; fk += len; }
+        mx = len > mx ? len : mx;
+    }
+    atomicAdd(&s_ne, ne); atomicAdd(&s_fb, fb); atomicAdd(&s_fk, fk); atomicMax(&s_mx, mx);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        st->buckets = B; st->nonempty_buckets = (int64_t)s_ne; st->fallback_buckets = (int64_t)s_fb;
+        st->fallback_keys = (int64_t)s_fk; st->max_bucket = (int64_t)s_mx;
+        st->loss_init = model->loss_init; st->loss_final = model->loss_final;
+    }
+}
+
+// ------------------------------------------------------------- host --
+namespace {
+inline unsigned grid1(uint64_t n, unsigned b = 256) { return (unsigned)ceil_div(n ? n : 1, b); }
+
+template <typename K>
+hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtmp, K* kout, uint32_t* vout,
+                       uint32_t n, int vmode, const vmps_cdf_model* Mdev, uint32_t B, int64_t* bucket_off,
+                       uint32_t* arena, hipStream_t s)
+{
+    // bucket id bits: level 1 takes the top 8 (or fewer), level 2 the rest
+    uint32_t bits = 0;
+    while ((1u << bits) < B) ++bits;
+    const uint32_t lo_bits = bits > 8 ? bits - 8 : 0;
+    const uint32_t F1 = B >> lo_bits, F2 = 1u << lo_bits;
+    const uint32_t nt1 = (uint32_t)ceil_div(n, PART_TILE);
+    const uint32_t nt2cap = nt1 + F1;
+    uint32_t* p1 = arena;            // pstart1[2], tbase1[2]
+    uint32_t* t1 = arena + 2;
+    uint32_t* p2 = arena + 4;        // 257
+    uint32_t* t2 = p2 + 260;         // 257
+    uint32_t* cnt_total = t2 + 260;  // 2 scalars
+    uint32_t* tot = cnt_total + 2;   // 2 scalars
+    uint32_t* c1 = tot + 4;
+    uint32_t* o1 = c1 + (uint64_t)nt1 * F1;
+    uint32_t* c2 = o1 + (uint64_t)nt1 * F1;
+    uint32_t* o2 = c2 + (uint64_t)nt2cap * F2;
+    uint32_t* stmp = o2 + (uint64_t)nt2cap * F2;
+    {
+        TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
+        k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
+        PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
+        k_part_hist<K><<<nt1, PART_NT, 0, s>>>(kin, L1, Mdev, B);
+        VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
+    }
+    {
+        TraceScope tr(VMPS_TRACE_SCATTER, s);
+        PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
+        if (vmode == 0) k_part_scatter<K, 0><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
+        else if (vmode == 1) k_part_scatter<K, 1><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
+        else k_part_scatter<K, 2><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
+    }
+    {
+        TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
+        k_part_level2<<<1, 256, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
+        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
+        k_part_hist<K><<<nt2cap, PART_NT, 0, s>>>(ktmp, L2, Mdev, B);
+        VMPS_HIP(scan_exclusive_u32(c2, o2, (uint64_t)nt2cap * F2, cnt_total + 1, tot + 1, stmp, s));
+    }
+    {
+        TraceScope tr(VMPS_TRACE_SCATTER, s);
+        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
+        if (vmode == 0) k_part_scatter<K, 0><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, kout, vout, L2, Mdev, B);
+        else k_part_scatter<K, 1><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, kout, vout, L2, Mdev, B);
+    }
+    k_bucket_offsets<<<grid1(B + 1), 256, 0, s>>>(p2, t2, o2, F2, lo_bits, B, n, bucket_off);
+    return hipGetLastError();
+}
+}  // namespace
+
+uint64_t partition_arena_words(uint64_t n, uint32_t B)
+{
+    uint32_t bits = 0;
+    while ((1u << bits) < B) ++bits;
+    const uint32_t lo_bits = bits > 8 ? bits - 8 : 0;
+    const uint64_t F1 = B >> lo_bits, F2 = 1ull << lo_bits;
+    const uint64_t nt1 = ceil_div(n ? n : 1, PART_TILE);
+    const uint64_t nt2cap = nt1 + F1;
+    const uint64_t big = nt1 * F1 > nt2cap * F2 ? nt1 * F1 : nt2cap * F2;
+    return 4 + 520 + 8 + 2 * nt1 * F1 + 2 * nt2cap * F2 + scan_tmp_words(big) + 64;
+}
+
+hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, uint32_t* vtmp, void* kout,
+                             uint32_t* vout, uint32_t n, int key_bits, int vmode, const vmps_cdf_model* model,
+                             uint32_t B, int64_t* bucket_off, uint32_t* arena, hipStream_t s)
+{
+    if (n == 0) {
+        k_zero_offsets<<<grid1(B + 1), 256, 0, s>>>(bucket_off, B);
+        return hipGetLastError();
+    }
+    if (key_bits == 32)
+        return partition_t<uint32_t>((const uint32_t*)kin, vin, (uint32_t*)ktmp, vtmp, (uint32_t*)kout, vout, n,
+                                     vmode, model, B, bucket_off, arena, s);
+    return partition_t<uint64_t>((const uint64_t*)kin, vin, (uint64_t*)ktmp, vtmp, (uint64_t*)kout, vout, n, vmode,
+                                 model, B, bucket_off, arena, s);
+}
+
+hipError_t sample_enqueue(const void* keys, uint64_t n, int key_bits, uint64_t m, uint64_t seed, void* out,
+                          hipStream_t s)
+{
+    if (key_bits == 32)
+        k_sample_gather<uint32_t><<<grid1(m), 256, 0, s>>>((const uint32_t*)keys, n, m, seed, (uint32_t*)out);
+    else
+        k_sample_gather<uint64_t><<<grid1(m), 256, 0, s>>>((const uint64_t*)keys, n, m, seed, (uint64_t*)out);
+    return hipGetLastError();
+}
+
+hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmps_learned_config& c, float* u,
+                         vmps_cdf_model* model, hipStream_t s)
+{
+    if (key_bits == 32)
+        k_cdf_features<uint32_t><<<grid1(m), 256, 0, s>>>((const uint32_t*)sorted, m, 32, c.feature_bits, u, model);
+    else
+        k_cdf_features<uint64_t><<<grid1(m), 256, 0, s>>>((const uint64_t*)sorted, m, 64, c.feature_bits, u, model);
+    switch (c.hidden) {
+    case 16: k_cdf_train<16><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
+    case 32: k_cdf_train<32><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
+    default: k_cdf_train<64><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t grad_enqueue(const float* params, int H, const float* u, const float* y, int nb, float* grad, float* loss,
+                        hipStream_t s)
+{
+    switch (H) {
+    case 16: k_cdf_grad<16><<<1, TRAIN_NT, 0, s>>>(params, u, y, nb, grad, loss); break;
+    case 32: k_cdf_grad<32><<<1, TRAIN_NT, 0, s>>>(params, u, y, nb, grad, loss); break;
+    default: k_cdf_grad<64><<<1, TRAIN_NT, 0, s>>>(params, u, y, nb, grad, loss); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t compile_enqueue(const float* params, int H, uint64_t z_lo, uint64_t z_hi, int key_bits, int fbits, int K,
+                           vmps_cdf_model* model, hipStream_t s)
+{
+    switch (H) {
+    case 16: k_cdf_compile<16><<<1, TRAIN_NT, 0, s>>>(params, z_lo, z_hi, key_bits, fbits, K, model); break;
+    case 32: k_cdf_compile<32><<<1, TRAIN_NT, 0, s>>>(params, z_lo, z_hi, key_bits, fbits, K, model); break;
+    default: k_cdf_compile<64><<<1, TRAIN_NT, 0, s>>>(params, z_lo, z_hi, key_bits, fbits, K, model); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t bucket_ids_enqueue(const void* keys, uint64_t n, int key_bits, const vmps_cdf_model* model, uint32_t B,
+                              uint32_t* ids, hipStream_t s)
+{
+    const unsigned g = (unsigned)(ceil_div(n ? n : 1, 256) < 8192 ? ceil_div(n ? n : 1, 256) : 8192);
+    if (key_bits == 32) k_bucket_ids<uint32_t><<<g, 256, 0, s>>>((const uint32_t*)keys, n, model, B, ids);
+    else k_bucket_ids<uint64_t><<<g, 256, 0, s>>>((const uint64_t*)keys, n, model, B, ids);
+    return hipGetLastError();
+}
+
+hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
+                                 vmps_learned_stats* st, hipStream_t s)
+{
+    k_learned_stats<<<1, 256, 0, s>>>(off, B, T, model, st);
+    return hipGetLastError();
+}
+
+}  // namespace vmps

@@ -202,6 +202,24 @@ hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, con
                              const uint32_t* vb, uint32_t nb, void* out, uint32_t* vout,
                              int key_bits, uint32_t* splits, hipStream_t s);
 
+// Learned partition (learned.hip).
+uint64_t partition_arena_words(uint64_t n, uint32_t B);
+hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, uint32_t* vtmp, void* kout,
+                             uint32_t* vout, uint32_t n, int key_bits, int vmode, const vmps_cdf_model* model,
+                             uint32_t B, int64_t* bucket_off, uint32_t* arena, hipStream_t s);
+hipError_t sample_enqueue(const void* keys, uint64_t n, int key_bits, uint64_t m, uint64_t seed, void* out,
+                          hipStream_t s);
+hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmps_learned_config& c, float* u,
+                         vmps_cdf_model* model, hipStream_t s);
+hipError_t grad_enqueue(const float* params, int H, const float* u, const float* y, int nb, float* grad,
+                        float* loss, hipStream_t s);
+hipError_t compile_enqueue(const float* params, int H, uint64_t z_lo, uint64_t z_hi, int key_bits, int fbits,
+                           int K, vmps_cdf_model* model, hipStream_t s);
+hipError_t bucket_ids_enqueue(const void* keys, uint64_t n, int key_bits, const vmps_cdf_model* model,
+                              uint32_t B, uint32_t* ids, hipStream_t s);
+hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
+                                 vmps_learned_stats* st, hipStream_t s);
+
 }  // namespace vmps
 
 #define VMPS_HIP(x)                                  \

@@ -1,0 +1,245 @@
+"""GPU parity of the learned CDF partitioner against the oracle.
+
+Inputs to both sides come from `workloads` or from seeded parameters; the
+model tables given to the GPU partition are built by the oracle.  Integer
+results (sample, bucket ids, partition, final sort) are compared exactly;
+fp32 gradients and tables against the oracle's fp64 within tolerances
+derived from fp32 rounding.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def vm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2605_27147_amd as vm
+    vm.load_library()
+    return vm
+
+
+def _t(x):
+    import torch
+    if x.dtype == np.uint64:
+        return torch.from_numpy(x.view(np.int64).copy()).cuda()
+    if x.dtype == np.uint32:
+        return torch.from_numpy(x.view(np.int32).copy()).cuda()
+    return torch.from_numpy(x.copy()).cuda()
+
+
+def _np(t, dtype):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy().view(dtype)
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _params(rng, H):
+    return {"w1": rng.normal(1, 0.5, H), "b1": rng.normal(-0.5, 0.3, H), "w2": rng.normal(0, 1, H),
+            "b2": float(rng.normal())}
+
+
+def _flat32(p):
+    return np.concatenate([p["w1"], p["b1"], p["w2"], [p["b2"]]]).astype(np.float32)
+
+
+def _as64(p32, H):
+    p = p32.astype(np.float64)
+    return {"w1": p[:H], "b1": p[H:2 * H], "w2": p[2 * H:3 * H], "b2": float(p[3 * H])}
+
+
+def _host_model(vm, orc, params64, tab, key_bits, fbits):
+    m = vm.CdfModel()
+    m.z_lo, m.z_hi = tab.z_lo, tab.z_hi
+    m.key_bits, m.feature_bits, m.hidden = key_bits, fbits, len(params64["w1"])
+    m.knots, m.shift = tab.knots, tab.shift
+    for i, v in enumerate(tab.table.tolist()):
+        m.table[i] = v
+    return m
+
+
+def test_sample_positions(vm, orc):
+    for n, m, seed in ((1000, 5000, 1234567), (1 << 20, 1 << 16, 55), (17, 100, 0)):
+        x = workloads.uniform(n, 64, seed % 1000)
+        pos = orc.sample_positions(n, m, seed)
+        got = _np(vm.sample(_t(x), m, seed), np.uint64)
+        assert np.array_equal(got, x[pos])
+
+
+@pytest.mark.parametrize("H", [16, 32, 64])
+def test_gradient_matches_fp64(vm, orc, H):
+    import torch
+    rng = np.random.default_rng(H)
+    for trial in range(4):
+        p32 = _flat32(_params(rng, H))
+        nb = [64, 1024, 4096, 192][trial]
+        u = rng.random(nb).astype(np.float32)
+        y = rng.random(nb).astype(np.float32)
+        grad, loss = vm.cdf_grad(torch.from_numpy(p32).cuda(), H, torch.from_numpy(u).cuda(),
+                                 torch.from_numpy(y).cuda())
+        g = grad.cpu().numpy().astype(np.float64)
+        ref_loss, ref = orc.mlp_grad(_as64(p32, H), u.astype(np.float64), y.astype(np.float64))
+        want = np.concatenate([ref["w1"], ref["b1"], ref["w2"], [ref["b2"]]])
+        scale = np.abs(want).max()
+        _say("grad", H, nb, float(np.abs(g - want).max()), scale)
+        assert np.allclose(g, want, rtol=1e-3, atol=2e-5 * scale)
+        assert float(loss.item()) == pytest.approx(ref_loss, rel=1e-4)
+
+
+@pytest.mark.parametrize("H", [16, 32])
+def test_compile_matches_oracle(vm, orc, H):
+    import torch
+    rng = np.random.default_rng(100 + H)
+    for trial in range(4):
+        p32 = _flat32(_params(rng, H))
+        z_lo = int(rng.integers(0, 2**30))
+        rng_ = int(rng.choice([0, 1, 1000, 2**20 + 3, 2**27]))
+        K = int(rng.choice([1, 64, 4096]))
+        t = vm.cdf_compile(torch.from_numpy(p32).cuda(), H, z_lo, z_lo + rng_, 64, 20, K)
+        got = vm.model_from_tensor(t)
+        tab = orc.cdf_table(_as64(p32, H), z_lo, z_lo + rng_, K)
+        assert (got.shift, got.knots) == (tab.shift, tab.knots)
+        gt = np.array(got.table[: tab.knots + 1], dtype=np.float64)
+        assert np.all(np.diff(gt) >= 0)
+        # fp32 evaluation (and fp32 knot positions) against fp64: within 1e-5
+        # of the full Q32 scale
+        assert np.abs(gt - tab.table.astype(np.float64)).max() <= 2**32 * 1e-5
+
+
+def _models(vm, orc, keys_sorted, key_bits, fbits, rng):
+    """Oracle-built tables: trained fp64, random, identity, constant."""
+    u, z_lo, z_hi = orc.normalised_features(keys_sorted, key_bits, fbits)
+    out = []
+    p, _ = orc.cdf_train(u, 16, 16, 256, 1e-4)
+    out.append(("trained", p))
+    out.append(("random", _params(rng, 8)))
+    out.append(("identity", {"w1": np.array([1.0]), "b1": np.array([0.0]), "w2": np.array([1.0]), "b2": 0.0}))
+    out.append(("constant", {"w1": np.array([0.0]), "b1": np.array([0.0]), "w2": np.array([0.0]), "b2": 0.37}))
+    return [(name, orc.cdf_table(prm, z_lo, z_hi, 512), prm) for name, prm in out]
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_bucket_ids_and_partition_exact(vm, orc, bits):
+    rng = np.random.default_rng(bits)
+    fbits = 20
+    dt = np.uint32 if bits == 32 else np.uint64
+    for maker in ("lognormal", "uniform", "dup16"):
+        n = 50001 if maker != "dup16" else 30000
+        if maker == "lognormal":
+            x = (workloads.lognormal(n, 3) >> np.uint64(0 if bits == 64 else 32)).astype(dt)
+        elif maker == "uniform":
+            x = workloads.uniform(n, bits, 4)
+        else:
+            x = workloads.dup16(n, 5).astype(dt)
+        xs = np.sort(x[:: max(1, n // 4000)])
+        for name, tab, prm in _models(vm, orc, xs, bits, fbits, rng):
+            model_t = vm.model_to_tensor(_host_model(vm, orc, prm, tab, bits, fbits))
+            for B in (2, 16, 256, 1024, 65536):
+                _say("partition", bits, maker, name, B)
+                ids = _np(vm.bucket_ids(_t(x), model_t, B), np.uint32)
+                want_ids = np.array([orc.bucket_of(int(k), bits, fbits, tab, B) for k in x[:2000]])
+                assert np.array_equal(ids[:2000], want_ids)
+                v = np.arange(n, dtype=np.uint32)
+                ko, vo, off = vm.partition(_t(x), model_t, B, _t(v))
+                wk, wv, woff = orc.partition(x, bits, fbits, tab, B, vals=v)
+                assert np.array_equal(_np(off, np.int64), woff)
+                assert np.array_equal(_np(vo, np.uint32), wv)
+                assert np.array_equal(_np(ko, dt), wk.astype(dt))
+
+
+def test_partition_tiny_and_ragged(vm, orc):
+    rng = np.random.default_rng(9)
+    for n in (1, 2, 4095, 4096, 4097, 3 * 4096 + 11):
+        x = workloads.lognormal(n, n)
+        tab = orc.cdf_table(_params(rng, 4), 0, int(orc.feature(int(x.max()), 64, 20)) + 1, 64)
+        model_t = vm.model_to_tensor(_host_model(vm, orc, _params(rng, 4), tab, 64, 20))
+        ko, _, off = vm.partition(_t(x), model_t, 4096)
+        wk, _, woff = orc.partition(x, 64, 20, tab, 4096)
+        assert np.array_equal(_np(off, np.int64), woff) and np.array_equal(_np(ko, np.uint64), wk)
+
+
+def test_training_reaches_oracle_quality(vm, orc):
+    import torch
+    keys = np.sort(workloads.lognormal(1 << 16, 21))
+    cfg = vm.learned_default_config(1 << 16, vm.U64)
+    cfg.hidden, cfg.steps, cfg.batch, cfg.lr = 32, 64, 1024, 1e-4
+    model = vm.cdf_train(_t(keys), cfg)
+    u, z_lo, z_hi = orc.normalised_features(keys, 64, 20)
+    assert (model.z_lo, model.z_hi) == (z_lo, z_hi)
+    p_ref, loss_ref = orc.cdf_train(u, 32, 64, 1024, 1e-4)
+    init_ref = orc.cdf_loss(orc.cdf_init(u, 32), u)
+    _say("train", model.loss_init, model.loss_final, init_ref, loss_ref)
+    assert model.loss_final <= model.loss_init
+    assert model.loss_init == pytest.approx(init_ref, rel=0.05, abs=1e-8)
+    assert model.loss_final <= 1.5 * loss_ref + 1e-8
+    assert np.all(np.diff(np.array(model.table[: model.knots + 1], dtype=np.float64)) >= 0)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+@pytest.mark.parametrize("values", ["none", "input", "iota"])
+def test_sort_learned_matches_oracle(vm, orc, bits, values):
+    import torch
+    dt = np.uint32 if bits == 32 else np.uint64
+    inputs = [
+        ("lognormal", (workloads.lognormal(1 << 20, 31) >> np.uint64(32 if bits == 32 else 0)).astype(dt)),
+        ("uniform", workloads.uniform((1 << 19) + 777, bits, 32)),
+        ("presorted", workloads.presorted(1 << 19, 33, mean_run=800, bits=bits).astype(dt)),
+        ("dup16", workloads.dup16(1 << 19, 34).astype(dt)),
+        ("dup16x16", workloads.dup16(1 << 18, 35, every_16=True).astype(dt)),
+        ("equal", np.full(1 << 18, 5, dtype=dt)),
+    ]
+    if bits == 64:
+        inputs.append(("mixture", workloads.mixture(1 << 20, 36)))
+    for name, x in inputs:
+        n = x.size
+        _say("learned sort", bits, values, name, n)
+        v = np.random.default_rng(n).integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+        want, wantv, _, _ = orc.powersort(x, v if values == "input" else np.arange(n, dtype=np.uint32))
+        keys = _t(x)
+        if values == "none":
+            stats, _ = vm.sort_learned_(keys)
+        elif values == "input":
+            vals = _t(v)
+            stats, _ = vm.sort_learned_(keys, vals)
+            assert np.array_equal(_np(vals, np.uint32), wantv), name
+        else:
+            vals = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            stats, _ = vm.sort_learned_(keys, vals, iota=True)
+            assert np.array_equal(_np(vals, np.uint32), wantv), name
+        _say("  stats", stats)
+        assert np.array_equal(_np(keys, dt), want.astype(dt)), name
+
+
+def test_trained_model_beats_untrained(vm, orc):
+    """What training buys: with the trained model the buckets are far more
+    even than with the untrained identity model f(u) = u, so far fewer keys
+    land in buckets that need the merge levels."""
+    import torch
+    n = 1 << 22
+    x = workloads.lognormal(n, 41)
+    keys = _t(x)
+    stats, model = vm.sort_learned_(keys, want_model=True)
+    assert np.array_equal(_np(keys, np.uint64), np.sort(x))
+    # f(u) = u with H = 16: w1 = 1, b1 = 0, w2 = (1, 0, ..., 0), b2 = 0
+    ident = [1.0] * 16 + [0.0] * 16 + [1.0] + [0.0] * 15 + [0.0]
+    id_t = vm.cdf_compile(torch.tensor(ident, dtype=torch.float32, device="cuda"), 16, model.z_lo, model.z_hi,
+                          64, 20, 4096)
+    B = stats["buckets"]
+    _, _, off_id = vm.partition(_t(x), id_t, B)
+    sizes = np.diff(_np(off_id, np.int64))
+    T = 8192
+    id_fallback = int(sizes[sizes > T].sum())
+    _say("trained", stats, "identity fallback keys", id_fallback, "identity max", int(sizes.max()))
+    assert stats["fallback_keys"] < id_fallback
+    assert stats["max_bucket"] < int(sizes.max())

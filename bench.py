@@ -1,14 +1,20 @@
-"""Throughput of the stable Powersort path on one MI355X.
+"""Throughput of stable Powersort on one MI355X: learned partition vs plain.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--path plain] [--log2n 28]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--path learned|plain] [--log2n 28]
 
-A step is one full sort of n = 2^28 uint64 keys drawn from the lognormal
-workload (sigma = 2, scaled by 2^40; seeded, synthetic) resident in HBM.
-The input is restored from a pristine device copy before every step; the
-restore is outside the timed events.  Output: one JSON line with the
-throughput (Gkeys/s), the roofline of the dominant kernel (its average
-launch time measured with HIP events on the sort's stream), and the CPU
-oracle timed on a bounded sample of the same workload.
+A step is one full stable sort of n = 2^28 uint64 keys drawn from the
+lognormal workload (floor(exp(2 N(0,1)) 2^40), seeded, synthetic) resident
+in HBM.  The default path is the learned one: sample, sort the sample with
+the plain path, train the CDF model, compile, stable two-level scatter,
+Powersort of every bucket (the segmented path).  The plain path (run
+detection, powers, merge tree, LDS subtrees, merge levels) is timed in the
+same run for comparison.  The input is restored from a pristine device copy
+before every step, outside the timed events.
+
+The JSON line carries the throughput (Gkeys/s), the roofline of the
+dominant kernel (its average launch time measured with HIP events on the
+sort's stream, bytes = what the method must move in that kernel), and the
+CPU oracle timed on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -35,32 +41,61 @@ def is_sorted_u64(t):
     return bool((s[1:] >= s[:-1]).all().item())
 
 
-def algorithmic_bytes(kind: str, n: int, key_bytes: int, val_bytes: int, m_hbm: int) -> float:
-    """Bytes the method must move per sort for one kernel kind (reads +
-    writes, each element once per pass; cache re-reads not counted)."""
-    kv = key_bytes + val_bytes
+def kernel_bytes(path: str, kind: str, n: int, kb: int, vb: int, m_hbm: int, sample: int) -> float:
+    """Algorithmic bytes per sort of one kernel kind: every pass reads and
+    writes each element once; cache re-reads are not counted."""
+    kv = kb + vb
     if kind == "level_merge":
-        return 2.0 * kv * m_hbm          # every merge longer than the tile: read + write
+        return 2.0 * kv * m_hbm                 # merges longer than the LDS tile
     if kind == "tilesort":
-        return float(key_bytes * n + kv * n)  # read keys, write keys (+ generated values)
+        return float(kb * n + kv * n)           # read keys, write keys (+ values)
+    if kind == "histogram":
+        return 2.0 * kb * n                     # two partition levels, keys read once each
+    if kind == "scatter":
+        return 2.0 * 2 * kv * n                 # two levels, read + write
     if kind == "plan":
-        return float(key_bytes * n)      # descent scan reads the keys once
+        return float(kb * n) if path == "plain" else 0.0
+    if kind == "sample":
+        return float(kb * sample)
     return 0.0
 
 
-def cpu_baseline(keys_np, sample_log2: int):
+def run_path(vm, path, keys, pristine, steps, warmup):
     import numpy as np
+    import torch
 
-    import oracle
-    oracle.build()
-    m = min(keys_np.size, 1 << sample_log2)
-    sample = np.ascontiguousarray(keys_np[:m])
-    t0 = time.perf_counter()
-    oracle.powersort(sample)
-    dt = time.perf_counter() - t0
-    return {"value": round(m / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first 2^{sample_log2} keys of the same lognormal input, one single-threaded "
-                      f"oracle Powersort (Pingpong) in {dt:.2f} s"}
+    stream = torch.cuda.current_stream()
+
+    def step():
+        if path == "learned":
+            vm.sort_learned_(keys, workspace=WS[0], read_stats=False)
+        else:
+            vm.sort_(keys, workspace=WS[0])
+
+    for _ in range(warmup):
+        keys.copy_(pristine)
+        step()
+    torch.cuda.synchronize()
+    vm.trace_collect()
+    vm.trace_enable(True)
+    ev = []
+    for _ in range(steps):
+        keys.copy_(pristine)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        step()
+        e1.record(stream)
+        ev.append((e0, e1))
+    torch.cuda.synchronize()
+    vm.trace_enable(False)
+    trace = vm.trace_collect()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    assert is_sorted_u64(keys), f"{path}: output not sorted"
+    return float(np.mean(ms)), trace
+
+
+WS = [None]
 
 
 def main():
@@ -68,14 +103,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--path", default="plain", choices=["plain"])
+    ap.add_argument("--path", default="learned", choices=["learned", "plain"])
     ap.add_argument("--log2n", type=int, default=28)
+    ap.add_argument("--compare-steps", type=int, default=3, help="steps of the other path (0: skip)")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is described in DESIGN.md but not run", file=sys.stderr)
+              "how the sort would shard over GPUs is described in DESIGN.md, not run", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -92,69 +128,76 @@ def main():
     pristine = torch.from_numpy(keys_np.view(np.int64)).to(dev)
     keys = torch.empty_like(pristine)
     checksum = int(pristine.sum().item())
-    ws = torch.empty(vm.sort_workspace_size(n, vm.U64, False), dtype=torch.uint8, device=dev)
-    stream = torch.cuda.current_stream(dev)
+    cfg = vm.learned_default_config(n, vm.U64)
+    ws_bytes = max(vm.sort_workspace_size(n, vm.U64, False), vm.learned_workspace_size(n, vm.U64, False, cfg))
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    WS[0] = ws
 
-    def step():
-        vm.sort_(keys, workspace=ws)
-
-    log("warmup")
-    for _ in range(args.warmup):
-        keys.copy_(pristine)
-        step()
-    torch.cuda.synchronize()
     sch = vm.sort_schedule(pristine)
-    node_len = sch["node_r"].astype(np.int64) - sch["node_l"].astype(np.int64)
-    m_hbm = int(node_len.sum())
+    m_hbm_plain = int((sch["node_r"].astype(np.int64) - sch["node_l"].astype(np.int64)).sum())
 
-    log("timed steps")
-    times = []
-    vm.trace_collect()
-    vm.trace_enable(True)
-    torch.cuda.synchronize()
-    for _ in range(args.steps):
-        keys.copy_(pristine)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        step()
-        e1.record(stream)
-        times.append((e0, e1))
-    torch.cuda.synchronize()
-    vm.trace_enable(False)
-    trace = vm.trace_collect()
-    ms = [a.elapsed_time(b) for a, b in times]
-    ms_per_step = float(np.mean(ms))
-    assert is_sorted_u64(keys), "output not sorted"
+    log(f"{args.path}: warmup {args.warmup}, timed {args.steps}")
+    ms, trace = run_path(vm, args.path, keys, pristine, args.steps, args.warmup)
     assert int(keys.sum().item()) == checksum, "output is not a permutation of the input"
+    stats = None
+    if args.path == "learned":
+        keys.copy_(pristine)
+        stats, _ = vm.sort_learned_(keys, workspace=ws)
+    other = "plain" if args.path == "learned" else "learned"
+    other_ms = None
+    if args.compare_steps > 0:
+        log(f"{other}: timed {args.compare_steps}")
+        other_ms, _ = run_path(vm, other, keys, pristine, args.compare_steps, 1)
 
-    value = n / (ms_per_step / 1e3) / 1e9
+    value = n / (ms / 1e3) / 1e9
     kinds = {k: v for k, v in trace.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
     dom_ms, dom_launches = kinds[dom]
-    bytes_per_sort = algorithmic_bytes(dom, n, 8, 0, m_hbm)
+    m_hbm = m_hbm_plain if args.path == "plain" else 0
+    bytes_per_sort = kernel_bytes(args.path, dom, n, 8, 0, m_hbm, cfg.sample_size)
     achieved = bytes_per_sort * args.steps / (dom_ms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
-                "avg_launch_ms": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches / args.steps}
+                "avg_launch_ms": round(dom_ms / dom_launches, 4),
+                "launches_per_step": dom_launches / args.steps,
+                "bytes_per_launch": bytes_per_sort * args.steps / dom_launches}
     breakdown = {k: {"ms_per_step": round(v[0] / args.steps, 4), "launches_per_step": v[1] / args.steps}
                  for k, v in kinds.items()}
+    path_bytes = sum(kernel_bytes(args.path, k, n, 8, 0, m_hbm, cfg.sample_size) for k in kinds)
 
+    cfgd = {"workload": f"lognormal64: n=2^{args.log2n} uint64 keys floor(exp(2 N(0,1)) 2^40), stable sort, "
+                        f"{args.path} Powersort path", "n": n, "key_bits": 64, "values": False, "path": args.path,
+            "lds_tile": sch["tile"]}
+    if args.path == "learned":
+        cfgd.update({"buckets": stats["buckets"], "sample": int(cfg.sample_size), "hidden": cfg.hidden,
+                     "adam_steps": cfg.steps, "fallback_keys": stats["fallback_keys"],
+                     "fallback_buckets": stats["fallback_buckets"], "max_bucket": stats["max_bucket"],
+                     "model_loss_init": stats["loss_init"], "model_loss_final": stats["loss_final"]})
+    else:
+        cfgd.update({"merge_cost": sch["merge_cost"], "merge_cost_hbm": m_hbm_plain, "runs": sch["runs"]})
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"lognormal64: n=2^{args.log2n} uint64 keys floor(exp(2 N(0,1)) 2^40), "
-                               f"stable sort, {args.path} Powersort path",
-                   "n": n, "key_bits": 64, "values": False, "path": args.path,
-                   "merge_cost": sch["merge_cost"], "merge_cost_hbm": m_hbm, "runs": sch["runs"],
-                   "lds_tile": sch["tile"]},
-        "roofline": roofline,
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": cfgd, "roofline": roofline,
+        "path_roofline": {"bytes_per_step": path_bytes, "achieved_GBs": round(path_bytes / (ms / 1e3) / 1e9, 1),
+                          "frac": round(path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "breakdown": breakdown,
     }
+    if other_ms is not None:
+        out["compare"] = {"path": other, "ms_per_step": round(other_ms, 4),
+                          "value": round(n / (other_ms / 1e3) / 1e9, 4), "unit": "Gkeys/s"}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(keys_np, args.cpu_sample_log2)
+        import oracle
+        oracle.build()
+        msz = min(n, 1 << args.cpu_sample_log2)
+        sample = np.ascontiguousarray(keys_np[:msz])
+        t0 = time.perf_counter()
+        oracle.powersort(sample)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(msz / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
+                               "sample": f"first 2^{args.cpu_sample_log2} keys of the same lognormal input, "
+                                         f"single-threaded oracle Powersort (Pingpong) in {dt:.2f} s"}
     print(json.dumps(out), flush=True)
 
 

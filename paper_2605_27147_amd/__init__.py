@@ -326,9 +326,10 @@ def model_from_tensor(t) -> CdfModel:
 
 
 def sort_learned_(keys, values=None, *, iota: bool = False, cfg: LearnedConfig | None = None, workspace=None,
-                  want_model: bool = False):
+                  want_model: bool = False, read_stats: bool = True):
     """Stable in-place sort through the learned partition.  Returns
-    (stats dict, model struct or None); synchronises to read them."""
+    (stats dict, model struct or None), synchronising to read them; with
+    read_stats=False it only enqueues the sort and returns (None, None)."""
     torch = _torch()
     lib = load_library()
     _require_cuda(keys, values)
@@ -340,11 +341,14 @@ def sort_learned_(keys, values=None, *, iota: bool = False, cfg: LearnedConfig |
     _check(lib.vmps_learned_workspace_size(n, kt, int(values is not None), ctypes.byref(cfg), ctypes.byref(need)),
            "vmps_learned_workspace_size")
     ws = workspace if workspace is not None else _workspace(need.value, keys.device)
+    want_model = want_model and read_stats
     model_t = torch.zeros(ctypes.sizeof(CdfModel), dtype=torch.uint8, device=keys.device) if want_model else None
-    stats_t = torch.zeros(ctypes.sizeof(LearnedStats), dtype=torch.uint8, device=keys.device)
+    stats_t = torch.zeros(ctypes.sizeof(LearnedStats), dtype=torch.uint8, device=keys.device) if read_stats else None
     _check(lib.vmps_sort_learned(_ptr(keys), _ptr(values), n, kt, VALUES_IOTA if iota else 0, ctypes.byref(cfg),
                                  _ptr(model_t), _ptr(stats_t), _ptr(ws), ws.numel(), _stream(keys.device)),
            "vmps_sort_learned")
+    if not read_stats:
+        return None, None
     st = _struct_from_tensor(stats_t, LearnedStats)
     stats = {name: getattr(st, name) for name, _ in LearnedStats._fields_}
     return stats, (model_from_tensor(model_t) if want_model else None)

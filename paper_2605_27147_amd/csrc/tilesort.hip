@@ -1,63 +1,115 @@
 // LDS Powersort of one segment per workgroup.
 //
 // A segment is either a whole small Powersort instance or a subtree of a
-// large instance's merge tree that fits the tile (the planner guarantees the
-// segment starts and ends on run boundaries).  Inside LDS the workgroup
-// repeats the method on the segment:
+// large instance's merge tree that fits the tile (the planner guarantees it
+// starts and ends on run boundaries).  Inside LDS the workgroup repeats the
+// method on the segment:
 //   ExtractRun with the minrun extension (Sections 2, 3 and 5): descent
 //     bitmap by ballot, long natural runs, the chain of run starts;
 //   Power of every boundary (theorem of Section 2) from the 32-bit midpoint
-//     expansions, with positions taken in the instance's coordinates so the
-//     powers equal those of the whole instance;
-//   forced runs sorted stably (rank of (key, position) inside the run,
-//     which yields exactly the straight insertion sort's result);
-//   merges of Algorithm 1 by decreasing power, each level split over the
-//     threads by merge path, StandardMerge semantics (Algorithm 2): on ties
-//     the left run goes first.
-// The result is written once, to the buffer the planner chose (Pingpong).
+//     expansions, with positions in the instance's coordinates so the powers
+//     equal those of the whole instance;
+//   forced runs sorted stably: bottom-up merges of aligned blocks inside the
+//     run, which gives exactly the insertion sort's result;
+//   merges of Algorithm 1 by decreasing power (StandardMerge: on ties the
+//     left run goes first).
+// Every merge pass is split over the threads by merge path: thread i owns
+// outputs [i*KI, (i+1)*KI), computes them into registers, and writes them
+// back into the single LDS buffer after a barrier.  The segment is written
+// once, to the buffer the planner chose (Pingpong).
 #include "vmps_internal.hpp"
 
 namespace vmps {
 
-template <typename K>
-__device__ inline K bcast_lane(K x, int j);
-
-template <>
-__device__ inline uint32_t bcast_lane<uint32_t>(uint32_t x, int j)
-{
-    return (uint32_t)__builtin_amdgcn_readlane((int)x, j);
-}
-
-template <>
-__device__ inline uint64_t bcast_lane<uint64_t>(uint64_t x, int j)
-{
-    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)x, j);
-    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(x >> 32), j);
-    return ((uint64_t)hi << 32) | lo;
-}
+// One spare LDS slot after every 32 elements: threads write KI = 16
+// consecutive outputs, and the padding spreads simultaneous writes of a wave
+// over distinct banks.
+__device__ __forceinline__ uint32_t px(uint32_t i) { return i + (i >> 5); }
 
 template <int TCAP>
 struct TileMeta {
-    static constexpr uint32_t RC = TCAP / 32 + 3;  // runs (each >= 32 long but the last)
+    static constexpr uint32_t RC = TCAP / 32 + 3;  // runs: each >= 32 long except the last
     static constexpr uint32_t BW = TCAP / 64 + 2;  // bitmap words
+    static constexpr uint32_t SP = TCAP + TCAP / 32 + 1;  // padded element slots
 };
 
 template <typename K, int NT, int TCAP, int VMODE>
 constexpr size_t tile_lds_bytes()
 {
     using M = TileMeta<TCAP>;
-    size_t b = 2 * sizeof(K) * TCAP;
-    if (VMODE) b += 2 * sizeof(uint32_t) * TCAP;
-    b += 8 * M::BW;                    // bitmap
-    b += 4 * (2 * M::RC);              // long runs (u, e)
-    b += 4 * (2 * (M::RC + 1));        // progressions (base, prefix)
-    b += 4 * (M::RC + 1);              // run starts
-    b += 4 * M::RC;                    // Q
-    b += 4 * (2 * M::RC);              // node L, R per boundary
-    b += 4 * M::RC;                    // node list of a level
-    b += M::RC;                        // powers
-    b += 4 * (NT / 64 + 1) + 64;       // scan scratch + scalars
+    size_t b = sizeof(K) * M::SP;
+    if (VMODE) b += 4 * M::SP;
+    b += 8 * M::BW;                   // bitmap
+    b += 4 * 2 * M::RC;               // long runs (u, e), later Q and the node list
+    b += 4 * 2 * (M::RC + 1);         // progressions (base, prefix), later node L, R
+    b += 4 * (M::RC + 1);             // run starts
+    b += 2 * M::RC;                   // powers, sorted-run flags
+    b += 4 * 2 * 34;                  // level start / count
+    b += 4 * (NT / 64) * 33;          // per-wave power counts
+    b += 4 * (NT / 64 + 1) + 64;      // scan scratch + scalars
     return (b + 15) & ~(size_t)15;
+}
+
+// One merge pass.  find(q, L, M, R) describes the node holding output q:
+// returns true when [L,M) and [M,R) are merged in this pass (R > q), else
+// false with R the first position after q where a node may start.  The
+// thread's outputs are produced node by node (outer dynamic loop); inside a
+// node a static, predicated loop keeps the register staging array indexed
+// by constants.
+template <typename K, int KI, int VMODE, typename Find>
+__device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, Find find)
+{
+    const uint32_t p0 = threadIdx.x * KI;
+    K rk[KI];
+    uint32_t rv[KI];
+    uint32_t done = 0;
+    const uint32_t pend = p0 + KI < len ? p0 + KI : len;
+    uint32_t q = p0;
+    while (q < pend) {
+        uint32_t L, M, R;
+        const bool mg = find(q, L, M, R);
+        const uint32_t stop = R < pend ? R : pend;
+        if (mg) {
+            const uint32_t na = M - L, nb = R - M, d = q - L;
+            uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (S[px(L + mid)] <= S[px(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
+            }
+            uint32_t ia = L + lo, jb = M + (d - lo);
+            K ha = ia < M ? S[px(ia)] : K(0);
+            K hb = jb < R ? S[px(jb)] : K(0);
+            const uint32_t j0 = q - p0, j1 = stop - p0;
+#pragma unroll
+            for (int j = 0; j < KI; ++j) {
+                if ((uint32_t)j >= j0 && (uint32_t)j < j1) {
+                    const bool takeA = ia < M && (jb >= R || ha <= hb);
+                    if (takeA) {
+                        rk[j] = ha;
+                        if (VMODE) rv[j] = SV[px(ia)];
+                        ++ia;
+                        if (ia < M) ha = S[px(ia)];
+                    } else {
+                        rk[j] = hb;
+                        if (VMODE) rv[j] = SV[px(jb)];
+                        ++jb;
+                        if (jb < R) hb = S[px(jb)];
+                    }
+                }
+            }
+            done |= ((j1 - j0 >= 32) ? ~0u : ((1u << (j1 - j0)) - 1u)) << j0;
+        }
+        q = stop;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KI; ++j) {
+        if ((done >> j) & 1u) {
+            S[px(p0 + j)] = rk[j];
+            if (VMODE) SV[px(p0 + j)] = rv[j];
+        }
+    }
+    __syncthreads();
 }
 
 template <typename K, int NT, int TCAP, int VMODE>
@@ -65,34 +117,41 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
                                                  uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                  const Seg* __restrict__ segs,
                                                  const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
-                                                 const uint32_t* __restrict__ inst_start, uint32_t ell_ovr)
+                                                 const uint32_t* __restrict__ inst_start)
 {
-    using M = TileMeta<TCAP>;
+    using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
-    constexpr uint32_t KI = TCAP / NT;
-    static_assert(TCAP % NT == 0, "tile must split evenly");
+    constexpr int KI = TCAP / NT;
+    constexpr uint32_t RC = MT::RC;
+    static_assert(TCAP % NT == 0 && KI <= 32, "tile must split evenly, at most 32 outputs per thread");
     static_assert(TCAP / 64 + 1 <= NT, "one thread per bitmap word");
+    static_assert(RC <= 64 * NW, "one thread per boundary in the power ranking");
 
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* sp = smem;
-    K* KA = (K*)sp; sp += sizeof(K) * TCAP;
-    K* KB = (K*)sp; sp += sizeof(K) * TCAP;
-    uint32_t* VA = nullptr;
-    uint32_t* VB = nullptr;
-    if (VMODE) { VA = (uint32_t*)sp; sp += 4 * TCAP; VB = (uint32_t*)sp; sp += 4 * TCAP; }
-    uint64_t* bm = (uint64_t*)sp; sp += 8 * M::BW;
-    uint32_t* LRu = (uint32_t*)sp; sp += 4 * M::RC;
-    uint32_t* LRe = (uint32_t*)sp; sp += 4 * M::RC;
-    uint32_t* PGb = (uint32_t*)sp; sp += 4 * (M::RC + 1);
-    uint32_t* PGc = (uint32_t*)sp; sp += 4 * (M::RC + 1);
-    uint32_t* RS = (uint32_t*)sp; sp += 4 * (M::RC + 1);
-    uint32_t* Qv = (uint32_t*)sp; sp += 4 * M::RC;
-    uint32_t* BL = (uint32_t*)sp; sp += 4 * M::RC;
-    uint32_t* BR = (uint32_t*)sp; sp += 4 * M::RC;
-    uint32_t* NLi = (uint32_t*)sp; sp += 4 * M::RC;
+    K* S = (K*)sp; sp += sizeof(K) * MT::SP;
+    uint32_t* SV = nullptr;
+    if (VMODE) { SV = (uint32_t*)sp; sp += 4 * MT::SP; }
+    uint64_t* bm = (uint64_t*)sp; sp += 8 * MT::BW;
+    uint32_t* R1 = (uint32_t*)sp; sp += 4 * 2 * RC;
+    uint32_t* R2 = (uint32_t*)sp; sp += 4 * 2 * (RC + 1);
+    uint32_t* RS = (uint32_t*)sp; sp += 4 * (RC + 1);
+    uint32_t* LVs = (uint32_t*)sp; sp += 4 * 34;
+    uint32_t* LVc = (uint32_t*)sp; sp += 4 * 34;
+    uint32_t* wcnt = (uint32_t*)sp; sp += 4 * NW * 33;
     uint32_t* scan_lds = (uint32_t*)sp; sp += 4 * (NW + 1);
-    uint32_t* scal = (uint32_t*)sp; sp += 4 * 8;  // [0] progressions [1] runs [2] power mask [3] nodes
-    uint8_t* PW = sp;
+    uint32_t* scal = (uint32_t*)sp; sp += 4 * 16;  // [0] progressions [1] runs [2] power mask [3] max unsorted run
+    uint8_t* PW = sp; sp += RC;
+    uint8_t* SR = sp;
+    // aliases: long runs -> (Q, node list); progressions -> (node L, node R)
+    uint32_t* LRu = R1;
+    uint32_t* LRe = R1 + RC;
+    uint32_t* Qv = R1;
+    uint32_t* NL = R1 + RC;
+    uint32_t* PGb = R2;
+    uint32_t* PGc = R2 + RC + 1;
+    uint32_t* BL = R2;
+    uint32_t* BR = R2 + RC + 1;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nseg = nseg_dev ? *nseg_dev : nseg_host;
@@ -117,22 +176,23 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
         }
         const uint32_t ib = inst_start[sg.inst];
         const uint32_t il = inst_start[sg.inst + 1] - ib;
-        const uint32_t ell = ell_ovr ? ell_ovr : minrun_of(il);
+        const uint32_t ell = minrun_of(il);
         const uint32_t g = a - ib;
 
         // 1. load
         for (uint32_t i = tid; i < len; i += NT) {
-            KA[i] = keysA[a + i];
-            if (VMODE == 1) VA[i] = valsA[a + i];
-            if (VMODE == 2) VA[i] = a + i;
+            S[px(i)] = keysA[a + i];
+            if (VMODE == 1) SV[px(i)] = valsA[a + i];
+            if (VMODE == 2) SV[px(i)] = a + i;
         }
+        if (tid < 16) scal[tid] = 0;
         __syncthreads();
 
         // 2. descent bitmap (positions >= len count as boundaries)
         const uint32_t W = len / 64 + 1;
         for (uint32_t w = wave; w < W; w += NW) {
             const uint32_t p = w * 64 + lane;
-            const bool bit = (p >= len) || (p == 0) || (KA[p - 1] > KA[p]);
+            const bool bit = (p >= len) || (p == 0) || (S[px(p - 1)] > S[px(p)]);
             const uint64_t word = __ballot(bit);
             if (lane == 0) bm[w] = word;
         }
@@ -191,8 +251,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
             ++np;
             PGc[np] = acc;
             scal[0] = np;
-            scal[1] = acc < M::RC - 1 ? acc : M::RC - 1;  // runs >= 32 long: never clamps
-            scal[2] = 0;
+            scal[1] = acc < RC - 1 ? acc : RC - 1;  // runs >= 32 long: never clamps
         }
         __syncthreads();
         const uint32_t np = scal[0], kr = scal[1];
@@ -209,9 +268,22 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
         if (tid == 0) RS[kr] = len;
         __syncthreads();
 
-        // 6. midpoint expansions and powers
+        // 6. sorted-run flags, midpoint expansions and powers
         for (uint32_t t = tid; t < kr; t += NT) {
-            const uint64_t s2 = 2ull * g + RS[t] + RS[t + 1];
+            const uint32_t s = RS[t], e = RS[t + 1];
+            bool sorted = true;  // no descent strictly inside (s, e)
+            if (s + 1 < e) {
+                for (uint32_t w = (s + 1) >> 6; w <= ((e - 1) >> 6); ++w) {
+                    uint64_t word = bm[w];
+                    const uint32_t base = w * 64;
+                    if (s + 1 > base) word &= ~0ull << (s + 1 - base);
+                    if (e - base < 64) word &= (1ull << (e - base)) - 1;
+                    if (word) { sorted = false; break; }
+                }
+            }
+            SR[t] = sorted ? 1 : 0;
+            if (!sorted) atomicMax(&scal[3], e - s);
+            const uint64_t s2 = 2ull * g + s + e;
             Qv[t] = (uint32_t)((s2 << 31) / il);
         }
         __syncthreads();
@@ -239,121 +311,103 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
             }
             BR[t] = (lo2 == (int)kr - 1) ? len : RS[lo2 + 1];
         }
-
-        // 7. forced runs: stable rank sort inside each run (one wave per run)
-        K* cur = KA;
-        K* oth = KB;
-        uint32_t* vcur = VA;
-        uint32_t* voth = VB;
-        for (uint32_t t = wave; t < kr; t += NW) {
-            const uint32_t s = RS[t], rl = RS[t + 1] - RS[t];
-            bool sorted = true;
-            K x = 0;
-            uint32_t v = 0;
-            if (rl <= 64) {
-                if ((uint32_t)lane < rl) {
-                    x = cur[s + lane];
-                    if (VMODE) v = vcur[s + lane];
-                }
-                const bool desc = lane > 0 && (uint32_t)lane < rl && cur[s + lane - 1] > x;
-                sorted = __ballot(desc) == 0;
+        // node list: boundaries ordered by (power descending, position), one
+        // thread per boundary, ranks from wave ballots on the power value
+        {
+            const uint32_t t = tid;
+            const bool valid = t + 1 < kr;
+            const uint32_t p = valid ? PW[t] : 0u;
+            uint64_t peers = __ballot(valid);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                const bool bit = (p >> k) & 1u;
+                const uint64_t bk = __ballot(bit);
+                peers &= bit ? bk : ~bk;
             }
-            if (sorted) {
-                for (uint32_t i = lane; i < rl; i += 64) {
-                    oth[s + i] = cur[s + i];
-                    if (VMODE) voth[s + i] = vcur[s + i];
-                }
-            } else {
-                uint32_t rank = 0;
-                for (uint32_t j = 0; j < rl; ++j) {
-                    const K y = bcast_lane<K>(x, (int)j);
-                    rank += (y < x || (y == x && j < (uint32_t)lane)) ? 1u : 0u;
-                }
-                if ((uint32_t)lane < rl) {
-                    oth[s + rank] = x;
-                    if (VMODE) voth[s + rank] = v;
-                }
+            const uint32_t rw = __popcll(peers & ((1ull << lane) - 1));
+            if (lane < 33) wcnt[wave * 33 + lane] = 0;
+            __syncthreads();
+            if (valid && rw == 0) wcnt[wave * 33 + p] = __popcll(peers);
+            __syncthreads();
+            if (tid <= 32) {
+                uint32_t tot = 0;
+                for (int w = 0; w < NW; ++w) tot += wcnt[w * 33 + tid];
+                LVc[tid] = tot;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t acc = 0;
+                for (int q = 32; q >= 1; --q) { LVs[q] = acc; acc += LVc[q]; }
+            }
+            __syncthreads();
+            if (valid) {
+                uint32_t r = LVs[p] + rw;
+                for (int w = 0; w < wave; ++w) r += wcnt[w * 33 + p];
+                NL[r] = t;
             }
         }
         __syncthreads();
-        { K* tk = cur; cur = oth; oth = tk; uint32_t* tv = vcur; vcur = voth; voth = tv; }
 
-        // 8. merges by decreasing power
+        // 7. forced runs: bottom-up merges of aligned blocks inside each run
+        const uint32_t maxf = scal[3];
+        uint32_t myrun = 0;  // run holding this thread's first output
+        {
+            const uint32_t q0 = tid * KI;
+            uint32_t lo = 0, hi = kr;
+            while (hi - lo > 1) {
+                const uint32_t m = (lo + hi) >> 1;
+                if (RS[m] <= q0) lo = m; else hi = m;
+            }
+            myrun = lo;
+        }
+        for (uint32_t wlog = 0; (1u << wlog) < maxf; ++wlog) {
+            const uint32_t w = 1u << wlog;
+            uint32_t rt = myrun;
+            merge_pass<K, KI, VMODE>(S, SV, len, [&](uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R) -> bool {
+                while (rt + 1 < kr && RS[rt + 1] <= q) ++rt;  // outputs only move right
+                const uint32_t lo = rt;
+                const uint32_t s = RS[lo], e = RS[lo + 1];
+                if (SR[lo] || e - s <= w) { R = e; return false; }
+                const uint32_t ps = s + (((q - s) >> (wlog + 1)) << (wlog + 1));
+                L = ps;
+                M = min(ps + w, e);
+                R = min(ps + 2 * w, e);
+                return M < R;
+            });
+        }
+
+        // 8. merges of Algorithm 1 by decreasing power
         uint32_t mask = scal[2];
         while (mask) {
             const uint32_t p = 32 - __clz(mask);
             mask &= ~(1u << (p - 1));
-            if (wave == 0) {
-                uint32_t base = 0;
-                for (uint32_t c0 = 0; c0 + 1 < kr; c0 += 64) {
-                    const uint32_t t = c0 + lane;
-                    const bool f = (t + 1 < kr) && PW[t] == p;
-                    const uint64_t bal = __ballot(f);
-                    if (f) NLi[base + __popcll(bal & ((1ull << lane) - 1))] = t;
-                    base += __popcll(bal);
+            const uint32_t b0 = LVs[p], cn = LVc[p];
+            merge_pass<K, KI, VMODE>(S, SV, len, [&](uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R) -> bool {
+                int lo = -1, hi = (int)cn;  // last node starting at or before q
+                while (hi - lo > 1) {
+                    const int m = (lo + hi) >> 1;
+                    if (BL[NL[b0 + m]] <= q) lo = m; else hi = m;
                 }
-                if (lane == 0) scal[3] = base;
-            }
-            __syncthreads();
-            const int nn = (int)scal[3];
-            uint32_t pos = tid * KI;
-            const uint32_t end = min(len, pos + KI);
-            if (pos < end) {
-                int ni = -1;
-                {
-                    int lo = -1, hi = nn;
-                    while (hi - lo > 1) {
-                        const int m = (lo + hi) >> 1;
-                        if (BL[NLi[m]] <= pos) lo = m; else hi = m;
-                    }
-                    ni = lo;
-                }
-                while (pos < end) {
-                    while (ni + 1 < nn && BL[NLi[ni + 1]] <= pos) ++ni;
-                    const bool inside = ni >= 0 && pos < BR[NLi[ni]];
-                    if (inside) {
-                        const uint32_t t = NLi[ni];
-                        const uint32_t L = BL[t], Mid = RS[t + 1], R = BR[t];
-                        const uint32_t stop = min(end, R);
-                        const uint32_t na = Mid - L, nb = R - Mid, d = pos - L;
-                        uint32_t lo = d > nb ? d - nb : 0u, hi = min(d, na);
-                        while (lo < hi) {
-                            const uint32_t mid = (lo + hi) >> 1;
-                            if (cur[L + mid] <= cur[Mid + d - 1 - mid]) lo = mid + 1; else hi = mid;
-                        }
-                        uint32_t ia = L + lo, jb = Mid + (d - lo);
-                        for (; pos < stop; ++pos) {
-                            const bool takeA = ia < Mid && (jb >= R || cur[ia] <= cur[jb]);
-                            if (takeA) {
-                                oth[pos] = cur[ia];
-                                if (VMODE) voth[pos] = vcur[ia];
-                                ++ia;
-                            } else {
-                                oth[pos] = cur[jb];
-                                if (VMODE) voth[pos] = vcur[jb];
-                                ++jb;
-                            }
-                        }
-                    } else {
-                        const uint32_t nextL = (ni + 1 < nn) ? BL[NLi[ni + 1]] : len;
-                        const uint32_t stop = min(end, nextL);
-                        for (; pos < stop; ++pos) {
-                            oth[pos] = cur[pos];
-                            if (VMODE) voth[pos] = vcur[pos];
-                        }
+                if (lo >= 0) {
+                    const uint32_t t = NL[b0 + lo];
+                    if (q < BR[t]) {
+                        L = BL[t];
+                        M = RS[t + 1];
+                        R = BR[t];
+                        return true;
                     }
                 }
-            }
-            __syncthreads();
-            { K* tk = cur; cur = oth; oth = tk; uint32_t* tv = vcur; vcur = voth; voth = tv; }
+                R = (lo + 1 < (int)cn) ? BL[NL[b0 + lo + 1]] : len;
+                return false;
+            });
         }
 
         // 9. one write to the planned buffer
         K* outK = sg.dst ? keysB : keysA;
         uint32_t* outV = sg.dst ? valsB : valsA;
         for (uint32_t i = tid; i < len; i += NT) {
-            outK[a + i] = cur[i];
-            if (VMODE) outV[a + i] = vcur[i];
+            outK[a + i] = S[px(i)];
+            if (VMODE) outV[a + i] = SV[px(i)];
         }
         __syncthreads();
     }
@@ -362,8 +416,7 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
 // ------------------------------------------------------------- host --
 template <typename K, int NT, int TCAP, int VMODE>
 static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                                  const uint32_t* nseg_dev, uint32_t nseg_host, uint32_t grid,
-                                  uint32_t ell_ovr, hipStream_t s)
+                                  const uint32_t* nseg_dev, uint32_t nseg_host, uint32_t grid, hipStream_t s)
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
     static bool attr_set = false;
@@ -374,7 +427,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     }
     TraceScope tr(VMPS_TRACE_TILESORT, s);
     k_tilesort<K, NT, TCAP, VMODE><<<grid, NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, nseg_dev,
-                                                        nseg_host, P.inst_start, ell_ovr);
+                                                        nseg_host, P.inst_start);
     return hipGetLastError();
 }
 
@@ -387,23 +440,23 @@ uint32_t tilesort_capacity(int key_bits, int has_values)
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 {
     if (key_bits == 32)
-        return has_values ? tile_lds_bytes<uint32_t, 1024, 8192, 1>() : tile_lds_bytes<uint32_t, 1024, 16384, 0>();
-    return has_values ? tile_lds_bytes<uint64_t, 512, 4096, 1>() : tile_lds_bytes<uint64_t, 1024, 8192, 0>();
+        return has_values ? tile_lds_bytes<uint32_t, 512, 8192, 1>() : tile_lds_bytes<uint32_t, 1024, 16384, 0>();
+    return has_values ? tile_lds_bytes<uint64_t, 256, 4096, 1>() : tile_lds_bytes<uint64_t, 512, 8192, 0>();
 }
 
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                            int key_bits, int vmode, uint32_t ell_override, hipStream_t s)
+                            int key_bits, int vmode, uint32_t, hipStream_t s)
 {
-    const uint32_t grid = P.seg_cap < 4096u ? P.seg_cap : 4096u;
+    const uint32_t grid = P.seg_cap < 8192u ? P.seg_cap : 8192u;
     const uint32_t* nseg_dev = P.counters + CNT_NSEG;
     if (key_bits == 32) {
-        if (vmode == 0) return launch_tilesort<uint32_t, 1024, 16384, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
-        if (vmode == 1) return launch_tilesort<uint32_t, 1024, 8192, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
-        return launch_tilesort<uint32_t, 1024, 8192, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
+        if (vmode == 0) return launch_tilesort<uint32_t, 1024, 16384, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        return launch_tilesort<uint32_t, 512, 8192, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
     }
-    if (vmode == 0) return launch_tilesort<uint64_t, 1024, 8192, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
-    if (vmode == 1) return launch_tilesort<uint64_t, 512, 4096, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
-    return launch_tilesort<uint64_t, 512, 4096, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, ell_override, s);
+    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    return launch_tilesort<uint64_t, 256, 4096, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
 }
 
 }  // namespace vmps

@@ -50,70 +50,138 @@ constexpr size_t tile_lds_bytes()
     return (b + 15) & ~(size_t)15;
 }
 
-// One merge pass.  find(q, L, M, R) describes the node holding output q:
-// returns true when [L,M) and [M,R) are merged in this pass (R > q), else
-// false with R the first position after q where a node may start.  The
-// thread's outputs are produced node by node (outer dynamic loop); inside a
-// node a static, predicated loop keeps the register staging array indexed
-// by constants.
-template <typename K, int KI, int VMODE, typename Find>
-__device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, Find find)
+// One merge pass.  Every output position belongs to one node of the pass:
+// a merge node [L,M)+[M,R) or a copy node (M == R: the range stays as it
+// is).  Thread i produces outputs [i*KI, (i+1)*KI) into registers: the first
+// node is found by nd.first (with a merge-path search when the thread starts
+// inside a merge node), every later node starts exactly where the previous one
+// ended, so nd.next needs no search.  The single static loop keeps the
+// register staging arrays indexed by constants.  After a barrier the outputs
+// go back into the same LDS buffer.
+template <typename K, int KI, int TCAP, int VMODE, typename Nodes>
+__device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, Nodes nd)
 {
     const uint32_t p0 = threadIdx.x * KI;
     K rk[KI];
     uint32_t rv[KI];
-    uint32_t done = 0;
-    const uint32_t pend = p0 + KI < len ? p0 + KI : len;
-    uint32_t q = p0;
-    while (q < pend) {
+    if (p0 < len) {
         uint32_t L, M, R;
-        const bool mg = find(q, L, M, R);
-        const uint32_t stop = R < pend ? R : pend;
-        if (mg) {
-            const uint32_t na = M - L, nb = R - M, d = q - L;
+        nd.first(p0, L, M, R);
+        uint32_t ia = p0, jb = R;
+        if (M < R) {
+            const uint32_t na = M - L, nb = R - M, d = p0 - L;
             uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
                 if (S[px(L + mid)] <= S[px(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
             }
-            uint32_t ia = L + lo, jb = M + (d - lo);
-            K ha = ia < M ? S[px(ia)] : K(0);
-            K hb = jb < R ? S[px(jb)] : K(0);
-            const uint32_t j0 = q - p0, j1 = stop - p0;
-#pragma unroll
-            for (int j = 0; j < KI; ++j) {
-                if ((uint32_t)j >= j0 && (uint32_t)j < j1) {
-                    const bool takeA = ia < M && (jb >= R || ha <= hb);
-                    if (takeA) {
-                        rk[j] = ha;
-                        if (VMODE) rv[j] = SV[px(ia)];
-                        ++ia;
-                        if (ia < M) ha = S[px(ia)];
-                    } else {
-                        rk[j] = hb;
-                        if (VMODE) rv[j] = SV[px(jb)];
-                        ++jb;
-                        if (jb < R) hb = S[px(jb)];
-                    }
-                }
-            }
-            done |= ((j1 - j0 >= 32) ? ~0u : ((1u << (j1 - j0)) - 1u)) << j0;
+            ia = L + lo;
+            jb = M + (d - lo);
         }
-        q = stop;
+        K ha = S[px(ia)], hb = S[px(jb)];
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+            const uint32_t q = p0 + j;
+            if (j > 0 && q == R) {
+                nd.next(q, M, R);
+                ia = q;
+                jb = M;
+                ha = S[px(ia)];
+                hb = S[px(jb)];
+            }
+            // StandardMerge: the left run wins ties; a copy node only has a left run
+            const bool takeA = ia < M && (jb >= R || ha <= hb);
+            const uint32_t cur = takeA ? ia : jb;
+            rk[j] = takeA ? ha : hb;
+            if (VMODE) rv[j] = SV[px(cur)];
+            const uint32_t nx = cur + 1;
+            ia = takeA ? nx : ia;
+            jb = takeA ? jb : nx;
+            const K nv = S[px(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
+            ha = takeA ? nv : ha;
+            hb = takeA ? hb : nv;
+        }
     }
     __syncthreads();
+    if (p0 < len) {
+        const uint32_t cnt = len - p0;
 #pragma unroll
-    for (int j = 0; j < KI; ++j) {
-        if ((done >> j) & 1u) {
-            S[px(p0 + j)] = rk[j];
-            if (VMODE) SV[px(p0 + j)] = rv[j];
+        for (int j = 0; j < KI; ++j) {
+            if ((uint32_t)j < cnt) {
+                S[px(p0 + j)] = rk[j];
+                if (VMODE) SV[px(p0 + j)] = rv[j];
+            }
         }
     }
     __syncthreads();
 }
 
+// Nodes of one bottom-up level inside the forced runs: aligned blocks of 2w
+// from each unsorted run's start are merged as [ps, ps+w) + [ps+w, ps+2w);
+// already sorted runs and runs of at most w elements are copy nodes.
+struct RunLevel {
+    const uint32_t* RS;
+    const uint8_t* SR;
+    uint32_t len, w, wlog, rt, rs, re;
+    bool srt;
+    __device__ void node_at(uint32_t q, uint32_t& M, uint32_t& R) const
+    {
+        if (srt || re - rs <= w) { M = re; R = re; return; }
+        M = min(q + w, re);
+        R = min(q + 2 * w, re);
+    }
+    __device__ void first(uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R)
+    {
+        rs = RS[rt]; re = RS[rt + 1]; srt = SR[rt] != 0;
+        L = rs + (((q - rs) >> (wlog + 1)) << (wlog + 1));
+        node_at(L, M, R);
+    }
+    __device__ void next(uint32_t q, uint32_t& M, uint32_t& R)
+    {
+        if (q >= len) { M = len; R = len; return; }
+        if (q == re) { ++rt; rs = q; re = RS[rt + 1]; srt = SR[rt] != 0; }
+        node_at(q, M, R);
+    }
+};
+
+// Nodes of one power level of the merge tree, in position order in
+// NL[b0, b0+cn): node t merges [BL[t], RS[t+1]) with [RS[t+1], BR[t]); the
+// gaps between them are copy nodes.
+struct TreeLevel {
+    const uint32_t* NL;
+    const uint32_t* BL;
+    const uint32_t* BR;
+    const uint32_t* RS;
+    uint32_t len, b0, cn, ni;
+    __device__ void first(uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R)
+    {
+        int lo = -1, hi = (int)cn;  // last node starting at or before q
+        while (hi - lo > 1) {
+            const int m = (lo + hi) >> 1;
+            if (BL[NL[b0 + m]] <= q) lo = m; else hi = m;
+        }
+        ni = (uint32_t)(lo + 1);
+        if (lo >= 0) {
+            const uint32_t t = NL[b0 + lo];
+            if (q < BR[t]) { L = BL[t]; M = RS[t + 1]; R = BR[t]; return; }
+        }
+        L = q;
+        M = R = ni < cn ? BL[NL[b0 + ni]] : len;
+    }
+    __device__ void next(uint32_t q, uint32_t& M, uint32_t& R)
+    {
+        if (ni < cn) {
+            const uint32_t t = NL[b0 + ni];
+            if (BL[t] == q) { ++ni; M = RS[t + 1]; R = BR[t]; return; }
+            M = R = BL[t];
+            return;
+        }
+        M = R = len;
+    }
+};
+
 template <typename K, int NT, int TCAP, int VMODE>
-__global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
+__global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
                                                  uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                  const Seg* __restrict__ segs,
                                                  const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
@@ -361,19 +429,8 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
             myrun = lo;
         }
         for (uint32_t wlog = 0; (1u << wlog) < maxf; ++wlog) {
-            const uint32_t w = 1u << wlog;
-            uint32_t rt = myrun;
-            merge_pass<K, KI, VMODE>(S, SV, len, [&](uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R) -> bool {
-                while (rt + 1 < kr && RS[rt + 1] <= q) ++rt;  // outputs only move right
-                const uint32_t lo = rt;
-                const uint32_t s = RS[lo], e = RS[lo + 1];
-                if (SR[lo] || e - s <= w) { R = e; return false; }
-                const uint32_t ps = s + (((q - s) >> (wlog + 1)) << (wlog + 1));
-                L = ps;
-                M = min(ps + w, e);
-                R = min(ps + 2 * w, e);
-                return M < R;
-            });
+            RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
+            merge_pass<K, KI, TCAP, VMODE>(S, SV, len, nd);
         }
 
         // 8. merges of Algorithm 1 by decreasing power
@@ -381,25 +438,8 @@ __global__ __launch_bounds__(NT) void k_tilesort(K* __restrict__ keysA, K* __res
         while (mask) {
             const uint32_t p = 32 - __clz(mask);
             mask &= ~(1u << (p - 1));
-            const uint32_t b0 = LVs[p], cn = LVc[p];
-            merge_pass<K, KI, VMODE>(S, SV, len, [&](uint32_t q, uint32_t& L, uint32_t& M, uint32_t& R) -> bool {
-                int lo = -1, hi = (int)cn;  // last node starting at or before q
-                while (hi - lo > 1) {
-                    const int m = (lo + hi) >> 1;
-                    if (BL[NL[b0 + m]] <= q) lo = m; else hi = m;
-                }
-                if (lo >= 0) {
-                    const uint32_t t = NL[b0 + lo];
-                    if (q < BR[t]) {
-                        L = BL[t];
-                        M = RS[t + 1];
-                        R = BR[t];
-                        return true;
-                    }
-                }
-                R = (lo + 1 < (int)cn) ? BL[NL[b0 + lo + 1]] : len;
-                return false;
-            });
+            TreeLevel nd{NL, BL, BR, RS, len, LVs[p], LVc[p], 0};
+            merge_pass<K, KI, TCAP, VMODE>(S, SV, len, nd);
         }
 
         // 9. one write to the planned buffer

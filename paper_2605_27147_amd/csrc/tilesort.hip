@@ -43,6 +43,7 @@ constexpr size_t tile_lds_bytes()
     b += 4 * 2 * M::RC;               // long runs (u, e), later Q and the node list
     b += 4 * 2 * (M::RC + 1);         // progressions (base, prefix), later node L, R
     b += 4 * (M::RC + 1);             // run starts
+    b += 4 * M::RC;                   // node starts in level order
     b += 2 * M::RC;                   // powers, sorted-run flags
     b += 4 * 2 * 34;                  // level start / count
     b += 4 * (NT / 64) * 33;          // per-wave power counts
@@ -59,9 +60,11 @@ constexpr size_t tile_lds_bytes()
 // register staging arrays indexed by constants.  After a barrier the outputs
 // go back into the same LDS buffer.
 template <typename K, int KI, int TCAP, int VMODE, typename Nodes>
-__device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, Nodes nd)
+__device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
+                                           Nodes nd)
 {
-    const uint32_t p0 = threadIdx.x * KI;
+    static_assert(32 % KI == 0, "outputs of a thread stay inside one padding block");
+    const uint32_t p0 = tid * KI;
     K rk[KI];
     uint32_t rv[KI];
     if (p0 < len) {
@@ -104,16 +107,72 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
     }
     __syncthreads();
     if (p0 < len) {
-        const uint32_t cnt = len - p0;
+        // KI divides 32 and p0 is a multiple of KI: the outputs share one
+        // padding block, px(p0 + j) = px(p0) + j
+        const uint32_t cnt = len - p0, w0 = px(p0);
 #pragma unroll
         for (int j = 0; j < KI; ++j) {
             if ((uint32_t)j < cnt) {
-                S[px(p0 + j)] = rk[j];
-                if (VMODE) SV[px(p0 + j)] = rv[j];
+                S[w0 + j] = rk[j];
+                if (VMODE) SV[w0 + j] = rv[j];
             }
         }
     }
     __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t wave_max(uint32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v)
+{
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) v |= (uint32_t)__shfl_xor((int)v, off, 64);
+    return v;
+}
+
+// Stable sort of S[s, s+cnt), cnt <= 16, in registers: odd-even
+// transposition network.  It only exchanges adjacent elements that are
+// strictly inverted, so equal keys keep their order (the result of the
+// insertion sort); the unused slots hold the largest key and stay last.
+template <typename K, int VMODE>
+__device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t s, uint32_t cnt)
+{
+    K x[16];
+    uint32_t v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const bool in = (uint32_t)j < cnt;
+        x[j] = in ? S[px(s + j)] : ~K(0);
+        v[j] = (VMODE && in) ? SV[px(s + j)] : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+#pragma unroll
+        for (int i = r & 1; i + 1 < 16; i += 2) {
+            const bool sw = x[i] > x[i + 1];
+            const K lo = sw ? x[i + 1] : x[i], hi = sw ? x[i] : x[i + 1];
+            x[i] = lo;
+            x[i + 1] = hi;
+            if (VMODE) {
+                const uint32_t vl = sw ? v[i + 1] : v[i], vh = sw ? v[i] : v[i + 1];
+                v[i] = vl;
+                v[i + 1] = vh;
+            }
+        }
+    }
+    asm volatile("" : "+v"(s));  // recompute the addresses rather than keep 16 of them live
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if ((uint32_t)j < cnt) {
+            S[px(s + j)] = x[j];
+            if (VMODE) SV[px(s + j)] = v[j];
+        }
+    }
 }
 
 // Nodes of one bottom-up level inside the forced runs: aligned blocks of 2w
@@ -145,11 +204,11 @@ struct RunLevel {
 };
 
 // Nodes of one power level of the merge tree, in position order in
-// NL[b0, b0+cn): node t merges [BL[t], RS[t+1]) with [RS[t+1], BR[t]); the
-// gaps between them are copy nodes.
+// NL[b0, b0+cn) (their starts in BLs): node t merges [BL[t], RS[t+1]) with
+// [RS[t+1], BR[t]); the gaps between them are copy nodes.
 struct TreeLevel {
     const uint32_t* NL;
-    const uint32_t* BL;
+    const uint32_t* BLs;
     const uint32_t* BR;
     const uint32_t* RS;
     uint32_t len, b0, cn, ni;
@@ -158,30 +217,134 @@ struct TreeLevel {
         int lo = -1, hi = (int)cn;  // last node starting at or before q
         while (hi - lo > 1) {
             const int m = (lo + hi) >> 1;
-            if (BL[NL[b0 + m]] <= q) lo = m; else hi = m;
+            if (BLs[b0 + m] <= q) lo = m; else hi = m;
         }
         ni = (uint32_t)(lo + 1);
         if (lo >= 0) {
             const uint32_t t = NL[b0 + lo];
-            if (q < BR[t]) { L = BL[t]; M = RS[t + 1]; R = BR[t]; return; }
+            if (q < BR[t]) { L = BLs[b0 + lo]; M = RS[t + 1]; R = BR[t]; return; }
         }
         L = q;
-        M = R = ni < cn ? BL[NL[b0 + ni]] : len;
+        M = R = ni < cn ? BLs[b0 + ni] : len;
     }
     __device__ void next(uint32_t q, uint32_t& M, uint32_t& R)
     {
         if (ni < cn) {
-            const uint32_t t = NL[b0 + ni];
-            if (BL[t] == q) { ++ni; M = RS[t + 1]; R = BR[t]; return; }
-            M = R = BL[t];
+            const uint32_t bl = BLs[b0 + ni];
+            if (bl == q) {
+                const uint32_t t = NL[b0 + ni];
+                ++ni;
+                M = RS[t + 1];
+                R = BR[t];
+                return;
+            }
+            M = R = bl;
             return;
         }
         M = R = len;
     }
 };
 
+// All merges of one segment with KI outputs per thread: the bottom-up
+// levels inside the forced runs above the sorted 16-element chunks, then
+// Algorithm 1's merges by decreasing power.
+template <typename K, int KI, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
+                                            uint32_t kr,
+                                            const uint32_t* RS, const uint8_t* SR, const uint32_t* NL,
+                                            const uint32_t* BLs, const uint32_t* BR, const uint32_t* LVs,
+                                            const uint32_t* LVc, uint32_t maxf, uint32_t mask)
+{
+    uint32_t myrun = 0;  // run holding this thread's first output
+    {
+        const uint32_t q0 = tid * KI;
+        uint32_t lo = 0, hi = kr;
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (RS[m] <= q0) lo = m; else hi = m;
+        }
+        myrun = lo;
+    }
+    for (uint32_t wlog = 4; (1u << wlog) < maxf; ++wlog) {
+        RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
+        merge_pass<K, KI, TCAP, VMODE>(S, SV, len, tid, nd);
+    }
+    while (mask) {
+        const uint32_t p = 32 - __clz(mask);
+        mask &= ~(1u << (p - 1));
+        TreeLevel nd{NL, BLs, BR, RS, len, LVs[p], LVc[p], 0};
+        merge_pass<K, KI, TCAP, VMODE>(S, SV, len, tid, nd);
+    }
+}
+
+// HBM -> LDS, batches of loads in flight before their LDS stores.
 template <typename K, int NT, int TCAP, int VMODE>
-__global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
+__device__ __forceinline__ void tile_load(K* __restrict__ S, uint32_t* __restrict__ SV, const K* __restrict__ src,
+                                          const uint32_t* __restrict__ vsrc, uint32_t a, uint32_t len, uint32_t tid)
+{
+    static_assert(NT % 32 == 0, "affine padded index");
+    constexpr int CH = TCAP / NT;
+    constexpr int BT = CH < 8 ? CH : 8;
+    const uint32_t pt = px(tid);
+#pragma unroll
+    for (int c = 0; c < CH; c += BT) {
+        K r[BT];
+        uint32_t v[BT];
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+            const uint32_t i = (uint32_t)((c + j) * NT) + tid;
+            r[j] = i < len ? src[a + i] : K(0);
+            v[j] = (VMODE == 1 && i < len) ? vsrc[a + i] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+            const uint32_t i = (uint32_t)((c + j) * NT) + tid;
+            const uint32_t pi = pt + (uint32_t)((c + j) * (NT + NT / 32));  // px(i), NT a multiple of 32
+            if (i < len) {
+                S[pi] = r[j];
+                if (VMODE == 1) SV[pi] = v[j];
+                if (VMODE == 2) SV[pi] = a + i;
+            }
+        }
+    }
+}
+
+// LDS -> HBM, the reverse of tile_load.
+template <typename K, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_store(const K* __restrict__ S, const uint32_t* __restrict__ SV,
+                                           K* __restrict__ dst, uint32_t* __restrict__ vdst, uint32_t a, uint32_t len,
+                                           uint32_t tid)
+{
+    static_assert(NT % 32 == 0, "affine padded index");
+    constexpr int CH = TCAP / NT;
+    constexpr int BT = CH < 8 ? CH : 8;
+    const uint32_t pt = px(tid);
+#pragma unroll
+    for (int c = 0; c < CH; c += BT) {
+        K r[BT];
+        uint32_t v[BT];
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+            const uint32_t i = (uint32_t)((c + j) * NT) + tid;
+            const uint32_t pi = pt + (uint32_t)((c + j) * (NT + NT / 32));  // px(i), NT a multiple of 32
+            r[j] = i < len ? S[pi] : K(0);
+            v[j] = (VMODE && i < len) ? SV[pi] : 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < BT; ++j) {
+            const uint32_t i = (uint32_t)((c + j) * NT) + tid;
+            if (i < len) {
+                dst[a + i] = r[j];
+                if (VMODE) vdst[a + i] = v[j];
+            }
+        }
+    }
+}
+
+// MINW: waves per SIMD that the LDS footprint lets run at once, which
+// bounds the registers a wave may use.
+template <typename K, int NT, int TCAP, int VMODE, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
                                                  uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                  const Seg* __restrict__ segs,
                                                  const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
@@ -193,7 +356,9 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
     constexpr uint32_t RC = MT::RC;
     static_assert(TCAP % NT == 0 && KI <= 32, "tile must split evenly, at most 32 outputs per thread");
     static_assert(TCAP / 64 + 1 <= NT, "one thread per bitmap word");
-    static_assert(RC <= 64 * NW, "one thread per boundary in the power ranking");
+    // every run but an instance's last is at least 32 long, so a tile holds
+    // fewer than TCAP / 32 boundaries
+    static_assert(TCAP / 32 <= 64 * NW, "one thread per boundary in the power ranking");
 
     extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* sp = smem;
@@ -209,6 +374,7 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
     uint32_t* wcnt = (uint32_t*)sp; sp += 4 * NW * 33;
     uint32_t* scan_lds = (uint32_t*)sp; sp += 4 * (NW + 1);
     uint32_t* scal = (uint32_t*)sp; sp += 4 * 16;  // [0] progressions [1] runs [2] power mask [3] max unsorted run
+    uint32_t* BLs = (uint32_t*)sp; sp += 4 * RC;  // BL of NL[i]: node starts in level order
     uint8_t* PW = sp; sp += RC;
     uint8_t* SR = sp;
     // aliases: long runs -> (Q, node list); progressions -> (node L, node R)
@@ -221,10 +387,14 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
     uint32_t* BL = R2;
     uint32_t* BR = R2 + RC + 1;
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const uint32_t nseg = nseg_dev ? *nseg_dev : nseg_host;
 
     for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
+        // the thread index is made opaque per segment so that the compiler
+        // does not keep every unrolled address live across the whole loop
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
+        const int lane = tid & 63, wave = tid >> 6;
         const Seg sg = segs[si];
         const uint32_t a = sg.start;
         const uint32_t len = sg.end - sg.start;
@@ -248,11 +418,7 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
         const uint32_t g = a - ib;
 
         // 1. load
-        for (uint32_t i = tid; i < len; i += NT) {
-            S[px(i)] = keysA[a + i];
-            if (VMODE == 1) SV[px(i)] = valsA[a + i];
-            if (VMODE == 2) SV[px(i)] = a + i;
-        }
+        tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
         if (tid < 16) scal[tid] = 0;
         __syncthreads();
 
@@ -271,7 +437,15 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
         if ((uint32_t)tid < W) {
             const uint64_t word = bm[tid];
             const uint32_t p0 = tid * 64;
-            uint64_t bits = word;
+            // a long run starting at bit b has no boundary in (b, b+31]:
+            // only such bits are examined
+            uint64_t o = word >> 1;
+            o |= o >> 1;
+            o |= o >> 2;
+            o |= o >> 4;
+            o |= o >> 8;
+            o |= o >> 15;
+            uint64_t bits = word & ~o;
             while (bits) {
                 const int b = ffs64(bits);
                 bits &= bits - 1;
@@ -337,6 +511,7 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
         __syncthreads();
 
         // 6. sorted-run flags, midpoint expansions and powers
+        uint32_t unsorted_max = 0, pmask = 0;
         for (uint32_t t = tid; t < kr; t += NT) {
             const uint32_t s = RS[t], e = RS[t + 1];
             bool sorted = true;  // no descent strictly inside (s, e)
@@ -350,16 +525,20 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
                 }
             }
             SR[t] = sorted ? 1 : 0;
-            if (!sorted) atomicMax(&scal[3], e - s);
+            if (!sorted) unsorted_max = max(unsorted_max, e - s);
             const uint64_t s2 = 2ull * g + s + e;
             Qv[t] = (uint32_t)((s2 << 31) / il);
         }
+        unsorted_max = wave_max(unsorted_max);
+        if (lane == 0 && unsorted_max) atomicMax(&scal[3], unsorted_max);
         __syncthreads();
         for (uint32_t t = tid; t + 1 < kr; t += NT) {
             const uint32_t p = __clz(Qv[t] ^ Qv[t + 1]) + 1;
             PW[t] = (uint8_t)p;
-            atomicOr(&scal[2], 1u << (p - 1));
+            pmask |= 1u << (p - 1);
         }
+        pmask = wave_or(pmask);
+        if (lane == 0 && pmask) atomicOr(&scal[2], pmask);
         __syncthreads();
         // node extents: nearest boundaries of smaller power inside the segment
         for (uint32_t t = tid; t + 1 < kr; t += NT) {
@@ -412,61 +591,53 @@ __global__ __launch_bounds__(NT, 4) void k_tilesort(K* __restrict__ keysA, K* __
                 uint32_t r = LVs[p] + rw;
                 for (int w = 0; w < wave; ++w) r += wcnt[w * 33 + p];
                 NL[r] = t;
+                BLs[r] = BL[t];
             }
         }
         __syncthreads();
 
-        // 7. forced runs: bottom-up merges of aligned blocks inside each run
-        const uint32_t maxf = scal[3];
-        uint32_t myrun = 0;  // run holding this thread's first output
-        {
-            const uint32_t q0 = tid * KI;
-            uint32_t lo = 0, hi = kr;
-            while (hi - lo > 1) {
-                const uint32_t m = (lo + hi) >> 1;
-                if (RS[m] <= q0) lo = m; else hi = m;
+        // 7./8. forced runs, then the merges of Algorithm 1; segments up to
+        // half the tile use half the outputs per thread, so every thread works
+        const uint32_t maxf = scal[3], mask = scal[2];
+        // 7a. the first four bottom-up levels of every forced run: 16-element
+        // chunks from the run start, sorted in registers (unsorted runs are
+        // forced runs, shorter than 64)
+        if (maxf > 1) {
+            const uint32_t cpr = (maxf + 15) >> 4;
+            for (uint32_t x = tid; x < cpr * kr; x += NT) {
+                const uint32_t r = x / cpr, c = x - r * cpr;
+                const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
+                if (!SR[r] && cs + 1 < ce) chunk_sort16<K, VMODE>(S, SV, cs, min(16u, ce - cs));
             }
-            myrun = lo;
+            __syncthreads();
         }
-        for (uint32_t wlog = 0; (1u << wlog) < maxf; ++wlog) {
-            RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
-            merge_pass<K, KI, TCAP, VMODE>(S, SV, len, nd);
-        }
-
-        // 8. merges of Algorithm 1 by decreasing power
-        uint32_t mask = scal[2];
-        while (mask) {
-            const uint32_t p = 32 - __clz(mask);
-            mask &= ~(1u << (p - 1));
-            TreeLevel nd{NL, BL, BR, RS, len, LVs[p], LVc[p], 0};
-            merge_pass<K, KI, TCAP, VMODE>(S, SV, len, nd);
-        }
+        if (len <= (uint32_t)(NT * (KI / 2)))
+            tile_merges<K, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        else
+            tile_merges<K, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
 
         // 9. one write to the planned buffer
-        K* outK = sg.dst ? keysB : keysA;
-        uint32_t* outV = sg.dst ? valsB : valsA;
-        for (uint32_t i = tid; i < len; i += NT) {
-            outK[a + i] = S[px(i)];
-            if (VMODE) outV[a + i] = SV[px(i)];
-        }
+        int tid_st = tid;
+        asm volatile("" : "+v"(tid_st));
+        tile_store<K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st);
         __syncthreads();
     }
 }
 
 // ------------------------------------------------------------- host --
-template <typename K, int NT, int TCAP, int VMODE>
+template <typename K, int NT, int TCAP, int VMODE, int MINW>
 static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
                                   const uint32_t* nseg_dev, uint32_t nseg_host, uint32_t grid, hipStream_t s)
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
     static bool attr_set = false;
     if (!attr_set) {
-        VMPS_HIP(hipFuncSetAttribute((const void*)k_tilesort<K, NT, TCAP, VMODE>,
+        VMPS_HIP(hipFuncSetAttribute((const void*)k_tilesort<K, NT, TCAP, VMODE, MINW>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
     TraceScope tr(VMPS_TRACE_TILESORT, s);
-    k_tilesort<K, NT, TCAP, VMODE><<<grid, NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, nseg_dev,
+    k_tilesort<K, NT, TCAP, VMODE, MINW><<<grid, NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, nseg_dev,
                                                         nseg_host, P.inst_start);
     return hipGetLastError();
 }
@@ -477,10 +648,15 @@ uint32_t tilesort_capacity(int key_bits, int has_values)
     return has_values ? 4096u : 8192u;
 }
 
+// Tile configurations (threads, elements, values mode, waves per SIMD):
+//   u32 keys          512 x 16384: 2 workgroups of 8 waves per CU (LDS)
+//   u32 keys + values 512 x  8192: 2 per CU
+//   u64 keys          512 x  8192: 2 per CU
+//   u64 keys + values 256 x  4096: 3 per CU of 4 waves
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 {
     if (key_bits == 32)
-        return has_values ? tile_lds_bytes<uint32_t, 512, 8192, 1>() : tile_lds_bytes<uint32_t, 1024, 16384, 0>();
+        return has_values ? tile_lds_bytes<uint32_t, 512, 8192, 1>() : tile_lds_bytes<uint32_t, 512, 16384, 0>();
     return has_values ? tile_lds_bytes<uint64_t, 256, 4096, 1>() : tile_lds_bytes<uint64_t, 512, 8192, 0>();
 }
 
@@ -490,13 +666,13 @@ hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* v
     const uint32_t grid = P.seg_cap < 8192u ? P.seg_cap : 8192u;
     const uint32_t* nseg_dev = P.counters + CNT_NSEG;
     if (key_bits == 32) {
-        if (vmode == 0) return launch_tilesort<uint32_t, 1024, 16384, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-        if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-        return launch_tilesort<uint32_t, 512, 8192, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        if (vmode == 0) return launch_tilesort<uint32_t, 512, 16384, 0, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
     }
-    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-    if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-    return launch_tilesort<uint64_t, 256, 4096, 2>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1, 3>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    return launch_tilesort<uint64_t, 256, 4096, 2, 3>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
 }
 
 }  // namespace vmps

@@ -13,9 +13,10 @@
 
 namespace vmps {
 
-constexpr uint32_t PART_TILE = 4096;  // keys per scatter workgroup
-constexpr int PART_NT = 256;
-constexpr int PART_KPT = PART_TILE / PART_NT;
+constexpr uint32_t PART_TILE = 8192;  // keys per histogram / scatter workgroup
+constexpr int PART_NT = 512;
+constexpr int PART_NW = PART_NT / 64;
+constexpr int PART_RND = PART_TILE / PART_NT;  // keys per thread
 constexpr uint64_t BATCH_STRIDE = 0x9E3779B1ull;  // odd: visits every sample mod 2^k
 constexpr int LOSS_STRIDE = 64;
 constexpr float KNOT_GAP = 1e-6f;
@@ -401,65 +402,113 @@ __device__ inline void part_tile(const PartLevel& L, uint32_t tile, uint32_t& c,
     s1 = min(L.pstart[c + 1], s0 + PART_TILE);
 }
 
-template <typename K>
-__global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ keys, PartLevel L,
+// Histogram of one tile.  Level 1 evaluates the model once per key and
+// writes the 16-bit bucket ids; level 2 reads them back.  Per-wave counters
+// keep LDS atomics on popular digits apart.
+template <typename K, bool IDS_IN>
+__global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ keys, const uint16_t* __restrict__ ids_in,
+                                                       uint16_t* __restrict__ ids_out, PartLevel L,
                                                        const vmps_cdf_model* __restrict__ model, uint32_t B)
 {
-    __shared__ uint32_t hist[256];
+    __shared__ uint32_t hist[PART_NW][256];
     const uint32_t tile = blockIdx.x;
     if (tile >= L.tbase[L.P]) return;
-    const ModelArgs M = model_args(model, B);
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
-    hist[threadIdx.x] = 0;
+    const uint32_t len = s1 - s0;
+    const int tid = threadIdx.x, wave = tid >> 6;
+    for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
     __syncthreads();
-    for (uint32_t i = s0 + threadIdx.x; i < s1; i += PART_NT)
-        atomicAdd(&hist[(bucket_of((uint64_t)keys[i], M) >> L.shift) & L.mask], 1u);
+    if (IDS_IN) {
+        uint32_t id[PART_RND];
+#pragma unroll
+        for (int r = 0; r < PART_RND; ++r) {
+            const uint32_t i = r * PART_NT + tid;
+            id[r] = i < len ? ids_in[s0 + i] : 0u;
+        }
+#pragma unroll
+        for (int r = 0; r < PART_RND; ++r)
+            if (r * PART_NT + tid < len) atomicAdd(&hist[wave][(id[r] >> L.shift) & L.mask], 1u);
+    } else {
+        const ModelArgs M = model_args(model, B);
+        constexpr int HB = PART_RND / 2;  // two halves keep the registers in check
+#pragma unroll
+        for (int h = 0; h < PART_RND; h += HB) {
+            K k[HB];
+#pragma unroll
+            for (int r = 0; r < HB; ++r) {
+                const uint32_t i = (h + r) * PART_NT + tid;
+                k[r] = i < len ? keys[s0 + i] : K(0);
+            }
+#pragma unroll
+            for (int r = 0; r < HB; ++r) {
+                const uint32_t i = (h + r) * PART_NT + tid;
+                if (i < len) {
+                    const uint32_t b = bucket_of((uint64_t)k[r], M);
+                    ids_out[s0 + i] = (uint16_t)b;
+                    atomicAdd(&hist[wave][(b >> L.shift) & L.mask], 1u);
+                }
+            }
+        }
+    }
     __syncthreads();
-    if (threadIdx.x < L.F) L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)threadIdx.x * nt + tl] = hist[threadIdx.x];
+    if ((uint32_t)tid < L.F) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
+        L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl] = t;
+    }
 }
 
-// Stable scatter of one tile: ranks by (digit, input position) from
-// wave ballots, a local reorder by digit in LDS, then runs of equal digit
-// are written contiguously.  VMODE 2 generates the values (input index).
-template <typename K, int VMODE>
+// Stable scatter of one tile by the digit of its bucket id.  Wave w ranks
+// the keys [w*TILE/NW, (w+1)*TILE/NW) of the tile in input order: a match
+// of the digit bits by ballots gives the rank among the wave's 64 keys, a
+// wave-private counter per digit the rank among its earlier keys.  One
+// block scan over (digit, wave) gives every key its place in an LDS reorder
+// by digit, and the runs of equal digit go out contiguously.  VMODE 2
+// generates the values (input index).  IDS_OUT: the ids travel with the keys.
+template <typename K, int VMODE, bool IDS_OUT>
 __global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                          K* __restrict__ kout, uint32_t* __restrict__ vout,
-                                                          PartLevel L, const vmps_cdf_model* __restrict__ model,
-                                                          uint32_t B)
+                                                          const uint16_t* __restrict__ idin, K* __restrict__ kout,
+                                                          uint32_t* __restrict__ vout, uint16_t* __restrict__ idout,
+                                                          PartLevel L)
 {
-    constexpr int NW = PART_NT / 64;
+    constexpr uint32_t WCH = PART_TILE / PART_NW;  // keys per wave
+    constexpr int RND = (int)(WCH / 64);
     __shared__ K skey[PART_TILE];
     __shared__ uint32_t sval[VMODE ? PART_TILE : 1];
-    __shared__ uint8_t sdig[PART_TILE];
-    __shared__ uint32_t cnt[256], loff[256], goff[256], wcnt[NW][256];
-    __shared__ uint32_t scan_lds[NW + 1];
+    __shared__ uint16_t sid[PART_TILE];
+    __shared__ uint32_t hc[PART_NW][256];
+    __shared__ uint32_t loff[256], goff[256];
+    __shared__ uint32_t scan_lds[PART_NW + 1];
     const uint32_t tile = blockIdx.x;
     if (tile >= L.tbase[L.P]) return;
-    const ModelArgs M = model_args(model, B);
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
     const uint32_t len = s1 - s0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    cnt[tid] = 0;
-    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hc[0][0])[i] = 0;
+    if ((uint32_t)tid < L.F) goff[tid] = L.offs[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl];
     __syncthreads();
-    K kr[PART_KPT];
-    uint32_t vr[PART_KPT], rk[PART_KPT], dg[PART_KPT];
-    const uint64_t lt = (1ull << lane) - 1;
+
+    const uint32_t wb = wave * WCH;
+    K kr[RND];
+    uint32_t vr[RND], ir[RND];
 #pragma unroll
-    for (int r = 0; r < PART_KPT; ++r) {
-        const uint32_t i = r * PART_NT + tid;
+    for (int r = 0; r < RND; ++r) {
+        const uint32_t i = wb + r * 64 + lane;
         const bool valid = i < len;
-        K key = 0;
-        uint32_t d = 0;
-        if (valid) {
-            key = kin[s0 + i];
-            d = (bucket_of((uint64_t)key, M) >> L.shift) & L.mask;
-            if (VMODE == 1) vr[r] = vin[s0 + i];
-            if (VMODE == 2) vr[r] = s0 + i;
-        }
-        kr[r] = key;
+        kr[r] = valid ? kin[s0 + i] : K(0);
+        ir[r] = valid ? idin[s0 + i] : 0u;
+        vr[r] = (VMODE == 1 && valid) ? vin[s0 + i] : s0 + i;
+    }
+    const uint64_t lt = (1ull << lane) - 1;
+    uint32_t rk[RND];
+#pragma unroll
+    for (int r = 0; r < RND; ++r) {
+        const uint32_t i = wb + r * 64 + lane;
+        const bool valid = i < len;
+        const uint32_t d = valid ? (ir[r] >> L.shift) & L.mask : 0u;
         uint64_t peers = __ballot(valid);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
@@ -467,44 +516,50 @@ __global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ 
             const uint64_t bk = __ballot(bit);
             peers &= bit ? bk : ~bk;
         }
+        const uint32_t before = valid ? hc[wave][d] : 0u;
         const uint32_t rw = __popcll(peers & lt);
-        if (valid && rw == 0) wcnt[wave][d] = __popcll(peers);
-        __syncthreads();
-        if (valid) {
-            uint32_t base = cnt[d];
-            for (int w = 0; w < wave; ++w) base += wcnt[w][d];
-            rk[r] = base + rw;
-            dg[r] = d;
-        }
-        __syncthreads();
-        {
-            uint32_t tot = 0;
-            for (int w = 0; w < NW; ++w) { tot += wcnt[w][tid]; wcnt[w][tid] = 0; }
-            cnt[tid] += tot;
-        }
-        __syncthreads();
+        rk[r] = before + rw;
+        // the wave's lowest lane of each digit advances the counter; LDS
+        // operations of one wave complete in order, after every lane's read
+        if (valid && rw == 0) hc[wave][d] = before + __popcll(peers);
     }
-    uint32_t total;
-    const uint32_t ex = block_excl_scan(cnt[tid], scan_lds, &total);
-    loff[tid] = ex;
-    if ((uint32_t)tid < L.F) goff[tid] = L.offs[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl];
+    __syncthreads();
+    uint32_t tot = 0;
+    if (tid < 256) {
+#pragma unroll
+        for (int w = 0; w < PART_NW; ++w) {
+            const uint32_t v = hc[w][tid];
+            hc[w][tid] = tot;
+            tot += v;
+        }
+    }
+    uint32_t all;
+    const uint32_t ex = block_excl_scan(tot, scan_lds, &all);
+    if (tid < 256) {
+        loff[tid] = ex;
+#pragma unroll
+        for (int w = 0; w < PART_NW; ++w) hc[w][tid] += ex;
+    }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < PART_KPT; ++r) {
-        const uint32_t i = r * PART_NT + tid;
+    for (int r = 0; r < RND; ++r) {
+        const uint32_t i = wb + r * 64 + lane;
         if (i < len) {
-            const uint32_t lp = loff[dg[r]] + rk[r];
+            const uint32_t d = (ir[r] >> L.shift) & L.mask;
+            const uint32_t lp = hc[wave][d] + rk[r];
             skey[lp] = kr[r];
+            sid[lp] = (uint16_t)ir[r];
             if (VMODE) sval[lp] = vr[r];
-            sdig[lp] = (uint8_t)dg[r];
         }
     }
     __syncthreads();
     for (uint32_t i = tid; i < len; i += PART_NT) {
-        const uint32_t d = sdig[i];
+        const uint32_t id = sid[i];
+        const uint32_t d = (id >> L.shift) & L.mask;
         const uint32_t o = goff[d] + (i - loff[d]);
         kout[o] = skey[i];
         if (VMODE) vout[o] = sval[i];
+        if (IDS_OUT) idout[o] = (uint16_t)id;
     }
 }
 
@@ -607,32 +662,35 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
     uint32_t* c2 = o1 + (uint64_t)nt1 * F1;
     uint32_t* o2 = c2 + (uint64_t)nt2cap * F2;
     uint32_t* stmp = o2 + (uint64_t)nt2cap * F2;
+    const uint64_t big = (uint64_t)nt1 * F1 > (uint64_t)nt2cap * F2 ? (uint64_t)nt1 * F1 : (uint64_t)nt2cap * F2;
+    uint16_t* id1 = (uint16_t*)(((uintptr_t)(stmp + scan_tmp_words(big)) + 255) & ~(uintptr_t)255);
+    uint16_t* id2 = id1 + ((n + 127) & ~127u);
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
         PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
-        k_part_hist<K><<<nt1, PART_NT, 0, s>>>(kin, L1, Mdev, B);
+        k_part_hist<K, false><<<nt1, PART_NT, 0, s>>>(kin, nullptr, id1, L1, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
     }
     {
         TraceScope tr(VMPS_TRACE_SCATTER, s);
         PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
-        if (vmode == 0) k_part_scatter<K, 0><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
-        else if (vmode == 1) k_part_scatter<K, 1><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
-        else k_part_scatter<K, 2><<<nt1, PART_NT, 0, s>>>(kin, vin, ktmp, vtmp, L1, Mdev, B);
+        if (vmode == 0) k_part_scatter<K, 0, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
+        else if (vmode == 1) k_part_scatter<K, 1, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
+        else k_part_scatter<K, 2, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
     }
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_level2<<<1, 256, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
         PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
-        k_part_hist<K><<<nt2cap, PART_NT, 0, s>>>(ktmp, L2, Mdev, B);
+        k_part_hist<K, true><<<nt2cap, PART_NT, 0, s>>>(ktmp, id2, nullptr, L2, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c2, o2, (uint64_t)nt2cap * F2, cnt_total + 1, tot + 1, stmp, s));
     }
     {
         TraceScope tr(VMPS_TRACE_SCATTER, s);
         PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
-        if (vmode == 0) k_part_scatter<K, 0><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, kout, vout, L2, Mdev, B);
-        else k_part_scatter<K, 1><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, kout, vout, L2, Mdev, B);
+        if (vmode == 0) k_part_scatter<K, 0, false><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, nullptr, L2);
+        else k_part_scatter<K, 1, false><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, nullptr, L2);
     }
     k_bucket_offsets<<<grid1(B + 1), 256, 0, s>>>(p2, t2, o2, F2, lo_bits, B, n, bucket_off);
     return hipGetLastError();
@@ -648,7 +706,8 @@ uint64_t partition_arena_words(uint64_t n, uint32_t B)
     const uint64_t nt1 = ceil_div(n ? n : 1, PART_TILE);
     const uint64_t nt2cap = nt1 + F1;
     const uint64_t big = nt1 * F1 > nt2cap * F2 ? nt1 * F1 : nt2cap * F2;
-    return 4 + 520 + 8 + 2 * nt1 * F1 + 2 * nt2cap * F2 + scan_tmp_words(big) + 64;
+    const uint64_t ids = 2 * ((n + 127) & ~127ull) / 2;  // two arrays of 16-bit bucket ids
+    return 4 + 520 + 8 + 2 * nt1 * F1 + 2 * nt2cap * F2 + scan_tmp_words(big) + 64 + ids + 64;
 }
 
 hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, uint32_t* vtmp, void* kout,

@@ -387,6 +387,15 @@ struct PartLevel {
     const uint32_t* offs;
 };
 
+// Workgroups are dealt to the 8 XCDs in turn; this numbering gives every
+// XCD a contiguous range of tiles, so the partly written cache lines where
+// one tile's digit run meets the next tile's are completed in one L2.
+__device__ inline uint32_t xcd_tile(uint32_t b, uint32_t G)
+{
+    const uint32_t x = b & 7, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 __device__ inline void part_tile(const PartLevel& L, uint32_t tile, uint32_t& c, uint32_t& tl, uint32_t& nt,
                                  uint32_t& s0, uint32_t& s1)
 {
@@ -465,23 +474,26 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ key
 // of the digit bits by ballots gives the rank among the wave's 64 keys, a
 // wave-private counter per digit the rank among its earlier keys.  One
 // block scan over (digit, wave) gives every key its place in an LDS reorder
-// by digit, and the runs of equal digit go out contiguously.  VMODE 2
-// generates the values (input index).  IDS_OUT: the ids travel with the keys.
+// by digit, and the runs of equal digit go out contiguously.  The reorder
+// goes through LDS in two halves of the tile, so that two workgroups share a
+// CU.  VMODE 2 generates the values (input index).  IDS_OUT: the ids travel
+// with the keys.
 template <typename K, int VMODE, bool IDS_OUT>
-__global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+__global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
                                                           const uint16_t* __restrict__ idin, K* __restrict__ kout,
                                                           uint32_t* __restrict__ vout, uint16_t* __restrict__ idout,
                                                           PartLevel L)
 {
     constexpr uint32_t WCH = PART_TILE / PART_NW;  // keys per wave
     constexpr int RND = (int)(WCH / 64);
-    __shared__ K skey[PART_TILE];
-    __shared__ uint32_t sval[VMODE ? PART_TILE : 1];
-    __shared__ uint16_t sid[PART_TILE];
+    constexpr uint32_t HALF = PART_TILE / 2;
+    __shared__ K skey[HALF];
+    __shared__ uint32_t sval[VMODE ? HALF : 1];
+    __shared__ uint16_t sid[HALF];
     __shared__ uint32_t hc[PART_NW][256];
     __shared__ uint32_t loff[256], goff[256];
     __shared__ uint32_t scan_lds[PART_NW + 1];
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= L.tbase[L.P]) return;
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
@@ -503,7 +515,7 @@ __global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ 
         vr[r] = (VMODE == 1 && valid) ? vin[s0 + i] : s0 + i;
     }
     const uint64_t lt = (1ull << lane) - 1;
-    uint32_t rk[RND];
+    // ir[r]: the 16-bit id below, the key's rank (< 2^13) above
 #pragma unroll
     for (int r = 0; r < RND; ++r) {
         const uint32_t i = wb + r * 64 + lane;
@@ -518,7 +530,7 @@ __global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ 
         }
         const uint32_t before = valid ? hc[wave][d] : 0u;
         const uint32_t rw = __popcll(peers & lt);
-        rk[r] = before + rw;
+        ir[r] |= (before + rw) << 16;
         // the wave's lowest lane of each digit advances the counter; LDS
         // operations of one wave complete in order, after every lane's read
         if (valid && rw == 0) hc[wave][d] = before + __popcll(peers);
@@ -543,23 +555,37 @@ __global__ __launch_bounds__(PART_NT) void k_part_scatter(const K* __restrict__ 
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RND; ++r) {
-        const uint32_t i = wb + r * 64 + lane;
-        if (i < len) {
-            const uint32_t d = (ir[r] >> L.shift) & L.mask;
-            const uint32_t lp = hc[wave][d] + rk[r];
-            skey[lp] = kr[r];
-            sid[lp] = (uint16_t)ir[r];
-            if (VMODE) sval[lp] = vr[r];
-        }
+        const uint32_t d = ((ir[r] & 0xffffu) >> L.shift) & L.mask;
+        ir[r] += hc[wave][d] << 16;  // place in the tile's order by digit
     }
-    __syncthreads();
-    for (uint32_t i = tid; i < len; i += PART_NT) {
-        const uint32_t id = sid[i];
-        const uint32_t d = (id >> L.shift) & L.mask;
-        const uint32_t o = goff[d] + (i - loff[d]);
-        kout[o] = skey[i];
-        if (VMODE) vout[o] = sval[i];
-        if (IDS_OUT) idout[o] = (uint16_t)id;
+#pragma unroll
+    for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t lo = h * HALF;
+        if (lo >= len) break;
+#pragma unroll
+        for (int r = 0; r < RND; ++r) {
+            const uint32_t i = wb + r * 64 + lane;
+            const uint32_t lp = (ir[r] >> 16) - lo;
+            if (i < len && lp < HALF) {
+                skey[lp] = kr[r];
+                sid[lp] = (uint16_t)ir[r];
+                if (VMODE) sval[lp] = vr[r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < PART_RND / 2; ++r) {
+            const uint32_t j = r * PART_NT + tid, i = lo + j;
+            if (i < len) {
+                const uint32_t id = sid[j];
+                const uint32_t d = (id >> L.shift) & L.mask;
+                const uint32_t o = goff[d] + (i - loff[d]);
+                kout[o] = skey[j];
+                if (VMODE) vout[o] = sval[j];
+                if (IDS_OUT) idout[o] = (uint16_t)id;
+            }
+        }
+        __syncthreads();
     }
 }
 

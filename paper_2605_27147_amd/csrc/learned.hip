@@ -127,13 +127,15 @@ struct TrainLds {
     float pw1[TRAIN_NT], pb1[TRAIN_NT], pw2[TRAIN_NT];
     float pb2[TRAIN_NT], pl[TRAIN_NT];
     float q[VMPS_CDF_MAX_HIDDEN], y[VMPS_CDF_MAX_HIDDEN];
+    float bu[TRAIN_NT], by[TRAIN_NT];  // minibatch points, staged per chunk
     float loss;
 };
 
 // Gradient of the minibatch MSE (forward pass, then backpropagation through
-// the hidden ReLU layer).  Thread t owns hidden unit t % H of lane group
-// t / H; groups take the batch points in turn; partial sums are reduced in
-// a fixed order, so the result does not depend on timing.
+// the hidden ReLU layer).  The points are staged in LDS, TRAIN_NT at a time
+// (one gather for all of them).  Thread t owns hidden unit t % H of lane
+// group t / H; groups take the staged points in turn; partial sums are
+// reduced in a fixed order, so the result does not depend on timing.
 // point(j, u, y) yields minibatch point j.  Writes S.g and S.loss.
 template <int H, typename Point>
 __device__ void batch_grad(TrainLds& S, int nb, Point point)
@@ -143,21 +145,31 @@ __device__ void batch_grad(TrainLds& S, int nb, Point point)
     const float w1 = S.p[h], b1 = S.p[H + h], w2 = S.p[2 * H + h], b2 = S.p[3 * H];
     const float inv = 2.f / (float)nb;
     float aw1 = 0.f, ab1 = 0.f, aw2 = 0.f, ab2 = 0.f, al = 0.f;
-    for (int j = grp; j < nb; j += G) {
-        float u, y;
-        point(j, u, y);
-        const float a = w1 * u + b1;
-        const float r = a > 0.f ? a : 0.f;
-        const float f = group_sum<H>(w2 * r) + b2;
-        const float e = f - y;
-        const float dfd = inv * e;
-        if (a > 0.f) {
-            aw2 += dfd * r;
-            aw1 += dfd * w2 * u;
-            ab1 += dfd * w2;
+    for (int base = 0; base < nb; base += TRAIN_NT) {
+        const int cnt = nb - base < TRAIN_NT ? nb - base : TRAIN_NT;
+        if (t < cnt) {
+            float uu, yy;
+            point(base + t, uu, yy);
+            S.bu[t] = uu;
+            S.by[t] = yy;
         }
-        ab2 += dfd;
-        al += e * e;
+        __syncthreads();
+        for (int j = grp; j < cnt; j += G) {
+            const float u = S.bu[j], y = S.by[j];
+            const float a = w1 * u + b1;
+            const float r = a > 0.f ? a : 0.f;
+            const float f = group_sum<H>(w2 * r) + b2;
+            const float e = f - y;
+            const float dfd = inv * e;
+            if (a > 0.f) {
+                aw2 += dfd * r;
+                aw1 += dfd * w2 * u;
+                ab1 += dfd * w2;
+            }
+            ab2 += dfd;
+            al += e * e;
+        }
+        __syncthreads();
     }
     S.pw1[t] = aw1; S.pb1[t] = ab1; S.pw2[t] = aw2;
     if (h == 0) { S.pb2[grp] = ab2; S.pl[grp] = al; }

@@ -24,47 +24,93 @@ __device__ inline uint32_t merge_path(const K* __restrict__ a, uint32_t na, cons
     return lo;
 }
 
-// Merge a[i0,i1) and b[j0,j1) into out[0, (i1-i0)+(j1-j0)) through LDS.
+// LDS slot of element i: one spare slot after every 32 elements, so that a
+// wave writing KI consecutive elements per lane spreads over the banks.
+__device__ __forceinline__ uint32_t mpx(uint32_t i) { return i + (i >> 5); }
+
+// LDS slots for a tile of TO elements (with slack for the reads one past the
+// end of the merge).
+template <uint32_t TO>
+struct MergeLds {
+    static constexpr uint32_t SP = TO + TO / 32 + 64;
+};
+
+// Merge a[i0,i1) and b[j0,j1) into out[0, (i1-i0)+(j1-j0)) through LDS:
+// all loads of the tile in flight at once, a merge-path split per thread,
+// KI outputs per thread into registers (ties to a), then back through the
+// same LDS buffer for coalesced stores.
 template <typename K, bool VAL, int NT, int KI>
 __device__ inline void merge_tile(const K* __restrict__ a, const uint32_t* __restrict__ va, uint32_t i0,
                                   uint32_t i1, const K* __restrict__ b, const uint32_t* __restrict__ vb,
                                   uint32_t j0, uint32_t j1, K* __restrict__ out, uint32_t* __restrict__ vout,
-                                  K* S, uint32_t* SV, K* SO, uint32_t* SOV)
+                                  K* S, uint32_t* SV)
 {
+    static_assert(NT % 32 == 0 && 32 % KI == 0, "affine padded indices");
     const uint32_t na = i1 - i0, nb = j1 - j0, nt = na + nb;
-    for (uint32_t i = threadIdx.x; i < na; i += NT) {
-        S[i] = a[i0 + i];
-        if (VAL) SV[i] = va[i0 + i];
-    }
-    for (uint32_t i = threadIdx.x; i < nb; i += NT) {
-        S[na + i] = b[j0 + i];
-        if (VAL) SV[na + i] = vb[j0 + i];
-    }
-    __syncthreads();
-    const uint32_t d = threadIdx.x * KI;
-    if (d < nt) {
-        const K* A = S;
-        const K* B = S + na;
-        uint32_t ia = merge_path<K>(A, na, B, nb, d);
-        uint32_t jb = d - ia;
-        const uint32_t stop = min(nt, d + KI);
-        for (uint32_t o = d; o < stop; ++o) {
-            const bool takeA = ia < na && (jb >= nb || A[ia] <= B[jb]);
-            if (takeA) {
-                SO[o] = A[ia];
-                if (VAL) SOV[o] = SV[ia];
-                ++ia;
-            } else {
-                SO[o] = B[jb];
-                if (VAL) SOV[o] = SV[na + jb];
-                ++jb;
+    const uint32_t tid = threadIdx.x, pt = mpx(tid);
+    {
+        K r[KI];
+        uint32_t v[KI];
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+            const uint32_t e = (uint32_t)j * NT + tid;
+            r[j] = e < na ? a[i0 + e] : (e < nt ? b[j0 + e - na] : K(0));
+            if (VAL) v[j] = e < na ? va[i0 + e] : (e < nt ? vb[j0 + e - na] : 0u);
+        }
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+            const uint32_t e = (uint32_t)j * NT + tid, pe = pt + (uint32_t)j * (NT + NT / 32);
+            if (e < nt) {
+                S[pe] = r[j];
+                if (VAL) SV[pe] = v[j];
             }
         }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < nt; i += NT) {
-        out[i] = SO[i];
-        if (VAL) vout[i] = SOV[i];
+    const uint32_t d = tid * KI;
+    K rk[KI];
+    uint32_t rv[KI];
+    if (d < nt) {
+        uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (S[mpx(mid)] <= S[mpx(na + d - 1 - mid)]) lo = mid + 1; else hi = mid;
+        }
+        uint32_t pa = lo, pb = na + (d - lo);
+        K ha = S[mpx(pa)], hb = S[mpx(pb)];
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+            const bool takeA = pa < na && (pb >= nt || ha <= hb);
+            const uint32_t cur = takeA ? pa : pb;
+            rk[j] = takeA ? ha : hb;
+            if (VAL) rv[j] = SV[mpx(cur)];
+            const uint32_t nx = cur + 1;  // at most nt + KI: inside the slack
+            pa = takeA ? nx : pa;
+            pb = takeA ? pb : nx;
+            const K nv = S[mpx(nx)];
+            ha = takeA ? nv : ha;
+            hb = takeA ? hb : nv;
+        }
+    }
+    __syncthreads();
+    if (d < nt) {
+        const uint32_t w0 = mpx(d);  // the KI outputs share one padding block
+#pragma unroll
+        for (int j = 0; j < KI; ++j) {
+            if (d + j < nt) {
+                S[w0 + j] = rk[j];
+                if (VAL) SV[w0 + j] = rv[j];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < KI; ++j) {
+        const uint32_t e = (uint32_t)j * NT + tid, pe = pt + (uint32_t)j * (NT + NT / 32);
+        if (e < nt) {
+            out[e] = S[pe];
+            if (VAL) vout[e] = SV[pe];
+        }
     }
     __syncthreads();
 }
@@ -108,11 +154,10 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
                                                     uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB)
 {
     constexpr uint32_t TO = NT * KI;
+    constexpr uint32_t SP = MergeLds<TO>::SP;
     extern __shared__ __align__(16) uint8_t smem[];
     K* S = (K*)smem;
-    K* SO = S + TO;
-    uint32_t* SV = (uint32_t*)(SO + TO);
-    uint32_t* SOV = SV + (VAL ? TO : 0);
+    uint32_t* SV = (uint32_t*)(S + SP);
     for (uint32_t tile = blockIdx.x; tile < A.n_tiles_out; tile += gridDim.x) {
         for (uint32_t slot = 0; slot < 2; ++slot) {
             const uint32_t q = A.table[((uint64_t)A.level * A.n_tiles_out + tile) * 2 + slot];
@@ -132,7 +177,7 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
             const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
             merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid,
                                        VAL ? vsrc + Mid : nullptr, j0, j1, dst + o0,
-                                       VAL ? vdst + o0 : nullptr, S, SV, SO, SOV);
+                                       VAL ? vdst + o0 : nullptr, S, SV);
         }
     }
 }
@@ -142,7 +187,7 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
                                 hipStream_t s)
 {
     constexpr uint32_t TO = NT * KI;
-    constexpr size_t lds = 2 * sizeof(K) * TO + (VAL ? 2 * sizeof(uint32_t) * TO : 0);
+    constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
     static bool attr_set = false;
     if (!attr_set) {
         VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI>,
@@ -214,19 +259,17 @@ __global__ __launch_bounds__(NT) void k_merge2(const K* __restrict__ a, const ui
                                                uint32_t ntiles, const uint32_t* __restrict__ splits)
 {
     constexpr uint32_t TO = NT * KI;
+    constexpr uint32_t SP = MergeLds<TO>::SP;
     extern __shared__ __align__(16) uint8_t smem[];
     K* S = (K*)smem;
-    K* SO = S + TO;
-    uint32_t* SV = (uint32_t*)(SO + TO);
-    uint32_t* SOV = SV + (VAL ? TO : 0);
+    uint32_t* SV = (uint32_t*)(S + SP);
     const uint64_t ntot = (uint64_t)na + nb;
     for (uint32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const uint64_t o0 = (uint64_t)tile * TO;
         const uint64_t o1 = o0 + TO < ntot ? o0 + TO : ntot;
         const uint32_t i0 = splits[tile], i1 = splits[tile + 1];
         const uint32_t j0 = (uint32_t)(o0 - i0), j1 = (uint32_t)(o1 - i1);
-        merge_tile<K, VAL, NT, KI>(a, va, i0, i1, b, vb, j0, j1, out + o0, VAL ? vout + o0 : nullptr, S, SV, SO,
-                                   SOV);
+        merge_tile<K, VAL, NT, KI>(a, va, i0, i1, b, vb, j0, j1, out + o0, VAL ? vout + o0 : nullptr, S, SV);
     }
 }
 
@@ -236,7 +279,7 @@ static hipError_t merge2_t(const K* a, const uint32_t* va, uint32_t na, const K*
 {
     constexpr int NT = 256, KI = 16;
     constexpr uint32_t TO = NT * KI;
-    constexpr size_t lds = 2 * sizeof(K) * TO + (VAL ? 2 * sizeof(uint32_t) * TO : 0);
+    constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
     static bool attr_set = false;
     if (!attr_set) {
         VMPS_HIP(hipFuncSetAttribute((const void*)k_merge2<K, VAL, NT, KI>, hipFuncAttributeMaxDynamicSharedMemorySize,

@@ -51,6 +51,8 @@ def _L():
         build()
         lib = ctypes.CDLL(_LIB_PATH)
         i64, i32, u64, vp, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_double
+        lib.orc_adam_update.restype = None
+        lib.orc_adam_update.argtypes = [vp, vp, vp, vp, i32, i64, dbl]
         lib.orc_minrun.restype = i32
         lib.orc_minrun.argtypes = [i64]
         lib.orc_power_def.restype = i32
@@ -313,6 +315,13 @@ def cdf_init(u, H: int) -> dict:
     _L().orc_cdf_init(_p(u), u.size, H, _p(p), p[H:].ctypes.data, p[2 * H:].ctypes.data, ctypes.byref(b2))
     p[3 * H] = b2.value
     return _unpack(p, H)
+
+
+def adam_update(p, g, m1, m2, step: int, lr: float):
+    """One Adam step on fp64 arrays, in place (p, m1, m2 are updated)."""
+    for a in (p, g, m1, m2):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    _L().orc_adam_update(_p(p), _p(g), _p(m1), _p(m2), p.size, step, lr)
 
 
 def cdf_loss(params: dict, u, stride: int = 64) -> float:

@@ -300,3 +300,21 @@ def test_plan_depth_perfect_tree(orc):
     assert np.array_equal(depth, P.astype(np.int32) - 1)
     assert M == 8 * n and Mh == 3 * n
     assert segs.shape[0] == n // 1024 and np.all(segs[:, 2] == 1)
+
+
+def test_segmented_equals_per_segment_library_sort(orc):
+    # each segment is an independent stable sort (library special case),
+    # values record the original positions
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        nseg = int(rng.integers(1, 40))
+        lens = rng.integers(0, 400, size=nseg)
+        off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        n = int(off[-1])
+        keys = rng.integers(0, 7 if trial % 2 else 2**63, size=n, dtype=np.uint64)
+        out, v = orc.segmented_powersort(keys, off, np.arange(n, dtype=np.uint32))[:2]
+        for s in range(nseg):
+            a, b = off[s], off[s + 1]
+            order = np.argsort(keys[a:b], kind="stable") + a
+            assert out[a:b].tolist() == keys[order].tolist()
+            assert v[a:b].tolist() == order.tolist()

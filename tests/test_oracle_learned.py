@@ -151,3 +151,24 @@ def test_training_does_not_increase_loss(orc):
     l0 = orc.cdf_loss(p0, u)
     p1, l1 = orc.cdf_train(u, 32, 64, 1024, 1e-4)
     assert l1 <= l0
+
+
+def test_adam_first_steps_closed_form(orc):
+    # Adam (Kingma and Ba): the bias-corrected first step moves every
+    # parameter by lr * g / (|g| + eps), i.e. almost exactly lr against the
+    # sign of its gradient; a second step with the same gradient does the
+    # same again (both moment estimates stay g and g^2 after correction).
+    rng = np.random.default_rng(3)
+    g = rng.normal(size=9) * 10.0 ** rng.integers(-3, 3, size=9)
+    g[0] = 0.0
+    p = rng.normal(size=9)
+    p0 = p.copy()
+    m1 = np.zeros(9)
+    m2 = np.zeros(9)
+    lr = 1e-3
+    orc.adam_update(p, g, m1, m2, 1, lr)
+    step = lr * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p0 - p, step, rtol=1e-12, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(m2, 0.001 * g * g)
+    orc.adam_update(p, g, m1, m2, 2, lr)
+    assert np.allclose(p0 - p, 2 * step, rtol=1e-9, atol=1e-15)

@@ -92,10 +92,12 @@ def run_path(vm, path, keys, pristine, steps, warmup):
     trace = vm.trace_collect()
     ms = [a.elapsed_time(b) for a, b in ev]
     assert is_sorted_u64(keys), f"{path}: output not sorted"
+    MEDIAN[path] = float(np.median(ms))
     return float(np.mean(ms)), trace
 
 
 WS = [None]
+MEDIAN = {}
 
 
 def main():
@@ -156,8 +158,15 @@ def main():
     m_hbm = m_hbm_plain if args.path == "plain" else 0
     bytes_per_sort = kernel_bytes(args.path, dom, n, 8, 0, m_hbm, cfg.sample_size)
     achieved = bytes_per_sort * args.steps / (dom_ms / 1e3) / 1e9
+    # HBM bytes per launch measured by rocprofv3 counters for this kernel, while
+    # its source is unchanged since they were taken
+    from paper_2605_27147_amd import profiling
+    tfile = os.path.join(ROOT, "profiles", f"traffic_{args.path}_lognormal64_2p{args.log2n}_{dom}.json")
+    tr = profiling.load_traffic(tfile)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(tr["traffic_bytes_per_launch"]) if tr else None,
+                "traffic_source": os.path.relpath(tfile, ROOT) if tr else None, "kernel": dom,
                 "avg_launch_ms": round(dom_ms / dom_launches, 4),
                 "launches_per_step": dom_launches / args.steps,
                 "bytes_per_launch": bytes_per_sort * args.steps / dom_launches}
@@ -177,7 +186,8 @@ def main():
         cfgd.update({"merge_cost": sch["merge_cost"], "merge_cost_hbm": m_hbm_plain, "runs": sch["runs"]})
     out = {
         "metric": METRIC, "value": round(value, 4), "unit": "Gkeys/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "scaling": "weak",
+        "warmup": args.warmup, "ms_per_step": round(ms, 4), "ms_per_step_median": round(MEDIAN[args.path], 4),
+        "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic", "config": cfgd, "roofline": roofline,
         "path_roofline": {"bytes_per_step": path_bytes, "achieved_GBs": round(path_bytes / (ms / 1e3) / 1e9, 1),
                           "frac": round(path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},

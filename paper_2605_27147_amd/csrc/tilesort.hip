@@ -17,7 +17,7 @@
 // outputs [i*KI, (i+1)*KI), computes them into registers, and writes them
 // back into the single LDS buffer after a barrier.  The segment is written
 // once, to the buffer the planner chose (Pingpong).
-#include "vmps_internal.hpp"
+#include "merge_tile.hpp"
 
 namespace vmps {
 
@@ -341,14 +341,12 @@ __device__ __forceinline__ void tile_store(const K* __restrict__ S, const uint32
     }
 }
 
-// MINW: waves per SIMD that the LDS footprint lets run at once, which
-// bounds the registers a wave may use.
-template <typename K, int NT, int TCAP, int VMODE, int MINW>
-__global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
-                                                 uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
-                                                 const Seg* __restrict__ segs,
-                                                 const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
-                                                 const uint32_t* __restrict__ inst_start)
+// One segment of the LDS pass, by all NT threads of the calling workgroup.
+// smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.
+template <typename K, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
+                                             uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
+                                             const Seg sg, const uint32_t* __restrict__ inst_start)
 {
     using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
@@ -360,7 +358,6 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     // fewer than TCAP / 32 boundaries
     static_assert(TCAP / 32 <= 64 * NW, "one thread per boundary in the power ranking");
 
-    extern __shared__ __align__(16) uint8_t smem[];
     uint8_t* sp = smem;
     K* S = (K*)sp; sp += sizeof(K) * MT::SP;
     uint32_t* SV = nullptr;
@@ -387,241 +384,251 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     uint32_t* BL = R2;
     uint32_t* BR = R2 + RC + 1;
 
-    const uint32_t nseg = nseg_dev ? *nseg_dev : nseg_host;
-
-    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x) {
-        // the thread index is made opaque per segment so that the compiler
-        // does not keep every unrolled address live across the whole loop
-        int tid = threadIdx.x;
-        asm volatile("" : "+v"(tid));
-        const int lane = tid & 63, wave = tid >> 6;
-        const Seg sg = segs[si];
-        const uint32_t a = sg.start;
-        const uint32_t len = sg.end - sg.start;
-        if (len == 0) continue;
-        if (len > TCAP) {
-            // a single natural run longer than the tile: already sorted
-            if (sg.dst == 1) {
-                for (uint32_t i = tid; i < len; i += NT) {
-                    keysB[a + i] = keysA[a + i];
-                    if (VMODE == 1) valsB[a + i] = valsA[a + i];
-                    if (VMODE == 2) valsB[a + i] = a + i;
-                }
-            } else if (VMODE == 2) {
-                for (uint32_t i = tid; i < len; i += NT) valsA[a + i] = a + i;
+    // the thread index is made opaque per segment so that the compiler
+    // does not keep every unrolled address live across the whole loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint32_t a = sg.start;
+    const uint32_t len = sg.end - sg.start;
+    if (len == 0) return;
+    if (len > TCAP) {
+        // a single natural run longer than the tile: already sorted
+        if (sg.dst == 1) {
+            for (uint32_t i = tid; i < len; i += NT) {
+                keysB[a + i] = keysA[a + i];
+                if (VMODE == 1) valsB[a + i] = valsA[a + i];
+                if (VMODE == 2) valsB[a + i] = a + i;
             }
-            continue;
+        } else if (VMODE == 2) {
+            for (uint32_t i = tid; i < len; i += NT) valsA[a + i] = a + i;
         }
-        const uint32_t ib = inst_start[sg.inst];
-        const uint32_t il = inst_start[sg.inst + 1] - ib;
-        const uint32_t ell = minrun_of(il);
-        const uint32_t g = a - ib;
+        return;
+    }
+    const uint32_t ib = inst_start[sg.inst];
+    const uint32_t il = inst_start[sg.inst + 1] - ib;
+    const uint32_t ell = minrun_of(il);
+    const uint32_t g = a - ib;
 
-        // 1. load
-        tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
-        if (tid < 16) scal[tid] = 0;
-        __syncthreads();
+    // 1. load
+    tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
+    if (tid < 16) scal[tid] = 0;
+    __syncthreads();
 
-        // 2. descent bitmap (positions >= len count as boundaries)
-        const uint32_t W = len / 64 + 1;
-        for (uint32_t w = wave; w < W; w += NW) {
-            const uint32_t p = w * 64 + lane;
-            const bool bit = (p >= len) || (p == 0) || (S[px(p - 1)] > S[px(p)]);
-            const uint64_t word = __ballot(bit);
-            if (lane == 0) bm[w] = word;
-        }
-        __syncthreads();
+    // 2. descent bitmap (positions >= len count as boundaries)
+    const uint32_t W = len / 64 + 1;
+    for (uint32_t w = wave; w < W; w += NW) {
+        const uint32_t p = w * 64 + lane;
+        const bool bit = (p >= len) || (p == 0) || (S[px(p - 1)] > S[px(p)]);
+        const uint64_t word = __ballot(bit);
+        if (lane == 0) bm[w] = word;
+    }
+    __syncthreads();
 
-        // 3. long natural runs (length >= minrun), one thread per word
-        uint32_t cnt = 0, lu0 = 0, le0 = 0, lu1 = 0, le1 = 0;
-        if ((uint32_t)tid < W) {
-            const uint64_t word = bm[tid];
-            const uint32_t p0 = tid * 64;
-            // a long run starting at bit b has no boundary in (b, b+31]:
-            // only such bits are examined
-            uint64_t o = word >> 1;
-            o |= o >> 1;
-            o |= o >> 2;
-            o |= o >> 4;
-            o |= o >> 8;
-            o |= o >> 15;
-            uint64_t bits = word & ~o;
-            while (bits) {
-                const int b = ffs64(bits);
-                bits &= bits - 1;
-                const uint32_t u = p0 + b;
-                if (u >= len) break;
-                const uint64_t above = (b == 63) ? 0ull : ((word >> (b + 1)) << (b + 1));
-                uint32_t next = len;
-                if (above) {
-                    next = p0 + ffs64(above);
-                } else {
-                    for (uint32_t ww = tid + 1; ww < W; ++ww) {
-                        const uint64_t x = bm[ww];
-                        if (x) { next = ww * 64 + ffs64(x); break; }
-                    }
-                }
-                if (next > len) next = len;
-                if (next - u >= ell) {
-                    if (cnt == 0) { lu0 = u; le0 = next; } else { lu1 = u; le1 = next; }
-                    ++cnt;
+    // 3. long natural runs (length >= minrun), one thread per word
+    uint32_t cnt = 0, lu0 = 0, le0 = 0, lu1 = 0, le1 = 0;
+    if ((uint32_t)tid < W) {
+        const uint64_t word = bm[tid];
+        const uint32_t p0 = tid * 64;
+        // a long run starting at bit b has no boundary in (b, b+31]:
+        // only such bits are examined
+        uint64_t o = word >> 1;
+        o |= o >> 1;
+        o |= o >> 2;
+        o |= o >> 4;
+        o |= o >> 8;
+        o |= o >> 15;
+        uint64_t bits = word & ~o;
+        while (bits) {
+            const int b = ffs64(bits);
+            bits &= bits - 1;
+            const uint32_t u = p0 + b;
+            if (u >= len) break;
+            const uint64_t above = (b == 63) ? 0ull : ((word >> (b + 1)) << (b + 1));
+            uint32_t next = len;
+            if (above) {
+                next = p0 + ffs64(above);
+            } else {
+                for (uint32_t ww = tid + 1; ww < W; ++ww) {
+                    const uint64_t x = bm[ww];
+                    if (x) { next = ww * 64 + ffs64(x); break; }
                 }
             }
+            if (next > len) next = len;
+            if (next - u >= ell) {
+                if (cnt == 0) { lu0 = u; le0 = next; } else { lu1 = u; le1 = next; }
+                ++cnt;
+            }
         }
-        if (cnt > 2) cnt = 2;  // runs of >= 32 elements: at most two start in a word
-        uint32_t nlr;
-        const uint32_t lro = block_excl_scan(cnt, scan_lds, &nlr);
-        if (cnt > 0) { LRu[lro] = lu0; LRe[lro] = le0; }
-        if (cnt > 1) { LRu[lro + 1] = lu1; LRe[lro + 1] = le1; }
-        __syncthreads();
+    }
+    if (cnt > 2) cnt = 2;  // runs of >= 32 elements: at most two start in a word
+    uint32_t nlr;
+    const uint32_t lro = block_excl_scan(cnt, scan_lds, &nlr);
+    if (cnt > 0) { LRu[lro] = lu0; LRe[lro] = le0; }
+    if (cnt > 1) { LRu[lro + 1] = lu1; LRe[lro + 1] = le1; }
+    __syncthreads();
 
-        // 4. chain of run starts: progressions of step minrun between jumps
-        if (tid == 0) {
-            uint32_t r = 0, np = 0, acc = 0;
-            for (uint32_t j = 0; j < nlr; ++j) {
-                const uint32_t u = LRu[j], e = LRe[j];
-                const uint32_t sf = u + ((r % ell) + ell - u % ell) % ell;
-                if (e - sf >= ell) {
-                    PGb[np] = r; PGc[np] = acc;
-                    acc += (sf - r) / ell + 1;
-                    ++np;
-                    r = e;
-                }
+    // 4. chain of run starts: progressions of step minrun between jumps
+    if (tid == 0) {
+        uint32_t r = 0, np = 0, acc = 0;
+        for (uint32_t j = 0; j < nlr; ++j) {
+            const uint32_t u = LRu[j], e = LRe[j];
+            const uint32_t sf = u + ((r % ell) + ell - u % ell) % ell;
+            if (e - sf >= ell) {
+                PGb[np] = r; PGc[np] = acc;
+                acc += (sf - r) / ell + 1;
+                ++np;
+                r = e;
             }
-            PGb[np] = r; PGc[np] = acc;
-            acc += (r < len) ? (len - r + ell - 1) / ell : 0u;
-            ++np;
-            PGc[np] = acc;
-            scal[0] = np;
-            scal[1] = acc < RC - 1 ? acc : RC - 1;  // runs >= 32 long: never clamps
         }
-        __syncthreads();
-        const uint32_t np = scal[0], kr = scal[1];
+        PGb[np] = r; PGc[np] = acc;
+        acc += (r < len) ? (len - r + ell - 1) / ell : 0u;
+        ++np;
+        PGc[np] = acc;
+        scal[0] = np;
+        scal[1] = acc < RC - 1 ? acc : RC - 1;  // runs >= 32 long: never clamps
+    }
+    __syncthreads();
+    const uint32_t np = scal[0], kr = scal[1];
 
-        // 5. run starts
-        for (uint32_t t = tid; t < kr; t += NT) {
-            uint32_t lo = 0, hi = np;
-            while (hi - lo > 1) {
-                const uint32_t m = (lo + hi) >> 1;
-                if (PGc[m] <= t) lo = m; else hi = m;
-            }
-            RS[t] = PGb[lo] + (t - PGc[lo]) * ell;
+    // 5. run starts
+    for (uint32_t t = tid; t < kr; t += NT) {
+        uint32_t lo = 0, hi = np;
+        while (hi - lo > 1) {
+            const uint32_t m = (lo + hi) >> 1;
+            if (PGc[m] <= t) lo = m; else hi = m;
         }
-        if (tid == 0) RS[kr] = len;
-        __syncthreads();
+        RS[t] = PGb[lo] + (t - PGc[lo]) * ell;
+    }
+    if (tid == 0) RS[kr] = len;
+    __syncthreads();
 
-        // 6. sorted-run flags, midpoint expansions and powers
-        uint32_t unsorted_max = 0, pmask = 0;
-        for (uint32_t t = tid; t < kr; t += NT) {
-            const uint32_t s = RS[t], e = RS[t + 1];
-            bool sorted = true;  // no descent strictly inside (s, e)
-            if (s + 1 < e) {
-                for (uint32_t w = (s + 1) >> 6; w <= ((e - 1) >> 6); ++w) {
-                    uint64_t word = bm[w];
-                    const uint32_t base = w * 64;
-                    if (s + 1 > base) word &= ~0ull << (s + 1 - base);
-                    if (e - base < 64) word &= (1ull << (e - base)) - 1;
-                    if (word) { sorted = false; break; }
-                }
+    // 6. sorted-run flags, midpoint expansions and powers
+    uint32_t unsorted_max = 0, pmask = 0;
+    for (uint32_t t = tid; t < kr; t += NT) {
+        const uint32_t s = RS[t], e = RS[t + 1];
+        bool sorted = true;  // no descent strictly inside (s, e)
+        if (s + 1 < e) {
+            for (uint32_t w = (s + 1) >> 6; w <= ((e - 1) >> 6); ++w) {
+                uint64_t word = bm[w];
+                const uint32_t base = w * 64;
+                if (s + 1 > base) word &= ~0ull << (s + 1 - base);
+                if (e - base < 64) word &= (1ull << (e - base)) - 1;
+                if (word) { sorted = false; break; }
             }
-            SR[t] = sorted ? 1 : 0;
-            if (!sorted) unsorted_max = max(unsorted_max, e - s);
-            const uint64_t s2 = 2ull * g + s + e;
-            Qv[t] = (uint32_t)((s2 << 31) / il);
         }
-        unsorted_max = wave_max(unsorted_max);
-        if (lane == 0 && unsorted_max) atomicMax(&scal[3], unsorted_max);
-        __syncthreads();
-        for (uint32_t t = tid; t + 1 < kr; t += NT) {
-            const uint32_t p = __clz(Qv[t] ^ Qv[t + 1]) + 1;
-            PW[t] = (uint8_t)p;
-            pmask |= 1u << (p - 1);
+        SR[t] = sorted ? 1 : 0;
+        if (!sorted) unsorted_max = max(unsorted_max, e - s);
+        const uint64_t s2 = 2ull * g + s + e;
+        Qv[t] = (uint32_t)((s2 << 31) / il);
+    }
+    unsorted_max = wave_max(unsorted_max);
+    if (lane == 0 && unsorted_max) atomicMax(&scal[3], unsorted_max);
+    __syncthreads();
+    for (uint32_t t = tid; t + 1 < kr; t += NT) {
+        const uint32_t p = __clz(Qv[t] ^ Qv[t + 1]) + 1;
+        PW[t] = (uint8_t)p;
+        pmask |= 1u << (p - 1);
+    }
+    pmask = wave_or(pmask);
+    if (lane == 0 && pmask) atomicOr(&scal[2], pmask);
+    __syncthreads();
+    // node extents: nearest boundaries of smaller power inside the segment
+    for (uint32_t t = tid; t + 1 < kr; t += NT) {
+        const uint32_t p = PW[t], sh = 32 - p;
+        const uint64_t c = (uint64_t)Qv[t + 1] >> sh;
+        const uint64_t V = (c - 1) << sh, Wd = (c + 1) << sh;
+        int lo = -1, hi = (int)t;
+        while (hi - lo > 1) {
+            const int m = (lo + hi) >> 1;
+            if (Qv[m] < V) lo = m; else hi = m;
         }
-        pmask = wave_or(pmask);
-        if (lane == 0 && pmask) atomicOr(&scal[2], pmask);
-        __syncthreads();
-        // node extents: nearest boundaries of smaller power inside the segment
-        for (uint32_t t = tid; t + 1 < kr; t += NT) {
-            const uint32_t p = PW[t], sh = 32 - p;
-            const uint64_t c = (uint64_t)Qv[t + 1] >> sh;
-            const uint64_t V = (c - 1) << sh, Wd = (c + 1) << sh;
-            int lo = -1, hi = (int)t;
-            while (hi - lo > 1) {
-                const int m = (lo + hi) >> 1;
-                if (Qv[m] < V) lo = m; else hi = m;
-            }
-            BL[t] = lo < 0 ? 0u : RS[lo + 1];
-            int lo2 = (int)t + 1, hi2 = (int)kr;
-            while (hi2 - lo2 > 1) {
-                const int m = (lo2 + hi2) >> 1;
-                if (Qv[m] < Wd) lo2 = m; else hi2 = m;
-            }
-            BR[t] = (lo2 == (int)kr - 1) ? len : RS[lo2 + 1];
+        BL[t] = lo < 0 ? 0u : RS[lo + 1];
+        int lo2 = (int)t + 1, hi2 = (int)kr;
+        while (hi2 - lo2 > 1) {
+            const int m = (lo2 + hi2) >> 1;
+            if (Qv[m] < Wd) lo2 = m; else hi2 = m;
         }
-        // node list: boundaries ordered by (power descending, position), one
-        // thread per boundary, ranks from wave ballots on the power value
-        {
-            const uint32_t t = tid;
-            const bool valid = t + 1 < kr;
-            const uint32_t p = valid ? PW[t] : 0u;
-            uint64_t peers = __ballot(valid);
+        BR[t] = (lo2 == (int)kr - 1) ? len : RS[lo2 + 1];
+    }
+    // node list: boundaries ordered by (power descending, position), one
+    // thread per boundary, ranks from wave ballots on the power value
+    {
+        const uint32_t t = tid;
+        const bool valid = t + 1 < kr;
+        const uint32_t p = valid ? PW[t] : 0u;
+        uint64_t peers = __ballot(valid);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) {
-                const bool bit = (p >> k) & 1u;
-                const uint64_t bk = __ballot(bit);
-                peers &= bit ? bk : ~bk;
-            }
-            const uint32_t rw = __popcll(peers & ((1ull << lane) - 1));
-            if (lane < 33) wcnt[wave * 33 + lane] = 0;
-            __syncthreads();
-            if (valid && rw == 0) wcnt[wave * 33 + p] = __popcll(peers);
-            __syncthreads();
-            if (tid <= 32) {
-                uint32_t tot = 0;
-                for (int w = 0; w < NW; ++w) tot += wcnt[w * 33 + tid];
-                LVc[tid] = tot;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                uint32_t acc = 0;
-                for (int q = 32; q >= 1; --q) { LVs[q] = acc; acc += LVc[q]; }
-            }
-            __syncthreads();
-            if (valid) {
-                uint32_t r = LVs[p] + rw;
-                for (int w = 0; w < wave; ++w) r += wcnt[w * 33 + p];
-                NL[r] = t;
-                BLs[r] = BL[t];
-            }
+        for (int k = 0; k < 6; ++k) {
+            const bool bit = (p >> k) & 1u;
+            const uint64_t bk = __ballot(bit);
+            peers &= bit ? bk : ~bk;
+        }
+        const uint32_t rw = __popcll(peers & ((1ull << lane) - 1));
+        if (lane < 33) wcnt[wave * 33 + lane] = 0;
+        __syncthreads();
+        if (valid && rw == 0) wcnt[wave * 33 + p] = __popcll(peers);
+        __syncthreads();
+        if (tid <= 32) {
+            uint32_t tot = 0;
+            for (int w = 0; w < NW; ++w) tot += wcnt[w * 33 + tid];
+            LVc[tid] = tot;
         }
         __syncthreads();
-
-        // 7./8. forced runs, then the merges of Algorithm 1; segments up to
-        // half the tile use half the outputs per thread, so every thread works
-        const uint32_t maxf = scal[3], mask = scal[2];
-        // 7a. the first four bottom-up levels of every forced run: 16-element
-        // chunks from the run start, sorted in registers (unsorted runs are
-        // forced runs, shorter than 64)
-        if (maxf > 1) {
-            const uint32_t cpr = (maxf + 15) >> 4;
-            for (uint32_t x = tid; x < cpr * kr; x += NT) {
-                const uint32_t r = x / cpr, c = x - r * cpr;
-                const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
-                if (!SR[r] && cs + 1 < ce) chunk_sort16<K, VMODE>(S, SV, cs, min(16u, ce - cs));
-            }
-            __syncthreads();
+        if (tid == 0) {
+            uint32_t acc = 0;
+            for (int q = 32; q >= 1; --q) { LVs[q] = acc; acc += LVc[q]; }
         }
-        if (len <= (uint32_t)(NT * (KI / 2)))
-            tile_merges<K, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
-        else
-            tile_merges<K, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        __syncthreads();
+        if (valid) {
+            uint32_t r = LVs[p] + rw;
+            for (int w = 0; w < wave; ++w) r += wcnt[w * 33 + p];
+            NL[r] = t;
+            BLs[r] = BL[t];
+        }
+    }
+    __syncthreads();
 
-        // 9. one write to the planned buffer
-        int tid_st = tid;
-        asm volatile("" : "+v"(tid_st));
-        tile_store<K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st);
+    // 7./8. forced runs, then the merges of Algorithm 1; segments up to
+    // half the tile use half the outputs per thread, so every thread works
+    const uint32_t maxf = scal[3], mask = scal[2];
+    // 7a. the first four bottom-up levels of every forced run: 16-element
+    // chunks from the run start, sorted in registers (unsorted runs are
+    // forced runs, shorter than 64)
+    if (maxf > 1) {
+        const uint32_t cpr = (maxf + 15) >> 4;
+        for (uint32_t x = tid; x < cpr * kr; x += NT) {
+            const uint32_t r = x / cpr, c = x - r * cpr;
+            const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
+            if (!SR[r] && cs + 1 < ce) chunk_sort16<K, VMODE>(S, SV, cs, min(16u, ce - cs));
+        }
         __syncthreads();
     }
+    if (len <= (uint32_t)(NT * (KI / 2)))
+        tile_merges<K, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+    else
+        tile_merges<K, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+
+    // 9. one write to the planned buffer
+    int tid_st = tid;
+    asm volatile("" : "+v"(tid_st));
+    tile_store<K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st);
+    __syncthreads();
+}
+
+// MINW: waves per SIMD that the LDS footprint lets run at once, which
+// bounds the registers a wave may use.
+template <typename K, int NT, int TCAP, int VMODE, int MINW>
+__global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
+                                                       uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
+                                                       const Seg* __restrict__ segs,
+                                                       const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
+                                                       const uint32_t* __restrict__ inst_start)
+{
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t nseg = nseg_dev ? *nseg_dev : nseg_host;
+    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x)
+        tile_segment<K, NT, TCAP, VMODE>(smem, keysA, keysB, valsA, valsB, segs[si], inst_start);
 }
 
 // ------------------------------------------------------------- host --

@@ -1,0 +1,160 @@
+"""Summaries of rocprofv3 runs for the profiles/ directory.
+
+    python -m paper_2605_27147_amd.profiling stats   DIR OUT.txt --title T --command C
+    python -m paper_2605_27147_amd.profiling traffic FETCH_DIR WRITE_DIR OUT.json --kind K --copy-bytes N
+        [--command C ...]
+
+`stats` turns a `rocprofv3 --kernel-trace --stats --output-format csv` output
+directory into a short text table (kernel, calls, total ms, average us, %).
+
+`traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
+the same command into HBM bytes per launch of one kernel kind.  Both counters
+are scaled by what they report for a device copy of known size in the same
+run (the runtime's copy kernel): the copy reads and writes N bytes each.  The
+JSON records the SHA-256 of the kernel's source files, so a reader can tell
+whether the kernel has changed since the counters were taken.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+
+# kernel kind (as traced by the library) -> (kernel name pattern, source files)
+KINDS = {
+    "tilesort": (r"k_tilesort<", ["tilesort.hip", "vmps_internal.hpp"]),
+    "level_merge": (r"k_level_merge<", ["merge.hip", "vmps_internal.hpp"]),
+    "level_partition": (r"k_level_partition<", ["merge.hip", "vmps_internal.hpp"]),
+    "scatter": (r"k_part_scatter<", ["learned.hip", "vmps_internal.hpp"]),
+    "histogram": (r"k_part_hist<", ["learned.hip", "vmps_internal.hpp"]),
+    "train": (r"k_cdf_train<", ["learned.hip", "vmps_internal.hpp"]),
+}
+COPY_PATTERN = r"copyBuffer"
+
+
+def source_hashes(kind: str) -> dict:
+    out = {}
+    for f in KINDS[kind][1]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            out[f] = hashlib.sha256(fh.read()).hexdigest()
+    return out
+
+
+def _one(pattern: str) -> str:
+    hits = sorted(glob.glob(pattern, recursive=True))
+    if not hits:
+        raise FileNotFoundError(pattern)
+    return hits[0]
+
+
+def _short(name: str) -> str:
+    name = re.sub(r"\(.*", "", name).replace("void ", "")
+    return name.replace("unsigned long", "u64").replace("unsigned int", "u32")
+
+
+def stats(directory: str, out: str, title: str, command: str) -> None:
+    path = _one(os.path.join(directory, "**", "*kernel_stats.csv"))
+    rows = list(csv.DictReader(open(path)))
+    lines = [f"# rocprofv3 kernel stats: {title}", f"# command (repo root): {command}",
+             "# kernel | calls | total_ms | average_us | percent"]
+    for r in rows[:40]:
+        lines.append(f"{_short(r['Name'])[:110]} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f}")
+    with open(out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _counters(directory: str, counter: str) -> list:
+    path = _one(os.path.join(directory, "**", "*counter_collection.csv"))
+    per = {}
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
+            continue
+        d = per.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"], "kib": 0.0})
+        d["kib"] += float(r["Counter_Value"])
+    return list(per.values())
+
+
+def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int, commands: list) -> dict:
+    pat = re.compile(KINDS[kind][0])
+    fetch = _counters(fetch_dir, "FETCH_SIZE")
+    write = _counters(write_dir, "WRITE_SIZE")
+
+    def avg(recs, p):
+        v = [r["kib"] * 1024.0 for r in recs if p.search(r["name"])]
+        if not v:
+            raise ValueError(f"no dispatch matches {p.pattern}")
+        return sum(v) / len(v), len(v)
+
+    copy = re.compile(COPY_PATTERN)
+    cf, _ = avg(fetch, copy)
+    cw, _ = avg(write, copy)
+    sf, sw = copy_bytes / cf, copy_bytes / cw
+    f, nf = avg(fetch, pat)
+    w, nw = avg(write, pat)
+    res = {
+        "kind": kind,
+        "kernel_pattern": KINDS[kind][0],
+        "launches_counted": [nf, nw],
+        "fetch_bytes_per_launch": f * sf,
+        "write_bytes_per_launch": w * sw,
+        "traffic_bytes_per_launch": f * sf + w * sw,
+        "scale_fetch": sf,
+        "scale_write": sw,
+        "calibration": f"device copy of {copy_bytes} bytes: FETCH_SIZE x{sf:.3f}, WRITE_SIZE x{sw:.3f}",
+        "sources": source_hashes(kind),
+        "commands": commands,
+    }
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    return res
+
+
+def load_traffic(path: str):
+    """Bytes per launch from a traffic JSON, or None when the kernel's source
+    has changed since the counters were taken (or the file is missing)."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+        if t["sources"] != source_hashes(t["kind"]):
+            return None
+        return t
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(prog="python -m paper_2605_27147_amd.profiling")
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("out")
+    s.add_argument("--title", required=True)
+    s.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("out")
+    t.add_argument("--kind", required=True, choices=sorted(KINDS))
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command", action="append", default=[])
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        stats(a.dir, a.out, a.title, a.command)
+    else:
+        r = traffic(a.fetch_dir, a.write_dir, a.out, a.kind, a.copy_bytes, a.command)
+        print(json.dumps({k: r[k] for k in ("kind", "traffic_bytes_per_launch", "calibration")}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -250,6 +250,45 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
                            uint32_t* vals_out, int64_t* bucket_offsets, void* ws, size_t ws_bytes,
                            void* stream);
 
+/* ---- launch parameters (autotuning) ----
+ * Parameters that change how the work is spread over the GPU, never the
+ * result.  One table entry per key type and with/without values, shared by
+ * every later call in the process (set it before sorting; not for use
+ * concurrently with sorts).  A zero field keeps the built-in default. */
+typedef struct {
+    int32_t tile_wg_per_cu; /* workgroups per CU in the persistent LDS pass
+                               (0: as many as LDS and registers allow) */
+    int32_t merge_grid;     /* workgroups of one HBM merge level (0: 2048) */
+    int32_t bucket_div;     /* learned path: buckets of about T/bucket_div
+                               keys, T the LDS tile (0: 2) */
+    int32_t reserved;       /* must be 0 */
+} vmps_tuning;
+
+/* t == NULL restores the defaults.  Negative fields, bucket_div > 64 or a
+ * non-zero reserved field -> INVALID_ARG. */
+vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t);
+vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t);
+
+/* ---- graph capture ----
+ * The whole enqueue sequence of one call captured into a HIP graph (on a
+ * private capture stream, with launch tracing suspended), so that the same
+ * sort of the same buffers can be replayed with one launch.  The buffers,
+ * sizes and workspace are bound at capture time and must stay allocated
+ * until vmps_graph_destroy; each replay sorts whatever the buffers then
+ * hold.  Nothing is executed by the capture itself.  Argument errors are
+ * those of the captured call. */
+typedef struct vmps_graph_s* vmps_graph;
+
+vmps_status vmps_segmented_sort_graph(void* keys, uint32_t* values, const int64_t* seg_offsets, int64_t nseg,
+                                      int64_t total, vmps_dtype kt, void* ws, size_t ws_bytes,
+                                      vmps_graph* graph);
+vmps_status vmps_sort_learned_graph(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                                    const vmps_learned_config* cfg, vmps_learned_stats* stats, void* ws,
+                                    size_t ws_bytes, vmps_graph* graph);
+/* Replays a captured graph on `stream` (asynchronous). */
+vmps_status vmps_graph_launch(vmps_graph graph, void* stream);
+vmps_status vmps_graph_destroy(vmps_graph graph);
+
 /* ---- launch timing (instrumentation) ----
  * When enabled, the library brackets its hot launches with HIP events on
  * the caller's stream.  vmps_trace_collect() waits for those events and

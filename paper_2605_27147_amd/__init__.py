@@ -11,6 +11,7 @@ torch.int64/uint64 (unsigned 64-bit), contiguous, on the current device.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 
 __all__ = [
@@ -45,6 +46,11 @@ class CdfModel(ctypes.Structure):
                 ("b1", ctypes.c_float * CDF_MAX_HIDDEN), ("w2", ctypes.c_float * CDF_MAX_HIDDEN),
                 ("b2", ctypes.c_float), ("reserved", ctypes.c_float),
                 ("table", ctypes.c_uint64 * (CDF_MAX_KNOTS + 1))]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
+                ("bucket_div", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class LearnedStats(ctypes.Structure):
@@ -97,6 +103,13 @@ def load_library():
         "vmps_bucket_ids": (st, [vp, i64, st, vp, i32, vp, vp]),
         "vmps_partition_workspace_size": (st, [i64, st, st, i32, ctypes.POINTER(sz)]),
         "vmps_partition": (st, [vp, vp, i64, st, vp, i32, vp, vp, vp, vp, sz, vp]),
+        "vmps_set_tuning": (st, [st, st, ctypes.POINTER(Tuning)]),
+        "vmps_get_tuning": (st, [st, st, ctypes.POINTER(Tuning)]),
+        "vmps_segmented_sort_graph": (st, [vp, vp, vp, i64, i64, st, vp, sz, ctypes.POINTER(vp)]),
+        "vmps_sort_learned_graph": (st, [vp, vp, i64, st, u32, ctypes.POINTER(LearnedConfig), vp, vp, sz,
+                                         ctypes.POINTER(vp)]),
+        "vmps_graph_launch": (st, [vp, vp]),
+        "vmps_graph_destroy": (st, [vp]),
         "vmps_trace_enable": (st, [st]),
         "vmps_trace_collect": (st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]),
     }
@@ -105,7 +118,54 @@ def load_library():
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    _apply_autotune(lib)
     return lib
+
+
+AUTOTUNE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune.json")
+
+
+def _apply_autotune(lib, path: str = AUTOTUNE_PATH):
+    """Loads the tuning table measured for this GPU (if there is one) into the
+    library.  Tuning changes speed, never results."""
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return
+    arch = _gpu_arch()
+    if arch is None or table.get("arch") != arch:
+        return
+    for e in table.get("entries", []):
+        t = Tuning(int(e.get("tile_wg_per_cu", 0)), int(e.get("merge_grid", 0)), int(e.get("bucket_div", 0)), 0)
+        kt = U64 if e["dtype"] == "u64" else U32
+        lib.vmps_set_tuning(kt, int(bool(e["values"])), ctypes.byref(t))
+
+
+def _gpu_arch():
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return None
+
+
+def set_tuning(dtype_code: int, has_values: bool, tile_wg_per_cu: int = 0, merge_grid: int = 0,
+               bucket_div: int = 0):
+    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, 0)
+    _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_set_tuning")
+
+
+def reset_tuning(dtype_code: int, has_values: bool):
+    _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), None), "vmps_set_tuning")
+
+
+def get_tuning(dtype_code: int, has_values: bool) -> dict:
+    t = Tuning()
+    _check(load_library().vmps_get_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_get_tuning")
+    return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div}
 
 
 def status_string(s: int) -> str:
@@ -299,6 +359,64 @@ def segmented_sort_(keys, offsets, values=None):
     _check(lib.vmps_segmented_sort(_ptr(keys), _ptr(values), _ptr(offsets), nseg, total, kt, _ptr(ws),
                                    ws.numel(), _stream(keys.device)), "vmps_segmented_sort")
     return keys
+
+
+class Graph:
+    """A captured sort (vmps_*_graph): replay() enqueues it on the current
+    stream.  It keeps the tensors it was captured with alive."""
+
+    def __init__(self, handle, keep):
+        self._h = handle
+        self._keep = keep
+
+    def replay(self):
+        _check(load_library().vmps_graph_launch(self._h, _stream()), "vmps_graph_launch")
+
+    def close(self):
+        if self._h:
+            load_library().vmps_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def segmented_sort_graph(keys, offsets, values=None) -> Graph:
+    """Captures segmented_sort_(keys, offsets, values) into a graph."""
+    lib = load_library()
+    _require_cuda(keys, values, offsets)
+    kt = _dtype_code(keys)
+    total = keys.numel()
+    nseg = offsets.numel() - 1
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_segmented_sort_workspace_size(total, max(nseg, 0), kt, int(values is not None),
+                                                  ctypes.byref(need)), "vmps_segmented_sort_workspace_size")
+    ws = _workspace(need.value, keys.device)
+    h = ctypes.c_void_p()
+    _check(lib.vmps_segmented_sort_graph(_ptr(keys), _ptr(values), _ptr(offsets), nseg, total, kt, _ptr(ws),
+                                         ws.numel(), ctypes.byref(h)), "vmps_segmented_sort_graph")
+    return Graph(h, (keys, values, offsets, ws))
+
+
+def sort_learned_graph(keys, values=None, *, iota: bool = False, cfg=None) -> Graph:
+    """Captures sort_learned_(keys, values) into a graph (no statistics)."""
+    lib = load_library()
+    _require_cuda(keys, values)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    if cfg is None:
+        cfg = learned_default_config(n, kt)
+    need = ctypes.c_size_t(0)
+    _check(lib.vmps_learned_workspace_size(n, kt, int(values is not None), ctypes.byref(cfg), ctypes.byref(need)),
+           "vmps_learned_workspace_size")
+    ws = _workspace(need.value, keys.device)
+    h = ctypes.c_void_p()
+    _check(lib.vmps_sort_learned_graph(_ptr(keys), _ptr(values), n, kt, VALUES_IOTA if iota else 0, ctypes.byref(cfg),
+                                       None, _ptr(ws), ws.numel(), ctypes.byref(h)), "vmps_sort_learned_graph")
+    return Graph(h, (keys, values, ws, cfg))
 
 
 # ------------------------------------------------------------- learned --

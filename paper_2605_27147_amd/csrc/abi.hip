@@ -5,7 +5,47 @@
 
 using namespace vmps;
 
+struct vmps_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
 namespace {
+Tuning (&tuning_table())[2][2]
+{
+    static Tuning t[2][2] = {};
+    return t;
+}
+
+// Captures what `enqueue` puts on a private stream into an instantiated graph.
+template <typename F>
+vmps_status capture_graph(vmps_graph* out, F enqueue)
+{
+    *out = nullptr;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return VMPS_ERR_DEVICE;
+    const bool tracing = trace_suspend();
+    vmps_status st = VMPS_OK;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        st = VMPS_ERR_DEVICE;
+    } else {
+        st = enqueue(cs);
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (st == VMPS_OK && e != hipSuccess) st = VMPS_ERR_DEVICE;
+    }
+    trace_resume(tracing);
+    hipGraphExec_t ex = nullptr;
+    if (st == VMPS_OK && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) st = VMPS_ERR_DEVICE;
+    if (st != VMPS_OK) {
+        if (g) (void)hipGraphDestroy(g);
+    } else {
+        *out = new vmps_graph_s{g, ex};
+    }
+    (void)hipStreamDestroy(cs);
+    return st;
+}
+
 
 inline int key_bits_of(vmps_dtype kt) { return kt == VMPS_U64 ? 64 : 32; }
 inline size_t key_bytes(vmps_dtype kt) { return kt == VMPS_U64 ? 8 : 4; }
@@ -357,10 +397,12 @@ vmps_status check_config(const vmps_learned_config& c, int64_t n)
     return VMPS_OK;
 }
 
-uint32_t auto_buckets(uint64_t n, uint32_t T)
+uint32_t auto_buckets(uint64_t n, uint32_t T, int key_bits, bool has_values)
 {
-    // about half an LDS tile per bucket, so uneven buckets still fit the tile
-    uint64_t target = T / 2;
+    // about half an LDS tile per bucket (tunable), so uneven buckets still fit
+    const int div = tuning_for(key_bits, has_values).bucket_div;
+    uint64_t target = T / (uint64_t)(div > 0 ? div : 2);
+    if (target < 1) target = 1;
     uint64_t b = 2;
     while (b < 65536 && b * target < n) b <<= 1;
     return (uint32_t)b;
@@ -377,7 +419,7 @@ LearnedLayout learned_layout(uint64_t n, vmps_dtype kt, int has_values, const vm
     const int kb = key_bits_of(kt);
     LearnedLayout L;
     L.T = tilesort_capacity(kb, has_values);
-    L.B = c.num_buckets ? (uint32_t)c.num_buckets : auto_buckets(n, L.T);
+    L.B = c.num_buckets ? (uint32_t)c.num_buckets : auto_buckets(n, L.T, kb, has_values != 0);
     L.m = (uint64_t)c.sample_size;
     size_t off = 0;
     L.keys_b = off; off += align256(key_bytes(kt) * n);
@@ -581,4 +623,71 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
     });
 }
 
+// ---------------------------------------------------------------- tuning --
+vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t)
+{
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    Tuning v{0, 0, 0};
+    if (t) {
+        if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 || t->reserved)
+            return VMPS_ERR_INVALID_ARG;
+        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div};
+    }
+    tuning_table()[kt == VMPS_U64][has_values ? 1 : 0] = v;
+    return VMPS_OK;
+}
+
+vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t)
+{
+    if ((kt != VMPS_U32 && kt != VMPS_U64) || !t) return VMPS_ERR_INVALID_ARG;
+    const Tuning& v = tuning_table()[kt == VMPS_U64][has_values ? 1 : 0];
+    t->tile_wg_per_cu = v.tile_wg_per_cu;
+    t->merge_grid = v.merge_grid;
+    t->bucket_div = v.bucket_div;
+    t->reserved = 0;
+    return VMPS_OK;
+}
+
+// ---------------------------------------------------------------- graphs --
+vmps_status vmps_segmented_sort_graph(void* keys, uint32_t* values, const int64_t* seg_offsets, int64_t nseg,
+                                      int64_t total, vmps_dtype kt, void* ws, size_t ws_bytes, vmps_graph* graph)
+{
+    if (!graph) return VMPS_ERR_INVALID_ARG;
+    return capture_graph(graph, [&](hipStream_t cs) {
+        return vmps_segmented_sort(keys, values, seg_offsets, nseg, total, kt, ws, ws_bytes, cs);
+    });
+}
+
+vmps_status vmps_sort_learned_graph(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                                    const vmps_learned_config* cfg, vmps_learned_stats* stats, void* ws,
+                                    size_t ws_bytes, vmps_graph* graph)
+{
+    if (!graph) return VMPS_ERR_INVALID_ARG;
+    return capture_graph(graph, [&](hipStream_t cs) {
+        return vmps_sort_learned(keys, values, n, kt, flags, cfg, nullptr, stats, ws, ws_bytes, cs);
+    });
+}
+
+vmps_status vmps_graph_launch(vmps_graph graph, void* stream)
+{
+    if (!graph) return VMPS_ERR_INVALID_ARG;
+    return hipGraphLaunch(graph->exec, (hipStream_t)stream) == hipSuccess ? VMPS_OK : VMPS_ERR_DEVICE;
+}
+
+vmps_status vmps_graph_destroy(vmps_graph graph)
+{
+    if (!graph) return VMPS_ERR_INVALID_ARG;
+    hipError_t e1 = hipGraphExecDestroy(graph->exec);
+    hipError_t e2 = hipGraphDestroy(graph->graph);
+    delete graph;
+    return (e1 == hipSuccess && e2 == hipSuccess) ? VMPS_OK : VMPS_ERR_DEVICE;
+}
+
 }  // extern "C"
+
+namespace vmps {
+const Tuning& tuning_for(int key_bits, bool has_values)
+{
+    return tuning_table()[key_bits == 64][has_values ? 1 : 0];
+}
+}  // namespace vmps

@@ -104,7 +104,9 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     uint32_t top = 1;
     while (top < 32 && (1ull << top) < P.n) ++top;  // powers never exceed ceil(log2 n)
     const unsigned pgrid = (unsigned)ceil_div((uint64_t)P.n_tiles_out * 2, 256);
-    const unsigned mgrid = P.n_tiles_out < 2048 ? P.n_tiles_out : 2048;
+    const int tg = tuning_for(sizeof(K) * 8, VAL).merge_grid;
+    const uint32_t gcap = tg > 0 ? (uint32_t)tg : 2048u;
+    const unsigned mgrid = P.n_tiles_out < gcap ? P.n_tiles_out : gcap;
     for (int lvl = (int)top; lvl >= 1; --lvl) {
         A.level = (uint32_t)lvl;
         {

@@ -616,36 +616,57 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     __syncthreads();
 }
 
+// The LDS pass as one persistent launch: as many workgroups as can be
+// resident, each taking the next segment from an atomic ticket (segments
+// differ in length by orders of magnitude in a batch, so a fixed assignment
+// would leave workgroups idle).  No workgroup ever waits for another.
+// The ticket is broadcast through LDS and made wave-uniform, so the segment
+// index lives in scalar registers as a block index would.
 // MINW: waves per SIMD that the LDS footprint lets run at once, which
 // bounds the registers a wave may use.
 template <typename K, int NT, int TCAP, int VMODE, int MINW>
 __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
                                                        uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
-                                                       const Seg* __restrict__ segs,
-                                                       const uint32_t* __restrict__ nseg_dev, uint32_t nseg_host,
+                                                       const Seg* __restrict__ segs, uint32_t* __restrict__ counters,
                                                        const uint32_t* __restrict__ inst_start)
 {
     extern __shared__ __align__(16) uint8_t smem[];
-    const uint32_t nseg = nseg_dev ? *nseg_dev : nseg_host;
-    for (uint32_t si = blockIdx.x; si < nseg; si += gridDim.x)
+    __shared__ uint32_t s_next;
+    const uint32_t nseg = counters[CNT_NSEG];
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(&counters[CNT_TICKET], 1u);
+        __syncthreads();
+        const uint32_t si = __builtin_amdgcn_readfirstlane(s_next);
+        __syncthreads();
+        if (si >= nseg) break;
         tile_segment<K, NT, TCAP, VMODE>(smem, keysA, keysB, valsA, valsB, segs[si], inst_start);
+    }
 }
 
 // ------------------------------------------------------------- host --
 template <typename K, int NT, int TCAP, int VMODE, int MINW>
 static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                                  const uint32_t* nseg_dev, uint32_t nseg_host, uint32_t grid, hipStream_t s)
+                                  int wg_per_cu, hipStream_t s)
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
+    auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW>;
     static bool attr_set = false;
+    static int resident = 0;
     if (!attr_set) {
-        VMPS_HIP(hipFuncSetAttribute((const void*)k_tilesort<K, NT, TCAP, VMODE, MINW>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        VMPS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)kern, NT, lds));
         attr_set = true;
     }
+    int dev = 0, cus = 0;
+    VMPS_HIP(hipGetDevice(&dev));
+    VMPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int per_cu = resident > 0 ? resident : 1;
+    if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)(cus > 0 ? cus : 1);
+    if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
-    k_tilesort<K, NT, TCAP, VMODE, MINW><<<grid, NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, nseg_dev,
-                                                        nseg_host, P.inst_start);
+    kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
+                                                     P.inst_start);
     return hipGetLastError();
 }
 
@@ -670,16 +691,15 @@ size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
                             int key_bits, int vmode, uint32_t, hipStream_t s)
 {
-    const uint32_t grid = P.seg_cap < 8192u ? P.seg_cap : 8192u;
-    const uint32_t* nseg_dev = P.counters + CNT_NSEG;
+    const int w = tuning_for(key_bits, vmode != 0).tile_wg_per_cu;
     if (key_bits == 32) {
-        if (vmode == 0) return launch_tilesort<uint32_t, 512, 16384, 0, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-        if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-        return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+        if (vmode == 0) return launch_tilesort<uint32_t, 512, 16384, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+        if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1, 4>(P, keysA, keysB, valsA, valsB, w, s);
+        return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, w, s);
     }
-    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-    if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1, 3>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
-    return launch_tilesort<uint64_t, 256, 4096, 2, 3>(P, keysA, keysB, valsA, valsB, nseg_dev, 0, grid, s);
+    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+    if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1, 3>(P, keysA, keysB, valsA, valsB, w, s);
+    return launch_tilesort<uint64_t, 256, 4096, 2, 3>(P, keysA, keysB, valsA, valsB, w, s);
 }
 
 }  // namespace vmps

@@ -38,6 +38,22 @@ TraceState& state()
 }
 }  // namespace
 
+bool trace_suspend()
+{
+    TraceState& S = state();
+    std::lock_guard<std::mutex> g(S.mu);
+    const bool was = S.on;
+    S.on = false;
+    return was;
+}
+
+void trace_resume(bool was_on)
+{
+    TraceState& S = state();
+    std::lock_guard<std::mutex> g(S.mu);
+    S.on = was_on;
+}
+
 TraceScope::TraceScope(int kind, hipStream_t s) : kind_(kind), stream_(s), a_(nullptr)
 {
     TraceState& st = state();

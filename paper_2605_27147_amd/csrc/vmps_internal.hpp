@@ -147,7 +147,7 @@ struct Plan {
 
 enum {
     CNT_NBIG = 0, CNT_NLONG, CNT_NENT, CNT_NRUNS, CNT_NHBM, CNT_NSEG, CNT_NPAIRS,
-    CNT_MAXPOW, CNT_BAD, CNT_COUNT = 16
+    CNT_MAXPOW, CNT_BAD, CNT_TICKET, CNT_COUNT = 16
 };
 
 // ------------------------------------------------------------ tracing --
@@ -165,6 +165,19 @@ private:
     hipStream_t stream_;
     void* a_;
 };
+
+// ------------------------------------------------------------ tuning --
+// Launch parameters that change speed, never results (vmps_set_tuning).
+struct Tuning {
+    int tile_wg_per_cu;  // workgroups per CU of the persistent LDS pass (0: as many as fit)
+    int merge_grid;      // workgroups of a merge level (0: 2048)
+    int bucket_div;      // learned buckets target the tile length / bucket_div (0: 2)
+};
+const Tuning& tuning_for(int key_bits, bool has_values);
+
+// Tracing is suspended while a graph is captured (events are not captured).
+bool trace_suspend();
+void trace_resume(bool was_on);
 
 // ------------------------------------------------------------ host API --
 size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);

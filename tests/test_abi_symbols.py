@@ -44,3 +44,35 @@ def test_host_side_entry_points_without_gpu():
     assert lib.vmps_sort(ctypes.c_void_p(18), None, 100, 1, 0, None, 0, None) == vm.INVALID_ARG  # misaligned
     assert lib.vmps_sort(ctypes.c_void_p(16), ctypes.c_void_p(20), 100, 0, 0, None, 0, None) == vm.INVALID_ARG
     assert lib.vmps_status_string(2).decode() == "workspace too small"
+
+
+def test_tuning_table_host_side():
+    # the tuning table lives on the host: set, read back, reject bad fields
+    import ctypes
+    import paper_2605_27147_amd as vm
+    lib = vm.load_library()
+    vm.set_tuning(vm.U64, False, tile_wg_per_cu=1, merge_grid=1024, bucket_div=3)
+    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 1, "merge_grid": 1024, "bucket_div": 3}
+    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0}
+    bad = vm.Tuning(-1, 0, 0, 0)
+    assert lib.vmps_set_tuning(vm.U64, 0, ctypes.byref(bad)) == 1
+    bad = vm.Tuning(0, 0, 65, 0)
+    assert lib.vmps_set_tuning(vm.U64, 0, ctypes.byref(bad)) == 1
+    bad = vm.Tuning(0, 0, 0, 7)
+    assert lib.vmps_set_tuning(vm.U32, 1, ctypes.byref(bad)) == 1
+    assert lib.vmps_set_tuning(5, 0, None) == 1
+    vm.reset_tuning(vm.U64, False)
+    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0}
+
+
+def test_graph_capture_rejects_bad_arguments_without_gpu_work():
+    import ctypes
+    import paper_2605_27147_amd as vm
+    lib = vm.load_library()
+    h = ctypes.c_void_p()
+    # n < 0 is rejected by the captured call's own validation
+    assert lib.vmps_segmented_sort_graph(None, None, None, -1, 0, vm.U32, None, 0, ctypes.byref(h)) != 0
+    assert not h.value
+    assert lib.vmps_segmented_sort_graph(None, None, None, 0, 0, vm.U32, None, 0, None) == 1
+    assert lib.vmps_graph_launch(None, None) == 1
+    assert lib.vmps_graph_destroy(None) == 1

@@ -50,9 +50,9 @@ def kernel_bytes(path: str, kind: str, n: int, kb: int, vb: int, m_hbm: int, sam
     if kind == "tilesort":
         return float(kb * n + kv * n)           # read keys, write keys (+ values)
     if kind == "histogram":
-        return 2.0 * kb * n                     # two partition levels, keys read once each
+        return (kb + 2 + 2) * float(n)          # level 1: keys in, 16-bit ids out; level 2: ids in
     if kind == "scatter":
-        return 2.0 * 2 * kv * n                 # two levels, read + write
+        return (2 * (kv + 2) + (kv + 2) + kv) * float(n)  # level 1 moves keys+ids, level 2 reads both, writes keys
     if kind == "plan":
         return float(kb * n) if path == "plain" else 0.0
     if kind == "sample":

@@ -78,9 +78,19 @@ def _counters(directory: str, counter: str) -> list:
     for r in csv.DictReader(open(path)):
         if r["Counter_Name"] != counter:
             continue
-        d = per.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"], "kib": 0.0})
+        d = per.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]), "kib": 0.0})
         d["kib"] += float(r["Counter_Value"])
     return list(per.values())
+
+
+def _largest_copies(recs: list) -> list:
+    """The runtime's copy dispatches of the largest grid: the known-size
+    copies (small readbacks also use the copy kernel)."""
+    copies = [r for r in recs if re.search(COPY_PATTERN, r["name"])]
+    if not copies:
+        raise ValueError("no copy dispatch to calibrate against")
+    g = max(r["grid"] for r in copies)
+    return [r for r in copies if r["grid"] == g]
 
 
 def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int, commands: list) -> dict:
@@ -94,9 +104,9 @@ def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int
             raise ValueError(f"no dispatch matches {p.pattern}")
         return sum(v) / len(v), len(v)
 
-    copy = re.compile(COPY_PATTERN)
-    cf, _ = avg(fetch, copy)
-    cw, _ = avg(write, copy)
+    anything = re.compile(".")
+    cf, _ = avg(_largest_copies(fetch), anything)
+    cw, _ = avg(_largest_copies(write), anything)
     sf, sw = copy_bytes / cf, copy_bytes / cw
     f, nf = avg(fetch, pat)
     w, nw = avg(write, pat)

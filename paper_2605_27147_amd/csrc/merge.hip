@@ -12,39 +12,38 @@
 namespace vmps {
 
 struct LevelArgs {
-    const uint32_t* table;
+    const uint32_t* level;   // pairs per level, then first pair of each level
+    const uint32_t* pairs;   // (HBM node, output tile)
     const uint32_t* hbm_list;
     const uint32_t* lpos;
     const uint32_t* rpos;
     const uint32_t* run_start;
     const uint32_t* depth;
-    const uint32_t* counters;
-    uint32_t* splits;
-    uint32_t n_tiles_out;
+    uint32_t* splits;        // split at both ends of every pair
     uint32_t T_out;
-    uint32_t level;
+    uint32_t lvl;
 };
 
+// Merge-path splits at both ends of every output tile of the level (one
+// thread per end); an empty level returns at once.
 template <typename K>
 __global__ void k_level_partition(LevelArgs A, const K* __restrict__ keysA, const K* __restrict__ keysB)
 {
-    const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t tile = (uint32_t)(x >> 1), slot = (uint32_t)(x & 1);
-    if (tile >= A.n_tiles_out) return;
-    const uint32_t q = A.table[((uint64_t)A.level * A.n_tiles_out + tile) * 2 + slot];
-    if (q == NONE) return;
-    const uint32_t t = A.hbm_list[q];
-    const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
-    const K* src = (A.depth[q] & 1u) ? keysA : keysB;  // node writes to depth parity, reads the other
-    const uint64_t t0 = (uint64_t)tile * A.T_out;
-    const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
-    const uint32_t o1 = (uint32_t)(R < t0 + A.T_out ? R : t0 + A.T_out);
-    const uint32_t i0 = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o0 - L);
-    const uint32_t i1 = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o1 - L);
-    A.splits[(uint64_t)tile * 4 + slot * 2 + 0] = i0;
-    A.splits[(uint64_t)tile * 4 + slot * 2 + 1] = i1;
+    const uint32_t cnt = A.level[A.lvl], off = A.level[MAX_LEVEL + A.lvl];
+    for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < 2ull * cnt;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t i = off + (uint32_t)(x >> 1), end = (uint32_t)(x & 1);
+        const uint32_t q = A.pairs[2 * (uint64_t)i], tt = A.pairs[2 * (uint64_t)i + 1];
+        const uint32_t t = A.hbm_list[q];
+        const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+        const K* src = (A.depth[q] & 1u) ? keysA : keysB;  // node writes to depth parity, reads the other
+        const uint64_t t0 = (uint64_t)tt * A.T_out;
+        const uint32_t o = end ? (uint32_t)(R < t0 + A.T_out ? R : t0 + A.T_out) : (uint32_t)(L > t0 ? L : t0);
+        A.splits[2 * (uint64_t)i + end] = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o - L);
+    }
 }
 
+// One output tile per workgroup iteration, over the level's pairs.
 template <typename K, bool VAL, int NT, int KI>
 __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__ keysA, K* __restrict__ keysB,
                                                     uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB)
@@ -54,27 +53,24 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
     extern __shared__ __align__(16) uint8_t smem[];
     K* S = (K*)smem;
     uint32_t* SV = (uint32_t*)(S + SP);
-    for (uint32_t tile = blockIdx.x; tile < A.n_tiles_out; tile += gridDim.x) {
-        for (uint32_t slot = 0; slot < 2; ++slot) {
-            const uint32_t q = A.table[((uint64_t)A.level * A.n_tiles_out + tile) * 2 + slot];
-            if (q == NONE) continue;
-            const uint32_t t = A.hbm_list[q];
-            const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
-            const bool dstB = (A.depth[q] & 1u) != 0;
-            K* src = dstB ? keysA : keysB;
-            K* dst = dstB ? keysB : keysA;
-            uint32_t* vsrc = dstB ? valsA : valsB;
-            uint32_t* vdst = dstB ? valsB : valsA;
-            const uint64_t t0 = (uint64_t)tile * TO;
-            const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
-            const uint32_t i0 = A.splits[(uint64_t)tile * 4 + slot * 2 + 0];
-            const uint32_t i1 = A.splits[(uint64_t)tile * 4 + slot * 2 + 1];
-            const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
-            const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
-            merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid,
-                                       VAL ? vsrc + Mid : nullptr, j0, j1, dst + o0,
-                                       VAL ? vdst + o0 : nullptr, S, SV);
-        }
+    const uint32_t cnt = A.level[A.lvl], off = A.level[MAX_LEVEL + A.lvl];
+    for (uint32_t j = blockIdx.x; j < cnt; j += gridDim.x) {
+        const uint32_t i = off + j;
+        const uint32_t q = A.pairs[2 * (uint64_t)i], tt = A.pairs[2 * (uint64_t)i + 1];
+        const uint32_t t = A.hbm_list[q];
+        const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+        const bool dstB = (A.depth[q] & 1u) != 0;
+        K* src = dstB ? keysA : keysB;
+        K* dst = dstB ? keysB : keysA;
+        uint32_t* vsrc = dstB ? valsA : valsB;
+        uint32_t* vdst = dstB ? valsB : valsA;
+        const uint64_t t0 = (uint64_t)tt * TO;
+        const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
+        const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
+        const uint32_t i0 = A.splits[2 * (uint64_t)i], i1 = A.splits[2 * (uint64_t)i + 1];
+        const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
+        merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid, VAL ? vsrc + Mid : nullptr,
+                                   j0, j1, dst + o0, VAL ? vdst + o0 : nullptr, S, SV);
     }
 }
 
@@ -91,24 +87,24 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
         attr_set = true;
     }
     LevelArgs A;
-    A.table = P.level_table;
+    A.level = P.level;
+    A.pairs = P.pairs;
     A.hbm_list = P.hbm_list;
     A.lpos = P.bnd_lpos;
     A.rpos = P.bnd_rpos;
     A.run_start = P.run_start;
     A.depth = P.hbm_depth;
-    A.counters = P.counters;
     A.splits = P.splits;
-    A.n_tiles_out = P.n_tiles_out;
     A.T_out = TO;
     uint32_t top = 1;
     while (top < 32 && (1ull << top) < P.n) ++top;  // powers never exceed ceil(log2 n)
-    const unsigned pgrid = (unsigned)ceil_div((uint64_t)P.n_tiles_out * 2, 256);
+    const uint64_t most = (uint64_t)P.n_tiles_out + 2 * ((uint64_t)P.n / (P.T ? P.T : 1) + 1);  // pairs of one level
+    const unsigned pgrid = (unsigned)(ceil_div(2 * most, 256) < 1024 ? ceil_div(2 * most, 256) : 1024);
     const int tg = tuning_for(sizeof(K) * 8, VAL).merge_grid;
-    const uint32_t gcap = tg > 0 ? (uint32_t)tg : 2048u;
-    const unsigned mgrid = P.n_tiles_out < gcap ? P.n_tiles_out : gcap;
+    const uint64_t gcap = tg > 0 ? (uint64_t)tg : 2048u;
+    const unsigned mgrid = (unsigned)(most < gcap ? most : gcap);
     for (int lvl = (int)top; lvl >= 1; --lvl) {
-        A.level = (uint32_t)lvl;
+        A.lvl = (uint32_t)lvl;
         {
             TraceScope tr(VMPS_TRACE_LEVEL_PARTITION, s);
             k_level_partition<K><<<pgrid, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);

@@ -590,21 +590,57 @@ __global__ void k_segs_inst(const uint32_t* __restrict__ hbm_list, const uint32_
 }
 
 // ------------------------------------------------------- level table --
+// Output tiles of every HBM node (T_out-aligned tiles of [L, R)), summed per
+// power level.  level[0, MAX_LEVEL): tiles of each level; level[MAX_LEVEL,
+// 2*MAX_LEVEL): their start in the level-ordered pair list; level[2*MAX_LEVEL,
+// 3*MAX_LEVEL): fill positions.
 __global__ void k_level_count(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ bnd_lpos,
-                              const uint32_t* __restrict__ bnd_rpos, uint32_t T_out,
-                              const uint32_t* counters, uint32_t* __restrict__ tiles)
+                              const uint32_t* __restrict__ bnd_rpos, const uint8_t* __restrict__ power,
+                              uint32_t T_out, const uint32_t* counters, uint32_t* __restrict__ tiles,
+                              uint32_t* __restrict__ level)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= counters[CNT_NHBM]) return;
     const uint32_t t = hbm_list[q];
     const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
-    tiles[q] = (R - 1) / T_out - L / T_out + 1;
+    const uint32_t nt = (R - 1) / T_out - L / T_out + 1;
+    tiles[q] = nt;
+    if (power[t] < MAX_LEVEL) atomicAdd(&level[power[t]], nt);
 }
 
+__global__ void k_level_offsets(uint32_t* __restrict__ level, uint32_t pair_cap)
+{
+    if (threadIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int p = 0; p < (int)MAX_LEVEL; ++p) {
+        // a count beyond the capacity cannot come from a consistent plan;
+        // clamping keeps every write of k_level_fill in range
+        const uint32_t c = acc + level[p] <= pair_cap ? level[p] : pair_cap - acc;
+        level[p] = c;
+        level[MAX_LEVEL + p] = acc;
+        level[2 * MAX_LEVEL + p] = 0;
+        acc += c;
+    }
+}
+
+// Every HBM node reserves the slots of its output tiles in its level (one
+// atomic per node, not per tile: a level's counter sees as many updates as
+// the level has nodes).
+__global__ void k_level_reserve(const uint32_t* __restrict__ hbm_list, const uint8_t* __restrict__ power,
+                                const uint32_t* __restrict__ tiles, const uint32_t* counters,
+                                uint32_t* __restrict__ level, uint32_t* __restrict__ node_base)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= counters[CNT_NHBM]) return;
+    const uint32_t p = power[hbm_list[q]];
+    node_base[q] = p < MAX_LEVEL ? level[MAX_LEVEL + p] + atomicAdd(&level[2 * MAX_LEVEL + p], tiles[q]) : NONE;
+}
+
+// Pair list by level: (HBM node, output tile) for every output tile.
 __global__ void k_level_fill(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ bnd_lpos,
                              const uint8_t* __restrict__ power, const uint32_t* __restrict__ tile_off,
-                             uint32_t T_out, uint32_t n_tiles_out, const uint32_t* counters,
-                             uint32_t* __restrict__ table)
+                             const uint32_t* __restrict__ node_base, uint32_t T_out, const uint32_t* counters,
+                             const uint32_t* __restrict__ level, uint32_t* __restrict__ pairs)
 {
     const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t h = counters[CNT_NHBM];
@@ -615,11 +651,12 @@ __global__ void k_level_fill(const uint32_t* __restrict__ hbm_list, const uint32
         if (tile_off[m] <= x) lo = m; else hi = m;
     }
     const uint32_t t = hbm_list[lo];
-    const uint32_t L = bnd_lpos[t];
-    const uint32_t tt = L / T_out + (x - tile_off[lo]);
-    const uint32_t slot = (L <= (uint64_t)tt * T_out) ? 0u : 1u;
-    if (tt >= n_tiles_out || power[t] >= MAX_LEVEL) return;
-    table[((uint64_t)power[t] * n_tiles_out + tt) * 2 + slot] = lo;
+    const uint32_t p = power[t];
+    if (p >= MAX_LEVEL || node_base[lo] == NONE) return;
+    const uint32_t pos = node_base[lo] + (x - tile_off[lo]);
+    if (pos >= level[MAX_LEVEL + p] + level[p]) return;  // only past a clamped count
+    pairs[2 * (uint64_t)pos] = lo;
+    pairs[2 * (uint64_t)pos + 1] = bnd_lpos[t] / T_out + (x - tile_off[lo]);
 }
 
 // ------------------------------------------------------------- host --
@@ -700,8 +737,17 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.hbm_tiles = c.take<uint32_t>(P.run_cap + 1);
     P.hbm_tile_off = c.take<uint32_t>(P.run_cap + 1);
     P.segs = c.take<Seg>(P.seg_cap);
-    P.level_table = c.take<uint32_t>((uint64_t)MAX_LEVEL * P.n_tiles_out * 2);
-    P.splits = c.take<uint32_t>((uint64_t)P.n_tiles_out * 4);
+    // output tiles of all HBM nodes: per level at most n_tiles_out plus two
+    // per node, and a level holds fewer than n / T + 1 nodes longer than T
+    {
+        const uint64_t per_level = (uint64_t)P.n_tiles_out + 2 * (n / (T ? T : 1) + 1);
+        const uint64_t cap = (uint64_t)MAX_LEVEL * per_level;
+        P.pair_cap = (uint32_t)(cap < 0xffffffffull ? cap : 0xffffffffull);
+    }
+    P.level = c.take<uint32_t>(3 * MAX_LEVEL);
+    P.node_base = c.take<uint32_t>(P.run_cap);
+    P.pairs = c.take<uint32_t>(2 * (uint64_t)P.pair_cap);
+    P.splits = c.take<uint32_t>(2 * (uint64_t)P.pair_cap);
     P.counters = c.take<uint32_t>(CNT_COUNT);
     P.stats = c.take<unsigned long long>(8);
     uint64_t cap = P.bm_tiles;
@@ -796,16 +842,17 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
                                                         P.hbm_depth, P.inst_start, C, P.segs);
     k_segs_inst<<<grid_for(k, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.hbm_depth,
                                                  P.inst_start, P.inst_big, P.inst_bigrank, k, C, P.segs);
-    k_level_count<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.T_out, C,
-                                                           P.hbm_tiles);
+    VMPS_HIP(fill_u32(P.level, 0, 3 * MAX_LEVEL, s));
+    k_level_count<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
+                                                           C, P.hbm_tiles, P.level);
     VMPS_HIP(scan_exclusive_u32(P.hbm_tiles, P.hbm_tile_off, P.run_cap, C + CNT_NHBM, C + CNT_NPAIRS,
                                 P.scan_tmp, s));
-    k_clamp<<<1, 64, 0, s>>>(C, CNT_NPAIRS, (uint32_t)((uint64_t)MAX_LEVEL * P.n_tiles_out + P.run_cap));
-    VMPS_HIP(fill_u32(P.level_table, NONE, (uint64_t)MAX_LEVEL * P.n_tiles_out * 2, s));
-    // pairs are at most MAX_LEVEL tiles per position plus one per node
-    const uint64_t pair_cap = (uint64_t)MAX_LEVEL * P.n_tiles_out + P.run_cap;
-    k_level_fill<<<grid_for(pair_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
-                                                         P.T_out, P.n_tiles_out, C, P.level_table);
+    k_clamp<<<1, 64, 0, s>>>(C, CNT_NPAIRS, P.pair_cap);
+    k_level_offsets<<<1, 64, 0, s>>>(P.level, P.pair_cap);
+    k_level_reserve<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, P.level,
+                                                             P.node_base);
+    k_level_fill<<<grid_for(P.pair_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
+                                                           P.node_base, P.T_out, C, P.level, P.pairs);
     return hipGetLastError();
 }
 

@@ -133,9 +133,12 @@ struct Plan {
     uint32_t* hbm_tile_off;
     // LDS segments
     Seg* segs;                     // seg_cap
-    // merge levels
-    uint32_t* level_table;         // MAX_LEVEL * n_tiles_out * 2
-    uint32_t* splits;              // n_tiles_out * 4
+    // merge levels: (HBM node, output tile) pairs grouped by power level
+    uint32_t pair_cap;
+    uint32_t* level;               // 3 * MAX_LEVEL: pairs per level, first pair, fill position
+    uint32_t* node_base;           // run_cap: first pair of every HBM node
+    uint32_t* pairs;               // 2 * pair_cap
+    uint32_t* splits;              // 2 * pair_cap: merge-path split at both ends of every pair
     // counters (device scalars)
     uint32_t* counters;            // see CNT_* below
     // scan scratch

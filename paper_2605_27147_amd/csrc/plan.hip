@@ -97,27 +97,43 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
                                                 uint64_t* __restrict__ bitmap,
                                                 uint32_t* __restrict__ tile_first)
 {
+    constexpr int WPW = (int)(BITMAP_TILE / 64 / 4);  // words per wave
     __shared__ uint32_t s_first[4];
     const uint32_t tile = blockIdx.x;
     const uint64_t base = (uint64_t)tile * BITMAP_TILE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t ii = 0;
-    if (k > 1 && base < n) ii = inst_of(inst_start, k, (uint32_t)base);
-    uint32_t first = NONE;
-    for (int w = wave; w < (int)(BITMAP_TILE / 64); w += 4) {
-        const uint64_t wpos = base + (uint64_t)w * 64;
-        const uint64_t p = wpos + lane;
-        bool bit = true;
-        if (wpos < n)
-            while (ii + 1 < k && inst_start[ii + 1] <= wpos) ++ii;  // uniform across the wave
+    uint32_t my = 0;
+    if (k > 1 && base < n) my = inst_of(inst_start, k, (uint32_t)base);
+    // which of the lane's positions compare with their predecessor: inside
+    // an instance that the planner handles (not its first element)
+    bool cmp[WPW];
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {
+        const uint64_t p = base + (uint64_t)(wave + 4 * j) * 64 + lane;
+        cmp[j] = false;
         if (p < n) {
-            uint32_t my = ii;
             while (my + 1 < k && inst_start[my + 1] <= p) ++my;
-            if (p != inst_start[my] && inst_big[my]) bit = keys[p - 1] > keys[p];
+            cmp[j] = p != inst_start[my] && inst_big[my];
         }
+    }
+    // all key loads of the lane in flight before the first compare
+    K x[WPW], y[WPW];
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {
+        const uint64_t p = base + (uint64_t)(wave + 4 * j) * 64 + lane;
+        x[j] = cmp[j] ? keys[p - 1] : K(0);
+        y[j] = cmp[j] ? keys[p] : K(0);
+    }
+    uint32_t first = NONE;
+#pragma unroll
+    for (int j = 0; j < WPW; ++j) {
+        const int w = wave + 4 * j;
+        // positions past n and instance heads are boundaries; so is every
+        // position of an instance the tile pass sorts whole
+        const bool bit = cmp[j] ? (x[j] > y[j]) : true;
         const uint64_t word = __ballot(bit);
         if (lane == 0) bitmap[(uint64_t)tile * 64 + w] = word;
-        if (word && first == NONE) first = (uint32_t)(wpos + ffs64(word));
+        if (word && first == NONE) first = (uint32_t)(base + (uint64_t)w * 64 + ffs64(word));
     }
     if (lane == 0) s_first[wave] = first;
     __syncthreads();
@@ -169,7 +185,18 @@ __global__ __launch_bounds__(64) void k_long_runs(const uint64_t* __restrict__ b
     // a word holds at most 4 starts of runs of length >= 16
     uint32_t cnt = 0;
     uint32_t ru[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0};
-    uint64_t bits = word;
+    // a run of length >= cand_min starting at bit b has no boundary in
+    // (b, b + cand_min): only such bits are examined (bits of the window past
+    // the word read as 0, so the last starts of a word stay candidates)
+    const uint32_t span = (cand_min < 33u ? (cand_min > 0u ? cand_min : 1u) : 33u) - 1u;
+    uint64_t o = span ? word >> 1 : 0ull;
+    uint32_t covered = 1;
+    while (span && 2 * covered <= span) {
+        o |= o >> covered;
+        covered *= 2;
+    }
+    if (covered < span) o |= o >> (span - covered);
+    uint64_t bits = word & ~o;
     while (bits) {
         const int b = ffs64(bits);
         bits &= bits - 1;
@@ -420,11 +447,13 @@ __global__ void k_boundaries(const uint32_t* __restrict__ run_start, const uint3
                              uint32_t* __restrict__ bnd_lpos, uint32_t* __restrict__ bnd_rpos,
                              uint32_t* __restrict__ hbm_flag, unsigned long long* stats)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nr = counters[CNT_NRUNS];
     uint64_t cost = 0, cost_hbm = 0;
-    uint32_t p = 0;
-    if (t < nr) {
+    uint32_t pmax = 0;
+    // grid-stride over the boundaries with a capped grid, so that the merge
+    // cost sums end in one atomic per workgroup
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
+        uint32_t p = 0;
         const uint32_t inst = run_inst[t];
         const uint32_t lo = inst_run_lo[inst], hi = inst_run_hi[inst];
         if (t == hi || lo == NONE || hi == NONE || t < lo || t > hi) {
@@ -470,20 +499,29 @@ __global__ void k_boundaries(const uint32_t* __restrict__ run_start, const uint3
             bnd_l[t] = uL; bnd_r[t] = uR;
             bnd_lpos[t] = L; bnd_rpos[t] = R;
             hbm_flag[t] = (R - L > T) ? 1u : 0u;
-            cost = R - L;
-            if (R - L > T) cost_hbm = R - L;
+            cost += R - L;
+            if (R - L > T) cost_hbm += R - L;
         }
+        pmax = max(pmax, p);
     }
-    // per-wave sums, one atomic each
+    // wave sums, then workgroup sums, then one atomic per workgroup
     for (int d = 32; d >= 1; d >>= 1) {
         cost += __shfl_down(cost, d, 64);
         cost_hbm += __shfl_down(cost_hbm, d, 64);
-        p = max(p, (uint32_t)__shfl_down((int)p, d, 64));
+        pmax = max(pmax, (uint32_t)__shfl_down((int)pmax, d, 64));
     }
-    if ((threadIdx.x & 63) == 0) {
-        if (cost) atomicAdd(&stats[0], (unsigned long long)cost);
-        if (cost_hbm) atomicAdd(&stats[1], (unsigned long long)cost_hbm);
-        if (p) atomicMax(&counters[CNT_MAXPOW], p);
+    __shared__ unsigned long long s_cost[4], s_hbm[4];
+    __shared__ uint32_t s_p[4];
+    const int wave = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) { s_cost[wave] = cost; s_hbm[wave] = cost_hbm; s_p[wave] = pmax; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long c = 0, ch = 0;
+        uint32_t pm = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { c += s_cost[w]; ch += s_hbm[w]; pm = max(pm, s_p[w]); }
+        if (c) atomicAdd(&stats[0], c);
+        if (ch) atomicAdd(&stats[1], ch);
+        if (pm) atomicMax(&counters[CNT_MAXPOW], pm);
     }
 }
 
@@ -820,10 +858,10 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     // 4-5. powers and tree
     k_run_q<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.run_start, P.run_inst, P.inst_start, C, P.run_q,
                                                      P.inst_run_lo, P.inst_run_hi);
-    k_boundaries<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.run_start, P.run_inst, P.run_q, P.inst_start,
-                                                          P.inst_run_lo, P.inst_run_hi, P.T, C, P.power,
-                                                          P.bnd_l, P.bnd_r, P.bnd_lpos, P.bnd_rpos,
-                                                          P.hbm_flag, P.stats);
+    const unsigned bgrid = grid_for(P.run_cap, 256) < 4096u ? grid_for(P.run_cap, 256) : 4096u;
+    k_boundaries<<<bgrid, 256, 0, s>>>(P.run_start, P.run_inst, P.run_q, P.inst_start, P.inst_run_lo,
+                                       P.inst_run_hi, P.T, C, P.power, P.bnd_l, P.bnd_r, P.bnd_lpos, P.bnd_rpos,
+                                       P.hbm_flag, P.stats);
     // 6. nodes longer than T and their depths
     VMPS_HIP(scan_exclusive_u32(P.hbm_flag, P.hbm_rank, P.run_cap, C + CNT_NRUNS, C + CNT_NHBM, P.scan_tmp, s));
     k_hbm_emit<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.hbm_list, P.hbm_idx);

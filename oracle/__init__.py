@@ -90,6 +90,10 @@ def _L():
                                       ctypes.POINTER(i32)]
         lib.orc_bucket_of.restype = ctypes.c_uint32
         lib.orc_bucket_of.argtypes = [u64, i32, i32, u64, u64, vp, i32, i32, ctypes.c_uint32]
+        lib.orc_cdf_pos.restype = u64
+        lib.orc_cdf_pos.argtypes = [u64, i32, i32, u64, u64, vp, i32, i32]
+        lib.orc_judge.restype = None
+        lib.orc_judge.argtypes = [vp, i64, i32, i32, u64, u64, vp, i32, i32, ctypes.c_uint32, vp, vp, vp, vp]
         lib.orc_cdf_init.restype = None
         lib.orc_cdf_init.argtypes = [vp, i64, i32, vp, vp, vp, vp]
         lib.orc_cdf_loss.restype = dbl
@@ -276,6 +280,35 @@ def cdf_table(params: dict, z_lo: int, z_hi: int, K: int) -> Table:
 def bucket_of(key: int, key_bits: int, fbits: int, tab: Table, B: int) -> int:
     t = np.ascontiguousarray(tab.table, dtype=np.uint64)
     return int(_L().orc_bucket_of(key, key_bits, fbits, tab.z_lo, tab.z_hi, _p(t), tab.shift, tab.knots, B))
+
+
+def cdf_pos(key: int, key_bits: int, fbits: int, tab: Table) -> int:
+    """F(key) of the compiled table in Q32."""
+    t = np.ascontiguousarray(tab.table, dtype=np.uint64)
+    return int(_L().orc_cdf_pos(key, key_bits, fbits, tab.z_lo, tab.z_hi, _p(t), tab.shift, tab.knots))
+
+
+def judge(sorted_keys, key_bits: int, fbits: int, tab: Table, B: int) -> dict:
+    """Error judge on a sorted sample (targets y_i = (i + 1/2)/m): maximum and
+    mean of |bucket(x_i) - floor(B y_i)| and of |B F(x_i) - B y_i|, the last
+    two as exact rationals rounded once to float."""
+    from fractions import Fraction
+    x = _keys64(sorted_keys)
+    m = x.size
+    t = np.ascontiguousarray(tab.table, dtype=np.uint64)
+    mb = np.zeros(1, dtype=np.uint64)
+    sb = np.zeros(1, dtype=np.uint64)
+    dm = np.zeros(2, dtype=np.uint64)
+    ds = np.zeros(2, dtype=np.uint64)
+    _L().orc_judge(_p(x), m, key_bits, fbits, tab.z_lo, tab.z_hi, _p(t), tab.shift, tab.knots, B,
+                   _p(mb), _p(sb), _p(dm), _p(ds))
+    d_max = int(dm[0]) + (int(dm[1]) << 64)
+    d_sum = int(ds[0]) + (int(ds[1]) << 64)
+    return {"samples": m, "max_bucket_err": int(mb[0]), "sum_bucket_err": int(sb[0]),
+            "mean_bucket_err": float(Fraction(int(sb[0]), m)) if m else 0.0,
+            "d_max": d_max, "d_sum": d_sum,
+            "max_err": float(Fraction(B * d_max, (1 << 33) * m)) if m else 0.0,
+            "mean_err": float(Fraction(B * d_sum, (1 << 33) * m * m)) if m else 0.0}
 
 
 def partition(keys, key_bits: int, fbits: int, tab: Table, B: int, vals=None):

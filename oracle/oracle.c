@@ -513,25 +513,62 @@ void orc_cdf_table(const double* w1, const double* b1, const double* w2, double 
     *knots_out = kn;
 }
 
-/* Bucket of a key: linear interpolation between the table's knots in the
- * feature coordinate, all in integers, then scaled to B buckets. */
-uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo,
-                       uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots,
-                       uint32_t B)
+/* Position of a key under the compiled model, F(key) in Q32: linear
+ * interpolation between the table's knots in the feature coordinate, all in
+ * integers. */
+uint64_t orc_cdf_pos(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
+                     const uint64_t* table, int32_t shift, int32_t knots)
 {
     uint64_t z = orc_feature(key, key_bits, fbits);
     uint64_t range = z_hi > z_lo ? z_hi - z_lo : 0;
     uint64_t d = z <= z_lo ? 0 : (z - z_lo > range ? range : z - z_lo);
     uint64_t seg = d >> shift;
-    uint64_t pos;
-    if (seg >= (uint64_t)knots) {
-        pos = table[knots];
-    } else {
-        uint64_t rem = d & ((1ull << shift) - 1);
-        pos = table[seg] + (((table[seg + 1] - table[seg]) * rem) >> shift);
-    }
+    if (seg >= (uint64_t)knots) return table[knots];
+    uint64_t rem = d & ((1ull << shift) - 1);
+    return table[seg] + (((table[seg + 1] - table[seg]) * rem) >> shift);
+}
+
+/* Bucket of a key: its position scaled to B buckets. */
+uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo,
+                       uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots,
+                       uint32_t B)
+{
+    uint64_t pos = orc_cdf_pos(key, key_bits, fbits, z_lo, z_hi, table, shift, knots);
     uint64_t b = (pos * (uint64_t)B) >> 32;
     return (uint32_t)(b >= B ? B - 1 : b);
+}
+
+/* Error judge of the compiled model on the sorted sample x_0 <= ... <=
+ * x_{m-1}, whose targets are y_i = (i + 1/2) / m.  Per sample point:
+ *   bucket error  |bucket(x_i) - floor(B y_i)|              (integer)
+ *   CDF error     |B F(x_i) - B y_i| = B d_i / (2^33 m),
+ *                 d_i = |2m pos_i - 2^32 (2i + 1)|           (exact, 128-bit)
+ * Returns the maximum and the sum of both over the sample (the 128-bit
+ * values as low/high words). */
+void orc_judge(const uint64_t* sorted, int64_t m, int32_t key_bits, int32_t fbits, uint64_t z_lo,
+               uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots, uint32_t B,
+               uint64_t* max_bucket_err, uint64_t* sum_bucket_err, uint64_t d_max[2], uint64_t d_sum[2])
+{
+    uint64_t mb = 0, sb = 0;
+    unsigned __int128 dm = 0, ds = 0;
+    for (int64_t i = 0; i < m; ++i) {
+        uint64_t pos = orc_cdf_pos(sorted[i], key_bits, fbits, z_lo, z_hi, table, shift, knots);
+        uint64_t b = (pos * (uint64_t)B) >> 32;
+        if (b >= B) b = B - 1;
+        uint64_t want = ((uint64_t)B * (uint64_t)(2 * i + 1)) / (uint64_t)(2 * m);
+        uint64_t eb = b > want ? b - want : want - b;
+        if (eb > mb) mb = eb;
+        sb += eb;
+        unsigned __int128 a = (unsigned __int128)pos * (unsigned __int128)(2 * m);
+        unsigned __int128 t = (unsigned __int128)(2 * i + 1) << 32;
+        unsigned __int128 d = a > t ? a - t : t - a;
+        if (d > dm) dm = d;
+        ds += d;
+    }
+    *max_bucket_err = mb;
+    *sum_bucket_err = sb;
+    d_max[0] = (uint64_t)dm; d_max[1] = (uint64_t)(dm >> 64);
+    d_sum[0] = (uint64_t)ds; d_sum[1] = (uint64_t)(ds >> 64);
 }
 
 /* Stable counting sort by bucket id: the plain definition of the partition. */

@@ -106,6 +106,8 @@ void     orc_cdf_grid(uint64_t z_lo, uint64_t z_hi, int32_t K, int32_t* shift, i
 void     orc_cdf_table(const double* w1, const double* b1, const double* w2, double b2,
                        int32_t H, uint64_t z_lo, uint64_t z_hi, int32_t K, uint64_t* table,
                        int32_t* shift, int32_t* knots);
+uint64_t orc_cdf_pos(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
+                     const uint64_t* table, int32_t shift, int32_t knots);
 uint32_t orc_bucket_of(uint64_t key, int32_t key_bits, int32_t fbits, uint64_t z_lo,
                        uint64_t z_hi, const uint64_t* table, int32_t shift, int32_t knots,
                        uint32_t B);
@@ -121,6 +123,10 @@ void     orc_partition(const uint64_t* keys, const uint32_t* vals, int64_t n,
                        int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
                        const uint64_t* table, int32_t shift, int32_t knots, uint32_t B,
                        uint64_t* keys_out, uint32_t* vals_out, int64_t* offsets);
+void     orc_judge(const uint64_t* sorted, int64_t m, int32_t key_bits, int32_t fbits,
+                   uint64_t z_lo, uint64_t z_hi, const uint64_t* table, int32_t shift,
+                   int32_t knots, uint32_t B, uint64_t* max_bucket_err, uint64_t* sum_bucket_err,
+                   uint64_t d_max[2], uint64_t d_sum[2]);
 
 #ifdef __cplusplus
 }

@@ -172,3 +172,55 @@ def test_adam_first_steps_closed_form(orc):
     assert np.allclose(m1, 0.1 * g) and np.allclose(m2, 0.001 * g * g)
     orc.adam_update(p, g, m1, m2, 2, lr)
     assert np.allclose(p0 - p, 2 * step, rtol=1e-9, atol=1e-15)
+
+
+def _ident_table(orc, K=64):
+    ident = {"w1": np.array([1.0]), "b1": np.array([0.0]), "w2": np.array([1.0]), "b2": 0.0}
+    z_lo = orc.feature(1 << 40, 64, 40)
+    return orc.cdf_table(ident, z_lo, z_lo + (1 << 20), K)
+
+
+def test_judge_zero_for_a_perfect_model(orc):
+    # identity table, keys 2^40 + d with F = d / 2^20 exactly below the last
+    # knot (pinned above; 4096 knots put it at d = 4095 * 2^8); sample points
+    # at d_i = (2i+1) 2^9 for m = 2^10 sit exactly on their targets
+    # (2i+1)/(2m): every error is zero
+    tab = _ident_table(orc, 4096)
+    assert tab.shift == 8
+    m, B = 1 << 10, 256
+    keys = np.array([(1 << 40) + (2 * i + 1) * (1 << 9) for i in range(m)], dtype=np.uint64)
+    j = orc.judge(keys, 64, 40, tab, B)
+    assert j["d_max"] == 0 and j["max_err"] == 0.0 and j["max_bucket_err"] == 0
+
+
+def test_judge_identity_model_brute_force(orc):
+    # the same identity model on random sorted offsets: the judge is the
+    # definition |B d_i / 2^20 - B (i + 1/2) / m| in exact rationals
+    from fractions import Fraction
+    tab = _ident_table(orc)
+    rng = np.random.default_rng(17)
+    for m, B in ((1000, 256), (4096, 65536), (3, 2)):
+        d = np.sort(rng.integers(0, 63 << 14, m))
+        keys = ((1 << 40) + d).astype(np.uint64)
+        errs = [abs(Fraction(B * int(di), 1 << 20) - Fraction(B * (2 * i + 1), 2 * m)) for i, di in enumerate(d)]
+        berrs = [abs((int(di) * B >> 20) - (B * (2 * i + 1)) // (2 * m)) for i, di in enumerate(d)]
+        j = orc.judge(keys, 64, 40, tab, B)
+        assert j["samples"] == m
+        assert j["max_err"] == float(max(errs))
+        assert j["mean_err"] == float(sum(errs) / m)
+        assert j["max_bucket_err"] == max(berrs) and j["sum_bucket_err"] == sum(berrs)
+
+
+def test_judge_constant_model_closed_form(orc):
+    # F = 0 everywhere: bucket(x_i) = 0, so the bucket error is floor(B y_i);
+    # with m = kB that is k copies of 0..B-1: mean (B-1)/2, maximum B-1.  The
+    # CDF error B y_i has maximum B (2m-1)/(2m) and mean B/2.
+    K = 16
+    tab = orc.Table(np.zeros(K + 1, dtype=np.uint64), 4, K, 0, K << 4)
+    for k, B in ((1, 8), (3, 1024), (7, 2)):
+        m = k * B
+        keys = np.sort(workloads.lognormal(m, B))
+        j = orc.judge(keys, 64, 20, tab, B)
+        assert j["max_bucket_err"] == B - 1 and j["mean_bucket_err"] == (B - 1) / 2
+        assert j["d_max"] == (2 * m - 1) << 32
+        assert j["max_err"] == B * (2 * m - 1) / (2 * m) and j["mean_err"] == B / 2

@@ -188,11 +188,24 @@ typedef struct {
     uint64_t table[VMPS_CDF_MAX_KNOTS + 1];
 } vmps_cdf_model;
 
+/* Bucket statistics and the model's error judge.  The judge runs over the
+ * sorted sample x_0 <= ... <= x_{m-1} with targets y_i = (i + 1/2)/m and F
+ * the compiled table (the function the partition uses):
+ *   bucket error |bucket(x_i) - floor(B y_i)|, an integer;
+ *   CDF error    |B F(x_i) - B y_i| in buckets, from exact 128-bit integer
+ *                numerators rounded to double at the end.
+ * All zero when the call took the plain path (judge_samples == 0). */
 typedef struct {
     int64_t buckets, nonempty_buckets;
     int64_t fallback_buckets, fallback_keys; /* buckets longer than the LDS tile */
     int64_t max_bucket;
     float loss_init, loss_final;
+    int64_t judge_samples;         /* m */
+    int64_t judge_max_bucket_err;  /* max_i bucket error */
+    double judge_mean_bucket_err;  /* mean bucket error */
+    double judge_max_err;          /* max_i CDF error (buckets) */
+    double judge_mean_err;         /* mean CDF error (buckets) */
+    double overflow_fraction;      /* fallback_buckets / buckets */
 } vmps_learned_stats;
 
 /* Defaults for n keys of type kt (host struct). */

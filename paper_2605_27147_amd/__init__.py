@@ -56,7 +56,10 @@ class Tuning(ctypes.Structure):
 class LearnedStats(ctypes.Structure):
     _fields_ = [("buckets", ctypes.c_int64), ("nonempty_buckets", ctypes.c_int64),
                 ("fallback_buckets", ctypes.c_int64), ("fallback_keys", ctypes.c_int64),
-                ("max_bucket", ctypes.c_int64), ("loss_init", ctypes.c_float), ("loss_final", ctypes.c_float)]
+                ("max_bucket", ctypes.c_int64), ("loss_init", ctypes.c_float), ("loss_final", ctypes.c_float),
+                ("judge_samples", ctypes.c_int64), ("judge_max_bucket_err", ctypes.c_int64),
+                ("judge_mean_bucket_err", ctypes.c_double), ("judge_max_err", ctypes.c_double),
+                ("judge_mean_err", ctypes.c_double), ("overflow_fraction", ctypes.c_double)]
 
 
 class VmpsError(RuntimeError):

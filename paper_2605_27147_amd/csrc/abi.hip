@@ -409,7 +409,7 @@ uint32_t auto_buckets(uint64_t n, uint32_t T, int key_bits, bool has_values)
 }
 
 struct LearnedLayout {
-    size_t keys_b, vals_b, sample, sample_ws, u, model, boff, arena, plan, total;
+    size_t keys_b, vals_b, sample, sample_ws, u, model, boff, judge, arena, plan, total;
     uint32_t B, T;
     uint64_t m;
 };
@@ -429,6 +429,7 @@ LearnedLayout learned_layout(uint64_t n, vmps_dtype kt, int has_values, const vm
     L.u = off; off += align256(4 * L.m);
     L.model = off; off += align256(sizeof(vmps_cdf_model));
     L.boff = off; off += align256(8 * ((uint64_t)L.B + 1));
+    L.judge = off; off += align256(8 * 6 * (size_t)JUDGE_GRID);
     L.arena = off; off += align256(4 * partition_arena_words(n, L.B));
     L.plan = off;
     off += plan_workspace_bytes(n, L.B, L.T, merge_tile_out(kb, has_values));
@@ -521,7 +522,9 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
         VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
-        if (stats) VMPS_HIP(learned_stats_enqueue(boff, L.B, T, M, stats, s));
+        if (stats)
+            VMPS_HIP(learned_stats_enqueue(boff, L.B, T, M, w + L.sample, L.m, kb, (uint64_t*)(w + L.judge), stats,
+                                           s));
         if (model) VMPS_HIP(hipMemcpyAsync(model, M, sizeof(vmps_cdf_model), hipMemcpyDeviceToDevice, s));
         return hipGetLastError();
     });

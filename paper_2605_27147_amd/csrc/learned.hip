@@ -48,19 +48,20 @@ struct ModelArgs {
     const uint64_t* table;
 };
 
-__device__ inline uint32_t bucket_of(uint64_t key, const ModelArgs& M)
+// F(key) of the compiled table in Q32: integer interpolation between knots.
+__device__ inline uint64_t cdf_pos(uint64_t key, const ModelArgs& M)
 {
     const uint64_t z = feature_of(key, M.fbits);
     const uint64_t d = z <= M.z_lo ? 0 : (z - M.z_lo > M.range ? M.range : z - M.z_lo);
     const uint64_t seg = d >> M.shift;
-    uint64_t pos;
-    if (seg >= (uint64_t)M.knots) {
-        pos = M.table[M.knots];
-    } else {
-        const uint64_t t0 = M.table[seg], t1 = M.table[seg + 1];
-        pos = t0 + (((t1 - t0) * (d & ((1ull << M.shift) - 1))) >> M.shift);
-    }
-    const uint64_t b = (pos * M.B) >> 32;
+    if (seg >= (uint64_t)M.knots) return M.table[M.knots];
+    const uint64_t t0 = M.table[seg], t1 = M.table[seg + 1];
+    return t0 + (((t1 - t0) * (d & ((1ull << M.shift) - 1))) >> M.shift);
+}
+
+__device__ inline uint32_t bucket_of(uint64_t key, const ModelArgs& M)
+{
+    const uint64_t b = (cdf_pos(key, M) * M.B) >> 32;
     return (uint32_t)(b >= M.B ? M.B - 1 : b);
 }
 
@@ -651,11 +652,78 @@ __global__ void k_bucket_offsets(const uint32_t* __restrict__ pstart2, const uin
     off[b] = nt ? offs2[(uint64_t)tbase2[c] * F2 + (uint64_t)f * nt] : pstart2[c];
 }
 
+// Error judge of the compiled model on the sorted sample x_0..x_{m-1},
+// targets y_i = (i + 1/2)/m.  Per point: the bucket error
+// |bucket(x_i) - floor(B y_i)| and the exact numerator
+// d_i = |2m F(x_i) 2^32 - 2^32 (2i+1)| of the CDF error B d_i / (2^33 m).
+// Each workgroup writes its maxima and sums (128-bit as two words) to
+// part[6 * blockIdx.x ...]; k_learned_stats combines them.
+typedef unsigned __int128 u128;
+
+template <typename K>
+__global__ __launch_bounds__(256) void k_learned_judge(const K* __restrict__ sample, uint64_t m,
+                                                       const vmps_cdf_model* model, uint32_t B,
+                                                       uint64_t* __restrict__ part)
+{
+    __shared__ uint64_t s_mb[256], s_sb[256];
+    __shared__ u128 s_dm[256], s_ds[256];
+    const ModelArgs M = model_args(model, B);
+    uint64_t mb = 0, sb = 0;
+    u128 dm = 0, ds = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < m; i += (uint64_t)gridDim.x * 256) {
+        const uint64_t pos = cdf_pos((uint64_t)sample[i], M);
+        uint64_t b = (pos * B) >> 32;
+        b = b >= B ? B - 1 : b;
+        const uint64_t want = ((uint64_t)B * (2 * i + 1)) / (2 * m);
+        const uint64_t eb = b > want ? b - want : want - b;
+        mb = eb > mb ? eb : mb;
+        sb += eb;
+        const u128 a = (u128)pos * (u128)(2 * m);
+        const u128 t = (u128)(2 * i + 1) << 32;
+        const u128 d = a > t ? a - t : t - a;
+        dm = d > dm ? d : dm;
+        ds += d;
+    }
+    s_mb[threadIdx.x] = mb; s_sb[threadIdx.x] = sb; s_dm[threadIdx.x] = dm; s_ds[threadIdx.x] = ds;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            s_mb[threadIdx.x] = s_mb[o] > s_mb[threadIdx.x] ? s_mb[o] : s_mb[threadIdx.x];
+            s_sb[threadIdx.x] += s_sb[o];
+            s_dm[threadIdx.x] = s_dm[o] > s_dm[threadIdx.x] ? s_dm[o] : s_dm[threadIdx.x];
+            s_ds[threadIdx.x] += s_ds[o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        uint64_t* p = part + 6 * (uint64_t)blockIdx.x;
+        p[0] = s_mb[0]; p[1] = s_sb[0];
+        p[2] = (uint64_t)s_dm[0]; p[3] = (uint64_t)(s_dm[0] >> 64);
+        p[4] = (uint64_t)s_ds[0]; p[5] = (uint64_t)(s_ds[0] >> 64);
+    }
+}
+
+__device__ inline double u128_to_double(u128 x)
+{
+    return (double)(uint64_t)(x >> 64) * 18446744073709551616.0 + (double)(uint64_t)x;
+}
+
 __global__ __launch_bounds__(256) void k_learned_stats(const int64_t* __restrict__ off, uint32_t B, uint32_t T,
-                                                       const vmps_cdf_model* model, vmps_learned_stats* st)
+                                                       const vmps_cdf_model* model, uint64_t m,
+                                                       const uint64_t* __restrict__ part, vmps_learned_stats* st)
 {
     __shared__ unsigned long long s_ne, s_fb, s_fk, s_mx;
+    __shared__ uint64_t s_mb[JUDGE_GRID], s_sb[JUDGE_GRID];
+    __shared__ u128 s_dm[JUDGE_GRID], s_ds[JUDGE_GRID];
+    static_assert(JUDGE_GRID == 256, "one judge partial per thread");
     if (threadIdx.x == 0) { s_ne = 0; s_fb = 0; s_fk = 0; s_mx = 0; }
+    {
+        const uint64_t* p = part + 6 * threadIdx.x;
+        s_mb[threadIdx.x] = p[0]; s_sb[threadIdx.x] = p[1];
+        s_dm[threadIdx.x] = ((u128)p[3] << 64) | p[2];
+        s_ds[threadIdx.x] = ((u128)p[5] << 64) | p[4];
+    }
     __syncthreads();
     unsigned long long ne = 0, fb = 0, fk = 0, mx = 0;
     for (uint32_t b = threadIdx.x; b < B; b += 256) {
@@ -665,11 +733,27 @@ __global__ __launch_bounds__(256) void k_learned_stats(const int64_t* __restrict
         mx = len > mx ? len : mx;
     }
     atomicAdd(&s_ne, ne); atomicAdd(&s_fb, fb); atomicAdd(&s_fk, fk); atomicMax(&s_mx, mx);
-    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            const int o = threadIdx.x + w;
+            s_mb[threadIdx.x] = s_mb[o] > s_mb[threadIdx.x] ? s_mb[o] : s_mb[threadIdx.x];
+            s_sb[threadIdx.x] += s_sb[o];
+            s_dm[threadIdx.x] = s_dm[o] > s_dm[threadIdx.x] ? s_dm[o] : s_dm[threadIdx.x];
+            s_ds[threadIdx.x] += s_ds[o];
+        }
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
         st->buckets = B; st->nonempty_buckets = (int64_t)s_ne; st->fallback_buckets = (int64_t)s_fb;
         st->fallback_keys = (int64_t)s_fk; st->max_bucket = (int64_t)s_mx;
         st->loss_init = model->loss_init; st->loss_final = model->loss_final;
+        const double dm = (double)m, denom = dm * 8589934592.0;  // 2^33 m
+        st->judge_samples = (int64_t)m;
+        st->judge_max_bucket_err = (int64_t)s_mb[0];
+        st->judge_mean_bucket_err = (double)s_sb[0] / dm;
+        st->judge_max_err = u128_to_double(s_dm[0]) * (double)B / denom;
+        st->judge_mean_err = u128_to_double(s_ds[0]) * (double)B / denom / dm;
+        st->overflow_fraction = (double)s_fb / (double)B;
     }
 }
 
@@ -820,9 +904,14 @@ hipError_t bucket_ids_enqueue(const void* keys, uint64_t n, int key_bits, const 
 }
 
 hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
+                                 const void* sample, uint64_t m, int key_bits, uint64_t* part,
                                  vmps_learned_stats* st, hipStream_t s)
 {
-    k_learned_stats<<<1, 256, 0, s>>>(off, B, T, model, st);
+    if (key_bits == 64)
+        k_learned_judge<uint64_t><<<JUDGE_GRID, 256, 0, s>>>((const uint64_t*)sample, m, model, B, part);
+    else
+        k_learned_judge<uint32_t><<<JUDGE_GRID, 256, 0, s>>>((const uint32_t*)sample, m, model, B, part);
+    k_learned_stats<<<1, 256, 0, s>>>(off, B, T, model, m, part, st);
     return hipGetLastError();
 }
 

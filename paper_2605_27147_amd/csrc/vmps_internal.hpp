@@ -233,7 +233,11 @@ hipError_t compile_enqueue(const float* params, int H, uint64_t z_lo, uint64_t z
                            int K, vmps_cdf_model* model, hipStream_t s);
 hipError_t bucket_ids_enqueue(const void* keys, uint64_t n, int key_bits, const vmps_cdf_model* model,
                               uint32_t B, uint32_t* ids, hipStream_t s);
+// Error judge over the sorted sample (JUDGE_GRID workgroups, 6 partial
+// words each in part), then the bucket statistics.
+constexpr uint32_t JUDGE_GRID = 256;
 hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
+                                 const void* sample, uint64_t m, int key_bits, uint64_t* part,
                                  vmps_learned_stats* st, hipStream_t s);
 
 }  // namespace vmps

@@ -76,3 +76,36 @@ def test_graph_capture_rejects_bad_arguments_without_gpu_work():
     assert lib.vmps_segmented_sort_graph(None, None, None, 0, 0, vm.U32, None, 0, None) == 1
     assert lib.vmps_graph_launch(None, None) == 1
     assert lib.vmps_graph_destroy(None) == 1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The binding's ctypes structs have the C header's size and field
+    offsets (compiled with the host C compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_2605_27147_amd as vm
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"vmps_learned_config": vm.LearnedConfig, "vmps_cdf_model": vm.CdfModel,
+               "vmps_tuning": vm.Tuning, "vmps_learned_stats": vm.LearnedStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vmps.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["return 0; }"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run([cc, "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        c, f, v = ln.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -245,3 +245,41 @@ def test_trained_model_beats_untrained(vm, orc):
     # levels as the untrained one (measured: 4% against 71% at n = 2^22)
     assert stats["fallback_keys"] * 4 < id_fallback
     assert stats["loss_final"] <= stats["loss_init"]
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_error_judge_matches_oracle(vm, orc, bits):
+    """The judge in the statistics equals the oracle's judge of the returned
+    compiled model on the same sorted sample: integer fields exactly, the
+    doubles (exact 128-bit numerators, rounded once or twice at the end) to a
+    relative 1e-12."""
+    dt = np.uint32 if bits == 32 else np.uint64
+    inputs = [("lognormal", (workloads.lognormal(1 << 20, 51) >> np.uint64(32 if bits == 32 else 0)).astype(dt)),
+              ("uniform", workloads.uniform((1 << 19) + 99, bits, 52)),
+              ("dup16", workloads.dup16(1 << 19, 53).astype(dt))]
+    for name, x in inputs:
+        n = x.size
+        cfg = vm.learned_default_config(n, vm.U32 if bits == 32 else vm.U64)
+        if name == "uniform":
+            cfg.sample_size = 5000   # not a power of two
+        _say("judge", bits, name, n, cfg.sample_size)
+        stats, model = vm.sort_learned_(_t(x), cfg=cfg, want_model=True)
+        sample = np.sort(x[orc.sample_positions(n, cfg.sample_size, cfg.seed)])
+        tab = orc.Table(np.array(model.table[: model.knots + 1], dtype=np.uint64), model.shift, model.knots,
+                        model.z_lo, model.z_hi)
+        B = stats["buckets"]
+        want = orc.judge(sample, bits, model.feature_bits, tab, B)
+        _say("  gpu", {k: v for k, v in stats.items() if k.startswith(("judge", "overflow"))})
+        _say("  oracle", {k: v for k, v in want.items() if k not in ("d_max", "d_sum")})
+        assert stats["judge_samples"] == cfg.sample_size
+        assert stats["judge_max_bucket_err"] == want["max_bucket_err"]
+        assert stats["judge_mean_bucket_err"] == want["mean_bucket_err"]
+        assert stats["judge_max_err"] == pytest.approx(want["max_err"], rel=1e-12, abs=0)
+        assert stats["judge_mean_err"] == pytest.approx(want["mean_err"], rel=1e-12, abs=0)
+        assert stats["overflow_fraction"] == stats["fallback_buckets"] / B
+
+
+def test_error_judge_zero_on_plain_path(vm):
+    x = workloads.lognormal(5000, 54)
+    stats, _ = vm.sort_learned_(_t(x))
+    assert stats["judge_samples"] == 0 and stats["buckets"] == 0

@@ -82,6 +82,27 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             jb = M + (d - lo);
         }
         K ha = S[px(ia)], hb = S[px(jb)];
+        if (__all(p0 + KI <= R)) {
+            // Every lane's KI outputs lie in its first node (runs and nodes
+            // aligned to KI, as in a large instance): no node changes, and
+            // every index stays <= R <= TCAP.  Wave-uniform, so a wave never
+            // runs both loops.
+#pragma unroll
+            for (int j = 0; j < KI; ++j) {
+                const bool takeA = ia < M && (jb >= R || ha <= hb);
+                const uint32_t cur = takeA ? ia : jb;
+                rk[j] = takeA ? ha : hb;
+                if (VMODE) rv[j] = SV[px(cur)];
+                const uint32_t nx = cur + 1;
+                ia = takeA ? nx : ia;
+                jb = takeA ? jb : nx;
+                if (j + 1 < KI) {
+                    const K nv = S[px(nx)];
+                    ha = takeA ? nv : ha;
+                    hb = takeA ? hb : nv;
+                }
+            }
+        } else {
 #pragma unroll
         for (int j = 0; j < KI; ++j) {
             const uint32_t q = p0 + j;
@@ -103,6 +124,7 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             const K nv = S[px(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
             ha = takeA ? nv : ha;
             hb = takeA ? hb : nv;
+        }
         }
     }
     __syncthreads();

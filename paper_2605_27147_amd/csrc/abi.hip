@@ -222,6 +222,7 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
             return tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s);
         }
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(level_probe_enqueue(P, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
@@ -374,6 +375,7 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
     hipStream_t s = (hipStream_t)stream;
     return guarded([&]() -> hipError_t {
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(level_probe_enqueue(P, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
@@ -520,6 +522,7 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         P.inst_off64 = boff;
         P.big_min = T;
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
+        VMPS_HIP(level_probe_enqueue(P, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
         VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
         if (stats)

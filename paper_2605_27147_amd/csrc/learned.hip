@@ -108,12 +108,28 @@ __global__ void k_cdf_features(const K* __restrict__ s, uint64_t m, int key_bits
 }
 
 // ------------------------------------------------------------- model --
-// Sum over the H lanes of a lane group (xor butterfly; H divides 64).
+// v of another lane by a DPP lane pattern (VALU only, no LDS traffic).
+template <int CTRL>
+__device__ inline float dpp_f32(float v)
+{
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum over the H lanes of a lane group (H divides 64), the xor butterfly
+// order: lane ^ 1 and lane ^ 2 by quad permutations; then, with every quad
+// (and later every 8 lanes) holding one common value, the mirror inside 8
+// and inside 16 lanes reads the same values as lane ^ 4 and lane ^ 8; lane
+// ^ 16 by a swizzle inside 32 lanes, lane ^ 32 by a shuffle.
 template <int H>
 __device__ inline float group_sum(float v)
 {
-#pragma unroll
-    for (int off = 1; off < H; off <<= 1) v += __shfl_xor(v, off, 64);
+    static_assert(H >= 2 && H <= 64 && (H & (H - 1)) == 0, "lane group of a power of two");
+    v += dpp_f32<0xB1>(v);                 // quad_perm [1,0,3,2]
+    if (H > 2) v += dpp_f32<0x4E>(v);      // quad_perm [2,3,0,1]
+    if (H > 4) v += dpp_f32<0x141>(v);     // row_half_mirror
+    if (H > 8) v += dpp_f32<0x140>(v);     // row_mirror
+    if (H > 16) v += __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v), 0x401F));  // xor 16
+    if (H > 32) v += __shfl_xor(v, 32, 64);
     return v;
 }
 
@@ -155,7 +171,36 @@ __device__ void batch_grad(TrainLds& S, int nb, Point point)
             S.by[t] = yy;
         }
         __syncthreads();
-        for (int j = grp; j < cnt; j += G) {
+        // UB points at a time: their cross-lane sums are independent, so the
+        // shuffles overlap; the accumulation below keeps the point order
+        constexpr int UB = 8;
+        int j = grp;
+        for (; j + (UB - 1) * G < cnt; j += UB * G) {
+            float uu[UB], yy[UB], aa[UB], rr[UB], ff[UB];
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                uu[q] = S.bu[j + q * G];
+                yy[q] = S.by[j + q * G];
+                aa[q] = w1 * uu[q] + b1;
+                rr[q] = aa[q] > 0.f ? aa[q] : 0.f;
+                ff[q] = w2 * rr[q];
+            }
+#pragma unroll
+            for (int q = 0; q < UB; ++q) ff[q] = group_sum<H>(ff[q]);
+#pragma unroll
+            for (int q = 0; q < UB; ++q) {
+                const float e = (ff[q] + b2) - yy[q];
+                const float dfd = inv * e;
+                if (aa[q] > 0.f) {
+                    aw2 += dfd * rr[q];
+                    aw1 += dfd * w2 * uu[q];
+                    ab1 += dfd * w2;
+                }
+                ab2 += dfd;
+                al += e * e;
+            }
+        }
+        for (; j < cnt; j += G) {
             const float u = S.bu[j], y = S.by[j];
             const float a = w1 * u + b1;
             const float r = a > 0.f ? a : 0.f;
@@ -230,11 +275,14 @@ __device__ float strided_loss(TrainLds& S, const float* __restrict__ u, uint64_t
         const float e = model_eval<H>(S.p, u[i]) - ((float)i + 0.5f) / (float)m;
         acc += e * e;
     }
-    S.pl[t] = acc;
+    // fixed-order reduction: a butterfly inside each wave, then the waves in order
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+    if ((t & 63) == 0) S.pl[t >> 6] = acc;
     __syncthreads();
     if (t == 0) {
         float s = 0.f;
-        for (int k = 0; k < TRAIN_NT; ++k) s += S.pl[k];
+        for (int k = 0; k < TRAIN_NT / 64; ++k) s += S.pl[k];
         S.loss = s / (float)cnt;
     }
     __syncthreads();

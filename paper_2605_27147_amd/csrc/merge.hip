@@ -74,6 +74,41 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
     }
 }
 
+// Per host thread and device: a pinned copy of the level counts and the
+// event that marks its arrival (allocated on first use, kept until exit).
+struct LevelProbe {
+    uint32_t* host = nullptr;
+    hipEvent_t ev = nullptr;
+    const uint32_t* src = nullptr;
+    bool armed = false;
+};
+
+static LevelProbe& level_probe()
+{
+    thread_local LevelProbe pr[16];
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) d = 0;
+    return pr[d & 15];
+}
+
+hipError_t level_probe_enqueue(const Plan& P, hipStream_t s)
+{
+    LevelProbe& pr = level_probe();
+    pr.armed = false;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    VMPS_HIP(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return hipSuccess;  // a graph launches every level
+    if (!pr.host) {
+        VMPS_HIP(hipHostMalloc((void**)&pr.host, sizeof(uint32_t) * MAX_LEVEL, hipHostMallocDefault));
+        VMPS_HIP(hipEventCreateWithFlags(&pr.ev, hipEventDisableTiming));
+    }
+    VMPS_HIP(hipMemcpyAsync(pr.host, P.level, sizeof(uint32_t) * MAX_LEVEL, hipMemcpyDeviceToHost, s));
+    VMPS_HIP(hipEventRecord(pr.ev, s));
+    pr.src = P.level;
+    pr.armed = true;
+    return hipSuccess;
+}
+
 template <typename K, bool VAL, int NT, int KI>
 static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
                                 hipStream_t s)
@@ -103,15 +138,31 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     const int tg = tuning_for(sizeof(K) * 8, VAL).merge_grid;
     const uint64_t gcap = tg > 0 ? (uint64_t)tg : 2048u;
     const unsigned mgrid = (unsigned)(most < gcap ? most : gcap);
+    uint32_t cnt[MAX_LEVEL];
+    bool known = false;
+    LevelProbe& pr = level_probe();
+    if (pr.armed && pr.src == P.level) {
+        pr.armed = false;
+        VMPS_HIP(hipEventSynchronize(pr.ev));
+        for (int l = 0; l < MAX_LEVEL; ++l) cnt[l] = pr.host[l];
+        known = true;
+    }
     for (int lvl = (int)top; lvl >= 1; --lvl) {
         A.lvl = (uint32_t)lvl;
+        unsigned pg = pgrid, mg = mgrid;
+        if (known) {
+            if (cnt[lvl] == 0) continue;
+            const uint64_t c = cnt[lvl];
+            pg = (unsigned)(ceil_div(2 * c, 256) < pgrid ? ceil_div(2 * c, 256) : pgrid);
+            mg = (unsigned)(c < mgrid ? c : mgrid);
+        }
         {
             TraceScope tr(VMPS_TRACE_LEVEL_PARTITION, s);
-            k_level_partition<K><<<pgrid, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
+            k_level_partition<K><<<pg, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
         }
         {
             TraceScope tr(VMPS_TRACE_LEVEL_MERGE, s);
-            k_level_merge<K, VAL, NT, KI><<<mgrid, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+            k_level_merge<K, VAL, NT, KI><<<mg, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
         }
     }
     return hipGetLastError();

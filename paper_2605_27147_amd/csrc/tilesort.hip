@@ -331,11 +331,12 @@ __device__ __forceinline__ void tile_load(K* __restrict__ S, uint32_t* __restric
     }
 }
 
-// LDS -> HBM, the reverse of tile_load.
-template <typename K, int NT, int TCAP, int VMODE>
-__device__ __forceinline__ void tile_store(const K* __restrict__ S, const uint32_t* __restrict__ SV,
+// LDS -> HBM, the reverse of tile_load; element x of the LDS copy goes out
+// as base + x (base = 0 for a full-width copy).
+template <typename KT, typename K, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint32_t* __restrict__ SV,
                                            K* __restrict__ dst, uint32_t* __restrict__ vdst, uint32_t a, uint32_t len,
-                                           uint32_t tid)
+                                           uint32_t tid, K base)
 {
     static_assert(NT % 32 == 0, "affine padded index");
     constexpr int CH = TCAP / NT;
@@ -349,7 +350,7 @@ __device__ __forceinline__ void tile_store(const K* __restrict__ S, const uint32
         for (int j = 0; j < BT; ++j) {
             const uint32_t i = (uint32_t)((c + j) * NT) + tid;
             const uint32_t pi = pt + (uint32_t)((c + j) * (NT + NT / 32));  // px(i), NT a multiple of 32
-            r[j] = i < len ? S[pi] : K(0);
+            r[j] = i < len ? base + (K)S[pi] : K(0);
             v[j] = (VMODE && i < len) ? SV[pi] : 0u;
         }
 #pragma unroll
@@ -363,79 +364,106 @@ __device__ __forceinline__ void tile_store(const K* __restrict__ S, const uint32
     }
 }
 
-// One segment of the LDS pass, by all NT threads of the calling workgroup.
-// smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.
-template <typename K, int NT, int TCAP, int VMODE>
-__device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
-                                             uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
-                                             const Seg sg, const uint32_t* __restrict__ inst_start)
+// HBM -> LDS for 64-bit keys: all CH keys of a thread in registers, the
+// segment's minimum and maximum by a block reduction (red: 4 * NT/64 words
+// of LDS), then either 32-bit offsets from the minimum (returns true, kmin
+// = the minimum) when the range spans less than 2^32, or the keys.
+template <int NT, int TCAP, int VMODE>
+__device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint32_t* __restrict__ SV,
+                                                 const uint64_t* __restrict__ src, const uint32_t* __restrict__ vsrc,
+                                                 uint32_t a, uint32_t len, uint32_t tid, uint32_t* red,
+                                                 uint64_t& kmin)
+{
+    static_assert(NT % 32 == 0, "affine padded index");
+    constexpr int CH = TCAP / NT;
+    constexpr int NW = NT / 64;
+    const uint32_t pt = px(tid);
+    uint64_t r[CH];
+    uint32_t v[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t i = (uint32_t)(c * NT) + tid;
+        r[c] = i < len ? src[a + i] : 0ull;
+        v[c] = (VMODE == 1 && i < len) ? vsrc[a + i] : 0u;
+    }
+    uint64_t lo = ~0ull, hi = 0;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        if ((uint32_t)(c * NT) + tid < len) {
+            lo = r[c] < lo ? r[c] : lo;
+            hi = r[c] > hi ? r[c] : hi;
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint64_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
+        lo = ol < lo ? ol : lo;
+        hi = oh > hi ? oh : hi;
+    }
+    const uint32_t wave = tid >> 6;
+    if ((tid & 63) == 0) {
+        red[4 * wave + 0] = (uint32_t)lo;
+        red[4 * wave + 1] = (uint32_t)(lo >> 32);
+        red[4 * wave + 2] = (uint32_t)hi;
+        red[4 * wave + 3] = (uint32_t)(hi >> 32);
+    }
+    __syncthreads();
+    lo = ~0ull;
+    hi = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const uint64_t wl = ((uint64_t)red[4 * w + 1] << 32) | red[4 * w + 0];
+        const uint64_t wh = ((uint64_t)red[4 * w + 3] << 32) | red[4 * w + 2];
+        lo = wl < lo ? wl : lo;
+        hi = wh > hi ? wh : hi;
+    }
+    const bool narrow = hi - lo <= 0xffffffffull;  // len >= 1, so lo <= hi
+    kmin = lo;
+    uint32_t* S32 = (uint32_t*)S;
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+        const uint32_t i = (uint32_t)(c * NT) + tid;
+        const uint32_t pi = pt + (uint32_t)(c * (NT + NT / 32));  // px(i), NT a multiple of 32
+        if (i < len) {
+            if (narrow) S32[pi] = (uint32_t)(r[c] - lo); else S[pi] = r[c];
+            if (VMODE == 1) SV[pi] = v[c];
+            if (VMODE == 2) SV[pi] = a + i;
+        }
+    }
+    return narrow;
+}
+
+// Pointers into the tile's LDS besides the elements and values.
+struct TileLds {
+    uint64_t* bm;
+    uint32_t *R1, *R2, *RS, *LVs, *LVc, *wcnt, *scan_lds, *scal, *BLs;
+    uint8_t *PW, *SR;
+};
+
+// Steps 2-8 of one segment on the LDS copy S (element type KT): ExtractRun,
+// powers, node lists, the forced runs' sort and the merges.
+template <typename KT, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restrict__ SV, const TileLds& T,
+                                          uint32_t len, uint32_t ell, uint32_t g, uint32_t il, int tid)
 {
     using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
     constexpr int KI = TCAP / NT;
     constexpr uint32_t RC = MT::RC;
-    static_assert(TCAP % NT == 0 && KI <= 32, "tile must split evenly, at most 32 outputs per thread");
-    static_assert(TCAP / 64 + 1 <= NT, "one thread per bitmap word");
-    // every run but an instance's last is at least 32 long, so a tile holds
-    // fewer than TCAP / 32 boundaries
-    static_assert(TCAP / 32 <= 64 * NW, "one thread per boundary in the power ranking");
-
-    uint8_t* sp = smem;
-    K* S = (K*)sp; sp += sizeof(K) * MT::SP;
-    uint32_t* SV = nullptr;
-    if (VMODE) { SV = (uint32_t*)sp; sp += 4 * MT::SP; }
-    uint64_t* bm = (uint64_t*)sp; sp += 8 * MT::BW;
-    uint32_t* R1 = (uint32_t*)sp; sp += 4 * 2 * RC;
-    uint32_t* R2 = (uint32_t*)sp; sp += 4 * 2 * (RC + 1);
-    uint32_t* RS = (uint32_t*)sp; sp += 4 * (RC + 1);
-    uint32_t* LVs = (uint32_t*)sp; sp += 4 * 34;
-    uint32_t* LVc = (uint32_t*)sp; sp += 4 * 34;
-    uint32_t* wcnt = (uint32_t*)sp; sp += 4 * NW * 33;
-    uint32_t* scan_lds = (uint32_t*)sp; sp += 4 * (NW + 1);
-    uint32_t* scal = (uint32_t*)sp; sp += 4 * 16;  // [0] progressions [1] runs [2] power mask [3] max unsorted run
-    uint32_t* BLs = (uint32_t*)sp; sp += 4 * RC;  // BL of NL[i]: node starts in level order
-    uint8_t* PW = sp; sp += RC;
-    uint8_t* SR = sp;
-    // aliases: long runs -> (Q, node list); progressions -> (node L, node R)
-    uint32_t* LRu = R1;
-    uint32_t* LRe = R1 + RC;
-    uint32_t* Qv = R1;
-    uint32_t* NL = R1 + RC;
-    uint32_t* PGb = R2;
-    uint32_t* PGc = R2 + RC + 1;
-    uint32_t* BL = R2;
-    uint32_t* BR = R2 + RC + 1;
-
-    // the thread index is made opaque per segment so that the compiler
-    // does not keep every unrolled address live across the whole loop
-    int tid = threadIdx.x;
-    asm volatile("" : "+v"(tid));
     const int lane = tid & 63, wave = tid >> 6;
-    const uint32_t a = sg.start;
-    const uint32_t len = sg.end - sg.start;
-    if (len == 0) return;
-    if (len > TCAP) {
-        // a single natural run longer than the tile: already sorted
-        if (sg.dst == 1) {
-            for (uint32_t i = tid; i < len; i += NT) {
-                keysB[a + i] = keysA[a + i];
-                if (VMODE == 1) valsB[a + i] = valsA[a + i];
-                if (VMODE == 2) valsB[a + i] = a + i;
-            }
-        } else if (VMODE == 2) {
-            for (uint32_t i = tid; i < len; i += NT) valsA[a + i] = a + i;
-        }
-        return;
-    }
-    const uint32_t ib = inst_start[sg.inst];
-    const uint32_t il = inst_start[sg.inst + 1] - ib;
-    const uint32_t ell = minrun_of(il);
-    const uint32_t g = a - ib;
-
-    // 1. load
-    tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
-    if (tid < 16) scal[tid] = 0;
-    __syncthreads();
+    uint64_t* bm = T.bm;
+    uint32_t *RS = T.RS, *LVs = T.LVs, *LVc = T.LVc, *wcnt = T.wcnt, *scan_lds = T.scan_lds, *scal = T.scal,
+             *BLs = T.BLs;
+    uint8_t *PW = T.PW, *SR = T.SR;
+    // aliases: long runs -> (Q, node list); progressions -> (node L, node R)
+    uint32_t* LRu = T.R1;
+    uint32_t* LRe = T.R1 + RC;
+    uint32_t* Qv = T.R1;
+    uint32_t* NL = T.R1 + RC;
+    uint32_t* PGb = T.R2;
+    uint32_t* PGc = T.R2 + RC + 1;
+    uint32_t* BL = T.R2;
+    uint32_t* BR = T.R2 + RC + 1;
 
     // 2. descent bitmap (positions >= len count as boundaries)
     const uint32_t W = len / 64 + 1;
@@ -622,21 +650,109 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
         for (uint32_t x = tid; x < cpr * kr; x += NT) {
             const uint32_t r = x / cpr, c = x - r * cpr;
             const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
-            if (!SR[r] && cs + 1 < ce) chunk_sort16<K, VMODE>(S, SV, cs, min(16u, ce - cs));
+            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE>(S, SV, cs, min(16u, ce - cs));
         }
         __syncthreads();
     }
     if (len <= (uint32_t)(NT * (KI / 2)))
-        tile_merges<K, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
     else
-        tile_merges<K, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+}
 
-    // 9. one write to the planned buffer
+// One segment of the LDS pass, by all NT threads of the calling workgroup.
+// smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.
+template <typename K, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
+                                             uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
+                                             const Seg sg, const uint32_t* __restrict__ inst_start)
+{
+    using MT = TileMeta<TCAP>;
+    constexpr int NW = NT / 64;
+    constexpr int KI = TCAP / NT;
+    constexpr uint32_t RC = MT::RC;
+    static_assert(TCAP % NT == 0 && KI <= 32, "tile must split evenly, at most 32 outputs per thread");
+    static_assert(TCAP / 64 + 1 <= NT, "one thread per bitmap word");
+    // every run but an instance's last is at least 32 long, so a tile holds
+    // fewer than TCAP / 32 boundaries
+    static_assert(TCAP / 32 <= 64 * NW, "one thread per boundary in the power ranking");
+
+    uint8_t* sp = smem;
+    K* S = (K*)sp; sp += sizeof(K) * MT::SP;
+    uint32_t* SV = nullptr;
+    if (VMODE) { SV = (uint32_t*)sp; sp += 4 * MT::SP; }
+    uint64_t* bm = (uint64_t*)sp; sp += 8 * MT::BW;
+    uint32_t* R1 = (uint32_t*)sp; sp += 4 * 2 * RC;
+    uint32_t* R2 = (uint32_t*)sp; sp += 4 * 2 * (RC + 1);
+    uint32_t* RS = (uint32_t*)sp; sp += 4 * (RC + 1);
+    uint32_t* LVs = (uint32_t*)sp; sp += 4 * 34;
+    uint32_t* LVc = (uint32_t*)sp; sp += 4 * 34;
+    uint32_t* wcnt = (uint32_t*)sp; sp += 4 * NW * 33;
+    uint32_t* scan_lds = (uint32_t*)sp; sp += 4 * (NW + 1);
+    uint32_t* scal = (uint32_t*)sp; sp += 4 * 16;  // [0] progressions [1] runs [2] power mask [3] max unsorted run
+    uint32_t* BLs = (uint32_t*)sp; sp += 4 * RC;  // BL of NL[i]: node starts in level order
+    uint8_t* PW = sp; sp += RC;
+    uint8_t* SR = sp;
+
+    // the thread index is made opaque per segment so that the compiler
+    // does not keep every unrolled address live across the whole loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int lane = tid & 63, wave = tid >> 6;
+    const uint32_t a = sg.start;
+    const uint32_t len = sg.end - sg.start;
+    if (len == 0) return;
+    if (len > TCAP) {
+        // a single natural run longer than the tile: already sorted
+        if (sg.dst == 1) {
+            for (uint32_t i = tid; i < len; i += NT) {
+                keysB[a + i] = keysA[a + i];
+                if (VMODE == 1) valsB[a + i] = valsA[a + i];
+                if (VMODE == 2) valsB[a + i] = a + i;
+            }
+        } else if (VMODE == 2) {
+            for (uint32_t i = tid; i < len; i += NT) valsA[a + i] = a + i;
+        }
+        return;
+    }
+    const uint32_t ib = inst_start[sg.inst];
+    const uint32_t il = inst_start[sg.inst + 1] - ib;
+    const uint32_t ell = minrun_of(il);
+    const uint32_t g = a - ib;
+
+    // 1. load; 64-bit keys whose range in the segment spans less than 2^32
+    // are kept as 32-bit offsets from the segment's minimum (an order- and
+    // equality-preserving map, so every step below gives the same result)
+    bool narrow = false;
+    K kmin = 0;
+    if constexpr (sizeof(K) == 8)
+        narrow = tile_load_narrow<NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid, wcnt, kmin);
+    else
+        tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
+    if (tid < 16) scal[tid] = 0;
+    __syncthreads();
+
+    // 2.-8. on the narrow or the full-width copy; 9. one write to the
+    // planned buffer
+    const TileLds T{bm, R1, R2, RS, LVs, LVc, wcnt, scan_lds, scal, BLs, PW, SR};
     int tid_st = tid;
     asm volatile("" : "+v"(tid_st));
-    tile_store<K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st);
+    if constexpr (sizeof(K) == 8) {
+        if (narrow) {
+            tile_body<uint32_t, NT, TCAP, VMODE>((uint32_t*)S, SV, T, len, ell, g, il, tid);
+            asm volatile("" : "+v"(tid_st));
+            tile_store<uint32_t, K, NT, TCAP, VMODE>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
+                                                    sg.dst ? valsB : valsA, a, len, tid_st, kmin);
+            __syncthreads();
+            return;
+        }
+    }
+    tile_body<K, NT, TCAP, VMODE>(S, SV, T, len, ell, g, il, tid);
+    asm volatile("" : "+v"(tid_st));
+    tile_store<K, K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
     __syncthreads();
 }
+
 
 // The LDS pass as one persistent launch: as many workgroups as can be
 // resident, each taking the next segment from an atomic ticket (segments

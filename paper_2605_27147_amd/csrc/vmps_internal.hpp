@@ -209,6 +209,11 @@ uint32_t tilesort_capacity(int key_bits, int has_values);
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
 
 // HBM merge levels.
+// Copies the planner's per-level pair counts to pinned host memory (not
+// while the stream is being captured).  The next merge_levels_enqueue for
+// the same plan waits for that copy only (the tile pass enqueued in between
+// keeps the GPU busy meanwhile) and launches the non-empty levels alone.
+hipError_t level_probe_enqueue(const Plan& P, hipStream_t s);
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                                 uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
 uint32_t merge_tile_out(int key_bits, int has_values);

@@ -530,6 +530,66 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ key
     }
 }
 
+// Level-1 histogram with the model: the level's tiles are the aligned
+// PART_TILE blocks of the whole array.  Each workgroup copies the knot
+// table into LDS once and then takes tiles tile, tile + grid, ...; keys
+// are read two at a time and the two 16-bit ids written as one word.
+template <typename K>
+__global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ keys, uint16_t* __restrict__ ids_out,
+                                                        uint32_t n, uint32_t nt1, uint32_t F, uint32_t shift,
+                                                        uint32_t mask, uint32_t* __restrict__ counts,
+                                                        const vmps_cdf_model* __restrict__ model, uint32_t B)
+{
+    struct alignas(2 * sizeof(K)) KPair { K a, b; };
+    constexpr int RP = PART_RND / 2;  // key pairs per thread
+    __shared__ uint64_t tab[VMPS_CDF_MAX_KNOTS + 1];
+    __shared__ uint32_t hist[PART_NW][256];
+    const int tid = threadIdx.x, wave = tid >> 6;
+    ModelArgs M = model_args(model, B);
+    for (int i = tid; i <= M.knots; i += PART_NT) tab[i] = M.table[i];
+    M.table = tab;
+    for (uint32_t tile = blockIdx.x; tile < nt1; tile += gridDim.x) {
+        for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t s0 = tile * PART_TILE;
+        const uint32_t len = n - s0 < PART_TILE ? n - s0 : PART_TILE;
+        KPair kp[RP];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const uint32_t q = 2 * (r * PART_NT + tid);
+            if (q + 1 < len) {
+                kp[r] = *(const KPair*)(keys + s0 + q);
+            } else {
+                kp[r].a = q < len ? keys[s0 + q] : K(0);
+                kp[r].b = K(0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            const uint32_t q = 2 * (r * PART_NT + tid);
+            if (q < len) {
+                const uint32_t b0 = bucket_of((uint64_t)kp[r].a, M);
+                atomicAdd(&hist[wave][(b0 >> shift) & mask], 1u);
+                if (q + 1 < len) {
+                    const uint32_t b1 = bucket_of((uint64_t)kp[r].b, M);
+                    atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
+                    *(uint32_t*)(ids_out + s0 + q) = b0 | (b1 << 16);
+                } else {
+                    ids_out[s0 + q] = (uint16_t)b0;
+                }
+            }
+        }
+        __syncthreads();
+        if ((uint32_t)tid < F) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
+            counts[(uint64_t)tid * nt1 + tile] = t;
+        }
+        __syncthreads();
+    }
+}
+
 // Stable scatter of one tile by the digit of its bucket id.  Wave w ranks
 // the keys [w*TILE/NW, (w+1)*TILE/NW) of the tile in input order: a match
 // of the digit bits by ballots gives the rank among the wave's 64 keys, a
@@ -838,8 +898,8 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
-        PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
-        k_part_hist<K, false><<<nt1, PART_NT, 0, s>>>(kin, nullptr, id1, L1, Mdev, B);
+        const unsigned g1 = nt1 < 1024u ? nt1 : 1024u;
+        k_part_hist1<K><<<g1, PART_NT, 0, s>>>(kin, id1, n, nt1, F1, lo_bits, F1 - 1, c1, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
     }
     {

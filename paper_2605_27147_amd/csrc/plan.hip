@@ -52,35 +52,65 @@ __device__ inline uint32_t inst_ell(const uint32_t* inst_start, uint32_t i, uint
 // Offsets are validated; a bad table (not starting at 0, decreasing, or not
 // ending at n) turns into one instance [0,n) marked "not to be sorted",
 // which the tile sorter leaves untouched.
-__global__ void k_inst_prep(const int64_t* __restrict__ off64, uint32_t k, uint32_t n, uint32_t big_min,
-                            uint32_t* inst_start, uint32_t* inst_big, uint32_t* inst_rfinal,
-                            uint32_t* inst_run_lo, uint32_t* inst_run_hi, uint32_t* counters)
+__global__ __launch_bounds__(1024) void k_inst_prep(const int64_t* __restrict__ off64, uint32_t k, uint32_t n,
+                                                   uint32_t big_min, uint32_t* inst_start, uint32_t* inst_big,
+                                                   uint32_t* inst_rfinal, uint32_t* inst_run_lo,
+                                                   uint32_t* inst_run_hi, uint32_t* counters)
 {
+    constexpr int U = 8;  // entries per thread per round (i = round + u * 1024 + tid), loads in flight together
+    constexpr uint32_t NTH = 1024;
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
     __syncthreads();
     // one workgroup validates the whole table
     if (off64) {
-        for (uint32_t i = threadIdx.x; i <= k; i += blockDim.x) {
-            int64_t v = off64[i];
-            if (v < 0 || v > (int64_t)n) bad = 1;
-            if (i == 0 && v != 0) bad = 1;
-            if (i == k && v != (int64_t)n) bad = 1;
-            if (i < k && off64[i + 1] < v) bad = 1;
+        int my_bad = 0;
+        for (uint32_t r0 = 0; r0 <= k; r0 += U * NTH) {
+            int64_t v[U], w[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = r0 + u * NTH + threadIdx.x;
+                v[u] = i <= k ? off64[i] : 0;
+                w[u] = i < k ? off64[i + 1] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t i = r0 + u * NTH + threadIdx.x;
+                if (i > k) continue;
+                if (v[u] < 0 || v[u] > (int64_t)n) my_bad = 1;
+                if (i == 0 && v[u] != 0) my_bad = 1;
+                if (i == k && v[u] != (int64_t)n) my_bad = 1;
+                if (i < k && w[u] < v[u]) my_bad = 1;
+            }
         }
+        if (my_bad) bad = 1;
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i <= k; i += blockDim.x) {
-        uint32_t s;
-        if (bad) s = (i == 0) ? 0 : n;
-        else s = off64 ? (uint32_t)off64[i] : (i == 0 ? 0 : n);
-        inst_start[i] = s;
-        if (i < k) {
-            uint32_t e = bad ? (i == 0 ? n : n) : (off64 ? (uint32_t)off64[i + 1] : n);
-            inst_big[i] = (!bad && e - s > big_min) ? 1u : 0u;
-            inst_rfinal[i] = 0;
-            inst_run_lo[i] = NONE;
-            inst_run_hi[i] = NONE;
+    const bool bd = bad != 0;
+    for (uint32_t r0 = 0; r0 <= k; r0 += U * NTH) {
+        uint32_t a[U], e[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = r0 + u * NTH + threadIdx.x;
+            if (bd || !off64) {
+                a[u] = i == 0 ? 0u : n;
+                e[u] = n;
+            } else {
+                a[u] = i <= k ? (uint32_t)off64[i] : n;
+                e[u] = i < k ? (uint32_t)off64[i + 1] : n;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t i = r0 + u * NTH + threadIdx.x;
+            if (i > k) continue;
+            inst_start[i] = a[u];
+            if (i < k) {
+                inst_big[i] = (!bd && e[u] - a[u] > big_min) ? 1u : 0u;
+                inst_rfinal[i] = 0;
+                inst_run_lo[i] = NONE;
+                inst_run_hi[i] = NONE;
+            }
         }
     }
     if (threadIdx.x == 0) {
@@ -89,48 +119,107 @@ __global__ void k_inst_prep(const int64_t* __restrict__ off64, uint32_t k, uint3
     }
 }
 
+// The instance holding the first position of every bitmap tile, and
+// whether the tile meets an instance the planner handles (one thread per
+// tile, all searches in flight together; a tile crossing more than 64
+// instance starts is counted as meeting one, which only costs time).
+__global__ void k_tile_inst(const uint32_t* __restrict__ inst_start, const uint32_t* __restrict__ inst_big,
+                            uint32_t k, uint32_t n, uint32_t ntile, uint32_t* __restrict__ tile_inst,
+                            uint32_t* __restrict__ tile_big)
+{
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ntile) return;
+    const uint64_t p = (uint64_t)t * BITMAP_TILE;
+    uint32_t my = 0, big = 0;
+    if (p < n) {
+        my = inst_of(inst_start, k, (uint32_t)p);
+        const uint64_t end = p + BITMAP_TILE < n ? p + BITMAP_TILE : n;
+        for (uint32_t i = my; i < k && inst_start[i] < end; ++i) {
+            if (inst_big[i] || i - my >= 64) { big = 1; break; }
+        }
+    }
+    tile_inst[t] = my;
+    tile_big[t] = big;
+}
+
 // ------------------------------------------------------------ bitmap --
 template <typename K>
 __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint32_t n,
                                                 const uint32_t* __restrict__ inst_start,
                                                 const uint32_t* __restrict__ inst_big, uint32_t k,
+                                                const uint32_t* __restrict__ tile_inst,
+                                                const uint32_t* __restrict__ tile_big,
                                                 uint64_t* __restrict__ bitmap,
                                                 uint32_t* __restrict__ tile_first)
 {
     constexpr int WPW = (int)(BITMAP_TILE / 64 / 4);  // words per wave
+    constexpr uint32_t IW = 255;                     // instances staged in LDS
     __shared__ uint32_t s_first[4];
+    __shared__ uint32_t s_start[IW + 1];
+    __shared__ uint32_t s_big[IW];
     const uint32_t tile = blockIdx.x;
     const uint64_t base = (uint64_t)tile * BITMAP_TILE;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    uint32_t my = 0;
-    if (k > 1 && base < n) my = inst_of(inst_start, k, (uint32_t)base);
-    // which of the lane's positions compare with their predecessor: inside
-    // an instance that the planner handles (not its first element)
-    bool cmp[WPW];
+    if (k > 1 && tile_big[tile] == 0) {
+        // only instances the tile pass sorts whole (or positions past n):
+        // every position is a boundary
+        if (lane < WPW) bitmap[(uint64_t)tile * 64 + wave + 4 * lane] = ~0ull;
+        if (threadIdx.x == 0) tile_first[tile] = (uint32_t)base;
+        return;
+    }
+    // instances overlapping the tile, from the one holding its first position
+    const uint32_t my0 = (k > 1 && base < n) ? tile_inst[tile] : 0u;
+    if (k > 1) {
+        const uint32_t i = my0 + threadIdx.x;
+        if (threadIdx.x <= IW) s_start[threadIdx.x] = i <= k ? inst_start[i] : n;
+        if (threadIdx.x < IW) s_big[threadIdx.x] = i < k ? inst_big[i] : 0u;
+        __syncthreads();
+    }
+    // the window holds every instance that overlaps the tile unless the tile
+    // crosses more than IW instance starts (then the table is read directly)
+    const bool window = k > 1 && (my0 + IW >= k || s_start[IW] >= base + BITMAP_TILE);
+    uint32_t my = my0;
+    // load[j]: the position lies in an instance the planner handles;
+    // cmp[j]: and it is not that instance's first element
+    bool load[WPW], cmp[WPW];
 #pragma unroll
     for (int j = 0; j < WPW; ++j) {
         const uint64_t p = base + (uint64_t)(wave + 4 * j) * 64 + lane;
+        load[j] = false;
         cmp[j] = false;
         if (p < n) {
-            while (my + 1 < k && inst_start[my + 1] <= p) ++my;
-            cmp[j] = p != inst_start[my] && inst_big[my];
+            if (window) {
+                while (my + 1 < k && s_start[my + 1 - my0] <= p) ++my;
+                load[j] = s_big[my - my0] != 0;
+                cmp[j] = load[j] && p != s_start[my - my0];
+            } else if (k > 1) {
+                while (my + 1 < k && inst_start[my + 1] <= p) ++my;
+                load[j] = inst_big[my] != 0;
+                cmp[j] = load[j] && p != inst_start[my];
+            } else {
+                load[j] = inst_big[0] != 0;
+                cmp[j] = load[j] && p != 0;
+            }
         }
     }
-    // all key loads of the lane in flight before the first compare
-    K x[WPW], y[WPW];
+    // every key once; the predecessor comes from the next lower lane (lane 0
+    // loads its own)
+    K y[WPW], x0[WPW];
 #pragma unroll
     for (int j = 0; j < WPW; ++j) {
         const uint64_t p = base + (uint64_t)(wave + 4 * j) * 64 + lane;
-        x[j] = cmp[j] ? keys[p - 1] : K(0);
-        y[j] = cmp[j] ? keys[p] : K(0);
+        y[j] = load[j] ? keys[p] : K(0);
+        x0[j] = (lane == 0 && cmp[j]) ? keys[p - 1] : K(0);
     }
     uint32_t first = NONE;
 #pragma unroll
     for (int j = 0; j < WPW; ++j) {
         const int w = wave + 4 * j;
+        K x = (K)__shfl_up((unsigned long long)y[j], 1, 64);
+        if (lane == 0) x = x0[j];
         // positions past n and instance heads are boundaries; so is every
         // position of an instance the tile pass sorts whole
-        const bool bit = cmp[j] ? (x[j] > y[j]) : true;
+        const bool bit = cmp[j] ? (x > y[j]) : true;
         const uint64_t word = __ballot(bit);
         if (lane == 0) bitmap[(uint64_t)tile * 64 + w] = word;
         if (word && first == NONE) first = (uint32_t)(base + (uint64_t)w * 64 + ffs64(word));
@@ -148,20 +237,51 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
 __global__ __launch_bounds__(1024) void k_suffix_min(const uint32_t* __restrict__ first,
                                                      uint32_t* __restrict__ next, uint32_t ntile)
 {
+    // rounds of R = 1024 * U entries from the right; the round passes through
+    // LDS so that global reads and writes are coalesced, thread t owning the
+    // U consecutive entries [U t, U t + U) of the round
+    constexpr uint32_t U = 16, R = 1024 * U;
+    __shared__ uint32_t buf[R];
     __shared__ uint32_t part[1024];
-    const uint32_t chunk = (ntile + 1023) / 1024;
-    const uint32_t a = threadIdx.x * chunk, b = min(ntile, a + chunk);
-    uint32_t m = NONE;
-    for (uint32_t t = a; t < b; ++t) m = min(m, first[t]);
-    part[threadIdx.x] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        uint32_t run = NONE;
-        for (int c = 1023; c >= 0; --c) { uint32_t v = part[c]; part[c] = run; run = min(run, v); }
+    const uint32_t t = threadIdx.x;
+    uint32_t carry = NONE;  // minimum of everything right of the round
+    const uint32_t rounds = (ntile + R - 1) / R;
+    for (uint32_t rr = rounds; rr-- > 0;) {
+        const uint32_t r0 = rr * R;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = r0 + u * 1024 + t;
+            buf[u * 1024 + t] = i < ntile ? first[i] : NONE;
+        }
+        __syncthreads();
+        uint32_t m = NONE;
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) m = min(m, buf[U * t + u]);
+        part[t] = m;
+        __syncthreads();
+        for (uint32_t d = 1; d < 1024; d <<= 1) {
+            const uint32_t o = t + d < 1024 ? part[t + d] : NONE;
+            __syncthreads();
+            part[t] = min(part[t], o);
+            __syncthreads();
+        }
+        uint32_t run = min(carry, t + 1 < 1024 ? part[t + 1] : NONE);
+        const uint32_t all = part[0];
+#pragma unroll
+        for (int u = (int)U - 1; u >= 0; --u) {
+            const uint32_t v = buf[U * t + u];
+            buf[U * t + u] = run;
+            run = min(run, v);
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t i = r0 + u * 1024 + t;
+            if (i < ntile) next[i] = buf[u * 1024 + t];
+        }
+        carry = min(carry, all);
+        __syncthreads();
     }
-    __syncthreads();
-    uint32_t run = part[threadIdx.x];
-    for (uint32_t t = b; t > a; --t) { next[t - 1] = run; run = min(run, first[t - 1]); }
 }
 
 // Long natural runs: count (EMIT=false) or write (EMIT=true).  One wave
@@ -825,12 +945,19 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
 {
     const uint32_t n = P.n, k = P.k;
     uint32_t* C = P.counters;
+    // tile_off and tile_cnt hold each bitmap tile's first instance and
+    // whether it meets an instance the planner handles, until the long-run
+    // counts take them over
     k_inst_prep<<<1, 1024, 0, s>>>(P.inst_off64, k, n, P.big_min, P.inst_start, P.inst_big, P.inst_rfinal,
                                    P.inst_run_lo, P.inst_run_hi, C);
+    if (k > 1)
+        k_tile_inst<<<grid_for(P.bm_tiles, 256), 256, 0, s>>>(P.inst_start, P.inst_big, k, n, P.bm_tiles, P.tile_off,
+                                                              P.tile_cnt);
     k_zero_stats<<<1, 64, 0, s>>>(P.stats);
     VMPS_HIP(scan_exclusive_u32(P.inst_big, P.inst_bigrank, k, nullptr, C + CNT_NBIG, P.scan_tmp, s));
     // 1. bitmap
-    k_bitmap<K><<<P.bm_tiles, 256, 0, s>>>(keys, n, P.inst_start, P.inst_big, k, P.bitmap, P.tile_first);
+    k_bitmap<K><<<P.bm_tiles, 256, 0, s>>>(keys, n, P.inst_start, P.inst_big, k, P.tile_off, P.tile_cnt,
+                                           P.bitmap, P.tile_first);
     k_suffix_min<<<1, 1024, 0, s>>>(P.tile_first, P.tile_next, P.bm_tiles);
     // 2. long natural runs
     const uint32_t cand_min = (k == 1) ? (ell_ovr ? ell_ovr : minrun_of(n)) : 32u;

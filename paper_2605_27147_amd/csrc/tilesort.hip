@@ -26,6 +26,13 @@ namespace vmps {
 // over distinct banks.
 __device__ __forceinline__ uint32_t px(uint32_t i) { return i + (i >> 5); }
 
+// The layout of a tile's elements: padded (px) where threads write long
+// stretches of wide elements, plain where they write 32-bit elements (the
+// write-back conflicts are then mild and the plain index saves the padding
+// arithmetic on every LDS read of the merges).
+template <bool PAD>
+__device__ __forceinline__ uint32_t pxp(uint32_t i) { return PAD ? px(i) : i; }
+
 template <int TCAP>
 struct TileMeta {
     static constexpr uint32_t RC = TCAP / 32 + 3;  // runs: each >= 32 long except the last
@@ -37,8 +44,9 @@ template <typename K, int NT, int TCAP, int VMODE>
 constexpr size_t tile_lds_bytes()
 {
     using M = TileMeta<TCAP>;
-    size_t b = sizeof(K) * M::SP;
-    if (VMODE) b += 4 * M::SP;
+    // every section starts 16-byte aligned
+    size_t b = (sizeof(K) * M::SP + 15) & ~(size_t)15;
+    if (VMODE) b += (4 * M::SP + 15) & ~(size_t)15;
     b += 8 * M::BW;                   // bitmap
     b += 4 * 2 * M::RC;               // long runs (u, e), later Q and the node list
     b += 4 * 2 * (M::RC + 1);         // progressions (base, prefix), later node L, R
@@ -59,7 +67,7 @@ constexpr size_t tile_lds_bytes()
 // ended, so nd.next needs no search.  The single static loop keeps the
 // register staging arrays indexed by constants.  After a barrier the outputs
 // go back into the same LDS buffer.
-template <typename K, int KI, int TCAP, int VMODE, typename Nodes>
+template <typename K, int KI, int TCAP, int VMODE, bool PAD, typename Nodes>
 __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                            Nodes nd)
 {
@@ -76,12 +84,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (S[px(L + mid)] <= S[px(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
+                if (S[pxp<PAD>(L + mid)] <= S[pxp<PAD>(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
             }
             ia = L + lo;
             jb = M + (d - lo);
         }
-        K ha = S[px(ia)], hb = S[px(jb)];
+        K ha = S[pxp<PAD>(ia)], hb = S[pxp<PAD>(jb)];
         if (__all(p0 + KI <= R)) {
             // Every lane's KI outputs lie in its first node (runs and nodes
             // aligned to KI, as in a large instance): no node changes, and
@@ -92,12 +100,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
                 const bool takeA = ia < M && (jb >= R || ha <= hb);
                 const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
-                if (VMODE) rv[j] = SV[px(cur)];
+                if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
                 const uint32_t nx = cur + 1;
                 ia = takeA ? nx : ia;
                 jb = takeA ? jb : nx;
                 if (j + 1 < KI) {
-                    const K nv = S[px(nx)];
+                    const K nv = S[pxp<PAD>(nx)];
                     ha = takeA ? nv : ha;
                     hb = takeA ? hb : nv;
                 }
@@ -110,18 +118,18 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
                 nd.next(q, M, R);
                 ia = q;
                 jb = M;
-                ha = S[px(ia)];
-                hb = S[px(jb)];
+                ha = S[pxp<PAD>(ia)];
+                hb = S[pxp<PAD>(jb)];
             }
             // StandardMerge: the left run wins ties; a copy node only has a left run
             const bool takeA = ia < M && (jb >= R || ha <= hb);
             const uint32_t cur = takeA ? ia : jb;
             rk[j] = takeA ? ha : hb;
-            if (VMODE) rv[j] = SV[px(cur)];
+            if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
             const uint32_t nx = cur + 1;
             ia = takeA ? nx : ia;
             jb = takeA ? jb : nx;
-            const K nv = S[px(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
+            const K nv = S[pxp<PAD>(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
             ha = takeA ? nv : ha;
             hb = takeA ? hb : nv;
         }
@@ -130,13 +138,33 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
     __syncthreads();
     if (p0 < len) {
         // KI divides 32 and p0 is a multiple of KI: the outputs share one
-        // padding block, px(p0 + j) = px(p0) + j
-        const uint32_t cnt = len - p0, w0 = px(p0);
+        // padding block, pxp<PAD>(p0 + j) = pxp<PAD>(p0) + j
+        const uint32_t cnt = len - p0, w0 = pxp<PAD>(p0);
+        if constexpr (!PAD && sizeof(K) == 4 && KI % 4 == 0) {
+            if (cnt >= (uint32_t)KI) {
+                // plain layout: 16-byte stores (p0 is a multiple of KI)
 #pragma unroll
-        for (int j = 0; j < KI; ++j) {
-            if ((uint32_t)j < cnt) {
-                S[w0 + j] = rk[j];
-                if (VMODE) SV[w0 + j] = rv[j];
+                for (int q = 0; q < KI / 4; ++q) {
+                    *(uint4*)(S + w0 + 4 * q) = make_uint4(rk[4 * q], rk[4 * q + 1], rk[4 * q + 2], rk[4 * q + 3]);
+                    if (VMODE)
+                        *(uint4*)(SV + w0 + 4 * q) = make_uint4(rv[4 * q], rv[4 * q + 1], rv[4 * q + 2], rv[4 * q + 3]);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < KI; ++j) {
+                    if ((uint32_t)j < cnt) {
+                        S[w0 + j] = rk[j];
+                        if (VMODE) SV[w0 + j] = rv[j];
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < KI; ++j) {
+                if ((uint32_t)j < cnt) {
+                    S[w0 + j] = rk[j];
+                    if (VMODE) SV[w0 + j] = rv[j];
+                }
             }
         }
     }
@@ -161,7 +189,7 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v)
 // transposition network.  It only exchanges adjacent elements that are
 // strictly inverted, so equal keys keep their order (the result of the
 // insertion sort); the unused slots hold the largest key and stay last.
-template <typename K, int VMODE>
+template <typename K, int VMODE, bool PAD>
 __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t s, uint32_t cnt)
 {
     K x[16];
@@ -169,8 +197,8 @@ __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __rest
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const bool in = (uint32_t)j < cnt;
-        x[j] = in ? S[px(s + j)] : ~K(0);
-        v[j] = (VMODE && in) ? SV[px(s + j)] : 0u;
+        x[j] = in ? S[pxp<PAD>(s + j)] : ~K(0);
+        v[j] = (VMODE && in) ? SV[pxp<PAD>(s + j)] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -191,8 +219,8 @@ __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __rest
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         if ((uint32_t)j < cnt) {
-            S[px(s + j)] = x[j];
-            if (VMODE) SV[px(s + j)] = v[j];
+            S[pxp<PAD>(s + j)] = x[j];
+            if (VMODE) SV[pxp<PAD>(s + j)] = v[j];
         }
     }
 }
@@ -270,7 +298,7 @@ struct TreeLevel {
 // All merges of one segment with KI outputs per thread: the bottom-up
 // levels inside the forced runs above the sorted 16-element chunks, then
 // Algorithm 1's merges by decreasing power.
-template <typename K, int KI, int TCAP, int VMODE>
+template <typename K, int KI, int TCAP, int VMODE, bool PAD>
 __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                             uint32_t kr,
                                             const uint32_t* RS, const uint8_t* SR, const uint32_t* NL,
@@ -289,13 +317,13 @@ __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restr
     }
     for (uint32_t wlog = 4; (1u << wlog) < maxf; ++wlog) {
         RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
-        merge_pass<K, KI, TCAP, VMODE>(S, SV, len, tid, nd);
+        merge_pass<K, KI, TCAP, VMODE, PAD>(S, SV, len, tid, nd);
     }
     while (mask) {
         const uint32_t p = 32 - __clz(mask);
         mask &= ~(1u << (p - 1));
         TreeLevel nd{NL, BLs, BR, RS, len, LVs[p], LVc[p], 0};
-        merge_pass<K, KI, TCAP, VMODE>(S, SV, len, tid, nd);
+        merge_pass<K, KI, TCAP, VMODE, PAD>(S, SV, len, tid, nd);
     }
 }
 
@@ -333,7 +361,7 @@ __device__ __forceinline__ void tile_load(K* __restrict__ S, uint32_t* __restric
 
 // LDS -> HBM, the reverse of tile_load; element x of the LDS copy goes out
 // as base + x (base = 0 for a full-width copy).
-template <typename KT, typename K, int NT, int TCAP, int VMODE>
+template <typename KT, typename K, int NT, int TCAP, int VMODE, bool PAD>
 __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint32_t* __restrict__ SV,
                                            K* __restrict__ dst, uint32_t* __restrict__ vdst, uint32_t a, uint32_t len,
                                            uint32_t tid, K base)
@@ -349,7 +377,8 @@ __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint3
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
             const uint32_t i = (uint32_t)((c + j) * NT) + tid;
-            const uint32_t pi = pt + (uint32_t)((c + j) * (NT + NT / 32));  // px(i), NT a multiple of 32
+            // px(i) = px(tid) + (c + j) * (NT + NT / 32), NT a multiple of 32
+            const uint32_t pi = PAD ? pt + (uint32_t)((c + j) * (NT + NT / 32)) : i;
             r[j] = i < len ? base + (K)S[pi] : K(0);
             v[j] = (VMODE && i < len) ? SV[pi] : 0u;
         }
@@ -425,9 +454,11 @@ __device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint3
         const uint32_t i = (uint32_t)(c * NT) + tid;
         const uint32_t pi = pt + (uint32_t)(c * (NT + NT / 32));  // px(i), NT a multiple of 32
         if (i < len) {
-            if (narrow) S32[pi] = (uint32_t)(r[c] - lo); else S[pi] = r[c];
-            if (VMODE == 1) SV[pi] = v[c];
-            if (VMODE == 2) SV[pi] = a + i;
+            // the narrow copy uses the plain layout, keys and values alike
+            const uint32_t si = narrow ? i : pi;
+            if (narrow) S32[si] = (uint32_t)(r[c] - lo); else S[si] = r[c];
+            if (VMODE == 1) SV[si] = v[c];
+            if (VMODE == 2) SV[si] = a + i;
         }
     }
     return narrow;
@@ -442,7 +473,7 @@ struct TileLds {
 
 // Steps 2-8 of one segment on the LDS copy S (element type KT): ExtractRun,
 // powers, node lists, the forced runs' sort and the merges.
-template <typename KT, int NT, int TCAP, int VMODE>
+template <typename KT, int NT, int TCAP, int VMODE, bool PAD>
 __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restrict__ SV, const TileLds& T,
                                           uint32_t len, uint32_t ell, uint32_t g, uint32_t il, int tid)
 {
@@ -469,7 +500,7 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     const uint32_t W = len / 64 + 1;
     for (uint32_t w = wave; w < W; w += NW) {
         const uint32_t p = w * 64 + lane;
-        const bool bit = (p >= len) || (p == 0) || (S[px(p - 1)] > S[px(p)]);
+        const bool bit = (p >= len) || (p == 0) || (S[pxp<PAD>(p - 1)] > S[pxp<PAD>(p)]);
         const uint64_t word = __ballot(bit);
         if (lane == 0) bm[w] = word;
     }
@@ -650,14 +681,14 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
         for (uint32_t x = tid; x < cpr * kr; x += NT) {
             const uint32_t r = x / cpr, c = x - r * cpr;
             const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
-            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE>(S, SV, cs, min(16u, ce - cs));
+            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE, PAD>(S, SV, cs, min(16u, ce - cs));
         }
         __syncthreads();
     }
     if (len <= (uint32_t)(NT * (KI / 2)))
-        tile_merges<KT, KI / 2, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI / 2, TCAP, VMODE, PAD>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
     else
-        tile_merges<KT, KI, TCAP, VMODE>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI, TCAP, VMODE, PAD>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
 }
 
 // One segment of the LDS pass, by all NT threads of the calling workgroup.
@@ -678,9 +709,9 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     static_assert(TCAP / 32 <= 64 * NW, "one thread per boundary in the power ranking");
 
     uint8_t* sp = smem;
-    K* S = (K*)sp; sp += sizeof(K) * MT::SP;
+    K* S = (K*)sp; sp += (sizeof(K) * MT::SP + 15) & ~(size_t)15;
     uint32_t* SV = nullptr;
-    if (VMODE) { SV = (uint32_t*)sp; sp += 4 * MT::SP; }
+    if (VMODE) { SV = (uint32_t*)sp; sp += (4 * MT::SP + 15) & ~(size_t)15; }
     uint64_t* bm = (uint64_t*)sp; sp += 8 * MT::BW;
     uint32_t* R1 = (uint32_t*)sp; sp += 4 * 2 * RC;
     uint32_t* R2 = (uint32_t*)sp; sp += 4 * 2 * (RC + 1);
@@ -739,17 +770,17 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     asm volatile("" : "+v"(tid_st));
     if constexpr (sizeof(K) == 8) {
         if (narrow) {
-            tile_body<uint32_t, NT, TCAP, VMODE>((uint32_t*)S, SV, T, len, ell, g, il, tid);
+            tile_body<uint32_t, NT, TCAP, VMODE, false>((uint32_t*)S, SV, T, len, ell, g, il, tid);
             asm volatile("" : "+v"(tid_st));
-            tile_store<uint32_t, K, NT, TCAP, VMODE>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
+            tile_store<uint32_t, K, NT, TCAP, VMODE, false>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
                                                     sg.dst ? valsB : valsA, a, len, tid_st, kmin);
             __syncthreads();
             return;
         }
     }
-    tile_body<K, NT, TCAP, VMODE>(S, SV, T, len, ell, g, il, tid);
+    tile_body<K, NT, TCAP, VMODE, true>(S, SV, T, len, ell, g, il, tid);
     asm volatile("" : "+v"(tid_st));
-    tile_store<K, K, NT, TCAP, VMODE>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
+    tile_store<K, K, NT, TCAP, VMODE, true>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
     __syncthreads();
 }
 

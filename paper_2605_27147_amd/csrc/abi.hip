@@ -523,7 +523,7 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         P.big_min = T;
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, s));
-        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
+        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 1, s));
         VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
         if (stats)
             VMPS_HIP(learned_stats_enqueue(boff, L.B, T, M, w + L.sample, L.m, kb, (uint64_t*)(w + L.judge), stats,

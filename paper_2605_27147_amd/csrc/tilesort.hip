@@ -446,6 +446,12 @@ __device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint3
         lo = wl < lo ? wl : lo;
         hi = wh > hi ? wh : hi;
     }
+    // every lane holds the same minimum and maximum: keep them in scalar
+    // registers (the decision and the minimum live across the whole segment)
+    lo = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(lo >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)lo);
+    hi = ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(hi >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)hi);
     const bool narrow = hi - lo <= 0xffffffffull;  // len >= 1, so lo <= hi
     kmin = lo;
     uint32_t* S32 = (uint32_t*)S;
@@ -692,8 +698,10 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
 }
 
 // One segment of the LDS pass, by all NT threads of the calling workgroup.
-// smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.
-template <typename K, int NT, int TCAP, int VMODE>
+// smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.  NARROW (64-bit
+// keys without values): segments whose keys span less than 2^32 run on
+// 32-bit offsets.
+template <typename K, int NT, int TCAP, int VMODE, bool NARROW>
 __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
                                              uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                              const Seg sg, const uint32_t* __restrict__ inst_start)
@@ -751,12 +759,12 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     const uint32_t ell = minrun_of(il);
     const uint32_t g = a - ib;
 
-    // 1. load; 64-bit keys whose range in the segment spans less than 2^32
-    // are kept as 32-bit offsets from the segment's minimum (an order- and
-    // equality-preserving map, so every step below gives the same result)
+    // 1. load; with NARROW, keys whose range in the segment spans less than
+    // 2^32 are kept as 32-bit offsets from the segment's minimum (an order-
+    // and equality-preserving map, so every step below gives the same result)
     bool narrow = false;
     K kmin = 0;
-    if constexpr (sizeof(K) == 8)
+    if constexpr (NARROW)
         narrow = tile_load_narrow<NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid, wcnt, kmin);
     else
         tile_load<K, NT, TCAP, VMODE>(S, SV, keysA, valsA, a, len, tid);
@@ -768,7 +776,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     const TileLds T{bm, R1, R2, RS, LVs, LVc, wcnt, scan_lds, scal, BLs, PW, SR};
     int tid_st = tid;
     asm volatile("" : "+v"(tid_st));
-    if constexpr (sizeof(K) == 8) {
+    if constexpr (NARROW) {
         if (narrow) {
             tile_body<uint32_t, NT, TCAP, VMODE, false>((uint32_t*)S, SV, T, len, ell, g, il, tid);
             asm volatile("" : "+v"(tid_st));
@@ -793,7 +801,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
 // index lives in scalar registers as a block index would.
 // MINW: waves per SIMD that the LDS footprint lets run at once, which
 // bounds the registers a wave may use.
-template <typename K, int NT, int TCAP, int VMODE, int MINW>
+template <typename K, int NT, int TCAP, int VMODE, int MINW, bool NARROW>
 __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
                                                        uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                        const Seg* __restrict__ segs, uint32_t* __restrict__ counters,
@@ -808,17 +816,17 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
         const uint32_t si = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (si >= nseg) break;
-        tile_segment<K, NT, TCAP, VMODE>(smem, keysA, keysB, valsA, valsB, segs[si], inst_start);
+        tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, segs[si], inst_start);
     }
 }
 
 // ------------------------------------------------------------- host --
-template <typename K, int NT, int TCAP, int VMODE, int MINW>
+template <typename K, int NT, int TCAP, int VMODE, int MINW, bool NARROW = false>
 static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
                                   int wg_per_cu, hipStream_t s)
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
-    auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW>;
+    auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW, NARROW>;
     static bool attr_set = false;
     static int resident = 0;
     if (!attr_set) {
@@ -858,7 +866,7 @@ size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 }
 
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                            int key_bits, int vmode, uint32_t, hipStream_t s)
+                            int key_bits, int vmode, uint32_t narrow, hipStream_t s)
 {
     const int w = tuning_for(key_bits, vmode != 0).tile_wg_per_cu;
     if (key_bits == 32) {
@@ -866,7 +874,10 @@ hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* v
         if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1, 4>(P, keysA, keysB, valsA, valsB, w, s);
         return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, w, s);
     }
-    if (vmode == 0) return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+    if (vmode == 0) {
+        if (narrow) return launch_tilesort<uint64_t, 512, 8192, 0, 4, true>(P, keysA, keysB, valsA, valsB, w, s);
+        return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+    }
     if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1, 3>(P, keysA, keysB, valsA, valsB, w, s);
     return launch_tilesort<uint64_t, 256, 4096, 2, 3>(P, keysA, keysB, valsA, valsB, w, s);
 }

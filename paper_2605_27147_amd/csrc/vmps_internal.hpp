@@ -202,8 +202,11 @@ uint64_t scan_tmp_words(uint64_t count);
 hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t count, hipStream_t s);
 
 // LDS Powersort over the segment list (k_tilesort).
+// narrow (64-bit keys without values): the tile pass variant that sorts
+// segments whose keys span less than 2^32 on 32-bit offsets; worth its
+// extra code where most segments are such (the learned buckets).
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
-                            uint32_t* valsB, int key_bits, int vmode, uint32_t ell_override,
+                            uint32_t* valsB, int key_bits, int vmode, uint32_t narrow,
                             hipStream_t s);
 uint32_t tilesort_capacity(int key_bits, int has_values);
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);

@@ -20,10 +20,17 @@
  *   - All pointers except those marked "host" are device pointers of the
  *     current HIP device.  The caller owns every buffer; the library
  *     allocates no device memory and keeps no pointer after its stream work
- *     ends.
+ *     ends.  (Each host thread gets one 132-byte pinned host buffer and one
+ *     event per device on its first sort, kept until the process ends.)
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
- *     Calls only enqueue work: they never synchronise the host, and their
- *     results are ready when the stream reaches that point.
+ *     Calls enqueue work and their results are ready when the stream
+ *     reaches that point.  The one host wait: the sorts that merge beyond
+ *     the LDS tile (vmps_sort, vmps_segmented_sort, vmps_sort_learned) copy
+ *     the planner's per-level merge counts to the host and wait for that
+ *     copy (the planning kernels only; the tile pass is already enqueued and
+ *     runs meanwhile) so that they launch only the non-empty merge levels.
+ *     On a stream under graph capture they do not wait and launch every
+ *     level.
  *   - Lengths are limited to n < 2^32.  Keys must be aligned to their size.
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is written.  VMPS_ERR_DEVICE reports a failed HIP launch.

@@ -490,15 +490,21 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ key
     for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
     __syncthreads();
     if (IDS_IN) {
-        uint32_t id[PART_RND];
+        // counting only, so the order is free: 16-byte chunks of 8 ids from
+        // the aligned position below s0 (the id arrays are padded to a
+        // multiple of 128), ids outside [s0, s1) skipped
+        const uint32_t a0 = s0 & ~7u;
+        const uint32_t chunks = (s1 - a0 + 7) / 8;
+        for (uint32_t c = tid; c < chunks; c += PART_NT) {
+            const uint4 w = *(const uint4*)(ids_in + a0 + 8 * c);
+            const uint32_t word[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int r = 0; r < PART_RND; ++r) {
-            const uint32_t i = r * PART_NT + tid;
-            id[r] = i < len ? ids_in[s0 + i] : 0u;
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t idx = a0 + 8 * c + e;
+                const uint32_t id = (word[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                if (idx >= s0 && idx < s1) atomicAdd(&hist[wave][(id >> L.shift) & L.mask], 1u);
+            }
         }
-#pragma unroll
-        for (int r = 0; r < PART_RND; ++r)
-            if (r * PART_NT + tid < len) atomicAdd(&hist[wave][(id[r] >> L.shift) & L.mask], 1u);
     } else {
         const ModelArgs M = model_args(model, B);
         constexpr int HB = PART_RND / 2;  // two halves keep the registers in check

@@ -60,25 +60,36 @@ __global__ __launch_bounds__(SCAN_NT) void k_scan_down(const uint32_t* in, uint3
                                                        const uint32_t* sums)
 {
     __shared__ uint32_t lds[SCAN_NT / WAVE + 1];
+    __shared__ uint32_t buf[SCAN_BLOCK];
     const uint64_t count = scan_count(count_host, count_dev);
     const uint64_t base = (uint64_t)blockIdx.x * SCAN_BLOCK;
     if (base >= count) return;
-    // each thread owns SCAN_PER consecutive elements
-    const uint64_t my = base + (uint64_t)threadIdx.x * SCAN_PER;
+    // coalesced load of the block into LDS; thread t then owns the SCAN_PER
+    // consecutive elements [SCAN_PER t, SCAN_PER t + SCAN_PER)
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const uint64_t i = base + (uint64_t)j * SCAN_NT + threadIdx.x;
+        buf[j * SCAN_NT + threadIdx.x] = i < count ? in[i] : 0u;
+    }
+    __syncthreads();
     uint32_t v[SCAN_PER];
     uint32_t acc = 0;
 #pragma unroll
     for (int j = 0; j < SCAN_PER; ++j) {
-        uint64_t i = my + j;
-        v[j] = i < count ? in[i] : 0;
+        v[j] = buf[threadIdx.x * SCAN_PER + j];
         acc += v[j];
     }
     uint32_t ex = block_excl_scan(acc, lds, nullptr) + sums[blockIdx.x];
 #pragma unroll
     for (int j = 0; j < SCAN_PER; ++j) {
-        uint64_t i = my + j;
-        if (i < count) out[i] = ex;
+        buf[threadIdx.x * SCAN_PER + j] = ex;
         ex += v[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; ++j) {
+        const uint64_t i = base + (uint64_t)j * SCAN_NT + threadIdx.x;
+        if (i < count) out[i] = buf[j * SCAN_NT + threadIdx.x];
     }
 }
 

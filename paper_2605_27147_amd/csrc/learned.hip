@@ -648,13 +648,18 @@ __global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict
         const uint32_t i = wb + r * 64 + lane;
         const bool valid = i < len;
         const uint32_t d = valid ? (ir[r] >> L.shift) & L.mask : 0u;
-        uint64_t peers = __ballot(valid);
+        const uint64_t vb = __ballot(valid);
+        uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const bool bit = (d >> k) & 1u;
-            const uint64_t bk = __ballot(bit);
-            peers &= bit ? bk : ~bk;
+            // nb = -bit (all ones or zero); the lanes agreeing with this lane
+            // on bit k are ~(ballot ^ nb)
+            const int nb = ((int)(d << (31 - k))) >> 31;
+            const uint64_t bk = __ballot(nb != 0);
+            plo &= ~((uint32_t)bk ^ (uint32_t)nb);
+            phi &= ~((uint32_t)(bk >> 32) ^ (uint32_t)nb);
         }
+        const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = valid ? hc[wave][d] : 0u;
         const uint32_t rw = __popcll(peers & lt);
         ir[r] |= (before + rw) << 16;

@@ -29,8 +29,8 @@
  *     the planner's per-level merge counts to the host and wait for that
  *     copy (the planning kernels only; the tile pass is already enqueued and
  *     runs meanwhile) so that they launch only the non-empty merge levels.
- *     On a stream under graph capture they do not wait and launch every
- *     level.
+ *     On a stream under graph capture, or with the tuning field
+ *     no_host_wait set, they do not wait and launch every level.
  *   - Lengths are limited to n < 2^32.  Keys must be aligned to their size.
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is written.  VMPS_ERR_DEVICE reports a failed HIP launch.
@@ -281,11 +281,13 @@ typedef struct {
     int32_t merge_grid;     /* workgroups of one HBM merge level (0: 2048) */
     int32_t bucket_div;     /* learned path: buckets of about T/bucket_div
                                keys, T the LDS tile (0: 2) */
-    int32_t reserved;       /* must be 0 */
+    int32_t no_host_wait;   /* 1: the sorts never wait on the host for the
+                               merge-level counts and launch every level
+                               (empty ones return at once); 0 or 1 only */
 } vmps_tuning;
 
-/* t == NULL restores the defaults.  Negative fields, bucket_div > 64 or a
- * non-zero reserved field -> INVALID_ARG. */
+/* t == NULL restores the defaults.  Negative fields, bucket_div > 64 or
+ * no_host_wait outside {0, 1} -> INVALID_ARG. */
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t);
 vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t);
 

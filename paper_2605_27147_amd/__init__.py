@@ -50,7 +50,7 @@ class CdfModel(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
-                ("bucket_div", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("bucket_div", ctypes.c_int32), ("no_host_wait", ctypes.c_int32)]
 
 
 class LearnedStats(ctypes.Structure):
@@ -156,8 +156,8 @@ def _gpu_arch():
 
 
 def set_tuning(dtype_code: int, has_values: bool, tile_wg_per_cu: int = 0, merge_grid: int = 0,
-               bucket_div: int = 0):
-    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, 0)
+               bucket_div: int = 0, no_host_wait: int = 0):
+    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, no_host_wait)
     _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_set_tuning")
 
 
@@ -168,7 +168,8 @@ def reset_tuning(dtype_code: int, has_values: bool):
 def get_tuning(dtype_code: int, has_values: bool) -> dict:
     t = Tuning()
     _check(load_library().vmps_get_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_get_tuning")
-    return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div}
+    return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div,
+            "no_host_wait": t.no_host_wait}
 
 
 def status_string(s: int) -> str:

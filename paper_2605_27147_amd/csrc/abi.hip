@@ -222,7 +222,7 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
             return tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s);
         }
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
-        VMPS_HIP(level_probe_enqueue(P, s));
+        VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
@@ -375,7 +375,7 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
     hipStream_t s = (hipStream_t)stream;
     return guarded([&]() -> hipError_t {
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
-        VMPS_HIP(level_probe_enqueue(P, s));
+        VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
@@ -522,7 +522,7 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         P.inst_off64 = boff;
         P.big_min = T;
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
-        VMPS_HIP(level_probe_enqueue(P, s));
+        VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 1, s));
         VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
         if (stats)
@@ -633,11 +633,12 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t)
 {
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    Tuning v{0, 0, 0};
+    Tuning v{0, 0, 0, 0};
     if (t) {
-        if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 || t->reserved)
+        if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 ||
+            (t->no_host_wait != 0 && t->no_host_wait != 1))
             return VMPS_ERR_INVALID_ARG;
-        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div};
+        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->no_host_wait};
     }
     tuning_table()[kt == VMPS_U64][has_values ? 1 : 0] = v;
     return VMPS_OK;
@@ -650,7 +651,7 @@ vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t)
     t->tile_wg_per_cu = v.tile_wg_per_cu;
     t->merge_grid = v.merge_grid;
     t->bucket_div = v.bucket_div;
-    t->reserved = 0;
+    t->no_host_wait = v.no_host_wait;
     return VMPS_OK;
 }
 

@@ -91,10 +91,11 @@ static LevelProbe& level_probe()
     return pr[d & 15];
 }
 
-hipError_t level_probe_enqueue(const Plan& P, hipStream_t s)
+hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s)
 {
     LevelProbe& pr = level_probe();
     pr.armed = false;
+    if (tuning_for(key_bits, has_values != 0).no_host_wait) return hipSuccess;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     VMPS_HIP(hipStreamIsCapturing(s, &cs));
     if (cs != hipStreamCaptureStatusNone) return hipSuccess;  // a graph launches every level
@@ -115,11 +116,13 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
 {
     constexpr uint32_t TO = NT * KI;
     constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static bool attr_set[16] = {};  // once per device
+    int dev = 0;
+    VMPS_HIP(hipGetDevice(&dev));
+    if (!attr_set[dev & 15]) {
         VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        attr_set = true;
+        attr_set[dev & 15] = true;
     }
     LevelArgs A;
     A.level = P.level;
@@ -225,11 +228,13 @@ static hipError_t merge2_t(const K* a, const uint32_t* va, uint32_t na, const K*
     constexpr int NT = 256, KI = 16;
     constexpr uint32_t TO = NT * KI;
     constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
-    static bool attr_set = false;
-    if (!attr_set) {
+    static bool attr_set[16] = {};  // once per device
+    int dev = 0;
+    VMPS_HIP(hipGetDevice(&dev));
+    if (!attr_set[dev & 15]) {
         VMPS_HIP(hipFuncSetAttribute((const void*)k_merge2<K, VAL, NT, KI>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)lds));
-        attr_set = true;
+        attr_set[dev & 15] = true;
     }
     const uint64_t ntot = (uint64_t)na + nb;
     const uint32_t ntiles = (uint32_t)ceil_div(ntot, TO);

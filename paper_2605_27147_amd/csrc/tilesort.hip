@@ -827,19 +827,23 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
     auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW, NARROW>;
-    static bool attr_set = false;
-    static int resident = 0;
-    if (!attr_set) {
-        VMPS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, (const void*)kern, NT, lds));
-        attr_set = true;
-    }
-    int dev = 0, cus = 0;
+    // the LDS limit and the occupancy, once per device (set before any
+    // launch on it; concurrent first calls only repeat the same setting)
+    static bool attr_set[16] = {};
+    static int resident[16] = {};
+    static int cus[16] = {};
+    int dev = 0;
     VMPS_HIP(hipGetDevice(&dev));
-    VMPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    int per_cu = resident > 0 ? resident : 1;
+    const int d = dev & 15;
+    if (!attr_set[d]) {
+        VMPS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[d], (const void*)kern, NT, lds));
+        VMPS_HIP(hipDeviceGetAttribute(&cus[d], hipDeviceAttributeMultiprocessorCount, dev));
+        attr_set[d] = true;
+    }
+    int per_cu = resident[d] > 0 ? resident[d] : 1;
     if (wg_per_cu > 0 && wg_per_cu < per_cu) per_cu = wg_per_cu;
-    uint64_t grid = (uint64_t)per_cu * (uint64_t)(cus > 0 ? cus : 1);
+    uint64_t grid = (uint64_t)per_cu * (uint64_t)(cus[d] > 0 ? cus[d] : 1);
     if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
     kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,

@@ -175,6 +175,7 @@ struct Tuning {
     int tile_wg_per_cu;  // workgroups per CU of the persistent LDS pass (0: as many as fit)
     int merge_grid;      // workgroups of a merge level (0: 2048)
     int bucket_div;      // learned buckets target the tile length / bucket_div (0: 2)
+    int no_host_wait;    // 1: never wait on the host for the level counts
 };
 const Tuning& tuning_for(int key_bits, bool has_values);
 
@@ -216,7 +217,7 @@ size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
 // while the stream is being captured).  The next merge_levels_enqueue for
 // the same plan waits for that copy only (the tile pass enqueued in between
 // keeps the GPU busy meanwhile) and launches the non-empty levels alone.
-hipError_t level_probe_enqueue(const Plan& P, hipStream_t s);
+hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s);
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                                 uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
 uint32_t merge_tile_out(int key_bits, int has_values);

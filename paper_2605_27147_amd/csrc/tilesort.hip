@@ -805,25 +805,33 @@ template <typename K, int NT, int TCAP, int VMODE, int MINW, bool NARROW>
 __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K* __restrict__ keysB,
                                                        uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                        const Seg* __restrict__ segs, uint32_t* __restrict__ counters,
-                                                       const uint32_t* __restrict__ inst_start)
+                                                       const uint32_t* __restrict__ inst_start,
+                                                       uint32_t len_lo, uint32_t len_hi, int ticket)
 {
+    // segments of length in (len_lo, len_hi] only, so that two launches of
+    // different workgroup sizes can share one segment list (each with its
+    // own ticket counter)
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_next;
     const uint32_t nseg = counters[CNT_NSEG];
     for (;;) {
-        if (threadIdx.x == 0) s_next = atomicAdd(&counters[CNT_TICKET], 1u);
+        if (threadIdx.x == 0) s_next = atomicAdd(&counters[ticket], 1u);
         __syncthreads();
         const uint32_t si = __builtin_amdgcn_readfirstlane(s_next);
         __syncthreads();
         if (si >= nseg) break;
-        tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, segs[si], inst_start);
+        const Seg sg = segs[si];
+        const uint32_t len = sg.end - sg.start;
+        if (len <= len_lo || len > len_hi) continue;
+        tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start);
     }
 }
 
 // ------------------------------------------------------------- host --
 template <typename K, int NT, int TCAP, int VMODE, int MINW, bool NARROW = false>
 static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                                  int wg_per_cu, hipStream_t s)
+                                  int wg_per_cu, hipStream_t s, uint32_t len_lo = 0, uint32_t len_hi = 0xffffffffu,
+                                  int ticket = CNT_TICKET)
 {
     constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
     auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW, NARROW>;
@@ -847,7 +855,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
     kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
-                                                     P.inst_start);
+                                                     P.inst_start, len_lo, len_hi, ticket);
     return hipGetLastError();
 }
 
@@ -879,7 +887,12 @@ hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* v
         return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, w, s);
     }
     if (vmode == 0) {
-        if (narrow) return launch_tilesort<uint64_t, 512, 8192, 0, 4, true>(P, keysA, keysB, valsA, valsB, w, s);
+        if (narrow) {
+            // segments up to 4096 keys: 256-thread workgroups, four per CU
+            VMPS_HIP((launch_tilesort<uint64_t, 256, 4096, 0, 4, true>(P, keysA, keysB, valsA, valsB, w, s, 0, 4096,
+                                                                      CNT_TICKET2)));
+            return launch_tilesort<uint64_t, 512, 8192, 0, 4, true>(P, keysA, keysB, valsA, valsB, w, s, 4096);
+        }
         return launch_tilesort<uint64_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
     }
     if (vmode == 1) return launch_tilesort<uint64_t, 256, 4096, 1, 3>(P, keysA, keysB, valsA, valsB, w, s);

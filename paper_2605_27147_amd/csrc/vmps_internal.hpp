@@ -150,7 +150,7 @@ struct Plan {
 
 enum {
     CNT_NBIG = 0, CNT_NLONG, CNT_NENT, CNT_NRUNS, CNT_NHBM, CNT_NSEG, CNT_NPAIRS,
-    CNT_MAXPOW, CNT_BAD, CNT_TICKET, CNT_COUNT = 16
+    CNT_MAXPOW, CNT_BAD, CNT_TICKET, CNT_TICKET2, CNT_COUNT = 16
 };
 
 // ------------------------------------------------------------ tracing --
@@ -204,8 +204,10 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t count, hipStream_t s);
 
 // LDS Powersort over the segment list (k_tilesort).
 // narrow (64-bit keys without values): the tile pass variant that sorts
-// segments whose keys span less than 2^32 on 32-bit offsets; worth its
-// extra code where most segments are such (the learned buckets).
+// segments whose keys span less than 2^32 on 32-bit offsets, with segments
+// of up to 4096 keys in a launch of 256-thread workgroups (four per CU) and
+// the longer ones in the 512-thread launch; worth it where most segments
+// are short and narrow (the learned buckets).
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                             uint32_t* valsB, int key_bits, int vmode, uint32_t narrow,
                             hipStream_t s);

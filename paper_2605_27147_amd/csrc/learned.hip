@@ -472,59 +472,31 @@ __device__ inline void part_tile(const PartLevel& L, uint32_t tile, uint32_t& c,
     s1 = min(L.pstart[c + 1], s0 + PART_TILE);
 }
 
-// Histogram of one tile.  Level 1 evaluates the model once per key and
-// writes the 16-bit bucket ids; level 2 reads them back.  Per-wave counters
-// keep LDS atomics on popular digits apart.
-template <typename K, bool IDS_IN>
-__global__ __launch_bounds__(PART_NT) void k_part_hist(const K* __restrict__ keys, const uint16_t* __restrict__ ids_in,
-                                                       uint16_t* __restrict__ ids_out, PartLevel L,
-                                                       const vmps_cdf_model* __restrict__ model, uint32_t B)
+// Level-2 histogram of one tile from the 16-bit ids the level-1 scatter
+// moved with the keys.  Counting only, so the order is free: 16-byte
+// chunks of 8 ids from the aligned position below s0 (the id arrays are
+// padded to a multiple of 128), ids outside [s0, s1) skipped.  Per-wave
+// counters keep LDS atomics on popular digits apart.
+__global__ __launch_bounds__(PART_NT) void k_part_hist2(const uint16_t* __restrict__ ids_in, PartLevel L)
 {
     __shared__ uint32_t hist[PART_NW][256];
     const uint32_t tile = blockIdx.x;
     if (tile >= L.tbase[L.P]) return;
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
-    const uint32_t len = s1 - s0;
     const int tid = threadIdx.x, wave = tid >> 6;
     for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
     __syncthreads();
-    if (IDS_IN) {
-        // counting only, so the order is free: 16-byte chunks of 8 ids from
-        // the aligned position below s0 (the id arrays are padded to a
-        // multiple of 128), ids outside [s0, s1) skipped
-        const uint32_t a0 = s0 & ~7u;
-        const uint32_t chunks = (s1 - a0 + 7) / 8;
-        for (uint32_t c = tid; c < chunks; c += PART_NT) {
-            const uint4 w = *(const uint4*)(ids_in + a0 + 8 * c);
-            const uint32_t word[4] = {w.x, w.y, w.z, w.w};
+    const uint32_t a0 = s0 & ~7u;
+    const uint32_t chunks = (s1 - a0 + 7) / 8;
+    for (uint32_t q = tid; q < chunks; q += PART_NT) {
+        const uint4 w = *(const uint4*)(ids_in + a0 + 8 * q);
+        const uint32_t word[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const uint32_t idx = a0 + 8 * c + e;
-                const uint32_t id = (word[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-                if (idx >= s0 && idx < s1) atomicAdd(&hist[wave][(id >> L.shift) & L.mask], 1u);
-            }
-        }
-    } else {
-        const ModelArgs M = model_args(model, B);
-        constexpr int HB = PART_RND / 2;  // two halves keep the registers in check
-#pragma unroll
-        for (int h = 0; h < PART_RND; h += HB) {
-            K k[HB];
-#pragma unroll
-            for (int r = 0; r < HB; ++r) {
-                const uint32_t i = (h + r) * PART_NT + tid;
-                k[r] = i < len ? keys[s0 + i] : K(0);
-            }
-#pragma unroll
-            for (int r = 0; r < HB; ++r) {
-                const uint32_t i = (h + r) * PART_NT + tid;
-                if (i < len) {
-                    const uint32_t b = bucket_of((uint64_t)k[r], M);
-                    ids_out[s0 + i] = (uint16_t)b;
-                    atomicAdd(&hist[wave][(b >> L.shift) & L.mask], 1u);
-                }
-            }
+        for (int e = 0; e < 8; ++e) {
+            const uint32_t idx = a0 + 8 * q + e;
+            const uint32_t id = (word[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+            if (idx >= s0 && idx < s1) atomicAdd(&hist[wave][(id >> L.shift) & L.mask], 1u);
         }
     }
     __syncthreads();
@@ -924,7 +896,7 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_level2<<<1, 256, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
         PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
-        k_part_hist<K, true><<<nt2cap, PART_NT, 0, s>>>(ktmp, id2, nullptr, L2, Mdev, B);
+        k_part_hist2<<<nt2cap, PART_NT, 0, s>>>(id2, L2);
         VMPS_HIP(scan_exclusive_u32(c2, o2, (uint64_t)nt2cap * F2, cnt_total + 1, tot + 1, stmp, s));
     }
     {

@@ -123,8 +123,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "how the sort would shard over GPUs is described in DESIGN.md, not run", file=sys.stderr)
+        print(f"bench.py: the sort runs on one GPU only (asked for --gpus {args.gpus}); "
+              "a sharded multi-GPU sort is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -448,9 +448,9 @@ vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_c
     memset(cfg, 0, sizeof *cfg);
     cfg->num_buckets = 0;
     cfg->hidden = 32;
-    cfg->steps = 64;
-    cfg->batch = 1024;
-    cfg->lr = 1e-4f;
+    cfg->steps = 32;
+    cfg->batch = 512;
+    cfg->lr = 3e-4f;
     cfg->knots = VMPS_CDF_MAX_KNOTS;
     cfg->feature_bits = 20;
     cfg->sample_size = n < (1 << 20) ? n : (1 << 20);

@@ -169,15 +169,16 @@ def test_partition_tiny_and_ragged(vm, orc):
         assert np.array_equal(_np(off, np.int64), woff) and np.array_equal(_np(ko, np.uint64), wk)
 
 
-def test_training_reaches_oracle_quality(vm, orc):
+@pytest.mark.parametrize("steps,batch,lr", [(64, 1024, 1e-4), (32, 512, 3e-4)])
+def test_training_reaches_oracle_quality(vm, orc, steps, batch, lr):
     import torch
     keys = np.sort(workloads.lognormal(1 << 16, 21))
     cfg = vm.learned_default_config(1 << 16, vm.U64)
-    cfg.hidden, cfg.steps, cfg.batch, cfg.lr = 32, 64, 1024, 1e-4
+    cfg.hidden, cfg.steps, cfg.batch, cfg.lr = 32, steps, batch, lr
     model = vm.cdf_train(_t(keys), cfg)
     u, z_lo, z_hi = orc.normalised_features(keys, 64, 20)
     assert (model.z_lo, model.z_hi) == (z_lo, z_hi)
-    p_ref, loss_ref = orc.cdf_train(u, 32, 64, 1024, 1e-4)
+    p_ref, loss_ref = orc.cdf_train(u, 32, steps, batch, lr)
     init_ref = orc.cdf_loss(orc.cdf_init(u, 32), u)
     _say("train", model.loss_init, model.loss_final, init_ref, loss_ref)
     assert model.loss_final <= model.loss_init

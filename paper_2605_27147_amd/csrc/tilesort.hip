@@ -90,14 +90,51 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             jb = M + (d - lo);
         }
         K ha = S[pxp<PAD>(ia)], hb = S[pxp<PAD>(jb)];
-        if (__all(p0 + KI <= R)) {
-            // Every lane's KI outputs lie in its first node (runs and nodes
-            // aligned to KI, as in a large instance): no node changes, and
-            // every index stays <= R <= TCAP.  Wave-uniform, so a wave never
-            // runs both loops.
+        // the lane's outputs that land in the segment: [p0, pe)
+        const uint32_t pe = min(p0 + KI, len);
+        uint32_t M2 = R, R2 = R;  // the node starting at R, when the outputs reach it
+        Nodes n2 = nd;
+        if (R < pe) n2.next(R, M2, R2);
+        if (__all(pe <= R)) {
+            // Every lane's outputs lie in its first node: no node changes.
+            // Indices stay <= max(R, p0 + KI) <= TCAP.  Wave-uniform, so a
+            // wave runs one of the three loops only.
 #pragma unroll
             for (int j = 0; j < KI; ++j) {
                 const bool takeA = ia < M && (jb >= R || ha <= hb);
+                const uint32_t cur = takeA ? ia : jb;
+                rk[j] = takeA ? ha : hb;
+                if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
+                const uint32_t nx = cur + 1;
+                ia = takeA ? nx : ia;
+                jb = takeA ? jb : nx;
+                if (j + 1 < KI) {
+                    const K nv = S[pxp<PAD>(nx)];
+                    ha = takeA ? nv : ha;
+                    hb = takeA ? hb : nv;
+                }
+            }
+        } else if (__all(pe <= R2)) {
+            // At most one node change per lane, at output R (nodes at least
+            // KI long, the usual case): the second node's state is set up
+            // in advance and swapped in by selects, without a branch.
+            const K ha2 = S[pxp<PAD>(R)], hb2 = S[pxp<PAD>(M2)];
+            uint32_t Mc = M, Rc = R;
+            // the change happens at step R - p0 (> 0): compared with the
+            // unrolled step number, no per-step position is kept live
+            const uint32_t jsw = R - p0;
+#pragma unroll
+            for (int j = 0; j < KI; ++j) {
+                if (j > 0) {
+                    const bool sw = jsw == (uint32_t)j;
+                    ia = sw ? R : ia;
+                    jb = sw ? M2 : jb;
+                    Mc = sw ? M2 : Mc;
+                    Rc = sw ? R2 : Rc;
+                    ha = sw ? ha2 : ha;
+                    hb = sw ? hb2 : hb;
+                }
+                const bool takeA = ia < Mc && (jb >= Rc || ha <= hb);
                 const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
                 if (VMODE) rv[j] = SV[pxp<PAD>(cur)];

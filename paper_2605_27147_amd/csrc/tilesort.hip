@@ -26,12 +26,18 @@ namespace vmps {
 // over distinct banks.
 __device__ __forceinline__ uint32_t px(uint32_t i) { return i + (i >> 5); }
 
-// The layout of a tile's elements: padded (px) where threads write long
-// stretches of wide elements, plain where they write 32-bit elements (the
-// write-back conflicts are then mild and the plain index saves the padding
-// arithmetic on every LDS read of the merges).
-template <bool PAD>
-__device__ __forceinline__ uint32_t pxp(uint32_t i) { return PAD ? px(i) : i; }
+// The layout of a tile's elements (LAY): 0 plain; 1 one spare slot after
+// every 32 elements (px); 2 one spare slot after every 16.  In a merge pass
+// lane t reads near position t * KI / 2 of each run and writes KI outputs
+// from t * KI, so in the plain layout lanes a few apart meet in one LDS
+// bank; a spare slot per 16 32-bit elements spreads both patterns over the
+// banks (the 16 outputs of a lane start 17 words after the previous lane's).
+template <int LAY>
+__device__ __forceinline__ uint32_t pxp(uint32_t i) { return LAY == 1 ? px(i) : (LAY == 2 ? i + (i >> 4) : i); }
+
+// Length of the blocks the spare slots separate (elements).
+template <int LAY>
+constexpr uint32_t lay_block() { return LAY == 2 ? 16u : 32u; }
 
 template <int TCAP>
 struct TileMeta {
@@ -67,11 +73,11 @@ constexpr size_t tile_lds_bytes()
 // ended, so nd.next needs no search.  The single static loop keeps the
 // register staging arrays indexed by constants.  After a barrier the outputs
 // go back into the same LDS buffer.
-template <typename K, int KI, int TCAP, int VMODE, bool PAD, typename Nodes>
+template <typename K, int KI, int TCAP, int VMODE, int LAY, typename Nodes>
 __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                            Nodes nd)
 {
-    static_assert(32 % KI == 0, "outputs of a thread stay inside one padding block");
+    static_assert(lay_block<LAY>() % KI == 0, "outputs of a thread stay inside one padding block");
     const uint32_t p0 = tid * KI;
     K rk[KI];
     uint32_t rv[KI];
@@ -84,12 +90,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             uint32_t lo = d > nb ? d - nb : 0u, hi = d < na ? d : na;
             while (lo < hi) {
                 const uint32_t mid = (lo + hi) >> 1;
-                if (S[pxp<PAD>(L + mid)] <= S[pxp<PAD>(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
+                if (S[pxp<LAY>(L + mid)] <= S[pxp<LAY>(M + d - 1 - mid)]) lo = mid + 1; else hi = mid;
             }
             ia = L + lo;
             jb = M + (d - lo);
         }
-        K ha = S[pxp<PAD>(ia)], hb = S[pxp<PAD>(jb)];
+        K ha = S[pxp<LAY>(ia)], hb = S[pxp<LAY>(jb)];
         // the lane's outputs that land in the segment: [p0, pe)
         const uint32_t pe = min(p0 + KI, len);
         uint32_t M2 = R, R2 = R;  // the node starting at R, when the outputs reach it
@@ -104,12 +110,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
                 const bool takeA = ia < M && (jb >= R || ha <= hb);
                 const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
-                if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
+                if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
                 const uint32_t nx = cur + 1;
                 ia = takeA ? nx : ia;
                 jb = takeA ? jb : nx;
                 if (j + 1 < KI) {
-                    const K nv = S[pxp<PAD>(nx)];
+                    const K nv = S[pxp<LAY>(nx)];
                     ha = takeA ? nv : ha;
                     hb = takeA ? hb : nv;
                 }
@@ -118,7 +124,7 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             // At most one node change per lane, at output R (nodes at least
             // KI long, the usual case): the second node's state is set up
             // in advance and swapped in by selects, without a branch.
-            const K ha2 = S[pxp<PAD>(R)], hb2 = S[pxp<PAD>(M2)];
+            const K ha2 = S[pxp<LAY>(R)], hb2 = S[pxp<LAY>(M2)];
             uint32_t Mc = M, Rc = R;
             // the change happens at step R - p0 (> 0): compared with the
             // unrolled step number, no per-step position is kept live
@@ -137,12 +143,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
                 const bool takeA = ia < Mc && (jb >= Rc || ha <= hb);
                 const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
-                if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
+                if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
                 const uint32_t nx = cur + 1;
                 ia = takeA ? nx : ia;
                 jb = takeA ? jb : nx;
                 if (j + 1 < KI) {
-                    const K nv = S[pxp<PAD>(nx)];
+                    const K nv = S[pxp<LAY>(nx)];
                     ha = takeA ? nv : ha;
                     hb = takeA ? hb : nv;
                 }
@@ -155,18 +161,18 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
                 nd.next(q, M, R);
                 ia = q;
                 jb = M;
-                ha = S[pxp<PAD>(ia)];
-                hb = S[pxp<PAD>(jb)];
+                ha = S[pxp<LAY>(ia)];
+                hb = S[pxp<LAY>(jb)];
             }
             // StandardMerge: the left run wins ties; a copy node only has a left run
             const bool takeA = ia < M && (jb >= R || ha <= hb);
             const uint32_t cur = takeA ? ia : jb;
             rk[j] = takeA ? ha : hb;
-            if (VMODE) rv[j] = SV[pxp<PAD>(cur)];
+            if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
             const uint32_t nx = cur + 1;
             ia = takeA ? nx : ia;
             jb = takeA ? jb : nx;
-            const K nv = S[pxp<PAD>(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
+            const K nv = S[pxp<LAY>(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
             ha = takeA ? nv : ha;
             hb = takeA ? hb : nv;
         }
@@ -174,10 +180,10 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
     }
     __syncthreads();
     if (p0 < len) {
-        // KI divides 32 and p0 is a multiple of KI: the outputs share one
-        // padding block, pxp<PAD>(p0 + j) = pxp<PAD>(p0) + j
-        const uint32_t cnt = len - p0, w0 = pxp<PAD>(p0);
-        if constexpr (!PAD && sizeof(K) == 4 && KI % 4 == 0) {
+        // KI divides the block length and p0 is a multiple of KI: the
+        // outputs share one padding block, pxp<LAY>(p0 + j) = pxp<LAY>(p0) + j
+        const uint32_t cnt = len - p0, w0 = pxp<LAY>(p0);
+        if constexpr (LAY == 0 && sizeof(K) == 4 && KI % 4 == 0) {
             if (cnt >= (uint32_t)KI) {
                 // plain layout: 16-byte stores (p0 is a multiple of KI)
 #pragma unroll
@@ -226,7 +232,7 @@ __device__ __forceinline__ uint32_t wave_or(uint32_t v)
 // transposition network.  It only exchanges adjacent elements that are
 // strictly inverted, so equal keys keep their order (the result of the
 // insertion sort); the unused slots hold the largest key and stay last.
-template <typename K, int VMODE, bool PAD>
+template <typename K, int VMODE, int LAY>
 __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t s, uint32_t cnt)
 {
     K x[16];
@@ -234,8 +240,8 @@ __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __rest
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const bool in = (uint32_t)j < cnt;
-        x[j] = in ? S[pxp<PAD>(s + j)] : ~K(0);
-        v[j] = (VMODE && in) ? SV[pxp<PAD>(s + j)] : 0u;
+        x[j] = in ? S[pxp<LAY>(s + j)] : ~K(0);
+        v[j] = (VMODE && in) ? SV[pxp<LAY>(s + j)] : 0u;
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
@@ -256,8 +262,8 @@ __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __rest
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         if ((uint32_t)j < cnt) {
-            S[pxp<PAD>(s + j)] = x[j];
-            if (VMODE) SV[pxp<PAD>(s + j)] = v[j];
+            S[pxp<LAY>(s + j)] = x[j];
+            if (VMODE) SV[pxp<LAY>(s + j)] = v[j];
         }
     }
 }
@@ -335,7 +341,7 @@ struct TreeLevel {
 // All merges of one segment with KI outputs per thread: the bottom-up
 // levels inside the forced runs above the sorted 16-element chunks, then
 // Algorithm 1's merges by decreasing power.
-template <typename K, int KI, int TCAP, int VMODE, bool PAD>
+template <typename K, int KI, int TCAP, int VMODE, int LAY>
 __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                             uint32_t kr,
                                             const uint32_t* RS, const uint8_t* SR, const uint32_t* NL,
@@ -354,13 +360,13 @@ __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restr
     }
     for (uint32_t wlog = 4; (1u << wlog) < maxf; ++wlog) {
         RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
-        merge_pass<K, KI, TCAP, VMODE, PAD>(S, SV, len, tid, nd);
+        merge_pass<K, KI, TCAP, VMODE, LAY>(S, SV, len, tid, nd);
     }
     while (mask) {
         const uint32_t p = 32 - __clz(mask);
         mask &= ~(1u << (p - 1));
         TreeLevel nd{NL, BLs, BR, RS, len, LVs[p], LVc[p], 0};
-        merge_pass<K, KI, TCAP, VMODE, PAD>(S, SV, len, tid, nd);
+        merge_pass<K, KI, TCAP, VMODE, LAY>(S, SV, len, tid, nd);
     }
 }
 
@@ -379,9 +385,12 @@ __device__ __forceinline__ void tile_load(K* __restrict__ S, uint32_t* __restric
         uint32_t v[BT];
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
+            // unmasked loads (positions past the end read the last element
+            // and are not stored), so that all of them are in flight at once
             const uint32_t i = (uint32_t)((c + j) * NT) + tid;
-            r[j] = i < len ? src[a + i] : K(0);
-            v[j] = (VMODE == 1 && i < len) ? vsrc[a + i] : 0u;
+            const uint32_t ic = i < len ? i : len - 1;
+            r[j] = src[a + ic];
+            v[j] = VMODE == 1 ? vsrc[a + ic] : 0u;
         }
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
@@ -398,7 +407,7 @@ __device__ __forceinline__ void tile_load(K* __restrict__ S, uint32_t* __restric
 
 // LDS -> HBM, the reverse of tile_load; element x of the LDS copy goes out
 // as base + x (base = 0 for a full-width copy).
-template <typename KT, typename K, int NT, int TCAP, int VMODE, bool PAD>
+template <typename KT, typename K, int NT, int TCAP, int VMODE, int LAY>
 __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint32_t* __restrict__ SV,
                                            K* __restrict__ dst, uint32_t* __restrict__ vdst, uint32_t a, uint32_t len,
                                            uint32_t tid, K base)
@@ -406,7 +415,6 @@ __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint3
     static_assert(NT % 32 == 0, "affine padded index");
     constexpr int CH = TCAP / NT;
     constexpr int BT = CH < 8 ? CH : 8;
-    const uint32_t pt = px(tid);
 #pragma unroll
     for (int c = 0; c < CH; c += BT) {
         K r[BT];
@@ -414,8 +422,8 @@ __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint3
 #pragma unroll
         for (int j = 0; j < BT; ++j) {
             const uint32_t i = (uint32_t)((c + j) * NT) + tid;
-            // px(i) = px(tid) + (c + j) * (NT + NT / 32), NT a multiple of 32
-            const uint32_t pi = PAD ? pt + (uint32_t)((c + j) * (NT + NT / 32)) : i;
+            // pxp(i) = pxp(tid) + (c + j) * pxp(NT), NT a multiple of 32
+            const uint32_t pi = LAY == 0 ? i : pxp<LAY>(tid) + (uint32_t)((c + j) * pxp<LAY>(NT));
             r[j] = i < len ? base + (K)S[pi] : K(0);
             v[j] = (VMODE && i < len) ? SV[pi] : 0u;
         }
@@ -448,9 +456,12 @@ __device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint3
     uint32_t v[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
+        // unmasked loads (positions past the end read the last element and
+        // are excluded below), so that all of them are in flight at once
         const uint32_t i = (uint32_t)(c * NT) + tid;
-        r[c] = i < len ? src[a + i] : 0ull;
-        v[c] = (VMODE == 1 && i < len) ? vsrc[a + i] : 0u;
+        const uint32_t ic = i < len ? i : len - 1;
+        r[c] = src[a + ic];
+        v[c] = VMODE == 1 ? vsrc[a + ic] : 0u;
     }
     uint64_t lo = ~0ull, hi = 0;
 #pragma unroll
@@ -497,8 +508,9 @@ __device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint3
         const uint32_t i = (uint32_t)(c * NT) + tid;
         const uint32_t pi = pt + (uint32_t)(c * (NT + NT / 32));  // px(i), NT a multiple of 32
         if (i < len) {
-            // the narrow copy uses the plain layout, keys and values alike
-            const uint32_t si = narrow ? i : pi;
+            // the narrow copy uses the one-per-16 padded layout (pxp<2>),
+            // keys and values alike
+            const uint32_t si = narrow ? pxp<2>(tid) + (uint32_t)(c * pxp<2>(NT)) : pi;
             if (narrow) S32[si] = (uint32_t)(r[c] - lo); else S[si] = r[c];
             if (VMODE == 1) SV[si] = v[c];
             if (VMODE == 2) SV[si] = a + i;
@@ -516,7 +528,7 @@ struct TileLds {
 
 // Steps 2-8 of one segment on the LDS copy S (element type KT): ExtractRun,
 // powers, node lists, the forced runs' sort and the merges.
-template <typename KT, int NT, int TCAP, int VMODE, bool PAD>
+template <typename KT, int NT, int TCAP, int VMODE, int LAY>
 __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restrict__ SV, const TileLds& T,
                                           uint32_t len, uint32_t ell, uint32_t g, uint32_t il, int tid)
 {
@@ -543,7 +555,7 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     const uint32_t W = len / 64 + 1;
     for (uint32_t w = wave; w < W; w += NW) {
         const uint32_t p = w * 64 + lane;
-        const bool bit = (p >= len) || (p == 0) || (S[pxp<PAD>(p - 1)] > S[pxp<PAD>(p)]);
+        const bool bit = (p >= len) || (p == 0) || (S[pxp<LAY>(p - 1)] > S[pxp<LAY>(p)]);
         const uint64_t word = __ballot(bit);
         if (lane == 0) bm[w] = word;
     }
@@ -724,14 +736,14 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
         for (uint32_t x = tid; x < cpr * kr; x += NT) {
             const uint32_t r = x / cpr, c = x - r * cpr;
             const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
-            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE, PAD>(S, SV, cs, min(16u, ce - cs));
+            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE, LAY>(S, SV, cs, min(16u, ce - cs));
         }
         __syncthreads();
     }
     if (len <= (uint32_t)(NT * (KI / 2)))
-        tile_merges<KT, KI / 2, TCAP, VMODE, PAD>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI / 2, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
     else
-        tile_merges<KT, KI, TCAP, VMODE, PAD>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
 }
 
 // One segment of the LDS pass, by all NT threads of the calling workgroup.
@@ -774,7 +786,6 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     // does not keep every unrolled address live across the whole loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
-    const int lane = tid & 63, wave = tid >> 6;
     const uint32_t a = sg.start;
     const uint32_t len = sg.end - sg.start;
     if (len == 0) return;
@@ -815,17 +826,17 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     asm volatile("" : "+v"(tid_st));
     if constexpr (NARROW) {
         if (narrow) {
-            tile_body<uint32_t, NT, TCAP, VMODE, false>((uint32_t*)S, SV, T, len, ell, g, il, tid);
+            tile_body<uint32_t, NT, TCAP, VMODE, 2>((uint32_t*)S, SV, T, len, ell, g, il, tid);
             asm volatile("" : "+v"(tid_st));
-            tile_store<uint32_t, K, NT, TCAP, VMODE, false>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
+            tile_store<uint32_t, K, NT, TCAP, VMODE, 2>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
                                                     sg.dst ? valsB : valsA, a, len, tid_st, kmin);
             __syncthreads();
             return;
         }
     }
-    tile_body<K, NT, TCAP, VMODE, true>(S, SV, T, len, ell, g, il, tid);
+    tile_body<K, NT, TCAP, VMODE, 1>(S, SV, T, len, ell, g, il, tid);
     asm volatile("" : "+v"(tid_st));
-    tile_store<K, K, NT, TCAP, VMODE, true>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
+    tile_store<K, K, NT, TCAP, VMODE, 1>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
     __syncthreads();
 }
 
@@ -851,16 +862,24 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     extern __shared__ __align__(16) uint8_t smem[];
     __shared__ uint32_t s_next;
     const uint32_t nseg = counters[CNT_NSEG];
+    // a ticket claims sb consecutive segments: every claim is an atomic on
+    // one counter shared by the whole grid, so claims are kept to about 16
+    // per workgroup (at most 16 segments each) when segments are many
+    uint32_t sb = nseg / (gridDim.x * 16u);
+    sb = sb < 1u ? 1u : (sb > 16u ? 16u : sb);
     for (;;) {
         if (threadIdx.x == 0) s_next = atomicAdd(&counters[ticket], 1u);
         __syncthreads();
-        const uint32_t si = __builtin_amdgcn_readfirstlane(s_next);
+        const uint32_t b0 = __builtin_amdgcn_readfirstlane(s_next) * sb;
         __syncthreads();
-        if (si >= nseg) break;
-        const Seg sg = segs[si];
-        const uint32_t len = sg.end - sg.start;
-        if (len <= len_lo || len > len_hi) continue;
-        tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start);
+        if (b0 >= nseg) break;
+        const uint32_t b1 = min(b0 + sb, nseg);
+        for (uint32_t si = b0; si < b1; ++si) {
+            const Seg sg = segs[si];
+            const uint32_t len = sg.end - sg.start;
+            if (len <= len_lo || len > len_hi) continue;
+            tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start);
+        }
     }
 }
 

@@ -625,11 +625,13 @@ __global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             // nb = -bit (all ones or zero); the lanes agreeing with this lane
-            // on bit k are ~(ballot ^ nb)
-            const int nb = ((int)(d << (31 - k))) >> 31;
+            // on bit k are ~(ballot ^ nb).  One bit-field extract and one
+            // three-input bitwise operation per half: p & ~(b ^ c) has the
+            // truth table 0x90 (operands 0xF0, 0xCC, 0xAA).
+            const int nb = __builtin_amdgcn_sbfe((int)d, (unsigned)k, 1u);
             const uint64_t bk = __ballot(nb != 0);
-            plo &= ~((uint32_t)bk ^ (uint32_t)nb);
-            phi &= ~((uint32_t)(bk >> 32) ^ (uint32_t)nb);
+            plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)bk, (uint32_t)nb, 0x90);
+            phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(bk >> 32), (uint32_t)nb, 0x90);
         }
         const uint64_t peers = ((uint64_t)phi << 32) | plo;
         const uint32_t before = valid ? hc[wave][d] : 0u;

@@ -450,10 +450,10 @@ vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_c
     cfg->hidden = 32;
     cfg->steps = 32;
     cfg->batch = 512;
-    cfg->lr = 3e-4f;
+    cfg->lr = 4e-4f;
     cfg->knots = VMPS_CDF_MAX_KNOTS;
     cfg->feature_bits = 20;
-    cfg->sample_size = n < (1 << 20) ? n : (1 << 20);
+    cfg->sample_size = n < (1 << 18) ? n : (1 << 18);
     cfg->seed = 55;
     return VMPS_OK;
 }

@@ -268,6 +268,72 @@ __device__ __forceinline__ void chunk_sort16(K* __restrict__ S, uint32_t* __rest
     }
 }
 
+// Batcher's merge-exchange network for N inputs (N a power of two), as a
+// list of comparators (a, b), a < b: Knuth's Algorithm M (The Art of
+// Computer Programming, Vol. 3, 5.2.2), 191 comparators for N = 32.
+template <int N>
+struct BatcherNet {
+    static constexpr int count()
+    {
+        int c = 0;
+        for (int p = N / 2; p >= 1; p >>= 1) {
+            int q = N / 2, r = 0, d = p;
+            for (;;) {
+                for (int i = 0; i + d < N; ++i)
+                    if ((i & p) == r) ++c;
+                if (q == p) break;
+                d = q - p;
+                q >>= 1;
+                r = p;
+            }
+        }
+        return c;
+    }
+    uint8_t a[count()], b[count()];
+    constexpr BatcherNet() : a(), b()
+    {
+        int c = 0;
+        for (int p = N / 2; p >= 1; p >>= 1) {
+            int q = N / 2, r = 0, d = p;
+            for (;;) {
+                for (int i = 0; i + d < N; ++i)
+                    if ((i & p) == r) {
+                        a[c] = (uint8_t)i;
+                        b[c] = (uint8_t)(i + d);
+                        ++c;
+                    }
+                if (q == p) break;
+                d = q - p;
+                q >>= 1;
+                r = p;
+            }
+        }
+    }
+};
+
+// Sort of S[s, s+cnt), cnt <= 32, keys without values: equal keys cannot be
+// told apart, so the result of any sorting network is the stable sort (the
+// result of the insertion sort).  Min/max comparators on the registers;
+// unused slots hold the largest key and stay last.
+template <typename K, int LAY>
+__device__ __forceinline__ void chunk_sort32(K* __restrict__ S, uint32_t s, uint32_t cnt)
+{
+    constexpr BatcherNet<32> net{};
+    K x[32];
+#pragma unroll
+    for (int j = 0; j < 32; ++j) x[j] = (uint32_t)j < cnt ? S[pxp<LAY>(s + j)] : ~K(0);
+#pragma unroll
+    for (int c = 0; c < BatcherNet<32>::count(); ++c) {
+        const K u = x[net.a[c]], v = x[net.b[c]];
+        x[net.a[c]] = u < v ? u : v;
+        x[net.b[c]] = u < v ? v : u;
+    }
+    asm volatile("" : "+v"(s));  // recompute the addresses rather than keep 32 of them live
+#pragma unroll
+    for (int j = 0; j < 32; ++j)
+        if ((uint32_t)j < cnt) S[pxp<LAY>(s + j)] = x[j];
+}
+
 // Nodes of one bottom-up level inside the forced runs: aligned blocks of 2w
 // from each unsorted run's start are merged as [ps, ps+w) + [ps+w, ps+2w);
 // already sorted runs and runs of at most w elements are copy nodes.
@@ -339,14 +405,14 @@ struct TreeLevel {
 };
 
 // All merges of one segment with KI outputs per thread: the bottom-up
-// levels inside the forced runs above the sorted 16-element chunks, then
-// Algorithm 1's merges by decreasing power.
+// levels inside the forced runs above the sorted chunks of 2^cwl elements,
+// then Algorithm 1's merges by decreasing power.
 template <typename K, int KI, int TCAP, int VMODE, int LAY>
 __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                             uint32_t kr,
                                             const uint32_t* RS, const uint8_t* SR, const uint32_t* NL,
                                             const uint32_t* BLs, const uint32_t* BR, const uint32_t* LVs,
-                                            const uint32_t* LVc, uint32_t maxf, uint32_t mask)
+                                            const uint32_t* LVc, uint32_t maxf, uint32_t mask, uint32_t cwl)
 {
     uint32_t myrun = 0;  // run holding this thread's first output
     {
@@ -358,7 +424,7 @@ __device__ __forceinline__ void tile_merges(K* __restrict__ S, uint32_t* __restr
         }
         myrun = lo;
     }
-    for (uint32_t wlog = 4; (1u << wlog) < maxf; ++wlog) {
+    for (uint32_t wlog = cwl; (1u << wlog) < maxf; ++wlog) {
         RunLevel nd{RS, SR, len, 1u << wlog, wlog, myrun, 0, 0, false};
         merge_pass<K, KI, TCAP, VMODE, LAY>(S, SV, len, tid, nd);
     }
@@ -728,22 +794,31 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     // 7./8. forced runs, then the merges of Algorithm 1; segments up to
     // half the tile use half the outputs per thread, so every thread works
     const uint32_t maxf = scal[3], mask = scal[2];
-    // 7a. the first four bottom-up levels of every forced run: 16-element
-    // chunks from the run start, sorted in registers (unsorted runs are
-    // forced runs, shorter than 64)
+    // 7a. the first bottom-up levels of every forced run: chunks of 2^CWL
+    // elements from the run start, sorted in registers (unsorted runs are
+    // forced runs, shorter than 64).  32-bit keys without values: 32-element
+    // chunks by a sorting network (five levels); otherwise 16-element chunks
+    // by the stable transposition network (four levels).
+    constexpr bool NET32 = sizeof(KT) == 4 && VMODE == 0;
+    constexpr uint32_t CWL = NET32 ? 5u : 4u;
     if (maxf > 1) {
-        const uint32_t cpr = (maxf + 15) >> 4;
+        const uint32_t cpr = (maxf + (1u << CWL) - 1) >> CWL;
         for (uint32_t x = tid; x < cpr * kr; x += NT) {
             const uint32_t r = x / cpr, c = x - r * cpr;
-            const uint32_t cs = RS[r] + 16 * c, ce = RS[r + 1];
-            if (!SR[r] && cs + 1 < ce) chunk_sort16<KT, VMODE, LAY>(S, SV, cs, min(16u, ce - cs));
+            const uint32_t cs = RS[r] + (c << CWL), ce = RS[r + 1];
+            if (!SR[r] && cs + 1 < ce) {
+                if constexpr (NET32)
+                    chunk_sort32<KT, LAY>(S, cs, min(32u, ce - cs));
+                else
+                    chunk_sort16<KT, VMODE, LAY>(S, SV, cs, min(16u, ce - cs));
+            }
         }
         __syncthreads();
     }
     if (len <= (uint32_t)(NT * (KI / 2)))
-        tile_merges<KT, KI / 2, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI / 2, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask, CWL);
     else
-        tile_merges<KT, KI, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask);
+        tile_merges<KT, KI, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask, CWL);
 }
 
 // One segment of the LDS pass, by all NT threads of the calling workgroup.

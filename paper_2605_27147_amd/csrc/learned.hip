@@ -883,7 +883,21 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
-        const unsigned g1 = nt1 < 1024u ? nt1 : 1024u;
+        // persistent: as many workgroups as are resident at once (a second
+        // round of workgroups would run its tiles on a mostly idle GPU)
+        static bool occ_set[16] = {};
+        static unsigned occ_grid[16] = {};
+        int dev = 0;
+        VMPS_HIP(hipGetDevice(&dev));
+        const int d = dev & 15;
+        if (!occ_set[d]) {
+            int per_cu = 0, cus = 0;
+            VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_part_hist1<K>, PART_NT, 0));
+            VMPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+            occ_grid[d] = (unsigned)((per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1));
+            occ_set[d] = true;
+        }
+        const unsigned g1 = nt1 < occ_grid[d] ? nt1 : occ_grid[d];
         k_part_hist1<K><<<g1, PART_NT, 0, s>>>(kin, id1, n, nt1, F1, lo_bits, F1 - 1, c1, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
     }

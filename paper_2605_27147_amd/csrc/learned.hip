@@ -65,6 +65,49 @@ __device__ inline uint32_t bucket_of(uint64_t key, const ModelArgs& M)
     return (uint32_t)(b >= M.B ? M.B - 1 : b);
 }
 
+// The same bucket in 32-bit arithmetic, for a monotone table whose values
+// fit 32 bits (every compiled table).  The feature has at most 6 + 24 bits,
+// so z_lo and the range clamped to 2^31 - 1 give the same d; (t1 - t0) times
+// the offset inside the segment is below 2^63 and its quotient by 2^shift
+// below t1 - t0, so every intermediate of cdf_pos is reproduced exactly.
+struct ModelArgs32 {
+    uint32_t z_lo, range, fbits, shift, seg_shift, frac_mask, knots, B;
+    const uint32_t* table;  // knots + 1 entries
+};
+
+__device__ inline ModelArgs32 model_args32(const ModelArgs& M, const uint32_t* table32)
+{
+    ModelArgs32 a;
+    a.z_lo = M.z_lo > 0x7fffffffull ? 0x7fffffffu : (uint32_t)M.z_lo;
+    a.range = M.range > 0x7fffffffull ? 0x7fffffffu : (uint32_t)M.range;
+    a.fbits = (uint32_t)M.fbits;
+    a.shift = (uint32_t)M.shift;
+    a.seg_shift = M.shift < 32 ? (uint32_t)M.shift : 31u;  // d < 2^31: a shift of 31 already gives 0
+    a.frac_mask = M.shift < 32 ? (1u << M.shift) - 1u : 0xffffffffu;
+    a.knots = (uint32_t)M.knots;
+    a.B = M.B;
+    a.table = table32;
+    return a;
+}
+
+__device__ inline uint32_t bucket_of32(uint64_t key, const ModelArgs32& M)
+{
+    // feature: bit length b, then the fbits bits below the leading one
+    const uint32_t hi = (uint32_t)(key >> 32), lo = (uint32_t)key;
+    const uint32_t c = hi ? (uint32_t)__clz(hi) : 32u + (uint32_t)__clz(lo);  // 64 for key 0
+    const uint32_t top = (uint32_t)((key << (c & 63)) >> 32);  // leading one at bit 31
+    const uint32_t mant = (top >> (31u - M.fbits)) & ((1u << M.fbits) - 1u);
+    const uint32_t z = key ? ((64u - c) << M.fbits) | mant : 0u;
+    const uint32_t d = z <= M.z_lo ? 0u : min(z - M.z_lo, M.range);
+    const uint32_t seg = d >> M.seg_shift;
+    const uint32_t sc = seg < M.knots ? seg : M.knots - 1u;
+    const uint32_t t0 = M.table[sc], t1 = M.table[sc + 1];
+    const uint64_t prod = (uint64_t)(t1 - t0) * (uint64_t)(d & M.frac_mask);
+    const uint32_t pos = seg < M.knots ? t0 + (uint32_t)(prod >> M.shift) : M.table[M.knots];
+    const uint32_t b = __umulhi(pos, M.B);
+    return b >= M.B ? M.B - 1u : b;
+}
+
 // Bucket arguments of a compiled model (uniform loads at kernel start).
 __device__ inline ModelArgs model_args(const vmps_cdf_model* model, uint32_t B)
 {
@@ -520,12 +563,21 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
 {
     struct alignas(2 * sizeof(K)) KPair { K a, b; };
     constexpr int RP = PART_RND / 2;  // key pairs per thread
-    __shared__ uint64_t tab[VMPS_CDF_MAX_KNOTS + 1];
+    __shared__ uint32_t tab[VMPS_CDF_MAX_KNOTS + 1];
     __shared__ uint32_t hist[PART_NW][256];
     const int tid = threadIdx.x, wave = tid >> 6;
-    ModelArgs M = model_args(model, B);
-    for (int i = tid; i <= M.knots; i += PART_NT) tab[i] = M.table[i];
-    M.table = tab;
+    const ModelArgs M = model_args(model, B);
+    // the table in LDS as 32-bit values when it is monotone and fits 32
+    // bits (a compiled table always does); otherwise the 64-bit evaluation
+    // reads the table in global memory
+    bool bad = false;
+    for (int i = tid; i <= M.knots; i += PART_NT) {
+        const uint64_t t = M.table[i];
+        tab[i] = (uint32_t)t;
+        bad |= (t >> 32) != 0 || (i > 0 && M.table[i - 1] > t);
+    }
+    const bool fast = !__syncthreads_or(bad);
+    const ModelArgs32 M32 = model_args32(M, tab);
     for (uint32_t tile = blockIdx.x; tile < nt1; tile += gridDim.x) {
         for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
         __syncthreads();
@@ -546,10 +598,10 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
         for (int r = 0; r < RP; ++r) {
             const uint32_t q = 2 * (r * PART_NT + tid);
             if (q < len) {
-                const uint32_t b0 = bucket_of((uint64_t)kp[r].a, M);
+                const uint32_t b0 = fast ? bucket_of32((uint64_t)kp[r].a, M32) : bucket_of((uint64_t)kp[r].a, M);
                 atomicAdd(&hist[wave][(b0 >> shift) & mask], 1u);
                 if (q + 1 < len) {
-                    const uint32_t b1 = bucket_of((uint64_t)kp[r].b, M);
+                    const uint32_t b1 = fast ? bucket_of32((uint64_t)kp[r].b, M32) : bucket_of((uint64_t)kp[r].b, M);
                     atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
                     *(uint32_t*)(ids_out + s0 + q) = b0 | (b1 << 16);
                 } else {

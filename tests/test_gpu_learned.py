@@ -169,6 +169,35 @@ def test_partition_tiny_and_ragged(vm, orc):
         assert np.array_equal(_np(off, np.int64), woff) and np.array_equal(_np(ko, np.uint64), wk)
 
 
+def test_partition_caller_tables(vm, orc):
+    """Tables a caller may build: not monotone, values of 2^32 and above, a
+    segment width of 2^40, a z_lo above every feature.  The histogram
+    evaluates monotone 32-bit tables in 32-bit arithmetic and every other
+    table in 64-bit arithmetic; the partition equals the oracle's in each
+    case."""
+    rng = np.random.default_rng(17)
+    x = workloads.lognormal(3 * 8192 + 77, 3)
+    zmax = int(orc.feature(int(x.max()), 64, 20)) + 1
+    sh, kn = orc.cdf_grid(0, zmax, 64)
+
+    def table(k, hi, sort=True):
+        t = rng.integers(0, hi, k + 1, dtype=np.uint64)
+        return np.sort(t) if sort else t
+
+    cases = [("not monotone", orc.Table(table(kn, 1 << 32, sort=False), sh, kn, 0, zmax)),
+             ("above 2^32", orc.Table(table(kn, 1 << 40), sh, kn, 0, zmax)),
+             ("monotone 32-bit", orc.Table(table(kn, 1 << 32), sh, kn, 0, zmax)),
+             ("shift 40", orc.Table(table(4, 1 << 32), 40, 4, 0, zmax)),
+             ("z_lo above the features", orc.Table(table(kn, 1 << 32), sh, kn, 1 << 33, (1 << 33) + zmax))]
+    for name, tab in cases:
+        _say("caller table", name)
+        model_t = vm.model_to_tensor(_host_model(vm, orc, _params(rng, 4), tab, 64, 20))
+        ko, _, off = vm.partition(_t(x), model_t, 4096)
+        wk, _, woff = orc.partition(x, 64, 20, tab, 4096)
+        assert np.array_equal(_np(off, np.int64), woff), name
+        assert np.array_equal(_np(ko, np.uint64), wk), name
+
+
 @pytest.mark.parametrize("steps,batch,lr", [(64, 1024, 1e-4), (32, 512, 4e-4)])
 def test_training_reaches_oracle_quality(vm, orc, steps, batch, lr):
     import torch

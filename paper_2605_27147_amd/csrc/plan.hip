@@ -480,13 +480,13 @@ __global__ void k_entries_lr(const uint32_t* __restrict__ lr_inst, const uint32_
                              uint32_t* __restrict__ ent_inst)
 {
     const uint32_t nl = counters[CNT_NLONG];
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= nl) return;
-    const uint32_t inst = lr_inst[j];
-    const uint32_t idx = j + inst_bigrank[inst];
-    ent_cnt[idx] = lr_cnt[j];
-    ent_base[idx] = lr_base[j];
-    ent_inst[idx] = inst;
+    for (uint32_t j = blockIdx.x * blockDim.x + threadIdx.x; j < nl; j += gridDim.x * blockDim.x) {
+        const uint32_t inst = lr_inst[j];
+        const uint32_t idx = j + inst_bigrank[inst];
+        ent_cnt[idx] = lr_cnt[j];
+        ent_base[idx] = lr_base[j];
+        ent_inst[idx] = inst;
+    }
 }
 
 __global__ void k_entries_tail(const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
@@ -521,20 +521,21 @@ __global__ void k_runs_emit(const uint32_t* __restrict__ ent_off, const uint32_t
                             uint32_t n, uint32_t ell_ovr, const uint32_t* counters,
                             uint32_t* __restrict__ run_start, uint32_t* __restrict__ run_inst)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nr = counters[CNT_NRUNS], ne = counters[CNT_NENT];
-    if (t == nr) run_start[t] = n;
-    if (t >= nr || ne == 0) return;
-    // largest entry e with ent_off[e] <= t (it has a non-zero count)
-    uint32_t lo = 0, hi = ne;
-    while (hi - lo > 1) {
-        uint32_t m = (lo + hi) >> 1;
-        if (ent_off[m] <= t) lo = m; else hi = m;
+    if (blockIdx.x == 0 && threadIdx.x == 0) run_start[nr] = n;
+    if (ne == 0) return;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
+        // largest entry e with ent_off[e] <= t (it has a non-zero count)
+        uint32_t lo = 0, hi = ne;
+        while (hi - lo > 1) {
+            uint32_t m = (lo + hi) >> 1;
+            if (ent_off[m] <= t) lo = m; else hi = m;
+        }
+        const uint32_t inst = ent_inst[lo];
+        const uint32_t ell = inst_ell(inst_start, inst, ell_ovr);
+        run_start[t] = inst_start[inst] + ent_base[lo] + (t - ent_off[lo]) * ell;
+        run_inst[t] = inst;
     }
-    const uint32_t inst = ent_inst[lo];
-    const uint32_t ell = inst_ell(inst_start, inst, ell_ovr);
-    run_start[t] = inst_start[inst] + ent_base[lo] + (t - ent_off[lo]) * ell;
-    run_inst[t] = inst;
 }
 
 // Q[t] = floor(2^31 (s_t + e_t) / len): the first 32 bits of the binary
@@ -544,17 +545,17 @@ __global__ void k_run_q(const uint32_t* __restrict__ run_start, const uint32_t* 
                         uint32_t* __restrict__ run_q, uint32_t* __restrict__ inst_run_lo,
                         uint32_t* __restrict__ inst_run_hi)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t nr = counters[CNT_NRUNS];
-    if (t >= nr) return;
-    const uint32_t inst = run_inst[t];
-    const uint32_t ib = inst_start[inst], il = inst_start[inst + 1] - ib;
-    const bool last = (t + 1 == nr) || run_inst[t + 1] != inst;
-    const uint64_t s = run_start[t] - ib;
-    const uint64_t e = last ? il : run_start[t + 1] - ib;
-    run_q[t] = (uint32_t)(((s + e) << 31) / il);
-    if (t == 0 || run_inst[t - 1] != inst) inst_run_lo[inst] = t;
-    if (last) inst_run_hi[inst] = t;
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
+        const uint32_t inst = run_inst[t];
+        const uint32_t ib = inst_start[inst], il = inst_start[inst + 1] - ib;
+        const bool last = (t + 1 == nr) || run_inst[t + 1] != inst;
+        const uint64_t s = run_start[t] - ib;
+        const uint64_t e = last ? il : run_start[t + 1] - ib;
+        run_q[t] = (uint32_t)(((s + e) << 31) / il);
+        if (t == 0 || run_inst[t - 1] != inst) inst_run_lo[inst] = t;
+        if (last) inst_run_hi[inst] = t;
+    }
 }
 
 // Power, witness, and the node [L,R) of every boundary.
@@ -650,11 +651,12 @@ __global__ void k_hbm_emit(const uint32_t* __restrict__ hbm_flag, const uint32_t
                            const uint32_t* counters, uint32_t* __restrict__ hbm_list,
                            uint32_t* __restrict__ hbm_idx)
 {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= counters[CNT_NRUNS]) return;
-    if (hbm_flag[t]) {
-        hbm_list[hbm_rank[t]] = t;
-        hbm_idx[t] = hbm_rank[t];
+    const uint32_t nr = counters[CNT_NRUNS];
+    for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
+        if (hbm_flag[t]) {
+            hbm_list[hbm_rank[t]] = t;
+            hbm_idx[t] = hbm_rank[t];
+        }
     }
 }
 
@@ -665,28 +667,30 @@ __global__ void k_depth_init(const uint32_t* __restrict__ hbm_list, const uint32
                              const uint8_t* __restrict__ power, const uint32_t* __restrict__ hbm_flag,
                              const uint32_t* counters, uint32_t* __restrict__ par, uint32_t* __restrict__ val)
 {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= counters[CNT_NHBM]) return;
-    const uint32_t t = hbm_list[q];
-    const uint32_t l = bnd_l[t], r = bnd_r[t];
-    uint32_t parent;
-    if (l == NONE) parent = r;
-    else if (r == NONE) parent = l;
-    else parent = power[l] > power[r] ? l : r;
-    const bool ok = parent != NONE && hbm_flag[parent];
-    par[q] = ok ? hbm_idx[parent] : q;
-    val[q] = ok ? 1u : 0u;
+    const uint32_t h = counters[CNT_NHBM];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
+        const uint32_t t = hbm_list[q];
+        const uint32_t l = bnd_l[t], r = bnd_r[t];
+        uint32_t parent;
+        if (l == NONE) parent = r;
+        else if (r == NONE) parent = l;
+        else parent = power[l] > power[r] ? l : r;
+        const bool ok = parent != NONE && hbm_flag[parent];
+        par[q] = ok ? hbm_idx[parent] : q;
+        val[q] = ok ? 1u : 0u;
+    }
 }
 
 __global__ void k_depth_jump(const uint32_t* __restrict__ par_in, const uint32_t* __restrict__ val_in,
                              const uint32_t* counters, uint32_t* __restrict__ par_out,
                              uint32_t* __restrict__ val_out)
 {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= counters[CNT_NHBM]) return;
-    const uint32_t p = par_in[q];
-    val_out[q] = val_in[q] + val_in[p];
-    par_out[q] = par_in[p];
+    const uint32_t h = counters[CNT_NHBM];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
+        const uint32_t p = par_in[q];
+        val_out[q] = val_in[q] + val_in[p];
+        par_out[q] = par_in[p];
+    }
 }
 
 // ------------------------------------------------------ LDS segments --
@@ -697,21 +701,22 @@ __global__ void k_segs_hbm(const uint32_t* __restrict__ hbm_list, const uint32_t
                            const uint32_t* __restrict__ depth, const uint32_t* __restrict__ inst_start,
                            const uint32_t* counters, Seg* __restrict__ segs)
 {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= counters[CNT_NHBM]) return;
-    const uint32_t t = hbm_list[q];
-    const uint32_t inst = run_inst[t];
-    uint32_t a = inst_start[inst], par = q;
-    if (q > 0) {
-        const uint32_t tp = hbm_list[q - 1];
-        if (run_inst[tp] == inst) {
-            a = run_start[tp + 1];
-            if (power[tp] > power[t]) par = q - 1;
+    const uint32_t h = counters[CNT_NHBM];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
+        const uint32_t t = hbm_list[q];
+        const uint32_t inst = run_inst[t];
+        uint32_t a = inst_start[inst], par = q;
+        if (q > 0) {
+            const uint32_t tp = hbm_list[q - 1];
+            if (run_inst[tp] == inst) {
+                a = run_start[tp + 1];
+                if (power[tp] > power[t]) par = q - 1;
+            }
         }
+        Seg s;
+        s.start = a; s.end = run_start[t + 1]; s.inst = inst; s.dst = seg_dst(depth[par]);
+        segs[q] = s;
     }
-    Seg s;
-    s.start = a; s.end = run_start[t + 1]; s.inst = inst; s.dst = seg_dst(depth[par]);
-    segs[q] = s;
 }
 
 __global__ void k_segs_inst(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ run_start,
@@ -757,13 +762,14 @@ __global__ void k_level_count(const uint32_t* __restrict__ hbm_list, const uint3
                               uint32_t T_out, const uint32_t* counters, uint32_t* __restrict__ tiles,
                               uint32_t* __restrict__ level)
 {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= counters[CNT_NHBM]) return;
-    const uint32_t t = hbm_list[q];
-    const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
-    const uint32_t nt = (R - 1) / T_out - L / T_out + 1;
-    tiles[q] = nt;
-    if (power[t] < MAX_LEVEL) atomicAdd(&level[power[t]], nt);
+    const uint32_t h = counters[CNT_NHBM];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
+        const uint32_t t = hbm_list[q];
+        const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
+        const uint32_t nt = (R - 1) / T_out - L / T_out + 1;
+        tiles[q] = nt;
+        if (power[t] < MAX_LEVEL) atomicAdd(&level[power[t]], nt);
+    }
 }
 
 __global__ void k_level_offsets(uint32_t* __restrict__ level, uint32_t pair_cap)
@@ -788,10 +794,11 @@ __global__ void k_level_reserve(const uint32_t* __restrict__ hbm_list, const uin
                                 const uint32_t* __restrict__ tiles, const uint32_t* counters,
                                 uint32_t* __restrict__ level, uint32_t* __restrict__ node_base)
 {
-    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= counters[CNT_NHBM]) return;
-    const uint32_t p = power[hbm_list[q]];
-    node_base[q] = p < MAX_LEVEL ? level[MAX_LEVEL + p] + atomicAdd(&level[2 * MAX_LEVEL + p], tiles[q]) : NONE;
+    const uint32_t h = counters[CNT_NHBM];
+    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
+        const uint32_t p = power[hbm_list[q]];
+        node_base[q] = p < MAX_LEVEL ? level[MAX_LEVEL + p] + atomicAdd(&level[2 * MAX_LEVEL + p], tiles[q]) : NONE;
+    }
 }
 
 // Pair list by level: (HBM node, output tile) for every output tile.
@@ -800,24 +807,33 @@ __global__ void k_level_fill(const uint32_t* __restrict__ hbm_list, const uint32
                              const uint32_t* __restrict__ node_base, uint32_t T_out, const uint32_t* counters,
                              const uint32_t* __restrict__ level, uint32_t* __restrict__ pairs)
 {
-    const uint32_t x = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t h = counters[CNT_NHBM];
-    if (x >= counters[CNT_NPAIRS]) return;
-    uint32_t lo = 0, hi = h;
-    while (hi - lo > 1) {
-        uint32_t m = (lo + hi) >> 1;
-        if (tile_off[m] <= x) lo = m; else hi = m;
+    const uint32_t h = counters[CNT_NHBM], np = counters[CNT_NPAIRS];
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < np; x += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = h;
+        while (hi - lo > 1) {
+            uint32_t m = (lo + hi) >> 1;
+            if (tile_off[m] <= x) lo = m; else hi = m;
+        }
+        const uint32_t t = hbm_list[lo];
+        const uint32_t p = power[t];
+        if (p >= MAX_LEVEL || node_base[lo] == NONE) continue;
+        const uint32_t pos = node_base[lo] + (x - tile_off[lo]);
+        if (pos >= level[MAX_LEVEL + p] + level[p]) continue;  // only past a clamped count
+        pairs[2 * (uint64_t)pos] = lo;
+        pairs[2 * (uint64_t)pos + 1] = bnd_lpos[t] / T_out + (x - tile_off[lo]);
     }
-    const uint32_t t = hbm_list[lo];
-    const uint32_t p = power[t];
-    if (p >= MAX_LEVEL || node_base[lo] == NONE) return;
-    const uint32_t pos = node_base[lo] + (x - tile_off[lo]);
-    if (pos >= level[MAX_LEVEL + p] + level[p]) return;  // only past a clamped count
-    pairs[2 * (uint64_t)pos] = lo;
-    pairs[2 * (uint64_t)pos + 1] = bnd_lpos[t] / T_out + (x - tile_off[lo]);
 }
 
 // ------------------------------------------------------------- host --
+// Grid of the per-element planner kernels: they loop over a count known
+// only on the device, and a grid sized for the capacity would mostly launch
+// workgroups that find nothing to do.
+static inline unsigned stride_grid(uint64_t cap)
+{
+    const uint64_t g = (cap + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g < 2048 ? g : 2048));
+}
+
 namespace {
 struct Carver {
     uint8_t* base;
@@ -973,17 +989,17 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     k_chain_scan<<<1, 64, 0, s>>>(P.lr_inst, P.inst_start, ell_ovr, C, P.chain_val, P.chain_known, P.chain_rin);
     k_chain_apply<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C, P.chain_rin,
                                                 P.lr_cnt, P.lr_base, P.inst_rfinal);
-    k_entries_lr<<<grid_for(P.lr_cap, 256), 256, 0, s>>>(P.lr_inst, P.lr_cnt, P.lr_base, P.inst_bigrank, C,
+    k_entries_lr<<<stride_grid(P.lr_cap), 256, 0, s>>>(P.lr_inst, P.lr_cnt, P.lr_base, P.inst_bigrank, C,
                                                          P.ent_cnt, P.ent_base, P.ent_inst);
     k_entries_tail<<<grid_for(k, 256), 256, 0, s>>>(P.lr_inst, P.inst_start, P.inst_big, P.inst_bigrank,
                                                     P.inst_rfinal, k, ell_ovr, C, P.ent_cnt, P.ent_base,
                                                     P.ent_inst);
     VMPS_HIP(scan_exclusive_u32(P.ent_cnt, P.ent_off, P.ent_cap, C + CNT_NENT, C + CNT_NRUNS, P.scan_tmp, s));
     k_clamp<<<1, 64, 0, s>>>(C, CNT_NRUNS, P.run_cap);
-    k_runs_emit<<<grid_for(P.run_cap + 1, 256), 256, 0, s>>>(P.ent_off, P.ent_base, P.ent_inst, P.inst_start, n,
+    k_runs_emit<<<stride_grid(P.run_cap + 1), 256, 0, s>>>(P.ent_off, P.ent_base, P.ent_inst, P.inst_start, n,
                                                              ell_ovr, C, P.run_start, P.run_inst);
     // 4-5. powers and tree
-    k_run_q<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.run_start, P.run_inst, P.inst_start, C, P.run_q,
+    k_run_q<<<stride_grid(P.run_cap), 256, 0, s>>>(P.run_start, P.run_inst, P.inst_start, C, P.run_q,
                                                      P.inst_run_lo, P.inst_run_hi);
     const unsigned bgrid = grid_for(P.run_cap, 256) < 4096u ? grid_for(P.run_cap, 256) : 4096u;
     k_boundaries<<<bgrid, 256, 0, s>>>(P.run_start, P.run_inst, P.run_q, P.inst_start, P.inst_run_lo,
@@ -991,32 +1007,32 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
                                        P.hbm_flag, P.stats);
     // 6. nodes longer than T and their depths
     VMPS_HIP(scan_exclusive_u32(P.hbm_flag, P.hbm_rank, P.run_cap, C + CNT_NRUNS, C + CNT_NHBM, P.scan_tmp, s));
-    k_hbm_emit<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.hbm_list, P.hbm_idx);
-    k_depth_init<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.hbm_idx, P.bnd_l, P.bnd_r, P.power,
+    k_hbm_emit<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.hbm_list, P.hbm_idx);
+    k_depth_init<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.hbm_idx, P.bnd_l, P.bnd_r, P.power,
                                                           P.hbm_flag, C,
                                                           P.hbm_par[0], P.hbm_val[0]);
     int cur = 0;
     for (int round = 0; round < 6; ++round) {
-        k_depth_jump<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_par[cur], P.hbm_val[cur], C,
+        k_depth_jump<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_par[cur], P.hbm_val[cur], C,
                                                               P.hbm_par[cur ^ 1], P.hbm_val[cur ^ 1]);
         cur ^= 1;
     }
     P.hbm_depth = P.hbm_val[cur];
     // 7. LDS segments and the level table
-    k_segs_hbm<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
+    k_segs_hbm<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
                                                         P.hbm_depth, P.inst_start, C, P.segs);
     k_segs_inst<<<grid_for(k, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.hbm_depth,
                                                  P.inst_start, P.inst_big, P.inst_bigrank, k, C, P.segs);
     VMPS_HIP(fill_u32(P.level, 0, 3 * MAX_LEVEL, s));
-    k_level_count<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
+    k_level_count<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
                                                            C, P.hbm_tiles, P.level);
     VMPS_HIP(scan_exclusive_u32(P.hbm_tiles, P.hbm_tile_off, P.run_cap, C + CNT_NHBM, C + CNT_NPAIRS,
                                 P.scan_tmp, s));
     k_clamp<<<1, 64, 0, s>>>(C, CNT_NPAIRS, P.pair_cap);
     k_level_offsets<<<1, 64, 0, s>>>(P.level, P.pair_cap);
-    k_level_reserve<<<grid_for(P.run_cap, 256), 256, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, P.level,
+    k_level_reserve<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, P.level,
                                                              P.node_base);
-    k_level_fill<<<grid_for(P.pair_cap, 256), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
+    k_level_fill<<<stride_grid(P.pair_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
                                                            P.node_base, P.T_out, C, P.level, P.pairs);
     return hipGetLastError();
 }

@@ -917,7 +917,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
 
 
 // The LDS pass as one persistent launch: as many workgroups as can be
-// resident, each taking the next segment from an atomic ticket (segments
+// resident, each claiming the next segments from an atomic ticket (segments
 // differ in length by orders of magnitude in a batch, so a fixed assignment
 // would leave workgroups idle).  No workgroup ever waits for another.
 // The ticket is broadcast through LDS and made wave-uniform, so the segment

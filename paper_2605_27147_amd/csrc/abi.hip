@@ -447,10 +447,10 @@ vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_c
     if (!cfg || n < 0 || (kt != VMPS_U32 && kt != VMPS_U64)) return VMPS_ERR_INVALID_ARG;
     memset(cfg, 0, sizeof *cfg);
     cfg->num_buckets = 0;
-    cfg->hidden = 32;
-    cfg->steps = 32;
+    cfg->hidden = 64;
+    cfg->steps = 8;
     cfg->batch = 512;
-    cfg->lr = 4e-4f;
+    cfg->lr = 2e-4f;
     cfg->knots = VMPS_CDF_MAX_KNOTS;
     cfg->feature_bits = 20;
     cfg->sample_size = n < (1 << 16) ? n : (1 << 16);

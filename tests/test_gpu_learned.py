@@ -198,17 +198,18 @@ def test_partition_caller_tables(vm, orc):
         assert np.array_equal(_np(ko, np.uint64), wk), name
 
 
-@pytest.mark.parametrize("steps,batch,lr", [(64, 1024, 1e-4), (32, 512, 4e-4)])
-def test_training_reaches_oracle_quality(vm, orc, steps, batch, lr):
+@pytest.mark.parametrize("H,steps,batch,lr", [(32, 64, 1024, 1e-4), (32, 32, 512, 4e-4), (64, 8, 512, 2e-4),
+                                               (64, 24, 512, 6e-4)])
+def test_training_reaches_oracle_quality(vm, orc, H, steps, batch, lr):
     import torch
     keys = np.sort(workloads.lognormal(1 << 16, 21))
     cfg = vm.learned_default_config(1 << 16, vm.U64)
-    cfg.hidden, cfg.steps, cfg.batch, cfg.lr = 32, steps, batch, lr
+    cfg.hidden, cfg.steps, cfg.batch, cfg.lr = H, steps, batch, lr
     model = vm.cdf_train(_t(keys), cfg)
     u, z_lo, z_hi = orc.normalised_features(keys, 64, 20)
     assert (model.z_lo, model.z_hi) == (z_lo, z_hi)
-    p_ref, loss_ref = orc.cdf_train(u, 32, steps, batch, lr)
-    init_ref = orc.cdf_loss(orc.cdf_init(u, 32), u)
+    p_ref, loss_ref = orc.cdf_train(u, H, steps, batch, lr)
+    init_ref = orc.cdf_loss(orc.cdf_init(u, H), u)
     _say("train", model.loss_init, model.loss_final, init_ref, loss_ref)
     assert model.loss_final <= model.loss_init
     assert model.loss_init == pytest.approx(init_ref, rel=0.05, abs=1e-8)

@@ -453,7 +453,7 @@ vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_c
     cfg->lr = 2e-4f;
     cfg->knots = VMPS_CDF_MAX_KNOTS;
     cfg->feature_bits = 20;
-    cfg->sample_size = n < (1 << 16) ? n : (1 << 16);
+    cfg->sample_size = n < 8192 ? n : 8192;  // one LDS tile: the sample sorts in one tile launch
     cfg->seed = 55;
     return VMPS_OK;
 }

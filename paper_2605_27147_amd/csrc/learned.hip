@@ -66,10 +66,11 @@ __device__ inline uint32_t bucket_of(uint64_t key, const ModelArgs& M)
 }
 
 // The same bucket in 32-bit arithmetic, for a monotone table whose values
-// fit 32 bits (every compiled table).  The feature has at most 6 + 24 bits,
-// so z_lo and the range clamped to 2^31 - 1 give the same d; (t1 - t0) times
-// the offset inside the segment is below 2^63 and its quotient by 2^shift
-// below t1 - t0, so every intermediate of cdf_pos is reproduced exactly.
+// fit 32 bits (every compiled table).  The feature is below 2^31 (bit length
+// at most 64, at most 24 fraction bits), so z_lo and the range clamped to
+// 2^31 - 1 give the same d; (t1 - t0) times the offset inside the segment is
+// below 2^63 and its quotient by 2^shift below t1 - t0, so every
+// intermediate of cdf_pos is reproduced exactly.
 struct ModelArgs32 {
     uint32_t z_lo, range, fbits, shift, seg_shift, frac_mask, knots, B;
     const uint32_t* table;  // knots + 1 entries

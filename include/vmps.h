@@ -168,6 +168,10 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
  * is (table interpolation * B) >> 32, all in integers. */
 #define VMPS_CDF_MAX_HIDDEN 64
 #define VMPS_CDF_MAX_KNOTS 4096
+/* vmps_learned_config.flags: keep the parameters after the last Adam step
+ * even when their loss exceeds the initial model's (the default keeps the
+ * better of the two); for checking the training trajectory. */
+#define VMPS_CDF_KEEP_TRAINED 1
 
 typedef struct {
     int32_t num_buckets;  /* B: power of two in [2, 65536]; 0 = automatic */
@@ -177,7 +181,7 @@ typedef struct {
     float lr;             /* Adam learning rate */
     int32_t knots;        /* K: at most this many table segments (1..4096) */
     int32_t feature_bits; /* F in [4, 24] */
-    int32_t reserved;
+    int32_t flags;        /* 0, or VMPS_CDF_KEEP_TRAINED */
     int64_t sample_size;  /* m: keys sampled at SplitMix64 positions (<= n) */
     uint64_t seed;        /* SplitMix64 seed of the sample positions */
 } vmps_learned_config;
@@ -245,7 +249,9 @@ vmps_status vmps_sample(const void* keys, int64_t n, vmps_dtype kt, int64_t m, u
 vmps_status vmps_cdf_grad(const float* params, int32_t hidden, const float* u, const float* y,
                           int32_t nb, float* grad, float* loss, void* stream);
 
-/* Train on a sorted sample and compile (model: device). */
+/* Train on a sorted sample and compile (model: device).  ws: at least 4m
+ * bytes; on return its first m floats hold the normalised features
+ * u_i = (z_i - z_lo)/(z_hi - z_lo) the model was trained on (fp32). */
 vmps_status vmps_cdf_train(const void* sorted_sample, int64_t m, vmps_dtype kt,
                            const vmps_learned_config* cfg, vmps_cdf_model* model, void* ws,
                            size_t ws_bytes, void* stream);

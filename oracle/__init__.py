@@ -66,7 +66,7 @@ def _L():
         lib.orc_powersort.restype = ctypes.c_int
         lib.orc_powersort.argtypes = [vp, vp, i64, i32, ctypes.c_int, ctypes.POINTER(Stats), vp, i64]
         lib.orc_segmented_powersort.restype = ctypes.c_int
-        lib.orc_segmented_powersort.argtypes = [vp, vp, vp, i64, ctypes.c_int]
+        lib.orc_segmented_powersort.argtypes = [vp, vp, vp, i64, i32, ctypes.c_int]
         lib.orc_standard_merge.restype = None
         lib.orc_standard_merge.argtypes = [vp, vp, i64, vp, vp, i64, vp, vp]
         lib.orc_tree_nodes.restype = None
@@ -98,6 +98,10 @@ def _L():
         lib.orc_cdf_init.argtypes = [vp, i64, i32, vp, vp, vp, vp]
         lib.orc_cdf_loss.restype = dbl
         lib.orc_cdf_loss.argtypes = [vp, vp, vp, dbl, i32, vp, i64, i64]
+        lib.orc_cdf_adam_steps.restype = None
+        lib.orc_cdf_adam_steps.argtypes = [vp, i64, i32, i32, i32, dbl, vp, vp]
+        lib.orc_cdf_train2.restype = dbl
+        lib.orc_cdf_train2.argtypes = [vp, i64, i32, i32, i32, dbl, vp, ctypes.POINTER(i32)]
         lib.orc_cdf_train.restype = dbl
         lib.orc_cdf_train.argtypes = [vp, i64, i32, i32, i32, dbl, vp]
         lib.orc_partition.restype = None
@@ -167,12 +171,14 @@ def powersort(keys, vals=None, variant: int = PINGPONG, ell: int = 0, log_merges
     return out, v, st.as_dict(), merges
 
 
-def segmented_powersort(keys, offsets, vals=None, variant: int = PINGPONG):
+def segmented_powersort(keys, offsets, vals=None, variant: int = PINGPONG, ell: int = 0):
+    """Every segment [offsets[s], offsets[s+1]) sorted as its own instance
+    (ell <= 0: the minrun rule for the segment's length)."""
     orig = np.asarray(keys)
     x = _keys64(orig).copy()
     v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
     off = np.ascontiguousarray(offsets, dtype=np.int64)
-    rc = _L().orc_segmented_powersort(_p(x), _p(v), _p(off), off.size - 1, variant)
+    rc = _L().orc_segmented_powersort(_p(x), _p(v), _p(off), off.size - 1, ell, variant)
     if rc != 0:
         raise RuntimeError("oracle segmented powersort failed")
     out = x.astype(orig.dtype) if orig.dtype in (np.uint32, np.int32) else x
@@ -363,9 +369,28 @@ def cdf_loss(params: dict, u, stride: int = 64) -> float:
     return float(_L().orc_cdf_loss(_p(w1), _p(b1), _p(w2), float(params["b2"]), w1.size, _p(u), u.size, stride))
 
 
-def cdf_train(u, H: int, steps: int, nb: int, lr: float):
-    """fp64 reference training: quantile init + Adam; returns (params, loss)."""
+def cdf_train(u, H: int, steps: int, nb: int, lr: float, want_trained: bool = False):
+    """fp64 reference training: quantile init + Adam, then the better of the
+    two models; returns (params, loss) or (params, loss, trained)."""
     u = np.ascontiguousarray(u, dtype=np.float64)
     p = np.zeros(3 * H + 1, dtype=np.float64)
-    loss = _L().orc_cdf_train(_p(u), u.size, H, steps, nb, lr, _p(p))
+    tr = ctypes.c_int32(0)
+    loss = _L().orc_cdf_train2(_p(u), u.size, H, steps, nb, lr, _p(p), ctypes.byref(tr))
+    if want_trained:
+        return _unpack(p, H), float(loss), bool(tr.value)
     return _unpack(p, H), float(loss)
+
+
+def flat_params(params: dict) -> np.ndarray:
+    return np.concatenate([params["w1"], params["b1"], params["w2"], [params["b2"]]]).astype(np.float64)
+
+
+def cdf_adam_steps(u, params: dict, steps: int, nb: int, lr: float):
+    """Adam from the given parameters (no initialisation, no model choice);
+    returns the trajectory, steps x (3H+1) fp64 (row s: after step s+1)."""
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    H = len(params["w1"])
+    p = np.ascontiguousarray(flat_params(params))
+    traj = np.zeros((max(steps, 1), 3 * H + 1), dtype=np.float64)
+    _L().orc_cdf_adam_steps(_p(u), u.size, H, steps, nb, lr, _p(p), _p(traj))
+    return traj[:steps].copy()

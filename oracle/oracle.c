@@ -298,12 +298,12 @@ int orc_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun,
 }
 
 int orc_segmented_powersort(uint64_t* keys, uint32_t* vals, const int64_t* seg_off,
-                            int64_t nseg, int variant)
+                            int64_t nseg, int32_t minrun, int variant)
 {
     for (int64_t s = 0; s < nseg; ++s) {
         int64_t a = seg_off[s], b = seg_off[s + 1];
         if (b < a) return -1;
-        if (orc_powersort(keys + a, vals ? vals + a : NULL, b - a, 0, variant, NULL, NULL, 0))
+        if (orc_powersort(keys + a, vals ? vals + a : NULL, b - a, minrun, variant, NULL, NULL, 0))
             return -1;
     }
     return 0;
@@ -649,24 +649,22 @@ double orc_cdf_loss(const double* w1, const double* b1, const double* w2, double
     return c ? s / (double)c : 0.0;
 }
 
-/* Full training: init, `steps` Adam steps on minibatches of nb points taken
- * at index (step*nb + j) * ORC_BATCH_STRIDE mod m, then keep whichever of the
- * initial and trained models has the smaller strided loss.
- * params = [w1(H) b1(H) w2(H) b2]. Returns the final strided loss. */
-double orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
-                     double lr, double* params)
+/* Adam steps on minibatches, from the parameters the caller passes in:
+ * minibatch j of step s (both 0-based) is the sample point at index
+ * (s*nb + j) * ORC_BATCH_STRIDE mod m with target (index + 1/2)/m, the
+ * gradient is the minibatch MSE's (orc_mlp_grad), and the Adam step count
+ * starts at 1.  params = [w1(H) b1(H) w2(H) b2] is updated in place; traj
+ * (nullable) receives the parameters after every step, steps x (3H+1). */
+void orc_cdf_adam_steps(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
+                        double lr, double* params, double* traj)
 {
     int32_t np_ = 3 * H + 1;
     double* p = params;
-    double* best = (double*)malloc(sizeof(double) * (size_t)np_);
     double* g = (double*)calloc((size_t)np_, sizeof(double));
     double* m1 = (double*)calloc((size_t)np_, sizeof(double));
     double* m2 = (double*)calloc((size_t)np_, sizeof(double));
     double* ub = (double*)malloc(sizeof(double) * (size_t)nb);
     double* yb = (double*)malloc(sizeof(double) * (size_t)nb);
-    orc_cdf_init(u, m, H, p, p + H, p + 2 * H, p + 3 * H);
-    double loss0 = orc_cdf_loss(p, p + H, p + 2 * H, p[3 * H], H, u, m, ORC_LOSS_STRIDE);
-    memcpy(best, p, sizeof(double) * (size_t)np_);
     for (int32_t s = 0; s < steps; ++s) {
         for (int32_t j = 0; j < nb; ++j) {
             uint64_t idx = (((uint64_t)s * (uint64_t)nb + (uint64_t)j) * ORC_BATCH_STRIDE) % (uint64_t)m;
@@ -675,9 +673,36 @@ double orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int32
         }
         orc_mlp_grad(p, p + H, p + 2 * H, p[3 * H], H, ub, yb, nb, g, g + H, g + 2 * H, g + 3 * H);
         orc_adam_update(p, g, m1, m2, np_, s + 1, lr);
+        if (traj) memcpy(traj + (size_t)s * (size_t)np_, p, sizeof(double) * (size_t)np_);
     }
+    free(g); free(m1); free(m2); free(ub); free(yb);
+}
+
+/* Full training: quantile initialisation, `steps` Adam steps
+ * (orc_cdf_adam_steps), then the trained model is kept when its strided
+ * loss is at most the initial model's, else the initial model is restored.
+ * params = [w1(H) b1(H) w2(H) b2].  Returns the final strided loss;
+ * *trained (nullable) is 1 when the trained model was kept. */
+double orc_cdf_train2(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
+                      double lr, double* params, int32_t* trained)
+{
+    int32_t np_ = 3 * H + 1;
+    double* p = params;
+    double* init = (double*)malloc(sizeof(double) * (size_t)np_);
+    orc_cdf_init(u, m, H, p, p + H, p + 2 * H, p + 3 * H);
+    double loss0 = orc_cdf_loss(p, p + H, p + 2 * H, p[3 * H], H, u, m, ORC_LOSS_STRIDE);
+    memcpy(init, p, sizeof(double) * (size_t)np_);
+    orc_cdf_adam_steps(u, m, H, steps, nb, lr, p, NULL);
     double loss1 = orc_cdf_loss(p, p + H, p + 2 * H, p[3 * H], H, u, m, ORC_LOSS_STRIDE);
-    if (!(loss1 <= loss0)) { memcpy(p, best, sizeof(double) * (size_t)np_); loss1 = loss0; }
-    free(best); free(g); free(m1); free(m2); free(ub); free(yb);
+    int32_t keep = loss1 <= loss0;
+    if (!keep) { memcpy(p, init, sizeof(double) * (size_t)np_); loss1 = loss0; }
+    if (trained) *trained = keep;
+    free(init);
     return loss1;
+}
+
+double orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
+                     double lr, double* params)
+{
+    return orc_cdf_train2(u, m, H, steps, nb, lr, params, NULL);
 }

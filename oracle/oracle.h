@@ -60,9 +60,10 @@ void orc_run_powers(const int64_t* bounds, int64_t r, int64_t n, uint8_t* powers
 int orc_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun,
                   int variant, orc_stats* st, int64_t* merge_log, int64_t log_cap);
 
-/* Same, over independent segments seg_off[0..nseg] of one array. */
+/* Same, over independent segments seg_off[0..nseg] of one array; every
+ * segment is an instance of its own (minrun <= 0: the rule for its length). */
 int orc_segmented_powersort(uint64_t* keys, uint32_t* vals, const int64_t* seg_off,
-                            int64_t nseg, int variant);
+                            int64_t nseg, int32_t minrun, int variant);
 
 /* StandardMerge (Algorithm 2, right) with the remainder appended. */
 void orc_standard_merge(const uint64_t* a, const uint32_t* va, int64_t na,
@@ -117,8 +118,13 @@ void     orc_adam_update(double* p, const double* g, double* m1, double* m2, int
                          int64_t step, double lr);
 double   orc_cdf_loss(const double* w1, const double* b1, const double* w2, double b2, int32_t H,
                       const double* u, int64_t m, int64_t stride);
+/* Adam steps from caller parameters, no initialisation, no model choice. */
+void     orc_cdf_adam_steps(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
+                            double lr, double* params, double* traj);
 double   orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
                        double lr, double* params);
+double   orc_cdf_train2(const double* u, int64_t m, int32_t H, int32_t steps, int32_t nb,
+                        double lr, double* params, int32_t* trained);
 void     orc_partition(const uint64_t* keys, const uint32_t* vals, int64_t n,
                        int32_t key_bits, int32_t fbits, uint64_t z_lo, uint64_t z_hi,
                        const uint64_t* table, int32_t shift, int32_t knots, uint32_t B,

@@ -26,12 +26,13 @@ _lib = None
 OK, INVALID_ARG, WORKSPACE_TOO_SMALL, UNSUPPORTED, DEVICE = range(5)
 U32, U64 = 0, 1
 VALUES_IOTA = 1
+CDF_KEEP_TRAINED = 1
 
 
 class LearnedConfig(ctypes.Structure):
     _fields_ = [("num_buckets", ctypes.c_int32), ("hidden", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("batch", ctypes.c_int32), ("lr", ctypes.c_float), ("knots", ctypes.c_int32),
-                ("feature_bits", ctypes.c_int32), ("reserved", ctypes.c_int32), ("sample_size", ctypes.c_int64),
+                ("feature_bits", ctypes.c_int32), ("flags", ctypes.c_int32), ("sample_size", ctypes.c_int64),
                 ("seed", ctypes.c_uint64)]
 
 
@@ -502,7 +503,9 @@ def cdf_grad(params, hidden: int, u, y):
     return grad, loss
 
 
-def cdf_train(sorted_sample, cfg: LearnedConfig) -> CdfModel:
+def cdf_train(sorted_sample, cfg: LearnedConfig, want_features: bool = False):
+    """Trains and compiles the model on a sorted sample; returns the model
+    (and with want_features the fp32 features u it was trained on)."""
     torch = _torch()
     _require_cuda(sorted_sample)
     m = sorted_sample.numel()
@@ -511,7 +514,10 @@ def cdf_train(sorted_sample, cfg: LearnedConfig) -> CdfModel:
     _check(load_library().vmps_cdf_train(_ptr(sorted_sample), m, _dtype_code(sorted_sample), ctypes.byref(cfg),
                                          _ptr(model_t), _ptr(ws), ws.numel(), _stream(sorted_sample.device)),
            "vmps_cdf_train")
-    return model_from_tensor(model_t)
+    model = model_from_tensor(model_t)
+    if want_features:
+        return model, ws[: 4 * m].view(torch.float32).clone()
+    return model
 
 
 def cdf_compile(params, hidden: int, z_lo: int, z_hi: int, key_bits: int, feature_bits: int, knots: int):

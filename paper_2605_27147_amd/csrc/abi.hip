@@ -396,6 +396,7 @@ vmps_status check_config(const vmps_learned_config& c, int64_t n)
     if (!(c.lr >= 0.f) || c.knots < 1 || c.knots > VMPS_CDF_MAX_KNOTS) return VMPS_ERR_INVALID_ARG;
     if (c.feature_bits < 4 || c.feature_bits > 24) return VMPS_ERR_INVALID_ARG;
     if (c.sample_size < 2 || c.sample_size > n) return VMPS_ERR_INVALID_ARG;
+    if (c.flags & ~VMPS_CDF_KEEP_TRAINED) return VMPS_ERR_INVALID_ARG;
     return VMPS_OK;
 }
 

@@ -408,10 +408,11 @@ __global__ __launch_bounds__(TRAIN_NT) void k_cdf_compile(const float* __restric
 
 // Whole training in one workgroup: quantile initialisation, `steps` Adam
 // steps on strided minibatches, keep the better of initial and trained
-// model, compile.
+// model (or the trained one when keep_trained is set), compile.
 template <int H>
 __global__ __launch_bounds__(TRAIN_NT) void k_cdf_train(const float* __restrict__ u, uint64_t m, int steps,
-                                                        int nb, float lr, int K, vmps_cdf_model* model)
+                                                        int nb, float lr, int K, int keep_trained,
+                                                        vmps_cdf_model* model)
 {
     __shared__ TrainLds S;
     __shared__ uint32_t scan_lds[TRAIN_NT];
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(TRAIN_NT) void k_cdf_train(const float* __restrict_
         __syncthreads();
     }
     const float loss1 = strided_loss<H>(S, u, m);
-    const bool keep = !(loss1 <= loss0);
+    const bool keep = !keep_trained && !(loss1 <= loss0);
     if (keep && t < NP) S.p[t] = S.best[t];
     __syncthreads();
     if (t == 0) {
@@ -1025,9 +1026,9 @@ hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmp
     else
         k_cdf_features<uint64_t><<<grid1(m), 256, 0, s>>>((const uint64_t*)sorted, m, 64, c.feature_bits, u, model);
     switch (c.hidden) {
-    case 16: k_cdf_train<16><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
-    case 32: k_cdf_train<32><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
-    default: k_cdf_train<64><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, model); break;
+    case 16: k_cdf_train<16><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
+    case 32: k_cdf_train<32><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
+    default: k_cdf_train<64><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
     }
     return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 // Stable merge of two sorted ranges through LDS (StandardMerge of
 // Algorithm 2: an element of the left range precedes an equal element of the
-// right one), shared by the merge levels and the persistent executor.
+// right one), shared by the merge levels, the two-array merge and the LDS
+// tile pass.
 #pragma once
 #include "vmps_internal.hpp"
 

@@ -30,8 +30,8 @@ CSRC = os.path.join(HERE, "csrc")
 
 # kernel kind (as traced by the library) -> (kernel name pattern, source files)
 KINDS = {
-    "tilesort": (r"k_tilesort<", ["tilesort.hip", "vmps_internal.hpp"]),
-    "level_merge": (r"k_level_merge<", ["merge.hip", "vmps_internal.hpp"]),
+    "tilesort": (r"k_tilesort<", ["tilesort.hip", "merge_tile.hpp", "vmps_internal.hpp"]),
+    "level_merge": (r"k_level_merge<", ["merge.hip", "merge_tile.hpp", "vmps_internal.hpp"]),
     "level_partition": (r"k_level_partition<", ["merge.hip", "vmps_internal.hpp"]),
     "scatter": (r"k_part_scatter<", ["learned.hip", "vmps_internal.hpp"]),
     "histogram": (r"k_part_hist1<", ["learned.hip", "vmps_internal.hpp"]),

@@ -318,3 +318,49 @@ def test_segmented_equals_per_segment_library_sort(orc):
             order = np.argsort(keys[a:b], kind="stable") + a
             assert out[a:b].tolist() == keys[order].tolist()
             assert v[a:b].tolist() == order.tolist()
+
+
+# ------------------------------------------- exhaustive small inputs --
+def _all_permutations(n):
+    return np.fromiter(itertools.chain.from_iterable(itertools.permutations(range(n))), dtype=np.uint8,
+                       count=math.factorial(n) * n).reshape(-1, n)
+
+
+def _all_words(n):
+    # row r is r written in base 3 with n digits (most significant first)
+    r = np.arange(3 ** n, dtype=np.int64)[:, None]
+    return ((r // (3 ** np.arange(n - 1, -1, -1, dtype=np.int64))) % 3).astype(np.uint8)
+
+
+def _sort_rows_with_oracle(orc, rows, ell, variant):
+    cnt, n = rows.shape
+    keys = rows.reshape(-1).astype(np.uint64)
+    off = np.arange(cnt + 1, dtype=np.int64) * n
+    vals = np.tile(np.arange(n, dtype=np.uint32), cnt)  # index inside the row
+    out, v = orc.segmented_powersort(keys, off, vals, variant=variant, ell=ell)
+    return out.reshape(cnt, n), v.reshape(cnt, n)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_exhaustive_permutations_up_to_10(orc, variant):
+    # every permutation of n <= 10 (3.6 million at n = 10), each sorted as
+    # its own instance with minrun 2 so that runs, powers and merges are
+    # exercised; with distinct keys the stable sort is the inverse
+    # permutation (numpy's argsort of the row)
+    for n in range(1, 11):
+        rows = _all_permutations(n)
+        out, v = _sort_rows_with_oracle(orc, rows, 2, variant)
+        assert np.array_equal(out, np.broadcast_to(np.arange(n, dtype=np.uint64), out.shape)), n
+        assert np.array_equal(v, np.argsort(rows, axis=1).astype(np.uint32)), n
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_exhaustive_words_up_to_12(orc, variant):
+    # every word over {0,1,2} of length <= 12: equal keys keep their order
+    # (numpy's stable argsort of the row is the definition)
+    for n in range(1, 13):
+        rows = _all_words(n)
+        out, v = _sort_rows_with_oracle(orc, rows, 2, variant)
+        want = np.argsort(rows, axis=1, kind="stable")
+        assert np.array_equal(v, want.astype(np.uint32)), n
+        assert np.array_equal(out, np.take_along_axis(rows, want, axis=1).astype(np.uint64)), n

@@ -144,13 +144,109 @@ def test_quantile_init_interpolates_ecdf(orc):
     assert orc.mlp_forward(p, -1.0) == pytest.approx(0.5 / m)
 
 
-def test_training_does_not_increase_loss(orc):
+BATCH_STRIDE = 0x9E3779B1  # minibatch rule of the training (odd multiplier mod m)
+
+
+def _minibatch(u, m, s, nb):
+    """Points of minibatch s: index (s*nb + j) * stride mod m, target (index + 1/2)/m."""
+    idx = np.array([((s * nb + j) * BATCH_STRIDE) % m for j in range(nb)], dtype=np.int64)
+    return u[idx], (idx + 0.5) / m
+
+
+def _flat(g):
+    return np.concatenate([g["w1"], g["b1"], g["w2"], [g["b2"]]])
+
+
+def test_adam_steps_zero_learning_rate_keeps_start(orc):
+    # lr = 0 leaves every parameter bit for bit where it started; a step
+    # counter starting at 0 (bias correction 1 - beta^0 = 0) would turn them
+    # into NaN here
+    rng = np.random.default_rng(8)
+    u = np.sort(rng.random(37))
+    p = _rand_params(rng, 3)
+    traj = orc.cdf_adam_steps(u, p, 5, 64, 0.0)
+    for row in traj:
+        assert np.array_equal(row, orc.flat_params(p))
+    keys = np.sort(workloads.lognormal(1 << 12, 3))
+    uu, _, _ = orc.normalised_features(keys, 64, 20)
+    p0 = orc.cdf_init(uu, 16)
+    p1, l1, trained = orc.cdf_train(uu, 16, 4, 256, 0.0, want_trained=True)
+    assert trained and np.array_equal(orc.flat_params(p1), orc.flat_params(p0))
+    assert l1 == orc.cdf_loss(p0, uu)
+
+
+@pytest.mark.parametrize("m,H,nb", [(4, 1, 8), (4, 2, 64), (37, 2, 64), (1000, 5, 128)])
+def test_adam_first_two_steps_on_their_minibatches(orc, m, H, nb):
+    # Step 1 of Adam moves every parameter by lr g / (|g| + eps) (both moment
+    # estimates are exact after bias correction), with g the gradient of the
+    # MSE on minibatch 0 (pinned by finite differences); step 2 uses the
+    # gradient at the new parameters on minibatch 1 and the moments
+    # m = (0.9*0.1 g1 + 0.1 g2) / (1 - 0.9^2), v = (0.999*0.001 g1^2 + 0.001 g2^2) / (1 - 0.999^2).
+    # A wrong minibatch index, target, step counter or gradient fails here.
+    rng = np.random.default_rng(m + H)
+    u = np.sort(rng.random(m))
+    p0 = _rand_params(rng, H)
+    lr = 1e-2
+    traj = orc.cdf_adam_steps(u, p0, 2, nb, lr)
+    ub, yb = _minibatch(u, m, 0, nb)
+    _, g1 = orc.mlp_grad(p0, ub, yb)
+    g1 = _flat(g1)
+    want1 = orc.flat_params(p0) - lr * g1 / (np.abs(g1) + 1e-8)
+    assert np.allclose(traj[0], want1, rtol=1e-12, atol=1e-15)
+    p1 = {"w1": traj[0][:H], "b1": traj[0][H:2 * H], "w2": traj[0][2 * H:3 * H], "b2": float(traj[0][3 * H])}
+    ub, yb = _minibatch(u, m, 1, nb)
+    _, g2 = orc.mlp_grad(p1, ub, yb)
+    g2 = _flat(g2)
+    mh = (0.9 * 0.1 * g1 + 0.1 * g2) / (1 - 0.9 ** 2)
+    vh = (0.999 * 0.001 * g1 * g1 + 0.001 * g2 * g2) / (1 - 0.999 ** 2)
+    want2 = traj[0] - lr * mh / (np.sqrt(vh) + 1e-8)
+    assert np.allclose(traj[1], want2, rtol=1e-10, atol=1e-14)
+
+
+def test_loss_identity_model_is_zero(orc):
+    # f(u) = u on u_i = (i + 1/2)/m puts every point on its target
+    ident = {"w1": np.array([1.0]), "b1": np.array([0.0]), "w2": np.array([1.0]), "b2": 0.0}
+    for m in (1, 7, 64, 1000, 4096):
+        u = (np.arange(m) + 0.5) / m
+        for stride in (1, 3, 64):
+            assert orc.cdf_loss(ident, u, stride) == 0.0
+
+
+def test_loss_constant_model_closed_form(orc):
+    # f = c: the mean over the k = ceil(m/s) points i = s*j of (c - (s*j + 1/2)/m)^2,
+    # from sum_j (s j + 1/2) = s k(k-1)/2 + k/2 and
+    # sum_j (s j + 1/2)^2 = s^2 (k-1)k(2k-1)/6 + s k(k-1)/2 + k/4
+    from fractions import Fraction
+    rng = np.random.default_rng(2)
+    for m, s in ((1, 1), (10, 1), (10, 3), (4096, 64), (5000, 64), (777, 5)):
+        c = float(rng.random())
+        const = {"w1": np.array([0.0]), "b1": np.array([0.0]), "w2": np.array([0.0]), "b2": c}
+        u = np.sort(rng.random(m))
+        k = -(-m // s)
+        C = Fraction(c)
+        s1 = Fraction(s * k * (k - 1), 2) + Fraction(k, 2)
+        s2 = Fraction(s * s * (k - 1) * k * (2 * k - 1), 6) + Fraction(s * k * (k - 1), 2) + Fraction(k, 4)
+        want = (k * C * C - 2 * C * s1 / m + s2 / (m * m)) / k
+        assert orc.cdf_loss(const, u, s) == pytest.approx(float(want), rel=1e-12, abs=1e-300)
+
+
+def test_training_keeps_the_better_model(orc):
+    # the trained parameters are the raw Adam trajectory's last row when
+    # their strided loss is at most the initial one, else the initial model
     keys = np.sort(workloads.lognormal(1 << 14, 6))
     u, _, _ = orc.normalised_features(keys, 64, 20)
-    p0 = orc.cdf_init(u, 32)
-    l0 = orc.cdf_loss(p0, u)
-    p1, l1 = orc.cdf_train(u, 32, 64, 1024, 1e-4)
-    assert l1 <= l0
+    H, steps, nb = 16, 24, 512
+    init = orc.cdf_init(u, H)
+    l0 = orc.cdf_loss(init, u)
+    for lr, improves in ((3e-4, True), (5.0, False)):
+        traj = orc.cdf_adam_steps(u, init, steps, nb, lr)
+        last = {"w1": traj[-1][:H], "b1": traj[-1][H:2 * H], "w2": traj[-1][2 * H:3 * H], "b2": float(traj[-1][3 * H])}
+        l_raw = orc.cdf_loss(last, u)
+        assert (l_raw <= l0) == improves, (lr, l_raw, l0)
+        p, l, trained = orc.cdf_train(u, H, steps, nb, lr, want_trained=True)
+        assert trained == improves
+        assert np.array_equal(orc.flat_params(p), traj[-1] if improves else orc.flat_params(init))
+        assert l == (l_raw if improves else l0)
 
 
 def test_adam_first_steps_closed_form(orc):

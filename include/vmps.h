@@ -20,17 +20,18 @@
  *   - All pointers except those marked "host" are device pointers of the
  *     current HIP device.  The caller owns every buffer; the library
  *     allocates no device memory and keeps no pointer after its stream work
- *     ends.  (Each host thread gets one 132-byte pinned host buffer and one
- *     event per device on its first sort, kept until the process ends.)
+ *     ends.  (Only with the opt-in host_wait tuning: each host thread gets
+ *     one 132-byte pinned host buffer and one event per device on its first
+ *     such sort, kept until the process ends.)
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
  *     Calls enqueue work and their results are ready when the stream
- *     reaches that point.  The one host wait: the sorts that merge beyond
- *     the LDS tile (vmps_sort, vmps_segmented_sort, vmps_sort_learned) copy
- *     the planner's per-level merge counts to the host and wait for that
- *     copy (the planning kernels only; the tile pass is already enqueued and
- *     runs meanwhile) so that they launch only the non-empty merge levels.
- *     On a stream under graph capture, or with the tuning field
- *     no_host_wait set, they do not wait and launch every level.
+ *     reaches that point; no call waits on the host.  The sorts that merge
+ *     beyond the LDS tile launch one merge-level pair per possible power
+ *     (at most ceil(log2 n)); a level the planner left empty returns at
+ *     once on the GPU.  Opt-in (tuning field host_wait = 1): they copy the
+ *     planner's per-level merge counts to a pinned host buffer, wait for
+ *     that copy and launch only the non-empty levels (not under graph
+ *     capture).
  *   - Lengths are limited to n < 2^32.  Keys must be aligned to their size.
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is written.  VMPS_ERR_DEVICE reports a failed HIP launch.
@@ -287,13 +288,15 @@ typedef struct {
     int32_t merge_grid;     /* workgroups of one HBM merge level (0: 2048) */
     int32_t bucket_div;     /* learned path: buckets of about T/bucket_div
                                keys, T the LDS tile (0: 2) */
-    int32_t no_host_wait;   /* 1: the sorts never wait on the host for the
-                               merge-level counts and launch every level
-                               (empty ones return at once); 0 or 1 only */
+    int32_t host_wait;      /* 1: the sorts wait on the host for the
+                               planner's merge-level counts and launch only
+                               the non-empty levels; 0 (default): fully
+                               asynchronous, every level launched (empty
+                               ones return at once); 0 or 1 only */
 } vmps_tuning;
 
 /* t == NULL restores the defaults.  Negative fields, bucket_div > 64 or
- * no_host_wait outside {0, 1} -> INVALID_ARG. */
+ * host_wait outside {0, 1} -> INVALID_ARG. */
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t);
 vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t);
 

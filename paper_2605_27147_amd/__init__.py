@@ -51,7 +51,7 @@ class CdfModel(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
-                ("bucket_div", ctypes.c_int32), ("no_host_wait", ctypes.c_int32)]
+                ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32)]
 
 
 class LearnedStats(ctypes.Structure):
@@ -157,8 +157,8 @@ def _gpu_arch():
 
 
 def set_tuning(dtype_code: int, has_values: bool, tile_wg_per_cu: int = 0, merge_grid: int = 0,
-               bucket_div: int = 0, no_host_wait: int = 0):
-    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, no_host_wait)
+               bucket_div: int = 0, host_wait: int = 0):
+    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, host_wait)
     _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_set_tuning")
 
 
@@ -170,7 +170,7 @@ def get_tuning(dtype_code: int, has_values: bool) -> dict:
     t = Tuning()
     _check(load_library().vmps_get_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_get_tuning")
     return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div,
-            "no_host_wait": t.no_host_wait}
+            "host_wait": t.host_wait}
 
 
 def status_string(s: int) -> str:

@@ -191,13 +191,29 @@ vmps_status vmps_sort_workspace_size(int64_t n, vmps_dtype kt, int has_values, s
 vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
                       size_t ws_bytes, void* stream)
 {
+    const vmps_status st = check_sort_args(keys, values, n, kt, flags);
+    if (st != VMPS_OK) return st;
+    return sort_in_workspace(keys, values, n, kt, flags, ws, ws_bytes, (hipStream_t)stream, true);
+}
+
+}  // extern "C"
+
+namespace vmps {
+
+vmps_status check_sort_args(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags)
+{
     vmps_status st = check_keys(keys, n, kt);
     if (st != VMPS_OK) return st;
     if (flags & ~VMPS_VALUES_IOTA) return VMPS_ERR_INVALID_ARG;
     if ((flags & VMPS_VALUES_IOTA) && !values && n > 0) return VMPS_ERR_INVALID_ARG;
     if (values && ((uintptr_t)values & 3)) return VMPS_ERR_INVALID_ARG;
     if (values && n > 0 && ranges_overlap(keys, key_bytes(kt) * n, values, 4 * (size_t)n)) return VMPS_ERR_INVALID_ARG;
-    hipStream_t s = (hipStream_t)stream;
+    return VMPS_OK;
+}
+
+vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
+                              size_t ws_bytes, hipStream_t s, bool allow_host_wait)
+{
     if (n <= 1) {
         if (n == 1 && (flags & VMPS_VALUES_IOTA))
             return guarded([&] { k_write_zero_u32<<<1, 1, 0, s>>>(values); return hipGetLastError(); });
@@ -222,11 +238,15 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
             return tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s);
         }
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
-        VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
+        VMPS_HIP(level_probe_enqueue(P, kb, has_values, s, allow_host_wait));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
 }
+
+}  // namespace vmps
+
+extern "C" {
 
 vmps_status vmps_merge_workspace_size(int64_t na, int64_t nb, vmps_dtype kt, size_t* bytes)
 {
@@ -637,9 +657,9 @@ vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t)
     Tuning v{0, 0, 0, 0};
     if (t) {
         if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 ||
-            (t->no_host_wait != 0 && t->no_host_wait != 1))
+            (t->host_wait != 0 && t->host_wait != 1))
             return VMPS_ERR_INVALID_ARG;
-        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->no_host_wait};
+        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->host_wait};
     }
     tuning_table()[kt == VMPS_U64][has_values ? 1 : 0] = v;
     return VMPS_OK;
@@ -652,7 +672,7 @@ vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t)
     t->tile_wg_per_cu = v.tile_wg_per_cu;
     t->merge_grid = v.merge_grid;
     t->bucket_div = v.bucket_div;
-    t->no_host_wait = v.no_host_wait;
+    t->host_wait = v.host_wait;
     return VMPS_OK;
 }
 

@@ -74,8 +74,9 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
     }
 }
 
-// Per host thread and device: a pinned copy of the level counts and the
-// event that marks its arrival (allocated on first use, kept until exit).
+// Opt-in host wait (tuning host_wait = 1).  Per host thread and device: a
+// pinned copy of the level counts and the event that marks its arrival
+// (allocated on first use, kept until exit).
 struct LevelProbe {
     uint32_t* host = nullptr;
     hipEvent_t ev = nullptr;
@@ -91,11 +92,11 @@ static LevelProbe& level_probe()
     return pr[d & 15];
 }
 
-hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s)
+hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s, bool allowed)
 {
     LevelProbe& pr = level_probe();
     pr.armed = false;
-    if (tuning_for(key_bits, has_values != 0).no_host_wait) return hipSuccess;
+    if (!allowed || !tuning_for(key_bits, has_values != 0).host_wait) return hipSuccess;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     VMPS_HIP(hipStreamIsCapturing(s, &cs));
     if (cs != hipStreamCaptureStatusNone) return hipSuccess;  // a graph launches every level

@@ -175,7 +175,7 @@ struct Tuning {
     int tile_wg_per_cu;  // workgroups per CU of the persistent LDS pass (0: as many as fit)
     int merge_grid;      // workgroups of a merge level (0: 2048)
     int bucket_div;      // learned buckets target the tile length / bucket_div (0: 2)
-    int no_host_wait;    // 1: never wait on the host for the level counts
+    int host_wait;       // 1: wait on the host for the level counts, launch the non-empty levels only
 };
 const Tuning& tuning_for(int key_bits, bool has_values);
 
@@ -215,11 +215,14 @@ uint32_t tilesort_capacity(int key_bits, int has_values);
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
 
 // HBM merge levels.
-// Copies the planner's per-level pair counts to pinned host memory (not
-// while the stream is being captured).  The next merge_levels_enqueue for
-// the same plan waits for that copy only (the tile pass enqueued in between
-// keeps the GPU busy meanwhile) and launches the non-empty levels alone.
-hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s);
+// With the opt-in host_wait tuning (and allowed by the caller): copies the
+// planner's per-level pair counts to pinned host memory (not while the
+// stream is being captured); the next merge_levels_enqueue for the same plan
+// waits for that copy only (the tile pass enqueued in between keeps the GPU
+// busy meanwhile) and launches the non-empty levels alone.  Otherwise it
+// disarms any earlier probe and every level is launched.
+hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s,
+                               bool allowed = true);
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                                 uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
 uint32_t merge_tile_out(int key_bits, int has_values);
@@ -250,6 +253,13 @@ constexpr uint32_t JUDGE_GRID = 256;
 hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
                                  const void* sample, uint64_t m, int key_bits, uint64_t* part,
                                  vmps_learned_stats* st, hipStream_t s);
+
+// The whole stable sort of one array with a caller-provided workspace
+// (vmps_sort's body after its argument checks; allow_host_wait = false never
+// waits on the host and allocates nothing, whatever the tuning says).
+vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
+                              size_t ws_bytes, hipStream_t s, bool allow_host_wait);
+vmps_status check_sort_args(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags);
 
 }  // namespace vmps
 

@@ -55,10 +55,10 @@ def test_tuning_table_host_side():
     lib = vm.load_library()
     vm.set_tuning(vm.U64, False, tile_wg_per_cu=1, merge_grid=1024, bucket_div=3)
     assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 1, "merge_grid": 1024, "bucket_div": 3,
-                                            "no_host_wait": 0}
-    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "no_host_wait": 0}
-    vm.set_tuning(vm.U32, True, no_host_wait=1)
-    assert vm.get_tuning(vm.U32, True)["no_host_wait"] == 1
+                                            "host_wait": 0}
+    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0}
+    vm.set_tuning(vm.U32, True, host_wait=1)
+    assert vm.get_tuning(vm.U32, True)["host_wait"] == 1
     vm.reset_tuning(vm.U32, True)
     bad = vm.Tuning(-1, 0, 0, 0)
     assert lib.vmps_set_tuning(vm.U64, 0, ctypes.byref(bad)) == 1
@@ -68,7 +68,7 @@ def test_tuning_table_host_side():
     assert lib.vmps_set_tuning(vm.U32, 1, ctypes.byref(bad)) == 1
     assert lib.vmps_set_tuning(5, 0, None) == 1
     vm.reset_tuning(vm.U64, False)
-    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "no_host_wait": 0}
+    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0}
 
 
 def test_graph_capture_rejects_bad_arguments_without_gpu_work():

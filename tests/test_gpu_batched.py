@@ -91,16 +91,16 @@ def test_learned_graph_replays_match_oracle(vm, orc):
     g.close()
 
 
-@pytest.mark.parametrize("tile_wg, merge_grid, bucket_div, no_wait", [(1, 256, 2, 0), (2, 4096, 4, 1), (0, 0, 3, 1)])
-def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, no_wait):
+@pytest.mark.parametrize("tile_wg, merge_grid, bucket_div, host_wait", [(1, 256, 2, 1), (2, 4096, 4, 0), (0, 0, 3, 0)])
+def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, host_wait):
     import torch
     keys_np, off = workloads.batch32(128, 45, lengths=workloads.batch_lengths(128, 45, hi_log2=17))
     want, _ = orc.segmented_powersort(keys_np, off)
     x = workloads.lognormal(1 << 19, 46)
     wantx, _, _, _ = orc.powersort(x)
     try:
-        vm.set_tuning(vm.U32, False, tile_wg, merge_grid, bucket_div, no_wait)
-        vm.set_tuning(vm.U64, False, tile_wg, merge_grid, bucket_div, no_wait)
+        vm.set_tuning(vm.U32, False, tile_wg, merge_grid, bucket_div, host_wait)
+        vm.set_tuning(vm.U64, False, tile_wg, merge_grid, bucket_div, host_wait)
         keys = _t(keys_np)
         vm.segmented_sort_(keys, torch.from_numpy(off).cuda())
         assert np.array_equal(_np(keys, np.uint32), want.astype(np.uint32))

@@ -83,6 +83,23 @@ vmps_status vmps_sort_workspace_size(int64_t n, vmps_dtype kt, int has_values, s
 vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
                       void* ws, size_t ws_bytes, void* stream);
 
+/* For callers that cannot allocate (code under graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): vmps_sort with its workspace in a
+ * fixed device array inside the library instead of `ws`.  Same arguments,
+ * result and errors as vmps_sort; it calls no allocator, never waits on the
+ * host (the host_wait tuning is ignored) and is asynchronous on `stream`.
+ *   - The array holds vmps_noalloc_scratch_bytes() bytes (96 MiB) on every
+ *     GPU the library runs on, from its first use there until the process
+ *     ends.  A sort whose vmps_sort_workspace_size exceeds it (n above 2^22
+ *     for some key types) -> WORKSPACE_TOO_SMALL, with nothing enqueued.
+ *   - All calls on one GPU share that GPU's array: calls that overlap in
+ *     time on one GPU (two streams, two host threads) race and give wrong
+ *     results; order them on one stream.  Each call overwrites what the last
+ *     one left there, and nothing in it needs clearing between calls. */
+vmps_status vmps_sort_noalloc(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                              void* stream);
+size_t vmps_noalloc_scratch_bytes(void);
+
 /* Workspace of vmps_merge. */
 vmps_status vmps_merge_workspace_size(int64_t na, int64_t nb, vmps_dtype kt, size_t* bytes);
 

@@ -89,6 +89,8 @@ def load_library():
         "vmps_max_runs": (i64, [i64, i32]),
         "vmps_sort_workspace_size": (st, [i64, st, st, ctypes.POINTER(sz)]),
         "vmps_sort": (st, [vp, vp, i64, st, u32, vp, sz, vp]),
+        "vmps_sort_noalloc": (st, [vp, vp, i64, st, u32, vp]),
+        "vmps_noalloc_scratch_bytes": (sz, []),
         "vmps_merge_workspace_size": (st, [i64, i64, st, ctypes.POINTER(sz)]),
         "vmps_merge": (st, [vp, vp, i64, vp, vp, i64, vp, vp, st, vp, sz, vp]),
         "vmps_extract_runs": (st, [vp, i64, st, i32, vp, vp, vp, sz, vp]),
@@ -251,6 +253,22 @@ def sort_(keys, values=None, *, iota: bool = False, workspace=None):
     _check(lib.vmps_sort(_ptr(keys), _ptr(values), n, kt, flags, _ptr(ws), ws.numel(), _stream(keys.device)),
            "vmps_sort")
     return keys
+
+
+def sort_noalloc_(keys, values=None, *, iota: bool = False):
+    """sort_ with the library's own device scratch array as the workspace
+    (no allocation; calls on one GPU must not overlap in time)."""
+    lib = load_library()
+    _require_cuda(keys, values)
+    kt = _dtype_code(keys)
+    flags = VALUES_IOTA if iota else 0
+    _check(lib.vmps_sort_noalloc(_ptr(keys), _ptr(values), keys.numel(), kt, flags, _stream(keys.device)),
+           "vmps_sort_noalloc")
+    return keys
+
+
+def noalloc_scratch_bytes() -> int:
+    return int(load_library().vmps_noalloc_scratch_bytes())
 
 
 def argsort_(keys, indices):

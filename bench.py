@@ -152,10 +152,16 @@ def main():
     log(f"{args.path}: warmup {args.warmup}, timed {args.steps}")
     ms, trace = run_path(vm, args.path, keys, pristine, args.steps, args.warmup, traced_steps=TRACED)
     assert int(keys.sum().item()) == checksum, "output is not a permutation of the input"
-    stats = None
+    stats = stats0 = None
     if args.path == "learned":
         keys.copy_(pristine)
         stats, _ = vm.sort_learned_(keys, workspace=ws)
+        # the same sort with the quantile initialisation alone (no Adam
+        # step), outside the timed steps: what training adds
+        cfg0 = vm.learned_default_config(n, vm.U64)
+        cfg0.steps = 0
+        keys.copy_(pristine)
+        stats0, _ = vm.sort_learned_(keys, workspace=ws, cfg=cfg0)
     other = "plain" if args.path == "learned" else "learned"
     other_ms = None
     if args.compare_steps > 0:
@@ -192,7 +198,9 @@ def main():
         cfgd.update({"buckets": stats["buckets"], "sample": int(cfg.sample_size), "hidden": cfg.hidden,
                      "adam_steps": cfg.steps, "fallback_keys": stats["fallback_keys"],
                      "fallback_buckets": stats["fallback_buckets"], "max_bucket": stats["max_bucket"],
-                     "model_loss_init": stats["loss_init"], "model_loss_final": stats["loss_final"]})
+                     "model_loss_init": stats["loss_init"], "model_loss_final": stats["loss_final"],
+                     "init_model_fallback_keys": stats0["fallback_keys"],
+                     "init_model_max_bucket": stats0["max_bucket"]})
     else:
         cfgd.update({"merge_cost": sch["merge_cost"], "merge_cost_hbm": m_hbm_plain, "runs": sch["runs"]})
     out = {
@@ -213,12 +221,32 @@ def main():
         oracle.build()
         msz = min(n, 1 << args.cpu_sample_log2)
         sample = np.ascontiguousarray(keys_np[:msz])
-        t0 = time.perf_counter()
-        oracle.powersort(sample)
-        dt = time.perf_counter() - t0
+        # one host core: the oracle is single-threaded; pin it so the time
+        # is one core's
+        prev = os.sched_getaffinity(0)
+        core = min(prev)
+        os.sched_setaffinity(0, {core})
+        try:
+            t0 = time.perf_counter()
+            oracle.powersort(sample)
+            dt = time.perf_counter() - t0
+        finally:
+            os.sched_setaffinity(0, prev)
+        cpu_model = "unknown"
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         out["cpu_baseline"] = {"value": round(msz / dt / 1e9, 6), "unit": "Gkeys/s", "cores": 1, "kind": "oracle",
                                "sample": f"first 2^{args.cpu_sample_log2} keys of the same lognormal input, "
-                                         f"single-threaded oracle Powersort (Pingpong) in {dt:.2f} s"}
+                                         f"single-threaded oracle Powersort (Pingpong) in {dt:.2f} s, "
+                                         f"pinned to host core {core}",
+                               "host_cpu": cpu_model, "host_nproc": os.cpu_count(),
+                               "host_cores_allowed": len(prev)}
     print(json.dumps(out), flush=True)
 
 

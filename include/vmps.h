@@ -186,21 +186,27 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
  * is (table interpolation * B) >> 32, all in integers. */
 #define VMPS_CDF_MAX_HIDDEN 64
 #define VMPS_CDF_MAX_KNOTS 4096
+#define VMPS_CDF_MAX_BATCH 32768
+#define VMPS_CDF_MAX_SAMPLE (1 << 24)
+/* Buckets: ids of at most 18 bits (two scatter levels of at most 9 bits). */
+#define VMPS_MAX_BUCKETS 262144
 /* vmps_learned_config.flags: keep the parameters after the last Adam step
  * even when their loss exceeds the initial model's (the default keeps the
  * better of the two); for checking the training trajectory. */
 #define VMPS_CDF_KEEP_TRAINED 1
 
 typedef struct {
-    int32_t num_buckets;  /* B: power of two in [2, 65536]; 0 = automatic */
+    int32_t num_buckets;  /* B: power of two in [2, VMPS_MAX_BUCKETS]; 0 = automatic */
     int32_t hidden;       /* H in {16, 32, 64} */
     int32_t steps;        /* Adam steps (>= 0) */
-    int32_t batch;        /* minibatch points per step, multiple of 64, >= 64 */
+    int32_t batch;        /* minibatch points per step, multiple of 64, in
+                             [64, VMPS_CDF_MAX_BATCH] */
     float lr;             /* Adam learning rate */
     int32_t knots;        /* K: at most this many table segments (1..4096) */
     int32_t feature_bits; /* F in [4, 24] */
     int32_t flags;        /* 0, or VMPS_CDF_KEEP_TRAINED */
-    int64_t sample_size;  /* m: keys sampled at SplitMix64 positions (<= n) */
+    int64_t sample_size;  /* m: keys sampled at SplitMix64 positions, in
+                             [2, min(n, VMPS_CDF_MAX_SAMPLE)] */
     uint64_t seed;        /* SplitMix64 seed of the sample positions */
 } vmps_learned_config;
 
@@ -237,7 +243,10 @@ typedef struct {
     double overflow_fraction;      /* fallback_buckets / buckets */
 } vmps_learned_stats;
 
-/* Defaults for n keys of type kt (host struct). */
+/* Defaults for n keys of type kt (host struct): automatic B, H = 64,
+ * 32 Adam steps of 8192 points at learning rate 5e-5, K = 4096 knots,
+ * F = 20, m = n/256 sample keys clamped to [8192, 2^20] (and to n),
+ * seed 55. */
 vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_config* cfg);
 
 vmps_status vmps_learned_workspace_size(int64_t n, vmps_dtype kt, int has_values,
@@ -267,9 +276,19 @@ vmps_status vmps_sample(const void* keys, int64_t n, vmps_dtype kt, int64_t m, u
 vmps_status vmps_cdf_grad(const float* params, int32_t hidden, const float* u, const float* y,
                           int32_t nb, float* grad, float* loss, void* stream);
 
-/* Train on a sorted sample and compile (model: device).  ws: at least 4m
- * bytes; on return its first m floats hold the normalised features
- * u_i = (z_i - z_lo)/(z_hi - z_lo) the model was trained on (fp32). */
+/* Workspace of vmps_cdf_train for m sample keys: the features and the
+ * training state between Adam steps. */
+vmps_status vmps_cdf_train_workspace_size(int64_t m, size_t* bytes);
+
+/* Train on a sorted sample and compile (model: device).  Quantile
+ * initialisation, cfg->steps Adam steps (minibatch j of step s is sample
+ * point ((s*batch + j) * 0x9E3779B1) mod m; one launch per step, the
+ * minibatch's gradient summed over workgroups in a fixed order), then the
+ * better of the initial and the trained model by the MSE over every 64th
+ * sample point (or the trained one with VMPS_CDF_KEEP_TRAINED).  ws: at
+ * least vmps_cdf_train_workspace_size(m) bytes, 256-byte aligned; on return
+ * its first m floats hold the normalised features u_i = (z_i - z_lo)/(z_hi -
+ * z_lo) the model was trained on (fp32). */
 vmps_status vmps_cdf_train(const void* sorted_sample, int64_t m, vmps_dtype kt,
                            const vmps_learned_config* cfg, vmps_cdf_model* model, void* ws,
                            size_t ws_bytes, void* stream);
@@ -304,7 +323,7 @@ typedef struct {
                                (0: as many as LDS and registers allow) */
     int32_t merge_grid;     /* workgroups of one HBM merge level (0: 2048) */
     int32_t bucket_div;     /* learned path: buckets of about T/bucket_div
-                               keys, T the LDS tile (0: 2) */
+                               keys, T the LDS tile (0: 8) */
     int32_t host_wait;      /* 1: the sorts wait on the host for the
                                planner's merge-level counts and launch only
                                the non-empty levels; 0 (default): fully

@@ -105,6 +105,7 @@ def load_library():
         "vmps_sample": (st, [vp, i64, st, i64, ctypes.c_uint64, vp, vp]),
         "vmps_cdf_grad": (st, [vp, i32, vp, vp, i32, vp, vp, vp]),
         "vmps_cdf_train": (st, [vp, i64, st, ctypes.POINTER(LearnedConfig), vp, vp, sz, vp]),
+        "vmps_cdf_train_workspace_size": (st, [i64, ctypes.POINTER(sz)]),
         "vmps_cdf_compile": (st, [vp, i32, ctypes.c_uint64, ctypes.c_uint64, i32, i32, i32, vp, vp]),
         "vmps_bucket_ids": (st, [vp, i64, st, vp, i32, vp, vp]),
         "vmps_partition_workspace_size": (st, [i64, st, st, i32, ctypes.POINTER(sz)]),
@@ -528,7 +529,9 @@ def cdf_train(sorted_sample, cfg: LearnedConfig, want_features: bool = False):
     _require_cuda(sorted_sample)
     m = sorted_sample.numel()
     model_t = torch.zeros(ctypes.sizeof(CdfModel), dtype=torch.uint8, device=sorted_sample.device)
-    ws = _workspace(4 * m, sorted_sample.device)
+    need = ctypes.c_size_t(0)
+    _check(load_library().vmps_cdf_train_workspace_size(m, ctypes.byref(need)), "vmps_cdf_train_workspace_size")
+    ws = _workspace(need.value, sorted_sample.device)
     _check(load_library().vmps_cdf_train(_ptr(sorted_sample), m, _dtype_code(sorted_sample), ctypes.byref(cfg),
                                          _ptr(model_t), _ptr(ws), ws.numel(), _stream(sorted_sample.device)),
            "vmps_cdf_train")

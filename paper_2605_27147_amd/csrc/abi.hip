@@ -409,30 +409,31 @@ bool pow2(uint64_t x) { return x && !(x & (x - 1)); }
 
 vmps_status check_config(const vmps_learned_config& c, int64_t n)
 {
-    if (c.num_buckets != 0 && (!pow2((uint64_t)c.num_buckets) || c.num_buckets < 2 || c.num_buckets > 65536))
+    if (c.num_buckets != 0 && (!pow2((uint64_t)c.num_buckets) || c.num_buckets < 2 || c.num_buckets > VMPS_MAX_BUCKETS))
         return VMPS_ERR_INVALID_ARG;
     if (c.hidden != 16 && c.hidden != 32 && c.hidden != 64) return VMPS_ERR_INVALID_ARG;
-    if (c.steps < 0 || c.batch < 64 || (c.batch % 64) || c.batch > (1 << 20)) return VMPS_ERR_INVALID_ARG;
+    if (c.steps < 0 || c.batch < 64 || (c.batch % 64) || c.batch > VMPS_CDF_MAX_BATCH) return VMPS_ERR_INVALID_ARG;
     if (!(c.lr >= 0.f) || c.knots < 1 || c.knots > VMPS_CDF_MAX_KNOTS) return VMPS_ERR_INVALID_ARG;
     if (c.feature_bits < 4 || c.feature_bits > 24) return VMPS_ERR_INVALID_ARG;
-    if (c.sample_size < 2 || c.sample_size > n) return VMPS_ERR_INVALID_ARG;
+    if (c.sample_size < 2 || c.sample_size > n || c.sample_size > VMPS_CDF_MAX_SAMPLE) return VMPS_ERR_INVALID_ARG;
     if (c.flags & ~VMPS_CDF_KEEP_TRAINED) return VMPS_ERR_INVALID_ARG;
     return VMPS_OK;
 }
 
 uint32_t auto_buckets(uint64_t n, uint32_t T, int key_bits, bool has_values)
 {
-    // about half an LDS tile per bucket (tunable), so uneven buckets still fit
+    // about an eighth of an LDS tile per bucket (tunable): small buckets,
+    // which the grouping packs into segments that fill the tile pass
     const int div = tuning_for(key_bits, has_values).bucket_div;
-    uint64_t target = T / (uint64_t)(div > 0 ? div : 2);
+    uint64_t target = T / (uint64_t)(div > 0 ? div : 8);
     if (target < 1) target = 1;
     uint64_t b = 2;
-    while (b < 65536 && b * target < n) b <<= 1;
+    while (b < VMPS_MAX_BUCKETS && b * target < n) b <<= 1;
     return (uint32_t)b;
 }
 
 struct LearnedLayout {
-    size_t keys_b, vals_b, sample, sample_ws, u, model, boff, judge, arena, plan, total;
+    size_t keys_b, vals_b, sample, sample_ws, u, tb, model, boff, goff, gscr, judge, arena, plan, total;
     uint32_t B, T;
     uint64_t m;
 };
@@ -450,8 +451,11 @@ LearnedLayout learned_layout(uint64_t n, vmps_dtype kt, int has_values, const vm
     L.sample = off; off += align256(key_bytes(kt) * L.m);
     L.sample_ws = off; off += align256(sort_layout(L.m, 1, kt, 0).total);
     L.u = off; off += align256(4 * L.m);
+    L.tb = off; off += align256(4 * train_buf_floats());
     L.model = off; off += align256(sizeof(vmps_cdf_model));
     L.boff = off; off += align256(8 * ((uint64_t)L.B + 1));
+    L.goff = off; off += align256(8 * ((uint64_t)L.B + 1));
+    L.gscr = off; off += align256(4 * group_scratch_words(L.B));
     L.judge = off; off += align256(8 * 6 * (size_t)JUDGE_GRID);
     L.arena = off; off += align256(4 * partition_arena_words(n, L.B));
     L.plan = off;
@@ -469,12 +473,15 @@ vmps_status vmps_learned_default_config(int64_t n, vmps_dtype kt, vmps_learned_c
     memset(cfg, 0, sizeof *cfg);
     cfg->num_buckets = 0;
     cfg->hidden = 64;
-    cfg->steps = 8;
-    cfg->batch = 512;
-    cfg->lr = 2e-4f;
+    cfg->steps = 32;
+    cfg->batch = 8192;
+    cfg->lr = 5e-5f;
     cfg->knots = VMPS_CDF_MAX_KNOTS;
     cfg->feature_bits = 20;
-    cfg->sample_size = n < 8192 ? n : 8192;  // one LDS tile: the sample sorts in one tile launch
+    // n/256 sample keys, at least 8192 and at most 2^20 (2^20 from n = 2^28 on)
+    int64_t m = n / 256;
+    m = m < 8192 ? 8192 : (m > (1 << 20) ? (1 << 20) : m);
+    cfg->sample_size = m < n ? m : n;
     cfg->seed = 55;
     return VMPS_OK;
 }
@@ -534,13 +541,19 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         }
         {
             TraceScope tr(VMPS_TRACE_TRAIN, s);
-            VMPS_HIP(train_enqueue(w + L.sample, L.m, kb, c, (float*)(w + L.u), M, s));
+            VMPS_HIP(train_enqueue(w + L.sample, L.m, kb, c, (float*)(w + L.u), (float*)(w + L.tb), M, s));
         }
         VMPS_HIP(partition_enqueue(keys, values, keysB, valsB, keys, values, (uint32_t)n, kb, vmode, M, L.B, boff,
                                    (uint32_t*)(w + L.arena), s));
+        // consecutive buckets grouped into instances that fill the tile
+        // pass's segments (the shorter class of 64-bit keys without values)
+        const uint32_t C = (kb == 64 && !has_values) ? T / 2 : T;
+        int64_t* goff = (int64_t*)(w + L.goff);
+        VMPS_HIP(group_enqueue(boff, L.B, (uint32_t)n, C, goff, (uint32_t*)(w + L.gscr), s));
         Plan P;
         plan_carve(P, w + L.plan, (uint64_t)n, L.B, T, merge_tile_out(kb, has_values));
-        P.inst_off64 = boff;
+        P.inst_off64 = goff;
+        P.off_trusted = true;
         P.big_min = T;
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
@@ -584,9 +597,22 @@ vmps_status vmps_cdf_train(const void* sorted_sample, int64_t m, vmps_dtype kt, 
     vmps_learned_config c = *cfg;
     c.sample_size = m;
     if (check_config(c, m) != VMPS_OK) return VMPS_ERR_INVALID_ARG;
-    if (!ws || ws_bytes < 4 * (size_t)m) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    size_t need = 0;
+    vmps_cdf_train_workspace_size(m, &need);
+    if (!ws || ws_bytes < need) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
-    return guarded([&] { return train_enqueue(sorted_sample, (uint64_t)m, key_bits_of(kt), c, (float*)ws, model, s); });
+    float* tb = (float*)((uint8_t*)ws + align256(4 * (size_t)m));
+    return guarded([&] {
+        return train_enqueue(sorted_sample, (uint64_t)m, key_bits_of(kt), c, (float*)ws, tb, model, s);
+    });
+}
+
+vmps_status vmps_cdf_train_workspace_size(int64_t m, size_t* bytes)
+{
+    if (!bytes || m < 0 || (uint64_t)m >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
+    *bytes = align256(4 * (size_t)m) + align256(4 * train_buf_floats());
+    return VMPS_OK;
 }
 
 vmps_status vmps_cdf_compile(const float* params, int32_t hidden, uint64_t z_lo, uint64_t z_hi, int32_t key_bits,
@@ -616,7 +642,7 @@ vmps_status vmps_partition_workspace_size(int64_t n, vmps_dtype kt, int has_valu
                                           size_t* bytes)
 {
     if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32) || (kt != VMPS_U32 && kt != VMPS_U64)) return VMPS_ERR_INVALID_ARG;
-    if (!pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > 65536) return VMPS_ERR_INVALID_ARG;
+    if (!pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > VMPS_MAX_BUCKETS) return VMPS_ERR_INVALID_ARG;
     *bytes = align256(key_bytes(kt) * (size_t)n) + (has_values ? align256(4 * (size_t)n) : 0) +
              align256(4 * partition_arena_words((uint64_t)n, (uint32_t)num_buckets));
     return VMPS_OK;
@@ -629,7 +655,7 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
     vmps_status st = check_keys(keys_in, n, kt);
     if (st == VMPS_OK) st = check_keys(keys_out, n, kt);
     if (st != VMPS_OK) return st;
-    if (!model || !bucket_offsets || !pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > 65536)
+    if (!model || !bucket_offsets || !pow2((uint64_t)num_buckets) || num_buckets < 2 || num_buckets > VMPS_MAX_BUCKETS)
         return VMPS_ERR_INVALID_ARG;
     if ((vals_in == nullptr) != (vals_out == nullptr)) return VMPS_ERR_INVALID_ARG;
     if (n > 0 && ranges_overlap(keys_in, key_bytes(kt) * n, keys_out, key_bytes(kt) * n)) return VMPS_ERR_INVALID_ARG;

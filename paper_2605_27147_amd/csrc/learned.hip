@@ -9,6 +9,8 @@
 // are, and buckets longer than the LDS tile fall back to the merge levels.
 #include <string.h>
 
+#include <type_traits>
+
 #include "vmps_internal.hpp"
 
 namespace vmps {
@@ -17,6 +19,7 @@ constexpr uint32_t PART_TILE = 8192;  // keys per histogram / scatter workgroup
 constexpr int PART_NT = 512;
 constexpr int PART_NW = PART_NT / 64;
 constexpr int PART_RND = PART_TILE / PART_NT;  // keys per thread
+constexpr int PART_DMAX = 512;                  // digits of a scatter level (9 bits)
 constexpr uint64_t BATCH_STRIDE = 0x9E3779B1ull;  // odd: visits every sample mod 2^k
 constexpr int LOSS_STRIDE = 64;
 constexpr float KNOT_GAP = 1e-6f;
@@ -177,37 +180,42 @@ __device__ inline float group_sum(float v)
     return v;
 }
 
-constexpr int TRAIN_NT = 1024;
+constexpr int TRAIN_NT = 1024;  // one-workgroup kernels (initialisation, loss, compile)
+constexpr int STEP_NT = 256;    // workgroups of one Adam step
+constexpr int STEP_PTS = 256;   // minibatch points per step workgroup
+constexpr int NP_PAD = 3 * VMPS_CDF_MAX_HIDDEN + 64;  // parameter slots, padded
 
+template <int NT>
 struct TrainLds {
     float p[3 * VMPS_CDF_MAX_HIDDEN + 1];
     float g[3 * VMPS_CDF_MAX_HIDDEN + 1];
     float m1[3 * VMPS_CDF_MAX_HIDDEN + 1];
     float m2[3 * VMPS_CDF_MAX_HIDDEN + 1];
     float best[3 * VMPS_CDF_MAX_HIDDEN + 1];
-    float pw1[TRAIN_NT], pb1[TRAIN_NT], pw2[TRAIN_NT];
-    float pb2[TRAIN_NT], pl[TRAIN_NT];
+    float pw1[NT], pb1[NT], pw2[NT];
+    float pb2[NT], pl[NT];
     float q[VMPS_CDF_MAX_HIDDEN], y[VMPS_CDF_MAX_HIDDEN];
-    float bu[TRAIN_NT], by[TRAIN_NT];  // minibatch points, staged per chunk
+    float bu[NT], by[NT];  // minibatch points, staged per chunk
     float loss;
 };
 
-// Gradient of the minibatch MSE (forward pass, then backpropagation through
-// the hidden ReLU layer).  The points are staged in LDS, TRAIN_NT at a time
-// (one gather for all of them).  Thread t owns hidden unit t % H of lane
+// Gradient of the squared error summed over `cnt` points, each term scaled
+// by `inv` (2/nb for the mean over a minibatch of nb points): forward pass,
+// then backpropagation through the hidden ReLU layer.  The points are
+// staged in LDS, NT at a time.  Thread t owns hidden unit t % H of lane
 // group t / H; groups take the staged points in turn; partial sums are
 // reduced in a fixed order, so the result does not depend on timing.
-// point(j, u, y) yields minibatch point j.  Writes S.g and S.loss.
-template <int H, typename Point>
-__device__ void batch_grad(TrainLds& S, int nb, Point point)
+// point(j, u, y) yields point j.  Writes S.g and S.loss (the sum of the
+// squared errors divided by cnt).
+template <int H, int NT, typename Point>
+__device__ void batch_grad(TrainLds<NT>& S, int cnt_all, float inv, Point point)
 {
-    constexpr int G = TRAIN_NT / H;
+    constexpr int G = NT / H;
     const int t = threadIdx.x, h = t % H, grp = t / H;
     const float w1 = S.p[h], b1 = S.p[H + h], w2 = S.p[2 * H + h], b2 = S.p[3 * H];
-    const float inv = 2.f / (float)nb;
     float aw1 = 0.f, ab1 = 0.f, aw2 = 0.f, ab2 = 0.f, al = 0.f;
-    for (int base = 0; base < nb; base += TRAIN_NT) {
-        const int cnt = nb - base < TRAIN_NT ? nb - base : TRAIN_NT;
+    for (int base = 0; base < cnt_all; base += NT) {
+        const int cnt = cnt_all - base < NT ? cnt_all - base : NT;
         if (t < cnt) {
             float uu, yy;
             point(base + t, uu, yy);
@@ -276,7 +284,7 @@ __device__ void batch_grad(TrainLds& S, int nb, Point point)
         float s = 0.f, l = 0.f;
         for (int gg = 0; gg < G; ++gg) { s += S.pb2[gg]; l += S.pl[gg]; }
         S.g[3 * H] = s;
-        S.loss = l / (float)nb;
+        S.loss = cnt_all > 0 ? l / (float)cnt_all : 0.f;
     }
     __syncthreads();
 }
@@ -286,11 +294,11 @@ __global__ __launch_bounds__(TRAIN_NT) void k_cdf_grad(const float* __restrict__
                                                        const float* __restrict__ y, int nb, float* __restrict__ grad,
                                                        float* __restrict__ loss)
 {
-    __shared__ TrainLds S;
+    __shared__ TrainLds<TRAIN_NT> S;
     const int t = threadIdx.x;
     if (t < 3 * H + 1) S.p[t] = params[t];
     __syncthreads();
-    batch_grad<H>(S, nb, [&](int j, float& uu, float& yy) { uu = u[j]; yy = y[j]; });
+    batch_grad<H, TRAIN_NT>(S, nb, 2.f / (float)nb, [&](int j, float& uu, float& yy) { uu = u[j]; yy = y[j]; });
     if (t < 3 * H + 1) grad[t] = S.g[t];
     if (t == 0) *loss = S.loss;
 }
@@ -305,32 +313,6 @@ __device__ float model_eval(const float* p, float u)
         f += p[2 * H + h] * (a > 0.f ? a : 0.f);
     }
     return f;
-}
-
-// Mean squared error over every LOSS_STRIDE-th sample point (block-wide).
-template <int H>
-__device__ float strided_loss(TrainLds& S, const float* __restrict__ u, uint64_t m)
-{
-    const int t = threadIdx.x;
-    float acc = 0.f;
-    uint64_t cnt = (m + LOSS_STRIDE - 1) / LOSS_STRIDE;
-    for (uint64_t k = t; k < cnt; k += TRAIN_NT) {
-        const uint64_t i = k * LOSS_STRIDE;
-        const float e = model_eval<H>(S.p, u[i]) - ((float)i + 0.5f) / (float)m;
-        acc += e * e;
-    }
-    // fixed-order reduction: a butterfly inside each wave, then the waves in order
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
-    if ((t & 63) == 0) S.pl[t >> 6] = acc;
-    __syncthreads();
-    if (t == 0) {
-        float s = 0.f;
-        for (int k = 0; k < TRAIN_NT / 64; ++k) s += S.pl[k];
-        S.loss = s / (float)cnt;
-    }
-    __syncthreads();
-    return S.loss;
 }
 
 // Compile the parameters in p into the model's knot table (block-wide).
@@ -406,71 +388,191 @@ __global__ __launch_bounds__(TRAIN_NT) void k_cdf_compile(const float* __restric
     compile_table<H>(p, model, z_lo, z_hi, K, scan_lds);
 }
 
-// Whole training in one workgroup: quantile initialisation, `steps` Adam
-// steps on strided minibatches, keep the better of initial and trained
-// model (or the trained one when keep_trained is set), compile.
-template <int H>
-__global__ __launch_bounds__(TRAIN_NT) void k_cdf_train(const float* __restrict__ u, uint64_t m, int steps,
-                                                        int nb, float lr, int K, int keep_trained,
-                                                        vmps_cdf_model* model)
+// Training runs as a chain of launches on the caller's stream: k_cdf_init
+// (one workgroup: the quantile initialisation), k_cdf_step for s = 0 ..
+// steps (Adam step s, then the gradient of minibatch s spread over
+// workgroups; the first and the last launch also split the strided loss of
+// their parameters over workgroups), k_cdf_finish (one workgroup: the choice
+// between the initial and the trained model, compilation).  Between launches
+// the state lives in a training buffer of floats (train_buf_floats):
+//   init[NP_PAD]                  the initial parameters
+//   state[2][3][NP_PAD]           parameters, Adam's m1 and m2 after step k
+//                                 in state[k & 1]
+//   part[2][TRAIN_GMAX][NP_PAD]   per-workgroup gradients of the minibatch
+//                                 of step s in part[s & 1]
+//   lpart[2][LOSS_GMAX]           per-workgroup squared-error sums of the
+//                                 strided loss, initial model in lpart[0],
+//                                 final one in lpart[1]
+constexpr int TRAIN_GMAX = 128;  // at most 128 * STEP_PTS = 32768 points per minibatch
+constexpr int LOSS_PTS = 1024;   // strided-loss points per step workgroup
+constexpr int LOSS_GMAX = 256;   // at most 2^18 strided points (m <= 2^24)
+
+__device__ inline float* tb_init(float* tb) { return tb; }
+__device__ inline float* tb_state(float* tb, int k) { return tb + NP_PAD + (size_t)(k & 1) * 3 * NP_PAD; }
+__device__ inline float* tb_part(float* tb, int s) { return tb + 7 * NP_PAD + (size_t)(s & 1) * TRAIN_GMAX * NP_PAD; }
+__device__ inline float* tb_loss(float* tb, int which)
 {
-    __shared__ TrainLds S;
-    __shared__ uint32_t scan_lds[TRAIN_NT];
+    return tb + 7 * NP_PAD + 2 * (size_t)TRAIN_GMAX * NP_PAD + (size_t)which * LOSS_GMAX;
+}
+
+// Adam (Kingma and Ba 2015) with bias correction, step k counted from 1.
+__device__ inline void adam_update(float& p, float& m1, float& m2, float g, int k, float lr)
+{
+    m1 = 0.9f * m1 + 0.1f * g;
+    m2 = 0.999f * m2 + 0.001f * g * g;
+    const float c1 = 1.f - powf(0.9f, (float)k);
+    const float c2 = 1.f - powf(0.999f, (float)k);
+    p -= lr * (m1 / c1) / (sqrtf(m2 / c2) + 1e-8f);
+}
+
+// x[0] + x[stride] + ... + x[(cnt - 1) * stride], added in that order; the
+// loads are issued 16 at a time so that they overlap.
+__device__ inline float ordered_sum(const float* x, int stride, int cnt)
+{
+    float sum = 0.f;
+    int k = 0;
+    for (; k + 16 <= cnt; k += 16) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) v[q] = x[(size_t)(k + q) * stride];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) sum += v[q];
+    }
+    for (; k < cnt; ++k) sum += x[(size_t)k * stride];
+    return sum;
+}
+
+// Hinges at H evenly spaced sample quantiles, slopes so that the model
+// interpolates (i + 1/2)/m there.
+template <int H>
+__global__ __launch_bounds__(256) void k_cdf_init(const float* __restrict__ u, uint64_t m, float* tb)
+{
+    __shared__ float q[VMPS_CDF_MAX_HIDDEN], y[VMPS_CDF_MAX_HIDDEN], p[3 * VMPS_CDF_MAX_HIDDEN + 1];
     const int t = threadIdx.x;
     constexpr int NP = 3 * H + 1;
-    // hinges at evenly spaced sample quantiles, interpolating (i + 1/2)/m
     if (t < H) {
         const uint64_t qi = (H > 1) ? ((uint64_t)t * (m - 1)) / (H - 1) : 0;
-        S.q[t] = u[qi];
-        S.y[t] = ((float)qi + 0.5f) / (float)m;
+        q[t] = u[qi];
+        y[t] = ((float)qi + 0.5f) / (float)m;
     }
     __syncthreads();
     if (t == 0)
         for (int h = 1; h < H; ++h)
-            if (S.q[h] <= S.q[h - 1]) S.q[h] = S.q[h - 1] + KNOT_GAP;
+            if (q[h] <= q[h - 1]) q[h] = q[h - 1] + KNOT_GAP;
     __syncthreads();
     if (t < H) {
-        const float right = (t + 1 < H) ? (S.y[t + 1] - S.y[t]) / (S.q[t + 1] - S.q[t]) : 0.f;
-        const float left = (t > 0) ? (S.y[t] - S.y[t - 1]) / (S.q[t] - S.q[t - 1]) : 0.f;
-        S.p[t] = 1.f;
-        S.p[H + t] = -S.q[t];
-        S.p[2 * H + t] = right - left;
+        const float right = (t + 1 < H) ? (y[t + 1] - y[t]) / (q[t + 1] - q[t]) : 0.f;
+        const float left = (t > 0) ? (y[t] - y[t - 1]) / (q[t] - q[t - 1]) : 0.f;
+        p[t] = 1.f;
+        p[H + t] = -q[t];
+        p[2 * H + t] = right - left;
     }
-    if (t == 0) S.p[3 * H] = S.y[0];
-    if (t < NP) { S.m1[t] = 0.f; S.m2[t] = 0.f; }
+    if (t == 0) p[3 * H] = y[0];
     __syncthreads();
-    const float loss0 = strided_loss<H>(S, u, m);
-    if (t < NP) S.best[t] = S.p[t];
+    if (t < NP) {
+        float* st = tb_state(tb, 0);
+        tb_init(tb)[t] = p[t];
+        st[t] = p[t];
+        st[NP_PAD + t] = 0.f;
+        st[2 * NP_PAD + t] = 0.f;
+    }
+}
+
+// Launch s of the chain (s = 0 .. steps): the parameters after Adam step s
+// (for s > 0 every workgroup applies the same update with the gradient of
+// minibatch s - 1, its workgroup parts summed in workgroup order, and
+// workgroup 0 stores the new state); then, for s < steps, this workgroup's
+// part of the gradient of minibatch s (points [blockIdx.x * STEP_PTS, ...)
+// of the nb points ((s nb + j) * stride) mod m); and for s = 0 (initial
+// model) and s = steps (final model), this workgroup's part of the squared
+// error over every LOSS_STRIDE-th sample point.
+template <int H>
+__global__ __launch_bounds__(STEP_NT) void k_cdf_step(const float* __restrict__ u, uint64_t m, int s, int steps,
+                                                      int nb, float lr, float* tb)
+{
+    __shared__ TrainLds<STEP_NT> S;
+    static_assert(STEP_NT >= 3 * VMPS_CDF_MAX_HIDDEN + 1, "one thread per parameter");
+    const int t = threadIdx.x;
+    constexpr int NP = 3 * H + 1;
+    const int G = (nb + STEP_PTS - 1) / STEP_PTS;
+    float gsum = 0.f;
+    if (s > 0 && t < NP) gsum = ordered_sum(tb_part(tb, s - 1) + t, NP_PAD, G);
+    if (t < NP) {
+        const float* prev = tb_state(tb, s > 0 ? s - 1 : 0);
+        float p = prev[t];
+        if (s > 0) {
+            float m1 = prev[NP_PAD + t], m2 = prev[2 * NP_PAD + t];
+            adam_update(p, m1, m2, gsum, s, lr);
+            if (blockIdx.x == 0) {
+                float* st = tb_state(tb, s);
+                st[t] = p;
+                st[NP_PAD + t] = m1;
+                st[2 * NP_PAD + t] = m2;
+            }
+        }
+        S.p[t] = p;
+    }
     __syncthreads();
-    const float fm = (float)m;
-    for (int s = 0; s < steps; ++s) {
-        batch_grad<H>(S, nb, [&](int j, float& uu, float& yy) {
-            const uint64_t idx = (((uint64_t)s * (uint64_t)nb + (uint64_t)j) * BATCH_STRIDE) % m;
+    const int j0 = (int)blockIdx.x * STEP_PTS;
+    if (s < steps && j0 < nb) {
+        const int cnt = nb - j0 < STEP_PTS ? nb - j0 : STEP_PTS;
+        const float fm = (float)m;
+        batch_grad<H, STEP_NT>(S, cnt, 2.f / (float)nb, [&](int j, float& uu, float& yy) {
+            const uint64_t idx = (((uint64_t)s * (uint64_t)nb + (uint64_t)(j0 + j)) * BATCH_STRIDE) % m;
             uu = u[idx];
             yy = ((float)idx + 0.5f) / fm;
         });
-        if (t < NP) {
-            // Adam (Kingma and Ba 2015) with bias correction
-            const float g = S.g[t];
-            const float m1 = 0.9f * S.m1[t] + 0.1f * g;
-            const float m2 = 0.999f * S.m2[t] + 0.001f * g * g;
-            S.m1[t] = m1; S.m2[t] = m2;
-            const float c1 = 1.f - powf(0.9f, (float)(s + 1));
-            const float c2 = 1.f - powf(0.999f, (float)(s + 1));
-            S.p[t] -= lr * (m1 / c1) / (sqrtf(m2 / c2) + 1e-8f);
-        }
-        __syncthreads();
+        if (t < NP) tb_part(tb, s)[(size_t)blockIdx.x * NP_PAD + t] = S.g[t];
     }
-    const float loss1 = strided_loss<H>(S, u, m);
-    const bool keep = !keep_trained && !(loss1 <= loss0);
-    if (keep && t < NP) S.p[t] = S.best[t];
+    if (s == 0 || s == steps) {
+        const uint64_t cnt = (m + LOSS_STRIDE - 1) / LOSS_STRIDE;
+        const uint64_t k0 = (uint64_t)blockIdx.x * LOSS_PTS;
+        float acc = 0.f;
+        for (uint64_t k = k0 + t; k < k0 + LOSS_PTS && k < cnt; k += STEP_NT) {
+            const uint64_t i = k * LOSS_STRIDE;
+            const float e = model_eval<H>(S.p, u[i]) - ((float)i + 0.5f) / (float)m;
+            acc += e * e;
+        }
+        // fixed order: a butterfly inside each wave, then the waves in order
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) acc += __shfl_xor(acc, off, 64);
+        if ((t & 63) == 0) S.pl[t >> 6] = acc;
+        __syncthreads();
+        if (t == 0 && k0 < cnt) {
+            float sum = 0.f;
+            for (int w = 0; w < STEP_NT / 64; ++w) sum += S.pl[w];
+            if (s == 0) tb_loss(tb, 0)[blockIdx.x] = sum;
+            if (s == steps) tb_loss(tb, 1)[blockIdx.x] = sum;
+        }
+    }
+}
+
+// The choice between the initial and the trained model by their strided
+// losses (or the trained one when keep_trained is set), and the
+// compilation of the chosen parameters into the knot table.
+template <int H>
+__global__ __launch_bounds__(TRAIN_NT) void k_cdf_finish(uint64_t m, int steps, int K, int keep_trained, float* tb,
+                                                         vmps_cdf_model* model)
+{
+    __shared__ float p[3 * VMPS_CDF_MAX_HIDDEN + 1];
+    __shared__ float losses[2];
+    __shared__ uint32_t scan_lds[TRAIN_NT];
+    const int t = threadIdx.x;
+    constexpr int NP = 3 * H + 1;
+    const uint64_t cnt = (m + LOSS_STRIDE - 1) / LOSS_STRIDE;
+    const int GL = (int)((cnt + LOSS_PTS - 1) / LOSS_PTS);
+    if (t < 2) losses[t] = ordered_sum(tb_loss(tb, t), 1, GL) / (float)cnt;
     __syncthreads();
+    const float loss0 = losses[0], loss1 = losses[1];
+    const bool keep = !keep_trained && !(loss1 <= loss0);
+    if (t < NP) p[t] = keep ? tb_init(tb)[t] : tb_state(tb, steps)[t];
     if (t == 0) {
         model->trained = keep ? 0 : 1;
         model->loss_init = loss0;
         model->loss_final = keep ? loss0 : loss1;
     }
-    compile_table<H>(S.p, model, model->z_lo, model->z_hi, K, scan_lds);
+    __syncthreads();
+    compile_table<H>(p, model, model->z_lo, model->z_hi, K, scan_lds);
 }
 
 // ------------------------------------------------------------ buckets --
@@ -488,7 +590,7 @@ __global__ void k_bucket_ids(const K* __restrict__ keys, uint64_t n, const vmps_
 struct PartLevel {
     const uint32_t* pstart;
     const uint32_t* tbase;
-    uint32_t P, F, shift, mask;
+    uint32_t P, F, shift, mask, dbits;
     uint32_t* counts;
     const uint32_t* offs;
 };
@@ -517,20 +619,46 @@ __device__ inline void part_tile(const PartLevel& L, uint32_t tile, uint32_t& c,
     s1 = min(L.pstart[c + 1], s0 + PART_TILE);
 }
 
-// Level-2 histogram of one tile from the 16-bit ids the level-1 scatter
-// moved with the keys.  Counting only, so the order is free: 16-byte
-// chunks of 8 ids from the aligned position below s0 (the id arrays are
-// padded to a multiple of 128), ids outside [s0, s1) skipped.  Per-wave
-// counters keep LDS atomics on popular digits apart.
+// The model's knot table in LDS as 32-bit values when it is monotone and
+// fits 32 bits (a compiled table always does): then buckets come from
+// bucket_of32; otherwise (fast = false) from the 64-bit evaluation that
+// reads the table in global memory.  Block-wide.
+struct PartModel {
+    ModelArgs M;
+    ModelArgs32 M32;
+    bool fast;
+    __device__ uint32_t bucket(uint64_t key) const { return fast ? bucket_of32(key, M32) : bucket_of(key, M); }
+};
+
+__device__ inline PartModel part_model(const vmps_cdf_model* model, uint32_t B, uint32_t* tab)
+{
+    PartModel P;
+    P.M = model_args(model, B);
+    bool bad = false;
+    for (int i = threadIdx.x; i <= P.M.knots; i += blockDim.x) {
+        const uint64_t t = P.M.table[i];
+        tab[i] = (uint32_t)t;
+        bad |= (t >> 32) != 0 || (i > 0 && P.M.table[i - 1] > t);
+    }
+    P.fast = !__syncthreads_or(bad);
+    P.M32 = model_args32(P.M, tab);
+    return P;
+}
+
+// Level-2 histogram of one tile from the 16-bit ids (the bucket's level-2
+// digit) the level-1 scatter moved with the keys.  Counting only, so the
+// order is free: 16-byte chunks of 8 ids from the aligned position below
+// s0 (the id arrays are padded to a multiple of 128), ids outside [s0, s1)
+// skipped.  Per-wave counters keep LDS atomics on popular digits apart.
 __global__ __launch_bounds__(PART_NT) void k_part_hist2(const uint16_t* __restrict__ ids_in, PartLevel L)
 {
-    __shared__ uint32_t hist[PART_NW][256];
+    __shared__ uint32_t hist[PART_NW][PART_DMAX];
     const uint32_t tile = blockIdx.x;
     if (tile >= L.tbase[L.P]) return;
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
     const int tid = threadIdx.x, wave = tid >> 6;
-    for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
+    for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
     __syncthreads();
     const uint32_t a0 = s0 & ~7u;
     const uint32_t chunks = (s1 - a0 + 7) / 8;
@@ -545,43 +673,38 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist2(const uint16_t* __restri
         }
     }
     __syncthreads();
-    if ((uint32_t)tid < L.F) {
+    for (uint32_t d = tid; d < L.F; d += PART_NT) {
         uint32_t t = 0;
 #pragma unroll
-        for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
-        L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl] = t;
+        for (int w = 0; w < PART_NW; ++w) t += hist[w][d];
+        L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)d * nt + tl] = t;
     }
 }
 
 // Level-1 histogram with the model: the level's tiles are the aligned
 // PART_TILE blocks of the whole array.  Each workgroup copies the knot
 // table into LDS once and then takes tiles tile, tile + grid, ...; keys
-// are read two at a time and the two 16-bit ids written as one word.
+// are read two at a time.  Every key's bucket id goes out for the level-1
+// scatter: its low 16 bits in ids_out (staged in LDS in tile order, then
+// 16 bytes per lane), and for B > 2^16 its bits 16 and 17 in hibits (bits
+// 2(i mod 16), 2(i mod 16) + 1 of word i / 16 for key i).
 template <typename K>
 __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ keys, uint16_t* __restrict__ ids_out,
-                                                        uint32_t n, uint32_t nt1, uint32_t F, uint32_t shift,
-                                                        uint32_t mask, uint32_t* __restrict__ counts,
+                                                        uint32_t* __restrict__ hibits, uint32_t n, uint32_t nt1,
+                                                        uint32_t F, uint32_t shift, uint32_t mask,
+                                                        uint32_t* __restrict__ counts,
                                                         const vmps_cdf_model* __restrict__ model, uint32_t B)
 {
     struct alignas(2 * sizeof(K)) KPair { K a, b; };
     constexpr int RP = PART_RND / 2;  // key pairs per thread
     __shared__ uint32_t tab[VMPS_CDF_MAX_KNOTS + 1];
-    __shared__ uint32_t hist[PART_NW][256];
-    const int tid = threadIdx.x, wave = tid >> 6;
-    const ModelArgs M = model_args(model, B);
-    // the table in LDS as 32-bit values when it is monotone and fits 32
-    // bits (a compiled table always does); otherwise the 64-bit evaluation
-    // reads the table in global memory
-    bool bad = false;
-    for (int i = tid; i <= M.knots; i += PART_NT) {
-        const uint64_t t = M.table[i];
-        tab[i] = (uint32_t)t;
-        bad |= (t >> 32) != 0 || (i > 0 && M.table[i - 1] > t);
-    }
-    const bool fast = !__syncthreads_or(bad);
-    const ModelArgs32 M32 = model_args32(M, tab);
+    __shared__ uint32_t hist[PART_NW][PART_DMAX];
+    __shared__ __align__(16) uint32_t stage[PART_TILE];  // bucket ids in tile order
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const PartModel PM = part_model(model, B, tab);
+    const bool hi = B > 65536;
     for (uint32_t tile = blockIdx.x; tile < nt1; tile += gridDim.x) {
-        for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hist[0][0])[i] = 0;
+        for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
         __syncthreads();
         const uint32_t s0 = tile * PART_TILE;
         const uint32_t len = n - s0 < PART_TILE ? n - s0 : PART_TILE;
@@ -600,15 +723,14 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
         for (int r = 0; r < RP; ++r) {
             const uint32_t q = 2 * (r * PART_NT + tid);
             if (q < len) {
-                const uint32_t b0 = fast ? bucket_of32((uint64_t)kp[r].a, M32) : bucket_of((uint64_t)kp[r].a, M);
+                const uint32_t b0 = PM.bucket((uint64_t)kp[r].a);
                 atomicAdd(&hist[wave][(b0 >> shift) & mask], 1u);
-                if (q + 1 < len) {
-                    const uint32_t b1 = fast ? bucket_of32((uint64_t)kp[r].b, M32) : bucket_of((uint64_t)kp[r].b, M);
-                    atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
-                    *(uint32_t*)(ids_out + s0 + q) = b0 | (b1 << 16);
-                } else {
-                    ids_out[s0 + q] = (uint16_t)b0;
-                }
+                stage[q] = b0;
+            }
+            if (q + 1 < len) {
+                const uint32_t b1 = PM.bucket((uint64_t)kp[r].b);
+                atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
+                stage[q + 1] = b1;
             }
         }
         __syncthreads();
@@ -618,9 +740,54 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
             for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
             counts[(uint64_t)tid * nt1 + tile] = t;
         }
+        // ids out: lane t of the workgroup holds keys [8t, 8t + 8) of the
+        // tile per round (PART_TILE / 8 / PART_NT rounds)
+#pragma unroll
+        for (int r = 0; r < (int)(PART_TILE / 8 / PART_NT); ++r) {
+            const uint32_t e = 8 * (r * PART_NT + tid);
+            const uint4 lo4 = *(const uint4*)&stage[e], hi4 = *(const uint4*)&stage[e + 4];
+            const uint32_t bs[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+            uint32_t w[4] = {0u, 0u, 0u, 0u}, hb = 0;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const uint32_t b = e + j < len ? bs[j] : 0u;
+                w[j >> 1] |= (b & 0xffffu) << (16 * (j & 1));
+                hb |= ((b >> 16) & 3u) << (2 * j);
+            }
+            if (e + 8 <= len) {
+                *(uint4*)(ids_out + s0 + e) = make_uint4(w[0], w[1], w[2], w[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (e + j < len) ids_out[s0 + e + j] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+            }
+            if (hi) {
+                // two lanes make one 16-key word (the tile start is a
+                // multiple of 16); lanes past the end contribute zeros
+                uint32_t word = hb << (16 * (lane & 1));
+                word |= __shfl_xor(word, 1, 64);
+                if ((lane & 1) == 0 && e < len) hibits[(s0 + e) >> 4] = word;
+            }
+        }
         __syncthreads();
     }
 }
+
+// LDS of one scatter workgroup: the tile goes back out in NPART parts.
+template <typename K, int VMODE, int LEVEL>
+struct ScatterLds {
+    static constexpr int NPART = (LEVEL == 1 && VMODE) ? 4 : 2;
+    static constexpr uint32_t PARTN = PART_TILE / NPART;
+    static constexpr int D = PART_DMAX;  // digits of the level: at most 9 bits
+    using Sid = typename std::conditional<LEVEL == 1, uint32_t, uint16_t>::type;
+    K skey[PARTN];
+    uint32_t sval[VMODE ? PARTN : 1];
+    Sid sid[PARTN];
+    uint32_t hc[PART_NW][D];
+    uint32_t loff[D], goff[D];
+    uint32_t scan[PART_NW + 1];
+    uint32_t hib[LEVEL == 1 ? PART_TILE / 16 : 1];  // bits 16-17 of the tile's bucket ids
+};
 
 // Stable scatter of one tile by the digit of its bucket id.  Wave w ranks
 // the keys [w*TILE/NW, (w+1)*TILE/NW) of the tile in input order: a match
@@ -628,32 +795,36 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
 // wave-private counter per digit the rank among its earlier keys.  One
 // block scan over (digit, wave) gives every key its place in an LDS reorder
 // by digit, and the runs of equal digit go out contiguously.  The reorder
-// goes through LDS in two halves of the tile, so that two workgroups share a
-// CU.  VMODE 2 generates the values (input index).  IDS_OUT: the ids travel
-// with the keys.
-template <typename K, int VMODE, bool IDS_OUT>
-__global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
-                                                          const uint16_t* __restrict__ idin, K* __restrict__ kout,
-                                                          uint32_t* __restrict__ vout, uint16_t* __restrict__ idout,
-                                                          PartLevel L)
+// goes through LDS in parts of the tile, so that two workgroups share a
+// CU.  VMODE 2 generates the values (input index).
+//   LEVEL 1: the whole array in aligned tiles; every key's bucket id comes
+//     from the level-1 histogram (16-bit ids, and bits 16-17 from hibits
+//     when it is not null); the bucket's level-2 digit goes out with the
+//     key as a 16-bit id.
+//   LEVEL 2: the tiles of every level-1 range; the digit is the 16-bit id.
+// A key's bucket (18 bits at most) and its place in the tile (13 bits) share
+// one 32-bit register: bucket below, place from bit 18.
+template <typename K, int VMODE, int LEVEL>
+__device__ inline void scatter_tile(ScatterLds<K, VMODE, LEVEL>& S, const uint32_t* __restrict__ hibits,
+                                    const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                    const uint16_t* __restrict__ idin, K* __restrict__ kout,
+                                    uint32_t* __restrict__ vout, uint16_t* __restrict__ idout, const PartLevel& L,
+                                    uint32_t tile, uint32_t id_mask)
 {
+    using SL = ScatterLds<K, VMODE, LEVEL>;
     constexpr uint32_t WCH = PART_TILE / PART_NW;  // keys per wave
     constexpr int RND = (int)(WCH / 64);
-    constexpr uint32_t HALF = PART_TILE / 2;
-    __shared__ K skey[HALF];
-    __shared__ uint32_t sval[VMODE ? HALF : 1];
-    __shared__ uint16_t sid[HALF];
-    __shared__ uint32_t hc[PART_NW][256];
-    __shared__ uint32_t loff[256], goff[256];
-    __shared__ uint32_t scan_lds[PART_NW + 1];
-    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= L.tbase[L.P]) return;
+    constexpr uint32_t BMASK = (1u << 18) - 1;
     uint32_t c, tl, nt, s0, s1;
     part_tile(L, tile, c, tl, nt, s0, s1);
     const uint32_t len = s1 - s0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int i = tid; i < PART_NW * 256; i += PART_NT) (&hc[0][0])[i] = 0;
-    if ((uint32_t)tid < L.F) goff[tid] = L.offs[(uint64_t)L.tbase[c] * L.F + (uint64_t)tid * nt + tl];
+    for (int i = tid; i < PART_NW * SL::D; i += PART_NT) (&S.hc[0][0])[i] = 0;
+    for (uint32_t d = tid; d < L.F; d += PART_NT) S.goff[d] = L.offs[(uint64_t)L.tbase[c] * L.F + (uint64_t)d * nt + tl];
+    // level 1 beyond 2^16 buckets: the words holding bits 16-17 of the
+    // tile's ids into LDS (the tile start is a multiple of 16)
+    static_assert(PART_TILE / 16 <= PART_NT, "one word per thread");
+    if (LEVEL == 1 && hibits && (uint32_t)tid < (len + 15) / 16) S.hib[tid] = hibits[(s0 >> 4) + tid];
     __syncthreads();
 
     const uint32_t wb = wave * WCH;
@@ -667,8 +838,14 @@ __global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict
         ir[r] = valid ? idin[s0 + i] : 0u;
         vr[r] = (VMODE == 1 && valid) ? vin[s0 + i] : s0 + i;
     }
+    if (LEVEL == 1 && hibits) {
+#pragma unroll
+        for (int r = 0; r < RND; ++r) {
+            const uint32_t i = wb + r * 64 + lane;
+            if (i < len) ir[r] |= ((S.hib[i >> 4] >> (2 * (i & 15))) & 3u) << 16;
+        }
+    }
     const uint64_t lt = (1ull << lane) - 1;
-    // ir[r]: the 16-bit id below, the key's rank (< 2^13) above
 #pragma unroll
     for (int r = 0; r < RND; ++r) {
         const uint32_t i = wb + r * 64 + lane;
@@ -676,77 +853,100 @@ __global__ __launch_bounds__(PART_NT, 4) void k_part_scatter(const K* __restrict
         const uint32_t d = valid ? (ir[r] >> L.shift) & L.mask : 0u;
         const uint64_t vb = __ballot(valid);
         uint32_t plo = (uint32_t)vb, phi = (uint32_t)(vb >> 32);
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (uint32_t k = 0; k < L.dbits; ++k) {
             // nb = -bit (all ones or zero); the lanes agreeing with this lane
             // on bit k are ~(ballot ^ nb).  One bit-field extract and one
             // three-input bitwise operation per half: p & ~(b ^ c) has the
             // truth table 0x90 (operands 0xF0, 0xCC, 0xAA).
-            const int nb = __builtin_amdgcn_sbfe((int)d, (unsigned)k, 1u);
+            const int nb = __builtin_amdgcn_sbfe((int)d, k, 1u);
             const uint64_t bk = __ballot(nb != 0);
             plo = __builtin_amdgcn_bitop3_b32(plo, (uint32_t)bk, (uint32_t)nb, 0x90);
             phi = __builtin_amdgcn_bitop3_b32(phi, (uint32_t)(bk >> 32), (uint32_t)nb, 0x90);
         }
         const uint64_t peers = ((uint64_t)phi << 32) | plo;
-        const uint32_t before = valid ? hc[wave][d] : 0u;
+        const uint32_t before = valid ? S.hc[wave][d] : 0u;
         const uint32_t rw = __popcll(peers & lt);
-        ir[r] |= (before + rw) << 16;
+        ir[r] |= (before + rw) << 18;
         // the wave's lowest lane of each digit advances the counter; LDS
         // operations of one wave complete in order, after every lane's read
-        if (valid && rw == 0) hc[wave][d] = before + __popcll(peers);
+        if (valid && rw == 0) S.hc[wave][d] = before + __popcll(peers);
     }
     __syncthreads();
+    static_assert(SL::D <= PART_NT, "one digit per thread");
     uint32_t tot = 0;
-    if (tid < 256) {
+    if (tid < SL::D) {
 #pragma unroll
         for (int w = 0; w < PART_NW; ++w) {
-            const uint32_t v = hc[w][tid];
-            hc[w][tid] = tot;
+            const uint32_t v = S.hc[w][tid];
+            S.hc[w][tid] = tot;
             tot += v;
         }
     }
     uint32_t all;
-    const uint32_t ex = block_excl_scan(tot, scan_lds, &all);
-    if (tid < 256) {
-        loff[tid] = ex;
+    const uint32_t ex = block_excl_scan(tot, S.scan, &all);
+    if (tid < SL::D) {
+        S.loff[tid] = ex;
 #pragma unroll
-        for (int w = 0; w < PART_NW; ++w) hc[w][tid] += ex;
+        for (int w = 0; w < PART_NW; ++w) S.hc[w][tid] += ex;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < RND; ++r) {
-        const uint32_t d = ((ir[r] & 0xffffu) >> L.shift) & L.mask;
-        ir[r] += hc[wave][d] << 16;  // place in the tile's order by digit
+        const uint32_t d = ((ir[r] & BMASK) >> L.shift) & L.mask;
+        ir[r] += S.hc[wave][d] << 18;  // place in the tile's order by digit
     }
 #pragma unroll
-    for (uint32_t h = 0; h < 2; ++h) {
-        const uint32_t lo = h * HALF;
+    for (uint32_t h = 0; h < (uint32_t)SL::NPART; ++h) {
+        const uint32_t lo = h * SL::PARTN;
         if (lo >= len) break;
 #pragma unroll
         for (int r = 0; r < RND; ++r) {
             const uint32_t i = wb + r * 64 + lane;
-            const uint32_t lp = (ir[r] >> 16) - lo;
-            if (i < len && lp < HALF) {
-                skey[lp] = kr[r];
-                sid[lp] = (uint16_t)ir[r];
-                if (VMODE) sval[lp] = vr[r];
+            const uint32_t lp = (ir[r] >> 18) - lo;
+            if (i < len && lp < SL::PARTN) {
+                S.skey[lp] = kr[r];
+                S.sid[lp] = (typename SL::Sid)(ir[r] & BMASK);
+                if (VMODE) S.sval[lp] = vr[r];
             }
         }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < PART_RND / 2; ++r) {
+        for (int r = 0; r < (int)(SL::PARTN / PART_NT); ++r) {
             const uint32_t j = r * PART_NT + tid, i = lo + j;
             if (i < len) {
-                const uint32_t id = sid[j];
+                const uint32_t id = S.sid[j];
                 const uint32_t d = (id >> L.shift) & L.mask;
-                const uint32_t o = goff[d] + (i - loff[d]);
-                kout[o] = skey[j];
-                if (VMODE) vout[o] = sval[j];
-                if (IDS_OUT) idout[o] = (uint16_t)id;
+                const uint32_t o = S.goff[d] + (i - S.loff[d]);
+                kout[o] = S.skey[j];
+                if (VMODE) vout[o] = S.sval[j];
+                if (LEVEL == 1) idout[o] = (uint16_t)(id & id_mask);
             }
         }
         __syncthreads();
     }
+}
+
+template <typename K, int VMODE>
+__global__ __launch_bounds__(PART_NT, 4) void k_part_scatter1(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                           const uint16_t* __restrict__ idin,
+                                                           const uint32_t* __restrict__ hibits, K* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, uint16_t* __restrict__ idout,
+                                                           PartLevel L, uint32_t id_mask)
+{
+    __shared__ ScatterLds<K, VMODE, 1> S;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    scatter_tile<K, VMODE, 1>(S, hibits, kin, vin, idin, kout, vout, idout, L, tile, id_mask);
+}
+
+template <typename K, int VMODE>
+__global__ __launch_bounds__(PART_NT, 4) void k_part_scatter2(const K* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                           const uint16_t* __restrict__ idin, K* __restrict__ kout,
+                                                           uint32_t* __restrict__ vout, PartLevel L)
+{
+    __shared__ ScatterLds<K, VMODE, 2> S;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.tbase[L.P]) return;
+    scatter_tile<K, VMODE, 2>(S, nullptr, kin, vin, idin, kout, vout, nullptr, L, tile, 0u);
 }
 
 // Level-1 parents: the whole array.
@@ -760,11 +960,12 @@ __global__ void k_part_init(uint32_t n, uint32_t* pstart, uint32_t* tbase, uint3
 }
 
 // Level-2 parents: the level-1 digit ranges.
-__global__ __launch_bounds__(256) void k_part_level2(const uint32_t* __restrict__ offs1, uint32_t nt1, uint32_t F1,
-                                                     uint32_t n, uint32_t F2, uint32_t* __restrict__ pstart,
-                                                     uint32_t* __restrict__ tbase, uint32_t* count_out)
+__global__ __launch_bounds__(PART_DMAX) void k_part_level2(const uint32_t* __restrict__ offs1, uint32_t nt1,
+                                                           uint32_t F1, uint32_t n, uint32_t F2,
+                                                           uint32_t* __restrict__ pstart, uint32_t* __restrict__ tbase,
+                                                           uint32_t* count_out)
 {
-    __shared__ uint32_t lds[256 / WAVE + 1];
+    __shared__ uint32_t lds[PART_DMAX / WAVE + 1];
     const uint32_t c = threadIdx.x;
     uint32_t s = 0, e = 0;
     if (c < F1) {
@@ -904,27 +1105,88 @@ __global__ __launch_bounds__(256) void k_learned_stats(const int64_t* __restrict
     }
 }
 
+// Grouping of consecutive buckets for the bucket sort.  Buckets are
+// increasing key ranges, so the stable sort of several consecutive buckets
+// as one Powersort instance is the concatenation of their stable sorts:
+// groups change only how the tile pass's workgroups are filled.  Greedy
+// packing inside chunks of GROUP_CHUNK buckets (a chunk boundary is always a
+// group boundary): a group takes the next bucket while its length stays
+// within C; a bucket longer than C is a group of its own.
+constexpr uint32_t GROUP_CHUNK = 64;
+
+__device__ inline uint32_t group_chunk(const int64_t* __restrict__ boff, uint32_t B, uint32_t chunk, uint64_t C,
+                                       int64_t* __restrict__ out)
+{
+    const uint32_t b0 = chunk * GROUP_CHUNK, b1 = min(B, b0 + GROUP_CHUNK);
+    uint32_t cnt = 0;
+    int64_t gs = boff[b0];
+    for (uint32_t b = b0 + 1; b < b1; ++b) {
+        const int64_t bs = boff[b], be = boff[b + 1];
+        if ((uint64_t)(be - gs) > C && bs > gs) {  // bucket b does not fit a non-empty group
+            if (out) out[cnt] = gs;
+            ++cnt;
+            gs = bs;
+        }
+    }
+    if (out) out[cnt] = gs;
+    return cnt + 1;
+}
+
+__global__ void k_group_count(const int64_t* __restrict__ boff, uint32_t B, uint64_t C, uint32_t* __restrict__ cnt)
+{
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c * GROUP_CHUNK < B) cnt[c] = group_chunk(boff, B, c, C, nullptr);
+}
+
+__global__ void k_group_emit(const int64_t* __restrict__ boff, uint32_t B, uint64_t C,
+                             const uint32_t* __restrict__ base, int64_t* __restrict__ goff)
+{
+    const uint32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c * GROUP_CHUNK < B) group_chunk(boff, B, c, C, goff + base[c]);
+}
+
+// goff[G, B] = n, G = the number of groups
+__global__ void k_group_pad(const uint32_t* __restrict__ total, uint32_t B, uint32_t n, int64_t* __restrict__ goff)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= B && i >= *total) goff[i] = n;
+}
+
 // ------------------------------------------------------------- host --
 namespace {
 inline unsigned grid1(uint64_t n, unsigned b = 256) { return (unsigned)ceil_div(n ? n : 1, b); }
+
+// Bucket id bits: level 2 takes the low 9 bits from 2^17 buckets on, else
+// the bits beyond the top 8; level 1 the rest (at most 9).
+struct PartBits {
+    uint32_t lo_bits, F1, F2;
+};
+
+inline PartBits part_bits(uint32_t B)
+{
+    uint32_t bits = 0;
+    while ((1u << bits) < B) ++bits;
+    PartBits p;
+    p.lo_bits = bits >= 17 ? 9 : (bits > 8 ? bits - 8 : 0);
+    p.F1 = B >> p.lo_bits;
+    p.F2 = 1u << p.lo_bits;
+    return p;
+}
 
 template <typename K>
 hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtmp, K* kout, uint32_t* vout,
                        uint32_t n, int vmode, const vmps_cdf_model* Mdev, uint32_t B, int64_t* bucket_off,
                        uint32_t* arena, hipStream_t s)
 {
-    // bucket id bits: level 1 takes the top 8 (or fewer), level 2 the rest
-    uint32_t bits = 0;
-    while ((1u << bits) < B) ++bits;
-    const uint32_t lo_bits = bits > 8 ? bits - 8 : 0;
-    const uint32_t F1 = B >> lo_bits, F2 = 1u << lo_bits;
+    const PartBits pb = part_bits(B);
+    const uint32_t lo_bits = pb.lo_bits, F1 = pb.F1, F2 = pb.F2;
     const uint32_t nt1 = (uint32_t)ceil_div(n, PART_TILE);
     const uint32_t nt2cap = nt1 + F1;
     uint32_t* p1 = arena;            // pstart1[2], tbase1[2]
     uint32_t* t1 = arena + 2;
-    uint32_t* p2 = arena + 4;        // 257
-    uint32_t* t2 = p2 + 260;         // 257
-    uint32_t* cnt_total = t2 + 260;  // 2 scalars
+    uint32_t* p2 = arena + 4;        // F1 + 1 <= 513
+    uint32_t* t2 = p2 + 520;         // F1 + 1
+    uint32_t* cnt_total = t2 + 520;  // 2 scalars
     uint32_t* tot = cnt_total + 2;   // 2 scalars
     uint32_t* c1 = tot + 4;
     uint32_t* o1 = c1 + (uint64_t)nt1 * F1;
@@ -934,46 +1196,51 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
     const uint64_t big = (uint64_t)nt1 * F1 > (uint64_t)nt2cap * F2 ? (uint64_t)nt1 * F1 : (uint64_t)nt2cap * F2;
     uint16_t* id1 = (uint16_t*)(((uintptr_t)(stmp + scan_tmp_words(big)) + 255) & ~(uintptr_t)255);
     uint16_t* id2 = id1 + ((n + 127) & ~127u);
+    uint32_t* hib = B > 65536 ? (uint32_t*)(id2 + ((n + 127) & ~127u)) : nullptr;  // (n + 15) / 16 words
+    uint32_t dbits1 = 0, dbits2 = 0;
+    while ((1u << dbits1) < F1) ++dbits1;
+    while ((1u << dbits2) < F2) ++dbits2;
+    // the level-1 histogram's grid is persistent: as many workgroups as are
+    // resident at once (a second round would run on a mostly idle GPU)
+    static bool occ_set[16] = {};
+    static unsigned occ_h1[16] = {};
+    int dev = 0;
+    VMPS_HIP(hipGetDevice(&dev));
+    const int d = dev & 15;
+    if (!occ_set[d]) {
+        int per_cu = 0, cus = 0;
+        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_part_hist1<K>, PART_NT, 0));
+        VMPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        occ_h1[d] = (unsigned)((per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1));
+        occ_set[d] = true;
+    }
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
-        // persistent: as many workgroups as are resident at once (a second
-        // round of workgroups would run its tiles on a mostly idle GPU)
-        static bool occ_set[16] = {};
-        static unsigned occ_grid[16] = {};
-        int dev = 0;
-        VMPS_HIP(hipGetDevice(&dev));
-        const int d = dev & 15;
-        if (!occ_set[d]) {
-            int per_cu = 0, cus = 0;
-            VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)k_part_hist1<K>, PART_NT, 0));
-            VMPS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-            occ_grid[d] = (unsigned)((per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1));
-            occ_set[d] = true;
-        }
-        const unsigned g1 = nt1 < occ_grid[d] ? nt1 : occ_grid[d];
-        k_part_hist1<K><<<g1, PART_NT, 0, s>>>(kin, id1, n, nt1, F1, lo_bits, F1 - 1, c1, Mdev, B);
+        const unsigned g1 = nt1 < occ_h1[d] ? nt1 : occ_h1[d];
+        k_part_hist1<K><<<g1, PART_NT, 0, s>>>(kin, id1, hib, n, nt1, F1, lo_bits, F1 - 1, c1, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
     }
     {
         TraceScope tr(VMPS_TRACE_SCATTER, s);
-        PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, c1, o1};
-        if (vmode == 0) k_part_scatter<K, 0, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
-        else if (vmode == 1) k_part_scatter<K, 1, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
-        else k_part_scatter<K, 2, true><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, ktmp, vtmp, id2, L1);
+        PartLevel L1{p1, t1, 1, F1, lo_bits, F1 - 1, dbits1, c1, o1};
+        const uint32_t idm = F2 - 1;
+        if (vmode == 0) k_part_scatter1<K, 0><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, hib, ktmp, vtmp, id2, L1, idm);
+        else if (vmode == 1) k_part_scatter1<K, 1><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, hib, ktmp, vtmp, id2, L1, idm);
+        else k_part_scatter1<K, 2><<<nt1, PART_NT, 0, s>>>(kin, vin, id1, hib, ktmp, vtmp, id2, L1, idm);
     }
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
-        k_part_level2<<<1, 256, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
-        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
+        k_part_level2<<<1, PART_DMAX, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
+        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, dbits2, c2, o2};
         k_part_hist2<<<nt2cap, PART_NT, 0, s>>>(id2, L2);
         VMPS_HIP(scan_exclusive_u32(c2, o2, (uint64_t)nt2cap * F2, cnt_total + 1, tot + 1, stmp, s));
     }
     {
         TraceScope tr(VMPS_TRACE_SCATTER, s);
-        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, c2, o2};
-        if (vmode == 0) k_part_scatter<K, 0, false><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, nullptr, L2);
-        else k_part_scatter<K, 1, false><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, nullptr, L2);
+        PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, dbits2, c2, o2};
+        if (vmode == 0) k_part_scatter2<K, 0><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, L2);
+        else k_part_scatter2<K, 1><<<nt2cap, PART_NT, 0, s>>>(ktmp, vtmp, id2, kout, vout, L2);
     }
     k_bucket_offsets<<<grid1(B + 1), 256, 0, s>>>(p2, t2, o2, F2, lo_bits, B, n, bucket_off);
     return hipGetLastError();
@@ -982,15 +1249,36 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
 
 uint64_t partition_arena_words(uint64_t n, uint32_t B)
 {
-    uint32_t bits = 0;
-    while ((1u << bits) < B) ++bits;
-    const uint32_t lo_bits = bits > 8 ? bits - 8 : 0;
-    const uint64_t F1 = B >> lo_bits, F2 = 1ull << lo_bits;
+    const PartBits pb = part_bits(B);
+    const uint64_t F1 = pb.F1, F2 = pb.F2;
     const uint64_t nt1 = ceil_div(n ? n : 1, PART_TILE);
     const uint64_t nt2cap = nt1 + F1;
     const uint64_t big = nt1 * F1 > nt2cap * F2 ? nt1 * F1 : nt2cap * F2;
-    const uint64_t ids = 2 * ((n + 127) & ~127ull) / 2;  // two arrays of 16-bit bucket ids
-    return 4 + 520 + 8 + 2 * nt1 * F1 + 2 * nt2cap * F2 + scan_tmp_words(big) + 64 + ids + 64;
+    // two arrays of 16-bit ids (level-1 bucket ids, level-2 digits), and
+    // bits 16-17 of the bucket ids beyond 2^16 buckets
+    const uint64_t ids = 2 * ((n + 127) & ~127ull) / 2 + (B > 65536 ? (n + 15) / 16 + 4 : 0);
+    return 4 + 1040 + 8 + 2 * nt1 * F1 + 2 * nt2cap * F2 + scan_tmp_words(big) + 64 + ids + 64;
+}
+
+uint64_t group_scratch_words(uint32_t B)
+{
+    const uint64_t nc = ceil_div(B ? B : 1, GROUP_CHUNK);
+    return 2 * nc + 8 + scan_tmp_words(nc);
+}
+
+hipError_t group_enqueue(const int64_t* boff, uint32_t B, uint32_t n, uint32_t C, int64_t* goff, uint32_t* scratch,
+                         hipStream_t s)
+{
+    const uint32_t nc = (uint32_t)ceil_div(B, GROUP_CHUNK);
+    uint32_t* cnt = scratch;
+    uint32_t* base = cnt + nc;
+    uint32_t* tot = base + nc;  // 8 words
+    uint32_t* tmp = tot + 8;
+    k_group_count<<<grid1(nc), 256, 0, s>>>(boff, B, C, cnt);
+    VMPS_HIP(scan_exclusive_u32(cnt, base, nc, nullptr, tot, tmp, s));
+    k_group_emit<<<grid1(nc), 256, 0, s>>>(boff, B, C, base, goff);
+    k_group_pad<<<grid1((uint64_t)B + 1), 256, 0, s>>>(tot, B, n, goff);
+    return hipGetLastError();
 }
 
 hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, uint32_t* vtmp, void* kout,
@@ -1018,17 +1306,34 @@ hipError_t sample_enqueue(const void* keys, uint64_t n, int key_bits, uint64_t m
     return hipGetLastError();
 }
 
+uint64_t train_buf_floats() { return 7ull * NP_PAD + 2ull * TRAIN_GMAX * NP_PAD + 2ull * LOSS_GMAX; }
+
+template <int H>
+static void train_launches(const float* u, uint64_t m, const vmps_learned_config& c, float* tb, vmps_cdf_model* model,
+                           hipStream_t s)
+{
+    k_cdf_init<H><<<1, 256, 0, s>>>(u, m, tb);
+    const unsigned Gg = (unsigned)((c.batch + STEP_PTS - 1) / STEP_PTS);
+    const uint64_t lcnt = (m + LOSS_STRIDE - 1) / LOSS_STRIDE;
+    const unsigned Gl = (unsigned)((lcnt + LOSS_PTS - 1) / LOSS_PTS);
+    for (int st = 0; st <= c.steps; ++st) {
+        const unsigned G = (st == 0 || st == c.steps) ? (Gg > Gl ? Gg : Gl) : Gg;
+        k_cdf_step<H><<<G, STEP_NT, 0, s>>>(u, m, st, c.steps, c.batch, c.lr, tb);
+    }
+    k_cdf_finish<H><<<1, TRAIN_NT, 0, s>>>(m, c.steps, c.knots, c.flags & 1, tb, model);
+}
+
 hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmps_learned_config& c, float* u,
-                         vmps_cdf_model* model, hipStream_t s)
+                         float* tb, vmps_cdf_model* model, hipStream_t s)
 {
     if (key_bits == 32)
         k_cdf_features<uint32_t><<<grid1(m), 256, 0, s>>>((const uint32_t*)sorted, m, 32, c.feature_bits, u, model);
     else
         k_cdf_features<uint64_t><<<grid1(m), 256, 0, s>>>((const uint64_t*)sorted, m, 64, c.feature_bits, u, model);
     switch (c.hidden) {
-    case 16: k_cdf_train<16><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
-    case 32: k_cdf_train<32><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
-    default: k_cdf_train<64><<<1, TRAIN_NT, 0, s>>>(u, m, c.steps, c.batch, c.lr, c.knots, c.flags & 1, model); break;
+    case 16: train_launches<16>(u, m, c, tb, model, s); break;
+    case 32: train_launches<32>(u, m, c, tb, model, s); break;
+    default: train_launches<64>(u, m, c, tb, model, s); break;
     }
     return hipGetLastError();
 }

@@ -119,6 +119,26 @@ __global__ __launch_bounds__(1024) void k_inst_prep(const int64_t* __restrict__ 
     }
 }
 
+// Instance table from offsets the library built itself (valid by
+// construction, so no check): one thread per entry over the whole grid.
+__global__ void k_inst_prep_trusted(const int64_t* __restrict__ off64, uint32_t k, uint32_t big_min,
+                                    uint32_t* inst_start, uint32_t* inst_big, uint32_t* inst_rfinal,
+                                    uint32_t* inst_run_lo, uint32_t* inst_run_hi, uint32_t* counters)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0)
+        for (int c = 0; c < CNT_COUNT; ++c) counters[c] = 0;
+    if (i > k) return;
+    const uint32_t a = (uint32_t)off64[i];
+    inst_start[i] = a;
+    if (i < k) {
+        inst_big[i] = (uint32_t)off64[i + 1] - a > big_min ? 1u : 0u;
+        inst_rfinal[i] = 0;
+        inst_run_lo[i] = NONE;
+        inst_run_hi[i] = NONE;
+    }
+}
+
 // The instance holding the first position of every bitmap tile, and
 // whether the tile meets an instance the planner handles (one thread per
 // tile, all searches in flight together; a tile crossing more than 64
@@ -932,6 +952,7 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.scan_tmp = c.take<uint32_t>(P.scan_tmp_words);
     P.hbm_depth = nullptr;
     P.inst_off64 = nullptr;
+    P.off_trusted = false;
     return c.off + 256;
 }
 
@@ -964,8 +985,13 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     // tile_off and tile_cnt hold each bitmap tile's first instance and
     // whether it meets an instance the planner handles, until the long-run
     // counts take them over
-    k_inst_prep<<<1, 1024, 0, s>>>(P.inst_off64, k, n, P.big_min, P.inst_start, P.inst_big, P.inst_rfinal,
-                                   P.inst_run_lo, P.inst_run_hi, C);
+    if (P.off_trusted && P.inst_off64)
+        k_inst_prep_trusted<<<grid_for((uint64_t)k + 1, 256), 256, 0, s>>>(P.inst_off64, k, P.big_min, P.inst_start,
+                                                                         P.inst_big, P.inst_rfinal, P.inst_run_lo,
+                                                                         P.inst_run_hi, C);
+    else
+        k_inst_prep<<<1, 1024, 0, s>>>(P.inst_off64, k, n, P.big_min, P.inst_start, P.inst_big, P.inst_rfinal,
+                                       P.inst_run_lo, P.inst_run_hi, C);
     if (k > 1)
         k_tile_inst<<<grid_for(P.bm_tiles, 256), 256, 0, s>>>(P.inst_start, P.inst_big, k, n, P.bm_tiles, P.tile_off,
                                                               P.tile_cnt);

@@ -77,7 +77,9 @@ template <typename K, int KI, int TCAP, int VMODE, int LAY, typename Nodes>
 __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restrict__ SV, uint32_t len, uint32_t tid,
                                            Nodes nd)
 {
-    static_assert(lay_block<LAY>() % KI == 0, "outputs of a thread stay inside one padding block");
+    // KI dividing the padding block keeps a thread's outputs inside one
+    // block (affine write-back); other KI compute each output's slot
+    constexpr bool AFFINE = lay_block<LAY>() % KI == 0;
     const uint32_t p0 = tid * KI;
     K rk[KI];
     uint32_t rv[KI];
@@ -179,7 +181,18 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
         }
     }
     __syncthreads();
-    if (p0 < len) {
+    if constexpr (!AFFINE) {
+        if (p0 < len) {
+            const uint32_t cnt = len - p0;
+#pragma unroll
+            for (int j = 0; j < KI; ++j) {
+                if ((uint32_t)j < cnt) {
+                    S[pxp<LAY>(p0 + j)] = rk[j];
+                    if (VMODE) SV[pxp<LAY>(p0 + j)] = rv[j];
+                }
+            }
+        }
+    } else if (p0 < len) {
         // KI divides the block length and p0 is a multiple of KI: the
         // outputs share one padding block, pxp<LAY>(p0 + j) = pxp<LAY>(p0) + j
         const uint32_t cnt = len - p0, w0 = pxp<LAY>(p0);
@@ -791,8 +804,7 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     }
     __syncthreads();
 
-    // 7./8. forced runs, then the merges of Algorithm 1; segments up to
-    // half the tile use half the outputs per thread, so every thread works
+    // 7./8. forced runs, then the merges of Algorithm 1
     const uint32_t maxf = scal[3], mask = scal[2];
     // 7a. the first bottom-up levels of every forced run: chunks of 2^CWL
     // elements from the run start, sorted in registers (unsorted runs are
@@ -815,8 +827,13 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
         }
         __syncthreads();
     }
+    // outputs per thread: the least of KI/2, 3KI/4 and KI that covers the
+    // segment, so that at least two thirds of the threads have work
     if (len <= (uint32_t)(NT * (KI / 2)))
         tile_merges<KT, KI / 2, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask, CWL);
+    else if (len <= (uint32_t)(NT * (3 * KI / 4)))
+        tile_merges<KT, 3 * KI / 4, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask,
+                                                      CWL);
     else
         tile_merges<KT, KI, TCAP, VMODE, LAY>(S, SV, len, tid, kr, RS, SR, NL, BLs, BR, LVs, LVc, maxf, mask, CWL);
 }

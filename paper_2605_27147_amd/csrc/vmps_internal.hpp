@@ -89,6 +89,7 @@ struct Plan {
     uint32_t lr_cap, run_cap, ent_cap, seg_cap, chain_blocks, bm_tiles, bm_words;
     // instances
     const int64_t* inst_off64;     // caller offsets (k+1), may be null for k = 1
+    bool off_trusted;              // offsets built by the library: valid by construction
     uint32_t* inst_start;          // k+1
     uint32_t* inst_big;            // k (0/1), scanned into inst_bigrank
     uint32_t* inst_bigrank;        // k
@@ -232,6 +233,13 @@ hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, con
                              const uint32_t* vb, uint32_t nb, void* out, uint32_t* vout,
                              int key_bits, uint32_t* splits, hipStream_t s);
 
+// Groups of consecutive learned buckets, at most C keys each (a bucket
+// longer than C alone): goff[0, G] the group starts and n, goff(G, B] = n
+// (empty instances).  Scratch: group_scratch_words(B) words.
+uint64_t group_scratch_words(uint32_t B);
+hipError_t group_enqueue(const int64_t* boff, uint32_t B, uint32_t n, uint32_t C, int64_t* goff,
+                         uint32_t* scratch, hipStream_t s);
+
 // Learned partition (learned.hip).
 uint64_t partition_arena_words(uint64_t n, uint32_t B);
 hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, uint32_t* vtmp, void* kout,
@@ -239,7 +247,11 @@ hipError_t partition_enqueue(const void* kin, const uint32_t* vin, void* ktmp, u
                              uint32_t B, int64_t* bucket_off, uint32_t* arena, hipStream_t s);
 hipError_t sample_enqueue(const void* keys, uint64_t n, int key_bits, uint64_t m, uint64_t seed, void* out,
                           hipStream_t s);
-hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmps_learned_config& c, float* u,
+// Training: features into u (m floats), then initialisation, one launch per
+// Adam step and the final choice and compilation, with their state in tb
+// (train_buf_floats() floats).
+uint64_t train_buf_floats();
+hipError_t train_enqueue(const void* sorted, uint64_t m, int key_bits, const vmps_learned_config& c, float* u, float* tb,
                          vmps_cdf_model* model, hipStream_t s);
 hipError_t grad_enqueue(const float* params, int H, const float* u, const float* y, int nb, float* grad,
                         float* loss, hipStream_t s);

@@ -35,7 +35,7 @@ KINDS = {
     "level_partition": (r"k_level_partition<", ["merge.hip", "vmps_internal.hpp"]),
     "scatter": (r"k_part_scatter<", ["learned.hip", "vmps_internal.hpp"]),
     "histogram": (r"k_part_hist1<", ["learned.hip", "vmps_internal.hpp"]),
-    "train": (r"k_cdf_train<", ["learned.hip", "vmps_internal.hpp"]),
+    "train": (r"k_cdf_step<", ["learned.hip", "vmps_internal.hpp"]),
 }
 COPY_PATTERN = r"copyBuffer"
 

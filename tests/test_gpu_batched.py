@@ -110,3 +110,44 @@ def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, 
     finally:
         vm.reset_tuning(vm.U32, False)
         vm.reset_tuning(vm.U64, False)
+
+
+def _brute_force_segments():
+    """Every permutation of 0..n-1 for n <= 9 and every word over {0,1,2} of
+    length n <= 12, each as one segment (u32 keys), in one array."""
+    import itertools
+    parts, lengths = [], []
+    for n in range(1, 10):
+        p = np.array(list(itertools.permutations(range(n))), dtype=np.uint32)
+        parts.append(p.ravel())
+        lengths += [n] * p.shape[0]
+    for n in range(1, 13):
+        w = np.indices((3,) * n, dtype=np.uint32).reshape(n, -1).T
+        parts.append(np.ascontiguousarray(w).ravel())
+        lengths += [n] * w.shape[0]
+    x = np.concatenate(parts)
+    off = np.zeros(len(lengths) + 1, dtype=np.int64)
+    np.cumsum(lengths, out=off[1:])
+    return x, off
+
+
+def test_segmented_brute_force_tiny_inputs(vm, orc):
+    """Tiny inputs exhaustively, through the batched path in one call: every
+    permutation of n <= 9 and every {0,1,2}^n word of n <= 12 (1.21 M
+    segments, 12.8 M keys) with their positions as values, against the
+    definition (the unique order by segment, key, then position) and the
+    oracle's per-segment Powersort."""
+    import torch
+    x, off = _brute_force_segments()
+    total, nseg = x.size, off.size - 1
+    _say("brute force segments", nseg, "keys", total)
+    seg = np.repeat(np.arange(nseg, dtype=np.int64), np.diff(off))
+    order = np.lexsort((np.arange(total), x, seg))
+    want_k, want_v = x[order], order.astype(np.uint32)
+    ok, ov = orc.segmented_powersort(x, off, vals=np.arange(total, dtype=np.uint32))
+    assert np.array_equal(ok.astype(np.uint32), want_k) and np.array_equal(ov, want_v)
+    keys = _t(x)
+    vals = _t(np.arange(total, dtype=np.uint32))
+    vm.segmented_sort_(keys, torch.from_numpy(off).cuda(), vals)
+    assert np.array_equal(_np(keys, np.uint32), want_k)
+    assert np.array_equal(_np(vals, np.uint32), want_v)

@@ -91,6 +91,27 @@ def test_full_learned_lognormal_2p28(vm):
     assert bool((k2 == keys).all().item())
 
 
+def test_full_learned_dup16_2p28(vm):
+    """The learned path's adversary at the benchmark size: n = 2^28 u64 keys
+    drawn from 16 distinct lognormal values (every bucket that is not empty
+    holds one value, far longer than the LDS tile, so all keys take the
+    fallback), with index values, checked by the properties."""
+    import torch
+    n = 1 << 28
+    _say("full dup16: generating", n)
+    x = workloads.dup16(n, 6)
+    x_dev = torch.from_numpy(x.view(np.int64)).cuda()
+    del x
+    keys = x_dev.clone()
+    vals = torch.empty(n, dtype=torch.int32, device="cuda")
+    _say("full dup16: sort with iota values")
+    stats, _ = vm.sort_learned_(keys, vals, iota=True)
+    _say("  stats", {k: stats[k] for k in ("buckets", "nonempty_buckets", "fallback_buckets", "fallback_keys",
+                                           "max_bucket")})
+    assert stats["nonempty_buckets"] <= 16 and stats["fallback_keys"] == n
+    _check_stable_sort(x_dev, keys, vals)
+
+
 def test_full_plain_pairs_mixture_2p28(vm):
     """(key, u32 index) pairs, n = 2^28 of the mixture input, plain path."""
     import torch

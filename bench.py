@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gkeys/s + % HBM roofline at n=2^28 u64, learned/batched vs plain GPU path"
 HBM_PEAK_GBS = 8000.0
+# LDS: 128 bytes per clock per CU, 256 CUs at 2.4 GHz
+LDS_PEAK_GBS = 128 * 256 * 2.4
+# VALU issue: one wave64 vector instruction per clock per CU (four SIMDs of
+# 16 lanes, 64 lane-operations per clock), 256 CUs at 2.4 GHz
+VALU_PEAK_GIPS = 256 * 2.4
 
 
 def log(*a):
@@ -187,6 +192,26 @@ def main():
                 "avg_launch_ms": round(dom_ms / dom_launches, 4),
                 "launches_per_step": dom_launches / TRACED,
                 "bytes_per_launch": bytes_per_sort * TRACED / dom_launches}
+    # the same kernel against the LDS and the VALU-issue roofs: LDS bytes and
+    # wave-level VALU instructions per launch from rocprofv3 SQ counters
+    # (while its source is unchanged since they were taken), over the live
+    # average launch time
+    cfile = os.path.join(ROOT, "profiles", f"counters_{args.path}_lognormal64_2p{args.log2n}_{dom}.json")
+    cn = profiling.load_counters(cfile)
+    if cn:
+        pl = cn["per_launch"]
+        launch_s = dom_ms / dom_launches / 1e3
+        lds_b = 64.0 * (pl["SQ_INSTS_LDS_LOAD_BANDWIDTH"] + pl["SQ_INSTS_LDS_STORE_BANDWIDTH"])
+        roofline["lds"] = {"achieved": round(lds_b / launch_s / 1e9, 1), "peak": LDS_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(lds_b / launch_s / 1e9 / LDS_PEAK_GBS, 4), "bytes_per_launch": lds_b,
+                           "bank_conflict_share": round(pl["SQ_LDS_BANK_CONFLICT"] / pl["SQ_LDS_IDX_ACTIVE"], 4)}
+        roofline["valu"] = {"achieved": round(pl["SQ_INSTS_VALU"] / launch_s / 1e9, 1), "peak": VALU_PEAK_GIPS,
+                            "unit": "G wave-instructions/s",
+                            "frac": round(pl["SQ_INSTS_VALU"] / launch_s / 1e9 / VALU_PEAK_GIPS, 4),
+                            "instructions_per_launch": pl["SQ_INSTS_VALU"]}
+        roofline["counters_source"] = os.path.relpath(cfile, ROOT)
+        roofline["binding_roof"] = max(("hbm", roofline["frac"]), ("lds", roofline["lds"]["frac"]),
+                                       ("valu", roofline["valu"]["frac"]), key=lambda t: t[1])[0]
     breakdown = {k: {"ms_per_step": round(v[0] / TRACED, 4), "launches_per_step": v[1] / TRACED}
                  for k, v in kinds.items()}
     path_bytes = sum(kernel_bytes(args.path, k, n, 8, 0, m_hbm, cfg.sample_size) for k in kinds)

@@ -554,6 +554,7 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         plan_carve(P, w + L.plan, (uint64_t)n, L.B, T, merge_tile_out(kb, has_values));
         P.inst_off64 = goff;
         P.off_trusted = true;
+        P.k_dev = group_count((const uint32_t*)(w + L.gscr), L.B);
         P.big_min = T;
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));

@@ -1266,6 +1266,11 @@ uint64_t group_scratch_words(uint32_t B)
     return 2 * nc + 8 + scan_tmp_words(nc);
 }
 
+const uint32_t* group_count(const uint32_t* scratch, uint32_t B)
+{
+    return scratch + 2 * ceil_div(B, GROUP_CHUNK);
+}
+
 hipError_t group_enqueue(const int64_t* boff, uint32_t B, uint32_t n, uint32_t C, int64_t* goff, uint32_t* scratch,
                          hipStream_t s)
 {

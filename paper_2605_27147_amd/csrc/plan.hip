@@ -742,12 +742,13 @@ __global__ void k_segs_hbm(const uint32_t* __restrict__ hbm_list, const uint32_t
 __global__ void k_segs_inst(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ run_start,
                             const uint32_t* __restrict__ run_inst, const uint32_t* __restrict__ depth,
                             const uint32_t* __restrict__ inst_start, const uint32_t* __restrict__ inst_big,
-                            const uint32_t* __restrict__ inst_bigrank, uint32_t k, uint32_t* counters,
-                            Seg* __restrict__ segs)
+                            const uint32_t* __restrict__ inst_bigrank, uint32_t k,
+                            const uint32_t* __restrict__ k_dev, uint32_t* counters, Seg* __restrict__ segs)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t h = counters[CNT_NHBM], nbig = counters[CNT_NBIG];
-    if (i == 0) counters[CNT_NSEG] = h + k;
+    // trailing empty instances (from *k_dev on) get no segment to visit
+    if (i == 0) counters[CNT_NSEG] = h + (k_dev ? min(k, *k_dev) : k);
     if (i >= k) return;
     const uint32_t ib = inst_start[i], ie = inst_start[i + 1];
     Seg s;
@@ -953,6 +954,7 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.hbm_depth = nullptr;
     P.inst_off64 = nullptr;
     P.off_trusted = false;
+    P.k_dev = nullptr;
     return c.off + 256;
 }
 
@@ -1048,7 +1050,7 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     k_segs_hbm<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
                                                         P.hbm_depth, P.inst_start, C, P.segs);
     k_segs_inst<<<grid_for(k, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.hbm_depth,
-                                                 P.inst_start, P.inst_big, P.inst_bigrank, k, C, P.segs);
+                                                 P.inst_start, P.inst_big, P.inst_bigrank, k, P.k_dev, C, P.segs);
     VMPS_HIP(fill_u32(P.level, 0, 3 * MAX_LEVEL, s));
     k_level_count<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
                                                            C, P.hbm_tiles, P.level);

@@ -90,6 +90,7 @@ struct Plan {
     // instances
     const int64_t* inst_off64;     // caller offsets (k+1), may be null for k = 1
     bool off_trusted;              // offsets built by the library: valid by construction
+    const uint32_t* k_dev;         // nullable: instances from this count on (device) are empty
     uint32_t* inst_start;          // k+1
     uint32_t* inst_big;            // k (0/1), scanned into inst_bigrank
     uint32_t* inst_bigrank;        // k
@@ -236,9 +237,11 @@ hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, con
 // Groups of consecutive learned buckets, at most C keys each (a bucket
 // longer than C alone): goff[0, G] the group starts and n, goff(G, B] = n
 // (empty instances).  Scratch: group_scratch_words(B) words.
+// The group count G goes to *group_count(scratch) (device).
 uint64_t group_scratch_words(uint32_t B);
 hipError_t group_enqueue(const int64_t* boff, uint32_t B, uint32_t n, uint32_t C, int64_t* goff,
                          uint32_t* scratch, hipStream_t s);
+const uint32_t* group_count(const uint32_t* scratch, uint32_t B);
 
 // Learned partition (learned.hip).
 uint64_t partition_arena_words(uint64_t n, uint32_t B);

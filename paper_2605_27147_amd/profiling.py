@@ -7,6 +7,10 @@
 `stats` turns a `rocprofv3 --kernel-trace --stats --output-format csv` output
 directory into a short text table (kernel, calls, total ms, average us, %).
 
+`counters` turns `rocprofv3 --pmc <SQ counters>` runs into the average per
+launch of every counter for one kernel kind (instruction counts, LDS bytes
+in 64-byte units, cycle counts), with the kernel's source hashes.
+
 `traffic` turns two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of
 the same command into HBM bytes per launch of one kernel kind.  Both counters
 are scaled by what they report for a device copy of known size in the same
@@ -33,7 +37,7 @@ KINDS = {
     "tilesort": (r"k_tilesort<", ["tilesort.hip", "merge_tile.hpp", "vmps_internal.hpp"]),
     "level_merge": (r"k_level_merge<", ["merge.hip", "merge_tile.hpp", "vmps_internal.hpp"]),
     "level_partition": (r"k_level_partition<", ["merge.hip", "vmps_internal.hpp"]),
-    "scatter": (r"k_part_scatter<", ["learned.hip", "vmps_internal.hpp"]),
+    "scatter": (r"k_part_scatter[12]<", ["learned.hip", "vmps_internal.hpp"]),
     "histogram": (r"k_part_hist1<", ["learned.hip", "vmps_internal.hpp"]),
     "train": (r"k_cdf_step<", ["learned.hip", "vmps_internal.hpp"]),
 }
@@ -70,6 +74,40 @@ def stats(directory: str, out: str, title: str, command: str) -> None:
                      f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['Percentage']):.2f}")
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+
+
+def _all_counters(directory: str) -> dict:
+    """counter -> list of per-dispatch records (summed over the counter's
+    hardware instances)."""
+    path = _one(os.path.join(directory, "**", "*counter_collection.csv"))
+    per = {}
+    for r in csv.DictReader(open(path)):
+        d = per.setdefault((r["Counter_Name"], r["Dispatch_Id"]),
+                           {"name": r["Kernel_Name"], "grid": int(r["Grid_Size"]), "value": 0.0})
+        d["value"] += float(r["Counter_Value"])
+    out = {}
+    for (c, _), rec in per.items():
+        out.setdefault(c, []).append(rec)
+    return out
+
+
+def counters(dirs: list, out: str, kind: str, commands: list) -> dict:
+    pat = re.compile(KINDS[kind][0])
+    per_launch, launches = {}, {}
+    for d in dirs:
+        for c, recs in _all_counters(d).items():
+            v = [r["value"] for r in recs if pat.search(r["name"])]
+            if v:
+                per_launch[c] = sum(v) / len(v)
+                launches[c] = len(v)
+    if not per_launch:
+        raise ValueError(f"no dispatch matches {KINDS[kind][0]}")
+    res = {"kind": kind, "kernel_pattern": KINDS[kind][0], "per_launch": per_launch, "launches_counted": launches,
+           "sources": source_hashes(kind), "commands": commands}
+    with open(out, "w") as fh:
+        json.dump(res, fh, indent=1)
+        fh.write("\n")
+    return res
 
 
 def _counters(directory: str, counter: str) -> list:
@@ -142,6 +180,12 @@ def load_traffic(path: str):
         return None
 
 
+def load_counters(path: str):
+    """Per-launch SQ counters from a counters JSON, or None when the
+    kernel's source has changed since they were taken (or it is missing)."""
+    return load_traffic(path)
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser(prog="python -m paper_2605_27147_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -150,6 +194,11 @@ def main(argv=None) -> int:
     s.add_argument("out")
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("out")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--kind", required=True, choices=sorted(KINDS))
+    c.add_argument("--command", action="append", default=[])
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -160,6 +209,9 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         stats(a.dir, a.out, a.title, a.command)
+    elif a.cmd == "counters":
+        r = counters(a.dirs, a.out, a.kind, a.command)
+        print(json.dumps(r["per_launch"]))
     else:
         r = traffic(a.fetch_dir, a.write_dir, a.out, a.kind, a.copy_bytes, a.command)
         print(json.dumps({k: r[k] for k in ("kind", "traffic_bytes_per_launch", "calibration")}))

@@ -24,12 +24,13 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 PINGPONG, PINGPONG_LASTPOP, CPYTHON = 0, 1, 2
+DESC_RUNS = 4  # flag or-ed into a variant: strictly decreasing runs are reversed
 
 
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "runs", "merges", "merge_cost", "max_stack", "cmp_run", "cmp_ins",
-        "cmp_merge", "mov_ins", "mov_push", "mov_merge")] + [("entropy", ctypes.c_double)]
+        "cmp_merge", "mov_ins", "mov_push", "mov_merge")] + [("entropy", ctypes.c_double), ("mov_rev", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -61,6 +62,8 @@ def _L():
         lib.orc_power_closed.argtypes = [i64, i64, i64, i64]
         lib.orc_extract_runs.restype = i64
         lib.orc_extract_runs.argtypes = [vp, i64, i32, vp]
+        lib.orc_extract_runs_dir.restype = i64
+        lib.orc_extract_runs_dir.argtypes = [vp, i64, i32, ctypes.c_int, vp, vp]
         lib.orc_run_powers.restype = None
         lib.orc_run_powers.argtypes = [vp, i64, i64, vp]
         lib.orc_powersort.restype = ctypes.c_int
@@ -134,14 +137,19 @@ def power_closed(n, i, j, k) -> int:
     return int(_L().orc_power_closed(n, i, j, k))
 
 
-def extract_runs(keys, ell: int | None = None) -> np.ndarray:
-    """Run bounds (r+1 int64) of the sequential ExtractRun chain."""
+def extract_runs(keys, ell: int | None = None, desc: bool = False, want_desc: bool = False):
+    """Run bounds (r+1 int64) of the sequential ExtractRun chain; with desc,
+    maximal strictly decreasing runs count too (want_desc: also the flags of
+    the runs that are reversed)."""
     x = _keys64(keys)
     n = x.size
     if ell is None:
         ell = minrun(n)
     bounds = np.zeros(n + 2, dtype=np.int64)
-    r = _L().orc_extract_runs(_p(x), n, ell, _p(bounds))
+    flags = np.zeros(n + 2, dtype=np.uint8)
+    r = _L().orc_extract_runs_dir(_p(x), n, ell, int(desc), _p(bounds), _p(flags))
+    if want_desc:
+        return bounds[: r + 1].copy(), flags[:r].copy()
     return bounds[: r + 1].copy()
 
 

@@ -67,17 +67,60 @@ static int64_t natural_run_end(const uint64_t* x, int64_t s, int64_t n, int64_t*
     return e;
 }
 
-int64_t orc_extract_runs(const uint64_t* x, int64_t n, int32_t minrun, int64_t* bounds)
+/* With descending runs (Section 5 remark): when x[s+1] < x[s] the run is
+ * the maximal strictly decreasing one from s (*desc = 1), else the maximal
+ * non-decreasing one.  A strictly decreasing run has no equal keys, so
+ * reversing it is its stable sort. */
+static int64_t natural_run_end_dir(const uint64_t* x, int64_t s, int64_t n, int64_t* cmps, int* desc)
+{
+    *desc = 0;
+    if (s + 1 >= n) return n;
+    if (cmps) ++*cmps;
+    if (x[s + 1] < x[s]) {
+        int64_t e = s + 2;
+        while (e < n) {
+            if (cmps) ++*cmps;
+            if (!(x[e] < x[e - 1])) break;
+            ++e;
+        }
+        *desc = 1;
+        return e;
+    }
+    return natural_run_end(x, s, n, cmps);
+}
+
+int64_t orc_extract_runs_dir(const uint64_t* x, int64_t n, int32_t minrun, int desc, int64_t* bounds,
+                             uint8_t* desc_run)
 {
     int64_t r = 0, s = 0;
     bounds[0] = 0;
     while (s < n) {
-        int64_t e = natural_run_end(x, s, n, NULL);
-        if (e - s < minrun) e = (s + minrun < n) ? s + minrun : n;
+        int d = 0;
+        int64_t e = desc ? natural_run_end_dir(x, s, n, NULL, &d) : natural_run_end(x, s, n, NULL);
+        if (e - s < minrun) {
+            e = (s + minrun < n) ? s + minrun : n;
+            d = 0;
+        }
+        if (desc_run) desc_run[r] = (uint8_t)d;
         bounds[++r] = e;
         s = e;
     }
     return r;
+}
+
+int64_t orc_extract_runs(const uint64_t* x, int64_t n, int32_t minrun, int64_t* bounds)
+{
+    return orc_extract_runs_dir(x, n, minrun, 0, bounds, NULL);
+}
+
+/* Reverse x[s,e) (and v) in place. */
+static void reverse_run(uint64_t* x, uint32_t* v, int64_t s, int64_t e, orc_stats* st)
+{
+    for (int64_t i = s, j = e - 1; i < j; ++i, --j) {
+        uint64_t t = x[i]; x[i] = x[j]; x[j] = t;
+        if (v) { uint32_t w = v[i]; v[i] = v[j]; v[j] = w; }
+        st->mov_rev += 2;
+    }
 }
 
 void orc_run_powers(const int64_t* bounds, int64_t r, int64_t n, uint8_t* powers)
@@ -111,11 +154,15 @@ static void insertion_extend(uint64_t* x, uint32_t* v, int64_t s, int64_t sorted
     }
 }
 
-/* ExtractRun with the minrun extension: returns the run end. */
-static int64_t extract_run(uint64_t* x, uint32_t* v, int64_t s, int64_t n, int32_t minrun,
+/* ExtractRun with the minrun extension: returns the run end.  With desc, a
+ * strictly decreasing natural run is reversed first (also a short one,
+ * before the insertion sort extends it). */
+static int64_t extract_run(uint64_t* x, uint32_t* v, int64_t s, int64_t n, int32_t minrun, int desc,
                            orc_stats* st, double* H)
 {
-    int64_t e = natural_run_end(x, s, n, &st->cmp_run);
+    int d = 0;
+    int64_t e = desc ? natural_run_end_dir(x, s, n, &st->cmp_run, &d) : natural_run_end(x, s, n, &st->cmp_run);
+    if (d) reverse_run(x, v, s, e, st);
     if (e - s < minrun) {
         int64_t forced = (s + minrun < n) ? s + minrun : n;
         insertion_extend(x, v, s, e, forced, st);
@@ -221,6 +268,8 @@ int orc_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun,
     orc_stats st;
     memset(&st, 0, sizeof st);
     st.n = n;
+    const int desc = (variant & ORC_DESC_RUNS) != 0;
+    variant &= ~ORC_DESC_RUNS;
     if (n < 0 || variant < 0 || variant > 2) return -1;
     if (n <= 1) {
         if (n == 1) st.runs = 1;
@@ -248,10 +297,10 @@ int orc_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun,
     } while (0)
 
     int64_t c_lo = 0;
-    int64_t c_hi = extract_run(keys, vals, 0, n, l, &st, &H);
+    int64_t c_hi = extract_run(keys, vals, 0, n, l, desc, &st, &H);
     int curr_in_stackbuf = 0; /* Pingpong: where curr currently lives */
     while (c_hi < n) {
-        int64_t nx_hi = extract_run(keys, vals, c_hi, n, l, &st, &H);
+        int64_t nx_hi = extract_run(keys, vals, c_hi, n, l, desc, &st, &H);
         int32_t p = orc_power_def(n, c_lo, c_hi, nx_hi);
         while (height > 0 && stack[height - 1].power >= p) {
             stack_entry top = stack[height - 1];

@@ -34,13 +34,18 @@ typedef struct {
     int64_t mov_push;    /* element copies input -> stack buffer          */
     int64_t mov_merge;   /* element writes by merges (incl. aux copies)   */
     double  entropy;     /* run-length entropy H over the extended runs   */
+    int64_t mov_rev;     /* element writes by descending-run reversals    */
 } orc_stats;
 
 /* Variants of Algorithm 1 the oracle can run. */
 enum {
     ORC_PINGPONG = 0,          /* Section 3: stack runs in stackBuf, curr in input   */
     ORC_PINGPONG_LASTPOP = 1,  /* Section 3 + right-to-left last pop into stackBuf   */
-    ORC_CPYTHON = 2            /* Section 2: copy smaller run to aux, merge back     */
+    ORC_CPYTHON = 2,           /* Section 2: copy smaller run to aux, merge back     */
+    /* flag, or-ed into any variant: ExtractRun also takes maximal strictly
+     * decreasing runs and reverses them (the remark on decreasing runs in
+     * Section 5); strictness keeps equal keys in input order */
+    ORC_DESC_RUNS = 4
 };
 
 int32_t orc_minrun(int64_t n);
@@ -50,6 +55,12 @@ int32_t orc_power_closed(int64_t n, int64_t i, int64_t j, int64_t k);
 /* Sequential ExtractRun chain over x[0,n) (no sorting). bounds gets r+1
  * entries (bounds[0]=0, bounds[r]=n); returns r. */
 int64_t orc_extract_runs(const uint64_t* x, int64_t n, int32_t minrun, int64_t* bounds);
+
+/* The same chain with descending runs (ORC_DESC_RUNS) when desc != 0; desc_run
+ * (nullable, r entries) gets 1 for every run that is a maximal strictly
+ * decreasing run of at least minrun elements (reversed by the sort). */
+int64_t orc_extract_runs_dir(const uint64_t* x, int64_t n, int32_t minrun, int desc, int64_t* bounds,
+                             uint8_t* desc_run);
 
 /* Power of every run boundary: powers[t] for runs t,t+1 (t < r-1). */
 void orc_run_powers(const int64_t* bounds, int64_t r, int64_t n, uint8_t* powers);

@@ -73,17 +73,22 @@ static void test_sorts(void)
         for (int kind = 0; kind < 5; ++kind) {
             fill(orig, n, kind);
             for (size_t mi = 0; mi < sizeof minruns / sizeof *minruns; ++mi) {
-                for (int variant = 0; variant < 3; ++variant) {
+                for (int variant = 0; variant < 3 + 3; ++variant) {  /* 3..5: with ORC_DESC_RUNS */
                     memcpy(keys, orig, sizeof(uint64_t) * (size_t)n);
                     for (int64_t i = 0; i < n; ++i) vals[i] = (uint32_t)i;
                     orc_stats st;
-                    int rc = orc_powersort(keys, vals, n, minruns[mi], variant, &st, log, n);
+                    const int v = variant < 3 ? variant : ((variant - 3) | ORC_DESC_RUNS);
+                    int rc = orc_powersort(keys, vals, n, minruns[mi], v, &st, log, n);
                     CHECK(rc == 0, "powersort rc %d", rc);
                     check_stable(orig, keys, vals, n, "powersort");
                 }
             }
             if (n < 2) continue;
             const int32_t ell = orc_minrun(n);
+            uint8_t* dflag = (uint8_t*)malloc((size_t)(n + 1));
+            const int64_t rd = orc_extract_runs_dir(orig, n, ell, 1, bounds, dflag);
+            CHECK(rd >= 1 && bounds[0] == 0 && bounds[rd] == n, "extract_runs_dir bounds");
+            free(dflag);
             const int64_t r = orc_extract_runs(orig, n, ell, bounds);
             CHECK(r >= 1 && bounds[0] == 0 && bounds[r] == n, "extract_runs bounds");
             uint8_t* powers = (uint8_t*)malloc((size_t)(r > 1 ? r - 1 : 1));

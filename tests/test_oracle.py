@@ -364,3 +364,74 @@ def test_exhaustive_words_up_to_12(orc, variant):
         want = np.argsort(rows, axis=1, kind="stable")
         assert np.array_equal(v, want.astype(np.uint32)), n
         assert np.array_equal(out, np.take_along_axis(rows, want, axis=1).astype(np.uint64)), n
+
+
+# ---------------------------------------------------- descending runs --
+DESC_VARIANTS = [0, 1, 2]
+
+
+def test_desc_runs_golden(orc):
+    for (ell,), keys, bounds, flags, (M,) in read_golden("desc_runs.txt"):
+        x = np.array(keys, dtype=np.uint64)
+        b, f = orc.extract_runs(x, ell, desc=True, want_desc=True)
+        assert b.tolist() == bounds and f.tolist() == flags, keys
+        for variant in DESC_VARIANTS:
+            k, v, st, _ = orc.powersort(x, np.arange(x.size, dtype=np.uint32), variant=variant | orc.DESC_RUNS, ell=ell)
+            assert st["merge_cost"] == M and st["runs"] == len(bounds) - 1
+            assert np.array_equal(k, np.sort(x)) and np.array_equal(v, np.argsort(x, kind="stable"))
+
+
+@pytest.mark.parametrize("variant", DESC_VARIANTS)
+def test_desc_runs_bruteforce(orc, variant):
+    """Every permutation of n <= 8 and every {0,1,2}^n word of n <= 10 (ties:
+    a reversed run must be strictly decreasing) sorts stably with the
+    reversal on, at minrun 2 and at the rule's minrun."""
+    cases = []
+    for n in range(1, 9):
+        cases += [np.array(p, dtype=np.uint64) for p in itertools.permutations(range(n))]
+    for n in range(1, 11):
+        cases += [np.array(w, dtype=np.uint64) for w in itertools.product(range(3), repeat=n)]
+    for x in cases:
+        order = np.argsort(x, kind="stable")
+        for ell in (2, 0):
+            k, v, _, _ = orc.powersort(x, np.arange(x.size, dtype=np.uint32), variant=variant | orc.DESC_RUNS, ell=ell)
+            assert np.array_equal(v, order), (x, ell)
+
+
+def test_desc_runs_special_cases(orc):
+    rng = np.random.default_rng(9)
+    for n in (2, 3, 64, 65, 1000, 4097):
+        # strictly decreasing: one reversed run, no merge, every element
+        # written once by the reversal except the middle one of an odd n
+        x = np.arange(n, 0, -1, dtype=np.uint64) * 3
+        k, v, st, _ = orc.powersort(x, np.arange(n, dtype=np.uint32), variant=orc.DESC_RUNS)
+        assert st["runs"] == 1 and st["merge_cost"] == 0 and st["mov_rev"] == 2 * (n // 2)
+        assert np.array_equal(k, np.sort(x)) and v[0] == n - 1
+        # no strict descent anywhere: the same runs and merges as without
+        y = np.sort(rng.integers(0, 50, n).astype(np.uint64))
+        y[: n // 3] = y[0]
+        b0 = orc.extract_runs(y)
+        b1, f1 = orc.extract_runs(y, desc=True, want_desc=True)
+        assert np.array_equal(b0, b1) and not f1.any()
+        # non-increasing with ties: only the strictly decreasing stretches
+        # are reversed, ties keep their input order
+        z = np.repeat(np.arange(n, 0, -1, dtype=np.uint64), 2)
+        kz, vz, _, _ = orc.powersort(z, np.arange(z.size, dtype=np.uint32), variant=orc.DESC_RUNS)
+        assert np.array_equal(vz, np.argsort(z, kind="stable"))
+
+
+def test_desc_runs_theorem_bound_and_counters(orc):
+    """M <= n (H + 2) (merge-cost theorem of Section 2) and the Pingpong
+    moves M + n (Section 3, with the last pop) hold for the reversed runs
+    too; on these inputs (runs of mean length 300, a tenth of them
+    decreasing) the reversal leaves fewer runs than the increasing-only
+    chain, which cuts each decreasing run into forced runs."""
+    for seed in range(6):
+        x = workloads.presorted(1 << 14, seed, mean_run=300)
+        _, _, s0, _ = orc.powersort(x)
+        _, _, s1, _ = orc.powersort(x, variant=orc.PINGPONG_LASTPOP | orc.DESC_RUNS)
+        n = x.size
+        assert s1["merge_cost"] <= n * (s1["entropy"] + 2)
+        assert s1["mov_push"] + s1["mov_merge"] <= s1["merge_cost"] + n
+        assert s1["runs"] <= s0["runs"]
+        assert s1["mov_rev"] > 0

@@ -59,6 +59,10 @@ typedef enum { VMPS_U32 = 0, VMPS_U64 = 1 } vmps_dtype;
 /* vmps_sort flags */
 #define VMPS_VALUES_IOTA 1u /* `values` is output only: receives the stable
                                permutation (original index of each output key) */
+#define VMPS_DESCENDING_RUNS 2u /* ExtractRun also takes maximal strictly
+                               decreasing runs and reverses them (the remark
+                               on decreasing runs in Section 5); the output is
+                               the same stable sort, runs and merges differ */
 
 /* Human-readable name of a status code (static string). */
 const char* vmps_status_string(vmps_status s);
@@ -77,6 +81,7 @@ vmps_status vmps_sort_workspace_size(int64_t n, vmps_dtype kt, int has_values, s
  *            it is output only and receives the stable argsort.
  *   ws     : at least vmps_sort_workspace_size() bytes, 256-byte aligned;
  *            holds the second Pingpong buffer and the merge schedule.
+ *   flags  : VMPS_VALUES_IOTA, VMPS_DESCENDING_RUNS (or-ed).
  * n in {0,1} is a no-op.  Errors: INVALID_ARG (n<0, n>=2^32, NULL keys or ws
  * with n>1, misaligned keys, values aliasing keys, unknown flags),
  * WORKSPACE_TOO_SMALL, DEVICE. */
@@ -124,6 +129,14 @@ vmps_status vmps_merge(const void* a, const uint32_t* va, int64_t na, const void
 vmps_status vmps_extract_runs(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun,
                               uint32_t* run_bounds, int64_t* num_runs, void* ws,
                               size_t ws_bytes, void* stream);
+
+/* The chain of vmps_sort with VMPS_DESCENDING_RUNS: at a chain point s the
+ * natural run is the maximal strictly decreasing one when x[s+1] < x[s] (it
+ * is reversed by the sort), else the maximal non-decreasing one; shorter
+ * than minrun, it is forced to minrun.  Arguments as vmps_extract_runs. */
+vmps_status vmps_extract_runs_desc(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun,
+                                   uint32_t* run_bounds, int64_t* num_runs, void* ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Upper bound on the number of runs for n elements and minimum run length
  * minrun (<= 0: vmps_minrun(n)). */

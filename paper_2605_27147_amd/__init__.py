@@ -26,6 +26,7 @@ _lib = None
 OK, INVALID_ARG, WORKSPACE_TOO_SMALL, UNSUPPORTED, DEVICE = range(5)
 U32, U64 = 0, 1
 VALUES_IOTA = 1
+DESCENDING_RUNS = 2
 CDF_KEEP_TRAINED = 1
 
 
@@ -94,6 +95,7 @@ def load_library():
         "vmps_merge_workspace_size": (st, [i64, i64, st, ctypes.POINTER(sz)]),
         "vmps_merge": (st, [vp, vp, i64, vp, vp, i64, vp, vp, st, vp, sz, vp]),
         "vmps_extract_runs": (st, [vp, i64, st, i32, vp, vp, vp, sz, vp]),
+        "vmps_extract_runs_desc": (st, [vp, i64, st, i32, vp, vp, vp, sz, vp]),
         "vmps_run_powers": (st, [vp, vp, i64, i64, vp, vp]),
         "vmps_sort_schedule": (st, [vp, i64, st, st, vp, vp, vp, vp, vp, vp, vp, vp, vp,
                                     ctypes.POINTER(i32), vp, sz, vp]),
@@ -241,16 +243,17 @@ def sort_workspace_size(n: int, dtype_code: int, has_values: bool) -> int:
     return out.value
 
 
-def sort_(keys, values=None, *, iota: bool = False, workspace=None):
+def sort_(keys, values=None, *, iota: bool = False, workspace=None, desc: bool = False):
     """Stable in-place sort of keys (and values).  iota=True fills `values`
-    with the stable permutation instead of reading it."""
+    with the stable permutation instead of reading it; desc=True reverses
+    strictly decreasing runs (VMPS_DESCENDING_RUNS)."""
     lib = load_library()
     _require_cuda(keys, values)
     kt = _dtype_code(keys)
     n = keys.numel()
     ws_bytes = sort_workspace_size(n, kt, values is not None)
     ws = workspace if workspace is not None else _workspace(ws_bytes, keys.device)
-    flags = VALUES_IOTA if iota else 0
+    flags = (VALUES_IOTA if iota else 0) | (DESCENDING_RUNS if desc else 0)
     _check(lib.vmps_sort(_ptr(keys), _ptr(values), n, kt, flags, _ptr(ws), ws.numel(), _stream(keys.device)),
            "vmps_sort")
     return keys
@@ -297,8 +300,9 @@ def merge(a, b, va=None, vb=None, out=None, vout=None):
     return out, vout
 
 
-def extract_runs(keys, minrun_: int = 0):
-    """(run_bounds int32 tensor of r+1 bounds, r) — synchronises to read r."""
+def extract_runs(keys, minrun_: int = 0, desc: bool = False):
+    """(run_bounds int32 tensor of r+1 bounds, r) — synchronises to read r.
+    desc: the chain with descending runs (vmps_extract_runs_desc)."""
     torch = _torch()
     lib = load_library()
     _require_cuda(keys)
@@ -308,8 +312,9 @@ def extract_runs(keys, minrun_: int = 0):
     bounds = torch.empty(cap + 1, dtype=torch.int32, device=keys.device)
     nr = torch.zeros(1, dtype=torch.int64, device=keys.device)
     ws = _workspace(sort_workspace_size(n, kt, False), keys.device)
-    _check(lib.vmps_extract_runs(_ptr(keys), n, kt, minrun_, _ptr(bounds), _ptr(nr), _ptr(ws), ws.numel(),
-                                 _stream(keys.device)), "vmps_extract_runs")
+    fn = lib.vmps_extract_runs_desc if desc else lib.vmps_extract_runs
+    _check(fn(_ptr(keys), n, kt, minrun_, _ptr(bounds), _ptr(nr), _ptr(ws), ws.numel(), _stream(keys.device)),
+           "vmps_extract_runs")
     r = int(nr.item())
     return bounds[: r + 1], r
 

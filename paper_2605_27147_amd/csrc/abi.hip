@@ -204,7 +204,7 @@ vmps_status check_sort_args(void* keys, uint32_t* values, int64_t n, vmps_dtype 
 {
     vmps_status st = check_keys(keys, n, kt);
     if (st != VMPS_OK) return st;
-    if (flags & ~VMPS_VALUES_IOTA) return VMPS_ERR_INVALID_ARG;
+    if (flags & ~(VMPS_VALUES_IOTA | VMPS_DESCENDING_RUNS)) return VMPS_ERR_INVALID_ARG;
     if ((flags & VMPS_VALUES_IOTA) && !values && n > 0) return VMPS_ERR_INVALID_ARG;
     if (values && ((uintptr_t)values & 3)) return VMPS_ERR_INVALID_ARG;
     if (values && n > 0 && ranges_overlap(keys, key_bytes(kt) * n, values, 4 * (size_t)n)) return VMPS_ERR_INVALID_ARG;
@@ -232,6 +232,7 @@ vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtyp
     const uint32_t T = tilesort_capacity(kb, has_values);
     plan_carve(P, w + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values));
     P.big_min = T;
+    P.desc = (flags & VMPS_DESCENDING_RUNS) ? 1u : 0u;
     return guarded([&]() -> hipError_t {
         if ((uint64_t)n <= T) {
             k_single_segment<<<1, 1, 0, s>>>(P.inst_start, (uint32_t)n, P.segs, P.counters);
@@ -282,8 +283,25 @@ vmps_status vmps_merge(const void* a, const uint32_t* va, int64_t na, const void
     });
 }
 
+static vmps_status extract_runs_impl(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun,
+                                     uint32_t* run_bounds, int64_t* num_runs, void* ws, size_t ws_bytes,
+                                     void* stream, bool desc);
+
 vmps_status vmps_extract_runs(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun, uint32_t* run_bounds,
                               int64_t* num_runs, void* ws, size_t ws_bytes, void* stream)
+{
+    return extract_runs_impl(keys, n, kt, minrun, run_bounds, num_runs, ws, ws_bytes, stream, false);
+}
+
+vmps_status vmps_extract_runs_desc(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun, uint32_t* run_bounds,
+                                   int64_t* num_runs, void* ws, size_t ws_bytes, void* stream)
+{
+    return extract_runs_impl(keys, n, kt, minrun, run_bounds, num_runs, ws, ws_bytes, stream, true);
+}
+
+static vmps_status extract_runs_impl(const void* keys, int64_t n, vmps_dtype kt, int32_t minrun,
+                                     uint32_t* run_bounds, int64_t* num_runs, void* ws, size_t ws_bytes,
+                                     void* stream, bool desc)
 {
     vmps_status st = check_keys(keys, n, kt);
     if (st != VMPS_OK) return st;
@@ -305,6 +323,7 @@ vmps_status vmps_extract_runs(const void* keys, int64_t n, vmps_dtype kt, int32_
     Plan P;
     plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, tilesort_capacity(kb, 0), merge_tile_out(kb, 0));
     P.big_min = 0;
+    P.desc = desc ? 1u : 0u;
     return guarded([&]() -> hipError_t {
         VMPS_HIP(plan_enqueue(P, keys, kb, minrun > 0 ? (uint32_t)minrun : 0u, s));
         const uint64_t cap = (uint64_t)vmps_max_runs(n, minrun);

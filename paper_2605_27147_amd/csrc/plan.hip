@@ -170,11 +170,12 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
                                                 const uint32_t* __restrict__ tile_inst,
                                                 const uint32_t* __restrict__ tile_big,
                                                 uint64_t* __restrict__ bitmap,
-                                                uint32_t* __restrict__ tile_first)
+                                                uint32_t* __restrict__ tile_first,
+                                                uint32_t* __restrict__ tile_first0)
 {
     constexpr int WPW = (int)(BITMAP_TILE / 64 / 4);  // words per wave
     constexpr uint32_t IW = 255;                     // instances staged in LDS
-    __shared__ uint32_t s_first[4];
+    __shared__ uint32_t s_first[4], s_first0[4];
     __shared__ uint32_t s_start[IW + 1];
     __shared__ uint32_t s_big[IW];
     const uint32_t tile = blockIdx.x;
@@ -185,6 +186,7 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
         // every position is a boundary
         if (lane < WPW) bitmap[(uint64_t)tile * 64 + wave + 4 * lane] = ~0ull;
         if (threadIdx.x == 0) tile_first[tile] = (uint32_t)base;
+        if (threadIdx.x == 0 && tile_first0) tile_first0[tile] = NONE;
         return;
     }
     // instances overlapping the tile, from the one holding its first position
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
         y[j] = load[j] ? keys[p] : K(0);
         x0[j] = (lane == 0 && cmp[j]) ? keys[p - 1] : K(0);
     }
-    uint32_t first = NONE;
+    uint32_t first = NONE, first0 = NONE;
 #pragma unroll
     for (int j = 0; j < WPW; ++j) {
         const int w = wave + 4 * j;
@@ -243,13 +245,17 @@ __global__ __launch_bounds__(256) void k_bitmap(const K* __restrict__ keys, uint
         const uint64_t word = __ballot(bit);
         if (lane == 0) bitmap[(uint64_t)tile * 64 + w] = word;
         if (word && first == NONE) first = (uint32_t)(base + (uint64_t)w * 64 + ffs64(word));
+        // positions that end a strictly decreasing run: compared, not a descent
+        const uint64_t word0 = __ballot(cmp[j] && !(x > y[j]));
+        if (word0 && first0 == NONE) first0 = (uint32_t)(base + (uint64_t)w * 64 + ffs64(word0));
     }
-    if (lane == 0) s_first[wave] = first;
+    if (lane == 0) { s_first[wave] = first; s_first0[wave] = first0; }
     __syncthreads();
     if (threadIdx.x == 0) {
-        uint32_t m = s_first[0];
-        for (int w = 1; w < 4; ++w) m = min(m, s_first[w]);
+        uint32_t m = s_first[0], m0 = s_first0[0];
+        for (int w = 1; w < 4; ++w) { m = min(m, s_first[w]); m0 = min(m0, s_first0[w]); }
         tile_first[tile] = m;
+        if (tile_first0) tile_first0[tile] = m0;
     }
 }
 
@@ -304,11 +310,32 @@ __global__ __launch_bounds__(1024) void k_suffix_min(const uint32_t* __restrict_
     }
 }
 
+// Run-start candidates of a word: bits of `ends` (positions that end a run of
+// the kind) whose next `span` positions hold no such end; the window past
+// the word reads as "no end", so the last starts of a word stay candidates.
+__device__ inline uint64_t run_start_candidates(uint64_t starts, uint64_t ends, uint32_t span)
+{
+    uint64_t o = span ? ends >> 1 : 0ull;
+    uint32_t covered = 1;
+    while (span && 2 * covered <= span) {
+        o |= o >> covered;
+        covered *= 2;
+    }
+    if (covered < span) o |= o >> (span - covered);
+    return starts & ~o;
+}
+
 // Long natural runs: count (EMIT=false) or write (EMIT=true).  One wave
-// per bitmap tile, one lane per 64-bit word.
+// per bitmap tile, one lane per 64-bit word.  Maximal non-decreasing runs
+// start at a set bit (a descent, an instance head) and end at the next one.
+// With tile_next0 (descending runs, one instance): maximal strictly
+// decreasing runs start at a clear bit or at position 0, hold only set bits
+// after their start and end at the next clear bit (or n); both kinds go to
+// one list in position order.
 template <bool EMIT>
 __global__ __launch_bounds__(64) void k_long_runs(const uint64_t* __restrict__ bitmap, uint32_t n,
                                                   const uint32_t* __restrict__ tile_next,
+                                                  const uint32_t* __restrict__ tile_next0,
                                                   const uint32_t* __restrict__ inst_start,
                                                   const uint32_t* __restrict__ inst_big, uint32_t k,
                                                   uint32_t ell_ovr, uint32_t cand_min, uint32_t lr_cap,
@@ -322,52 +349,59 @@ __global__ __launch_bounds__(64) void k_long_runs(const uint64_t* __restrict__ b
     const uint64_t w = (uint64_t)tile * 64 + lane;
     const uint64_t word = bitmap[w];
     const uint64_t p0 = w * 64;
-    // a word holds at most 4 starts of runs of length >= 16
+    // a word holds at most 4 starts of increasing runs of length >= 16, and
+    // with descending runs at most 4 more
+    constexpr int CAP = 8;
     uint32_t cnt = 0;
-    uint32_t ru[4] = {0, 0, 0, 0}, re[4] = {0, 0, 0, 0}, ri[4] = {0, 0, 0, 0};
-    // a run of length >= cand_min starting at bit b has no boundary in
-    // (b, b + cand_min): only such bits are examined (bits of the window past
-    // the word read as 0, so the last starts of a word stay candidates)
+    uint32_t ru[CAP] = {}, re[CAP] = {}, ri[CAP] = {};
+    // a run of length >= cand_min starting at bit b has no end in
+    // (b, b + cand_min)
     const uint32_t span = (cand_min < 33u ? (cand_min > 0u ? cand_min : 1u) : 33u) - 1u;
-    uint64_t o = span ? word >> 1 : 0ull;
-    uint32_t covered = 1;
-    while (span && 2 * covered <= span) {
-        o |= o >> covered;
-        covered *= 2;
-    }
-    if (covered < span) o |= o >> (span - covered);
-    uint64_t bits = word & ~o;
-    while (bits) {
-        const int b = ffs64(bits);
-        bits &= bits - 1;
-        const uint64_t u = p0 + b;
-        if (u >= n) break;
-        const uint64_t above = (b == 63) ? 0ull : ((word >> (b + 1)) << (b + 1));
-        uint64_t next;
-        if (above) {
-            next = p0 + ffs64(above);
-        } else {
-            next = NONE;
-            for (uint64_t ww = w + 1; ww < (uint64_t)(tile + 1) * 64; ++ww) {
-                const uint64_t x = bitmap[ww];
-                if (x) { next = ww * 64 + ffs64(x); break; }
+    for (int kind = 0; kind < (tile_next0 ? 2 : 1); ++kind) {
+        const uint64_t ends = kind == 0 ? word : ~word;
+        const uint64_t starts = kind == 0 ? word : (~word | (p0 == 0 ? 1ull : 0ull));
+        uint64_t bits = run_start_candidates(starts, ends, span);
+        while (bits) {
+            const int b = ffs64(bits);
+            bits &= bits - 1;
+            const uint64_t u = p0 + b;
+            if (u >= n) break;
+            const uint64_t above = (b == 63) ? 0ull : ((ends >> (b + 1)) << (b + 1));
+            uint64_t next;
+            if (above) {
+                next = p0 + ffs64(above);
+            } else {
+                next = NONE;
+                for (uint64_t ww = w + 1; ww < (uint64_t)(tile + 1) * 64; ++ww) {
+                    const uint64_t x = kind == 0 ? bitmap[ww] : ~bitmap[ww];
+                    if (x) { next = ww * 64 + ffs64(x); break; }
+                }
+                if (next == NONE) next = kind == 0 ? tile_next[tile] : tile_next0[tile];
             }
-            if (next == NONE) next = tile_next[tile];
+            if (next > n) next = n;
+            if (next - u < cand_min) continue;
+            const uint32_t inst = k > 1 ? inst_of(inst_start, k, (uint32_t)u) : 0;
+            if (!inst_big[inst]) continue;
+            if (next - u < inst_ell(inst_start, inst, ell_ovr)) continue;
+            if (cnt < CAP) {
+                // keep the lane's runs in position order
+                uint32_t at = cnt;
+                while (at > 0 && ru[at - 1] > (uint32_t)u) {
+                    ru[at] = ru[at - 1]; re[at] = re[at - 1]; ri[at] = ri[at - 1];
+                    --at;
+                }
+                ru[at] = (uint32_t)u; re[at] = (uint32_t)next; ri[at] = inst;
+            }
+            ++cnt;
         }
-        if (next > n) next = n;
-        if (next - u < cand_min) continue;
-        const uint32_t inst = k > 1 ? inst_of(inst_start, k, (uint32_t)u) : 0;
-        if (!inst_big[inst]) continue;
-        if (next - u < inst_ell(inst_start, inst, ell_ovr)) continue;
-        if (cnt < 4) { ru[cnt] = (uint32_t)u; re[cnt] = (uint32_t)next; ri[cnt] = inst; }
-        ++cnt;
     }
+    if (cnt > CAP) cnt = CAP;
     const uint32_t inc = wave_incl_scan(cnt);
     if (!EMIT) {
         if (lane == 63) tile_cnt[tile] = inc;
     } else {
         uint32_t o = tile_off[tile] + inc - cnt;
-        for (uint32_t c = 0; c < cnt && c < 4 && o + c < lr_cap; ++c) {
+        for (uint32_t c = 0; c < cnt && o + c < lr_cap; ++c) {
             lr_u[o + c] = ru[c];
             lr_e[o + c] = re[c];
             lr_inst[o + c] = ri[c];
@@ -883,7 +917,9 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.n_tiles_out = (uint32_t)ceil_div(n ? n : 1, T_out);
     // runs are at least 16 long (explicit minrun >= 16, rule >= 32) except
     // the last of each instance
-    P.lr_cap = (uint32_t)(n / 16 + 2);
+    // long runs are >= 16 long; an increasing and a decreasing one share at
+    // most one element
+    P.lr_cap = (uint32_t)(n / 15 + 3);
     P.run_cap = (uint32_t)(n / 16 + k + 2);
     P.ent_cap = P.lr_cap + (uint32_t)k + 1;
     P.seg_cap = P.run_cap + (uint32_t)k + 1;
@@ -899,6 +935,9 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.bitmap = c.take<uint64_t>(P.bm_words);
     P.tile_first = c.take<uint32_t>(P.bm_tiles);
     P.tile_next = c.take<uint32_t>(P.bm_tiles);
+    P.tile_first0 = c.take<uint32_t>(P.bm_tiles);
+    P.tile_next0 = c.take<uint32_t>(P.bm_tiles);
+    P.desc = 0;
     P.tile_cnt = c.take<uint32_t>(P.bm_tiles);
     P.tile_off = c.take<uint32_t>(P.bm_tiles);
     P.lr_u = c.take<uint32_t>(P.lr_cap);
@@ -1000,17 +1039,21 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     k_zero_stats<<<1, 64, 0, s>>>(P.stats);
     VMPS_HIP(scan_exclusive_u32(P.inst_big, P.inst_bigrank, k, nullptr, C + CNT_NBIG, P.scan_tmp, s));
     // 1. bitmap
+    const bool desc = P.desc && k == 1;
     k_bitmap<K><<<P.bm_tiles, 256, 0, s>>>(keys, n, P.inst_start, P.inst_big, k, P.tile_off, P.tile_cnt,
-                                           P.bitmap, P.tile_first);
+                                           P.bitmap, P.tile_first, desc ? P.tile_first0 : nullptr);
     k_suffix_min<<<1, 1024, 0, s>>>(P.tile_first, P.tile_next, P.bm_tiles);
+    if (desc) k_suffix_min<<<1, 1024, 0, s>>>(P.tile_first0, P.tile_next0, P.bm_tiles);
     // 2. long natural runs
     const uint32_t cand_min = (k == 1) ? (ell_ovr ? ell_ovr : minrun_of(n)) : 32u;
-    k_long_runs<false><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, P.inst_start, P.inst_big, k, ell_ovr,
-                                                 cand_min, P.lr_cap, P.tile_cnt, nullptr, nullptr, nullptr, nullptr);
+    k_long_runs<false><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, desc ? P.tile_next0 : nullptr,
+                                                 P.inst_start, P.inst_big, k, ell_ovr, cand_min, P.lr_cap, P.tile_cnt,
+                                                 nullptr, nullptr, nullptr, nullptr);
     VMPS_HIP(scan_exclusive_u32(P.tile_cnt, P.tile_off, P.bm_tiles, nullptr, C + CNT_NLONG, P.scan_tmp, s));
     k_clamp<<<1, 64, 0, s>>>(C, CNT_NLONG, P.lr_cap);
-    k_long_runs<true><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, P.inst_start, P.inst_big, k, ell_ovr,
-                                                cand_min, P.lr_cap, nullptr, P.tile_off, P.lr_u, P.lr_e, P.lr_inst);
+    k_long_runs<true><<<P.bm_tiles, 64, 0, s>>>(P.bitmap, n, P.tile_next, desc ? P.tile_next0 : nullptr,
+                                                P.inst_start, P.inst_big, k, ell_ovr, cand_min, P.lr_cap, nullptr,
+                                                P.tile_off, P.lr_u, P.lr_e, P.lr_inst);
     // 3. chain of run starts
     k_chain_blocks<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C,
                                                  P.chain_val, P.chain_known);

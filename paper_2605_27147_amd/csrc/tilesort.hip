@@ -609,7 +609,7 @@ struct TileLds {
 // powers, node lists, the forced runs' sort and the merges.
 template <typename KT, int NT, int TCAP, int VMODE, int LAY>
 __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restrict__ SV, const TileLds& T,
-                                          uint32_t len, uint32_t ell, uint32_t g, uint32_t il, int tid)
+                                          uint32_t len, uint32_t ell, uint32_t g, uint32_t il, int tid, bool desc)
 {
     using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
@@ -640,47 +640,58 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     }
     __syncthreads();
 
-    // 3. long natural runs (length >= minrun), one thread per word
-    uint32_t cnt = 0, lu0 = 0, le0 = 0, lu1 = 0, le1 = 0;
+    // 3. long natural runs (length >= minrun), one thread per word: maximal
+    // non-decreasing runs start at a set bit and end at the next one; with
+    // desc, maximal strictly decreasing runs start at a clear bit (or 0),
+    // hold set bits only and end at the next clear bit (or len)
+    constexpr int LRW = 4;  // runs of >= 32 elements, overlapping by at most one: at most 3 start in a word
+    uint32_t cnt = 0, lu[LRW] = {}, le[LRW] = {};
     if ((uint32_t)tid < W) {
         const uint64_t word = bm[tid];
         const uint32_t p0 = tid * 64;
-        // a long run starting at bit b has no boundary in (b, b+31]:
-        // only such bits are examined
-        uint64_t o = word >> 1;
-        o |= o >> 1;
-        o |= o >> 2;
-        o |= o >> 4;
-        o |= o >> 8;
-        o |= o >> 15;
-        uint64_t bits = word & ~o;
-        while (bits) {
-            const int b = ffs64(bits);
-            bits &= bits - 1;
-            const uint32_t u = p0 + b;
-            if (u >= len) break;
-            const uint64_t above = (b == 63) ? 0ull : ((word >> (b + 1)) << (b + 1));
-            uint32_t next = len;
-            if (above) {
-                next = p0 + ffs64(above);
-            } else {
-                for (uint32_t ww = tid + 1; ww < W; ++ww) {
-                    const uint64_t x = bm[ww];
-                    if (x) { next = ww * 64 + ffs64(x); break; }
+        for (int kind = 0; kind < (desc ? 2 : 1); ++kind) {
+            const uint64_t ends = kind == 0 ? word : ~word;
+            const uint64_t starts = kind == 0 ? word : (~word | (p0 == 0 ? 1ull : 0ull));
+            // a long run starting at bit b has no end in (b, b+31]: only such
+            // bits are examined
+            uint64_t o = ends >> 1;
+            o |= o >> 1;
+            o |= o >> 2;
+            o |= o >> 4;
+            o |= o >> 8;
+            o |= o >> 15;
+            uint64_t bits = starts & ~o;
+            while (bits) {
+                const int b = ffs64(bits);
+                bits &= bits - 1;
+                const uint32_t u = p0 + b;
+                if (u >= len) break;
+                const uint64_t above = (b == 63) ? 0ull : ((ends >> (b + 1)) << (b + 1));
+                uint32_t next = len;
+                if (above) {
+                    next = p0 + ffs64(above);
+                } else {
+                    for (uint32_t ww = tid + 1; ww < W; ++ww) {
+                        const uint64_t x = kind == 0 ? bm[ww] : ~bm[ww];
+                        if (x) { next = ww * 64 + ffs64(x); break; }
+                    }
                 }
-            }
-            if (next > len) next = len;
-            if (next - u >= ell) {
-                if (cnt == 0) { lu0 = u; le0 = next; } else { lu1 = u; le1 = next; }
-                ++cnt;
+                if (next > len) next = len;
+                if (next - u >= ell && cnt < (uint32_t)LRW) {
+                    uint32_t at = cnt;  // position order
+                    while (at > 0 && lu[at - 1] > u) { lu[at] = lu[at - 1]; le[at] = le[at - 1]; --at; }
+                    lu[at] = u;
+                    le[at] = next;
+                    ++cnt;
+                }
             }
         }
     }
-    if (cnt > 2) cnt = 2;  // runs of >= 32 elements: at most two start in a word
     uint32_t nlr;
     const uint32_t lro = block_excl_scan(cnt, scan_lds, &nlr);
-    if (cnt > 0) { LRu[lro] = lu0; LRe[lro] = le0; }
-    if (cnt > 1) { LRu[lro + 1] = lu1; LRe[lro + 1] = le1; }
+#pragma unroll
+    for (int c = 0; c < LRW; ++c)
+        if ((uint32_t)c < cnt) { LRu[lro + c] = lu[c]; LRe[lro + c] = le[c]; }
     __syncthreads();
 
     // 4. chain of run starts: progressions of step minrun between jumps
@@ -722,17 +733,24 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     uint32_t unsorted_max = 0, pmask = 0;
     for (uint32_t t = tid; t < kr; t += NT) {
         const uint32_t s = RS[t], e = RS[t + 1];
-        bool sorted = true;  // no descent strictly inside (s, e)
+        bool sorted = true;     // no descent strictly inside (s, e)
+        bool reversed = desc && s + 1 < e;  // with desc: only descents inside (s, e)
         if (s + 1 < e) {
             for (uint32_t w = (s + 1) >> 6; w <= ((e - 1) >> 6); ++w) {
-                uint64_t word = bm[w];
                 const uint32_t base = w * 64;
-                if (s + 1 > base) word &= ~0ull << (s + 1 - base);
-                if (e - base < 64) word &= (1ull << (e - base)) - 1;
-                if (word) { sorted = false; break; }
+                uint64_t m = ~0ull;
+                if (s + 1 > base) m &= ~0ull << (s + 1 - base);
+                if (e - base < 64) m &= (1ull << (e - base)) - 1;
+                const uint64_t word = bm[w] & m;
+                if (word) sorted = false;
+                if (word != m) reversed = false;
+                if (!sorted && !reversed) break;
             }
         }
-        SR[t] = sorted ? 1 : 0;
+        // 1: already sorted; 2: strictly decreasing, reversed below, then
+        // sorted (no equal keys inside, so the reversal is its stable sort)
+        sorted = sorted || reversed;
+        SR[t] = reversed ? 2 : (sorted ? 1 : 0);
         if (!sorted) unsorted_max = max(unsorted_max, e - s);
         const uint64_t s2 = 2ull * g + s + e;
         Qv[t] = (uint32_t)((s2 << 31) / il);
@@ -804,6 +822,25 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     }
     __syncthreads();
 
+    // 6b. with desc: reverse the strictly decreasing runs in place
+    if (desc) {
+        for (uint32_t t = 0; t < kr; ++t) {
+            if (SR[t] != 2) continue;  // the same for every thread
+            const uint32_t s = RS[t], e = RS[t + 1];
+            for (uint32_t i = tid; i < (e - s) / 2; i += NT) {
+                const uint32_t pa = pxp<LAY>(s + i), pb = pxp<LAY>(e - 1 - i);
+                const KT ka = S[pa];
+                S[pa] = S[pb];
+                S[pb] = ka;
+                if (VMODE) {
+                    const uint32_t va = SV[pa];
+                    SV[pa] = SV[pb];
+                    SV[pb] = va;
+                }
+            }
+            __syncthreads();
+        }
+    }
     // 7./8. forced runs, then the merges of Algorithm 1
     const uint32_t maxf = scal[3], mask = scal[2];
     // 7a. the first bottom-up levels of every forced run: chunks of 2^CWL
@@ -845,7 +882,7 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
 template <typename K, int NT, int TCAP, int VMODE, bool NARROW>
 __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
                                              uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
-                                             const Seg sg, const uint32_t* __restrict__ inst_start)
+                                             const Seg sg, const uint32_t* __restrict__ inst_start, bool desc)
 {
     using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
@@ -882,7 +919,30 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     const uint32_t len = sg.end - sg.start;
     if (len == 0) return;
     if (len > TCAP) {
-        // a single natural run longer than the tile: already sorted
+        // a single natural run longer than the tile: already sorted, or
+        // (with desc) strictly decreasing, which its first two keys tell
+        if (desc && keysA[a] > keysA[a + 1]) {
+            // reversed: position i takes element len - 1 - i (in place, or
+            // into B); values follow, iota values are the source positions
+            const uint32_t half = sg.dst == 1 ? len : len / 2;
+            for (uint32_t i = tid; i < half; i += NT) {
+                const uint32_t j = len - 1 - i;
+                const K ki = keysA[a + i], kj = keysA[a + j];
+                uint32_t vi = 0, vj = 0;
+                if (VMODE == 1) { vi = valsA[a + i]; vj = valsA[a + j]; }
+                if (VMODE == 2) { vi = a + i; vj = a + j; }
+                if (sg.dst == 1) {
+                    keysB[a + i] = kj;
+                    if (VMODE) valsB[a + i] = vj;
+                } else {
+                    keysA[a + i] = kj;
+                    keysA[a + j] = ki;
+                    if (VMODE) { valsA[a + i] = vj; valsA[a + j] = vi; }
+                }
+            }
+            if (VMODE == 2 && sg.dst != 1 && (len & 1) && tid == 0) valsA[a + len / 2] = a + len / 2;
+            return;
+        }
         if (sg.dst == 1) {
             for (uint32_t i = tid; i < len; i += NT) {
                 keysB[a + i] = keysA[a + i];
@@ -918,7 +978,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     asm volatile("" : "+v"(tid_st));
     if constexpr (NARROW) {
         if (narrow) {
-            tile_body<uint32_t, NT, TCAP, VMODE, 2>((uint32_t*)S, SV, T, len, ell, g, il, tid);
+            tile_body<uint32_t, NT, TCAP, VMODE, 2>((uint32_t*)S, SV, T, len, ell, g, il, tid, desc);
             asm volatile("" : "+v"(tid_st));
             tile_store<uint32_t, K, NT, TCAP, VMODE, 2>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
                                                     sg.dst ? valsB : valsA, a, len, tid_st, kmin);
@@ -926,7 +986,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
             return;
         }
     }
-    tile_body<K, NT, TCAP, VMODE, 1>(S, SV, T, len, ell, g, il, tid);
+    tile_body<K, NT, TCAP, VMODE, 1>(S, SV, T, len, ell, g, il, tid, desc);
     asm volatile("" : "+v"(tid_st));
     tile_store<K, K, NT, TCAP, VMODE, 1>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
     __syncthreads();
@@ -946,7 +1006,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
                                                        uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
                                                        const Seg* __restrict__ segs, uint32_t* __restrict__ counters,
                                                        const uint32_t* __restrict__ inst_start,
-                                                       uint32_t len_lo, uint32_t len_hi, int ticket)
+                                                       uint32_t len_lo, uint32_t len_hi, int ticket, int desc)
 {
     // segments of length in (len_lo, len_hi] only, so that two launches of
     // different workgroup sizes can share one segment list (each with its
@@ -970,7 +1030,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
             const Seg sg = segs[si];
             const uint32_t len = sg.end - sg.start;
             if (len <= len_lo || len > len_hi) continue;
-            tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start);
+            tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start, desc != 0);
         }
     }
 }
@@ -1003,7 +1063,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
     kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
-                                                     P.inst_start, len_lo, len_hi, ticket);
+                                                     P.inst_start, len_lo, len_hi, ticket, (int)P.desc);
     return hipGetLastError();
 }
 

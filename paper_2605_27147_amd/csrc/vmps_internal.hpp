@@ -101,6 +101,11 @@ struct Plan {
     uint64_t* bitmap;              // bm_words
     uint32_t* tile_first;          // bm_tiles
     uint32_t* tile_next;           // bm_tiles
+    // descending runs (vmps_sort with VMPS_DESCENDING_RUNS, one instance):
+    // first position that is not a descent, per bitmap tile, and after it
+    uint32_t desc;                 // 0 or 1
+    uint32_t* tile_first0;         // bm_tiles
+    uint32_t* tile_next0;          // bm_tiles
     uint32_t* tile_cnt;            // bm_tiles
     uint32_t* tile_off;            // bm_tiles
     uint32_t* lr_u;                // lr_cap

@@ -41,7 +41,7 @@ def test_host_side_entry_points_without_gpu():
     assert lib.vmps_sort_workspace_size(1 << 32, 1, 0, ctypes.byref(sz)) == vm.INVALID_ARG
     # argument errors are reported before any device work
     assert lib.vmps_sort(None, None, 5, 0, 0, None, 0, None) == vm.INVALID_ARG
-    assert lib.vmps_sort(ctypes.c_void_p(16), None, 5, 0, 2, None, 0, None) == vm.INVALID_ARG
+    assert lib.vmps_sort(ctypes.c_void_p(16), None, 5, 0, 4, None, 0, None) == vm.INVALID_ARG  # unknown flag
     assert lib.vmps_sort(ctypes.c_void_p(16), None, 100, 0, 0, None, 0, None) == vm.WORKSPACE_TOO_SMALL
     assert lib.vmps_sort(ctypes.c_void_p(18), None, 100, 1, 0, None, 0, None) == vm.INVALID_ARG  # misaligned
     assert lib.vmps_sort(ctypes.c_void_p(16), ctypes.c_void_p(20), 100, 0, 0, None, 0, None) == vm.INVALID_ARG

@@ -30,7 +30,16 @@ DESC_RUNS = 4  # flag or-ed into a variant: strictly decreasing runs are reverse
 class Stats(ctypes.Structure):
     _fields_ = [(name, ctypes.c_int64) for name in (
         "n", "runs", "merges", "merge_cost", "max_stack", "cmp_run", "cmp_ins",
-        "cmp_merge", "mov_ins", "mov_push", "mov_merge")] + [("entropy", ctypes.c_double), ("mov_rev", ctypes.c_int64)]
+        "cmp_merge", "mov_ins", "mov_push", "mov_merge")] + [("entropy", ctypes.c_double), ("mov_rev", ctypes.c_int64),
+                                                               ("mov_copy", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+class VmStats(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_int64) for name in (
+        "page", "input_pages", "extra_pages", "meta_words", "max_buffers")]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -68,6 +77,11 @@ def _L():
         lib.orc_run_powers.argtypes = [vp, i64, i64, vp]
         lib.orc_powersort.restype = ctypes.c_int
         lib.orc_powersort.argtypes = [vp, vp, i64, i32, ctypes.c_int, ctypes.POINTER(Stats), vp, i64]
+        lib.orc_vm_powersort.restype = ctypes.c_int
+        lib.orc_vm_powersort.argtypes = [vp, vp, i64, i32, i64, ctypes.c_int, ctypes.POINTER(Stats),
+                                         ctypes.POINTER(VmStats), vp, i64]
+        lib.orc_vm_page.restype = i64
+        lib.orc_vm_page.argtypes = [i64, i32]
         lib.orc_segmented_powersort.restype = ctypes.c_int
         lib.orc_segmented_powersort.argtypes = [vp, vp, vp, i64, i32, ctypes.c_int]
         lib.orc_standard_merge.restype = None
@@ -177,6 +191,29 @@ def powersort(keys, vals=None, variant: int = PINGPONG, ell: int = 0, log_merges
     out = x.astype(orig.dtype) if orig.dtype in (np.uint32, np.int32) else x.view(orig.dtype) if orig.dtype == np.int64 else x
     merges = log[: 3 * st.merges].reshape(-1, 3).copy() if log_merges else None
     return out, v, st.as_dict(), merges
+
+
+def vm_page(n: int, rec_words: int) -> int:
+    return int(_L().orc_vm_page(n, rec_words))
+
+
+def vm_powersort(keys, vals=None, page: int = 0, ell: int = 0, desc: bool = False, log_merges: bool = False):
+    """Virtual-Memory Powersort (Section 4) on a copy: (keys, vals, stats,
+    vm_stats, merge_log)."""
+    orig = np.asarray(keys)
+    x = _keys64(orig).copy()
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    n = x.size
+    st, vst = Stats(), VmStats()
+    cap = n if log_merges else 0
+    log = np.zeros(3 * max(cap, 1), dtype=np.int64)
+    rc = _L().orc_vm_powersort(_p(x), _p(v), n, ell, page, DESC_RUNS if desc else 0, ctypes.byref(st),
+                               ctypes.byref(vst), _p(log) if log_merges else None, cap)
+    if rc != 0:
+        raise RuntimeError("oracle vm powersort failed")
+    out = x.astype(orig.dtype) if orig.dtype in (np.uint32, np.int32) else x
+    merges = log[: 3 * st.merges].reshape(-1, 3).copy() if log_merges else None
+    return out, v, st.as_dict(), vst.as_dict(), merges
 
 
 def segmented_powersort(keys, offsets, vals=None, variant: int = PINGPONG, ell: int = 0):

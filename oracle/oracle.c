@@ -755,3 +755,354 @@ double orc_cdf_train(const double* u, int64_t m, int32_t H, int32_t steps, int32
 {
     return orc_cdf_train2(u, m, H, steps, nb, lr, params, NULL);
 }
+
+/* ------------------------------------------------------------------ */
+/* Virtual-Memory Powersort (Section 4).                                */
+/* Memory is cut into pages of P elements: the input array's pages and  */
+/* extra pages appended on demand.  A buffer is a list of pages whose   */
+/* concatenation, from an offset into its first page, holds its         */
+/* elements in order; every page but the first and the last is full.   */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int64_t* pages;  /* physical page ids */
+    int64_t npages, cap;
+    int64_t head;    /* offset of the first element inside pages[0] */
+    int64_t len;     /* elements */
+} vm_buffer;
+
+typedef struct {
+    uint64_t* key;     /* memory: input pages first, then extra pages */
+    uint32_t* val;     /* NULL when sorting keys only */
+    int64_t P, n;
+    int64_t input_pages, npages_total, cap_pages;
+    int64_t* free_list;
+    int64_t nfree, free_cap;
+    int64_t live_meta, live_buffers;
+    orc_stats* st;
+    orc_vm_stats* vst;
+    int failed;
+} vm_mem;
+
+static int64_t vm_log2_ceil(int64_t n)
+{
+    int64_t l = 0;
+    while (((int64_t)1 << l) < n) ++l;
+    return l;
+}
+
+int64_t orc_vm_page(int64_t n, int32_t rec_words)
+{
+    if (n < 2) return 1;
+    const double t = rec_words > 0 ? (double)rec_words : 1.0;
+    const double target = sqrt((double)n / (t * (double)vm_log2_ceil(n)));
+    int64_t p = 1;
+    while ((double)(2 * p) <= target) p *= 2;
+    return p;
+}
+
+static void vm_note_meta(vm_mem* m)
+{
+    const int64_t words = m->live_meta + m->nfree;
+    if (words > m->vst->meta_words) m->vst->meta_words = words;
+    if (m->live_buffers > m->vst->max_buffers) m->vst->max_buffers = m->live_buffers;
+    const int64_t extra = m->npages_total - m->input_pages;
+    if (extra > m->vst->extra_pages) m->vst->extra_pages = extra;
+}
+
+static int64_t vm_new_page(vm_mem* m)
+{
+    if (m->nfree > 0) return m->free_list[--m->nfree];
+    if (m->npages_total == m->cap_pages) {
+        /* grow the memory by whole pages (the extra pages of Section 4) */
+        int64_t cap = m->cap_pages * 2 + 4;
+        uint64_t* k = (uint64_t*)realloc(m->key, sizeof(uint64_t) * (size_t)(cap * m->P));
+        if (!k) { m->failed = 1; return 0; }
+        m->key = k;
+        if (m->val) {
+            uint32_t* v = (uint32_t*)realloc(m->val, sizeof(uint32_t) * (size_t)(cap * m->P));
+            if (!v) { m->failed = 1; return 0; }
+            m->val = v;
+        }
+        m->cap_pages = cap;
+    }
+    const int64_t p = m->npages_total++;
+    vm_note_meta(m);
+    return p;
+}
+
+static void vm_free_page(vm_mem* m, int64_t p)
+{
+    /* the input's last page, when partial, is never handed out again */
+    if (p == m->input_pages - 1 && m->n % m->P) return;
+    if (m->nfree == m->free_cap) {
+        m->free_cap = m->free_cap * 2 + 16;
+        int64_t* f = (int64_t*)realloc(m->free_list, sizeof(int64_t) * (size_t)m->free_cap);
+        if (!f) { m->failed = 1; return; }
+        m->free_list = f;
+    }
+    m->free_list[m->nfree++] = p;
+    vm_note_meta(m);
+}
+
+static void vm_buf_init(vm_mem* m, vm_buffer* b)
+{
+    b->pages = NULL; b->npages = 0; b->cap = 0; b->head = 0; b->len = 0;
+    m->live_buffers++;
+    vm_note_meta(m);
+}
+
+static void vm_buf_add_page(vm_mem* m, vm_buffer* b, int64_t p)
+{
+    if (b->npages == b->cap) {
+        b->cap = b->cap * 2 + 4;
+        int64_t* q = (int64_t*)realloc(b->pages, sizeof(int64_t) * (size_t)b->cap);
+        if (!q) { m->failed = 1; return; }
+        b->pages = q;
+    }
+    b->pages[b->npages++] = p;
+    m->live_meta++;
+    vm_note_meta(m);
+}
+
+static void vm_buf_done(vm_mem* m, vm_buffer* b)
+{
+    m->live_meta -= b->npages;
+    m->live_buffers--;
+    free(b->pages);
+    b->pages = NULL; b->npages = 0; b->cap = 0; b->len = 0; b->head = 0;
+}
+
+/* PushBack: one element into the buffer's last page (a new page when it is
+ * full). */
+static void vm_push_back(vm_mem* m, vm_buffer* b, uint64_t k, uint32_t v)
+{
+    const int64_t pos = b->head + b->len;
+    if (pos == b->npages * m->P) vm_buf_add_page(m, b, vm_new_page(m));
+    if (m->failed) return;
+    const int64_t at = b->pages[pos / m->P] * m->P + pos % m->P;
+    m->key[at] = k;
+    if (m->val) m->val[at] = v;
+    b->len++;
+}
+
+/* PopFront: drop the first element; a page left empty goes to the free list. */
+static void vm_pop_front(vm_mem* m, vm_buffer* b)
+{
+    b->head++;
+    b->len--;
+    if (b->head == m->P || b->len == 0) {
+        /* the page leaves the buffer's list before it joins the free list */
+        const int64_t p = b->pages[0];
+        memmove(b->pages, b->pages + 1, sizeof(int64_t) * (size_t)(b->npages - 1));
+        b->npages--;
+        m->live_meta--;
+        b->head = 0;
+        vm_free_page(m, p);
+        if (b->len == 0) {
+            /* an emptied buffer gives back every page it still holds */
+            const int64_t k = b->npages;
+            m->live_meta -= k;
+            b->npages = 0;
+            for (int64_t i = 0; i < k; ++i) vm_free_page(m, b->pages[i]);
+        }
+    }
+}
+
+static inline uint64_t vm_front_key(const vm_mem* m, const vm_buffer* b)
+{
+    return m->key[b->pages[0] * m->P + b->head];
+}
+
+static inline uint32_t vm_front_val(const vm_mem* m, const vm_buffer* b)
+{
+    return m->val ? m->val[b->pages[0] * m->P + b->head] : 0u;
+}
+
+/* MergeRuns page by page: StandardMerge's rule (ties to a), consuming a and
+ * b from the front and appending to r (PageMerge of Algorithm 2 in its
+ * simplest form: one element per step, page ends handled by the buffer
+ * operations). */
+static void vm_merge(vm_mem* m, vm_buffer* a, vm_buffer* b, vm_buffer* r)
+{
+    while (a->len > 0 && b->len > 0 && !m->failed) {
+        m->st->cmp_merge++;
+        if (vm_front_key(m, a) <= vm_front_key(m, b)) {
+            vm_push_back(m, r, vm_front_key(m, a), vm_front_val(m, a));
+            vm_pop_front(m, a);
+        } else {
+            vm_push_back(m, r, vm_front_key(m, b), vm_front_val(m, b));
+            vm_pop_front(m, b);
+        }
+        m->st->mov_merge++;
+    }
+    while (a->len > 0 && !m->failed) {
+        vm_push_back(m, r, vm_front_key(m, a), vm_front_val(m, a));
+        vm_pop_front(m, a);
+        m->st->mov_merge++;
+    }
+    while (b->len > 0 && !m->failed) {
+        vm_push_back(m, r, vm_front_key(m, b), vm_front_val(m, b));
+        vm_pop_front(m, b);
+        m->st->mov_merge++;
+    }
+}
+
+/* Copy (Section 4): the final buffer r (head 0) into the input array, page
+ * by page: when input page t is still in use by r at another position, its
+ * contents move to a new page first; then r's page t moves into place.  A
+ * page that receives its final contents leaves the free list (linear scan,
+ * as the paper allows), so no later step hands it out again. */
+static void vm_copy_out(vm_mem* m, vm_buffer* r)
+{
+    const int64_t P = m->P, n = m->n;
+    for (int64_t t = 0; t < r->npages && !m->failed; ++t) {
+        for (int64_t f = 0; f < m->nfree; ++f)
+            if (m->free_list[f] == t) { m->free_list[f] = m->free_list[--m->nfree]; break; }
+        if (r->pages[t] == t) continue;
+        for (int64_t j = t + 1; j < r->npages; ++j) {
+            if (r->pages[j] != t) continue;
+            const int64_t q = vm_new_page(m);
+            if (m->failed) return;
+            const int64_t cnt = (j + 1) * P <= n ? P : n - j * P;
+            for (int64_t i = 0; i < cnt; ++i) {
+                m->key[q * P + i] = m->key[t * P + i];
+                if (m->val) m->val[q * P + i] = m->val[t * P + i];
+                m->st->mov_copy++;
+            }
+            r->pages[j] = q;
+            break;
+        }
+        const int64_t src = r->pages[t];
+        const int64_t cnt = (t + 1) * P <= n ? P : n - t * P;
+        for (int64_t i = 0; i < cnt; ++i) {
+            m->key[t * P + i] = m->key[src * P + i];
+            if (m->val) m->val[t * P + i] = m->val[src * P + i];
+            m->st->mov_copy++;
+        }
+        r->pages[t] = t;
+        vm_free_page(m, src);
+    }
+}
+
+int orc_vm_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun, int64_t page, int desc,
+                     orc_stats* st_out, orc_vm_stats* vst_out, int64_t* merge_log, int64_t log_cap)
+{
+    orc_stats st;
+    orc_vm_stats vst;
+    memset(&st, 0, sizeof st);
+    memset(&vst, 0, sizeof vst);
+    st.n = n;
+    if (n < 0) return -1;
+    const int64_t P = page > 0 ? page : orc_vm_page(n, vals ? 2 : 1);
+    vst.page = P;
+    if (n <= 1) {
+        if (n == 1) st.runs = 1;
+        if (st_out) *st_out = st;
+        if (vst_out) *vst_out = vst;
+        return 0;
+    }
+    int32_t l = minrun > 0 ? minrun : orc_minrun(n);
+    vm_mem m;
+    memset(&m, 0, sizeof m);
+    m.P = P; m.n = n; m.st = &st; m.vst = &vst;
+    m.input_pages = (n + P - 1) / P;
+    m.npages_total = m.input_pages;
+    m.cap_pages = m.input_pages + 4;
+    vst.input_pages = m.input_pages;
+    m.key = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(m.cap_pages * P));
+    m.val = vals ? (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(m.cap_pages * P)) : NULL;
+    vm_buffer* stack = (vm_buffer*)malloc(sizeof(vm_buffer) * 130);
+    int32_t* spow = (int32_t*)malloc(sizeof(int32_t) * 130);
+    int64_t* slo = (int64_t*)malloc(sizeof(int64_t) * 130);
+    if (!m.key || (vals && !m.val) || !stack || !spow || !slo) {
+        free(m.key); free(m.val); free(stack); free(spow); free(slo);
+        return -1;
+    }
+    memcpy(m.key, keys, sizeof(uint64_t) * (size_t)n);
+    if (vals) memcpy(m.val, vals, sizeof(uint32_t) * (size_t)n);
+    /* work: the input's pages, consumed from the front */
+    vm_buffer work;
+    vm_buf_init(&m, &work);
+    for (int64_t p = 0; p < m.input_pages; ++p) vm_buf_add_page(&m, &work, p);
+    work.len = n;
+    int64_t height = 0, nlog = 0, s = 0;
+    double H = 0.0;
+
+#define VM_LOG(I, J, K)                                                       \
+    do {                                                                      \
+        st.merges++;                                                          \
+        st.merge_cost += (K) - (I);                                           \
+        if (merge_log && nlog < log_cap) {                                    \
+            merge_log[3 * nlog] = (I); merge_log[3 * nlog + 1] = (J);         \
+            merge_log[3 * nlog + 2] = (K);                                    \
+        }                                                                     \
+        ++nlog;                                                               \
+    } while (0)
+
+    /* ExtractRun: the run [s, e) is formed where it lies in the input (the
+     * insertion sort of a forced run and the reversal of a decreasing one
+     * act there, on elements work still owns), then moved into a buffer of
+     * its own by PushBack / PopFront */
+    vm_buffer curr, next;
+    int64_t c_lo = 0, c_hi = 0;
+#define VM_EXTRACT(BUF, LO, HI)                                                         \
+    do {                                                                                \
+        (LO) = s;                                                                       \
+        (HI) = extract_run(m.key, m.val, s, n, l, desc, &st, &H);                       \
+        vm_buf_init(&m, &(BUF));                                                        \
+        for (int64_t i = s; i < (HI) && !m.failed; ++i) {                               \
+            vm_push_back(&m, &(BUF), vm_front_key(&m, &work), vm_front_val(&m, &work)); \
+            vm_pop_front(&m, &work);                                                    \
+            st.mov_push++;                                                              \
+        }                                                                               \
+        s = (HI);                                                                       \
+    } while (0)
+
+    VM_EXTRACT(curr, c_lo, c_hi);
+    while (c_hi < n && !m.failed) {
+        int64_t nx_lo = 0, nx_hi = 0;
+        VM_EXTRACT(next, nx_lo, nx_hi);
+        int32_t p = orc_power_def(n, c_lo, c_hi, nx_hi);
+        while (height > 0 && spow[height - 1] >= p && !m.failed) {
+            vm_buffer r;
+            vm_buf_init(&m, &r);
+            VM_LOG(slo[height - 1], c_lo, c_hi);
+            vm_merge(&m, &stack[height - 1], &curr, &r);
+            vm_buf_done(&m, &stack[height - 1]);
+            vm_buf_done(&m, &curr);
+            curr = r;
+            c_lo = slo[height - 1];
+            --height;
+        }
+        stack[height] = curr; spow[height] = p; slo[height] = c_lo;
+        ++height;
+        if (height > st.max_stack) st.max_stack = height;
+        curr = next; c_lo = nx_lo; c_hi = nx_hi;
+    }
+    while (height > 0 && !m.failed) {
+        vm_buffer r;
+        vm_buf_init(&m, &r);
+        VM_LOG(slo[height - 1], c_lo, c_hi);
+        vm_merge(&m, &stack[height - 1], &curr, &r);
+        vm_buf_done(&m, &stack[height - 1]);
+        vm_buf_done(&m, &curr);
+        curr = r;
+        c_lo = slo[height - 1];
+        --height;
+    }
+#undef VM_EXTRACT
+#undef VM_LOG
+    if (!m.failed) vm_copy_out(&m, &curr);
+    vm_buf_done(&m, &curr);
+    vm_buf_done(&m, &work);
+    const int failed = m.failed;
+    if (!failed) {
+        memcpy(keys, m.key, sizeof(uint64_t) * (size_t)n);
+        if (vals) memcpy(vals, m.val, sizeof(uint32_t) * (size_t)n);
+    }
+    st.entropy = H;
+    if (st_out) *st_out = st;
+    if (vst_out) *vst_out = vst;
+    free(m.key); free(m.val); free(m.free_list); free(stack); free(spow); free(slo);
+    return failed ? -1 : 0;
+}

@@ -35,7 +35,17 @@ typedef struct {
     int64_t mov_merge;   /* element writes by merges (incl. aux copies)   */
     double  entropy;     /* run-length entropy H over the extended runs   */
     int64_t mov_rev;     /* element writes by descending-run reversals    */
+    int64_t mov_copy;    /* element writes by the final Copy (VM variant) */
 } orc_stats;
+
+/* Memory of the virtual-memory variant (Section 4). */
+typedef struct {
+    int64_t page;          /* P: elements per page                           */
+    int64_t input_pages;   /* pages the input array is cut into              */
+    int64_t extra_pages;   /* most pages beyond the input's in use at once   */
+    int64_t meta_words;    /* most page-list and free-list entries at once   */
+    int64_t max_buffers;   /* most live buffers (stack + curr + next + merge) */
+} orc_vm_stats;
 
 /* Variants of Algorithm 1 the oracle can run. */
 enum {
@@ -70,6 +80,21 @@ void orc_run_powers(const int64_t* bounds, int64_t r, int64_t n, uint8_t* powers
  * Returns 0 on success, -1 on allocation failure or bad arguments. */
 int orc_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun,
                   int variant, orc_stats* st, int64_t* merge_log, int64_t log_cap);
+
+/* Virtual-Memory Powersort (Section 4): Algorithm 1 with every buffer a list
+ * of pages of `page` elements taken from a free list (consumed pages of the
+ * input and of merged runs go back to it; an empty free list allocates an
+ * extra page), merges page by page (PageMerge of Algorithm 2), and a final
+ * Copy that permutes pages into the input array.  page <= 0: the rule of
+ * orc_vm_page.  desc: ORC_DESC_RUNS or 0.  Counters as orc_powersort
+ * (mov_push: run extraction into pages, mov_copy: the final Copy).
+ * Returns 0, or -1 on bad arguments / allocation failure. */
+int orc_vm_powersort(uint64_t* keys, uint32_t* vals, int64_t n, int32_t minrun, int64_t page, int desc,
+                     orc_stats* st, orc_vm_stats* vst, int64_t* merge_log, int64_t log_cap);
+
+/* Page size of Section 4: about sqrt(n / (T log2 n)) elements for records of
+ * T words, rounded down to a power of two (at least 1). */
+int64_t orc_vm_page(int64_t n, int32_t rec_words);
 
 /* Same, over independent segments seg_off[0..nseg] of one array; every
  * segment is an instance of its own (minrun <= 0: the rule for its length). */

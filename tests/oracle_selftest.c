@@ -82,6 +82,21 @@ static void test_sorts(void)
                     CHECK(rc == 0, "powersort rc %d", rc);
                     check_stable(orig, keys, vals, n, "powersort");
                 }
+                /* the virtual-memory variant at small pages and at the page rule */
+                static const int64_t pages[] = {0, 1, 2, 3, 7, 64};
+                for (size_t pi = 0; pi < sizeof pages / sizeof *pages; ++pi)
+                    for (int desc = 0; desc <= ORC_DESC_RUNS; desc += ORC_DESC_RUNS) {
+                        memcpy(keys, orig, sizeof(uint64_t) * (size_t)n);
+                        for (int64_t i = 0; i < n; ++i) vals[i] = (uint32_t)i;
+                        orc_stats st;
+                        orc_vm_stats vst;
+                        const int rc = orc_vm_powersort(keys, pi % 2 ? vals : NULL, n, minruns[mi], pages[pi], desc,
+                                                        &st, &vst, log, n);
+                        CHECK(rc == 0, "vm powersort rc %d", rc);
+                        if (pi % 2) check_stable(orig, keys, vals, n, "vm powersort");
+                        for (int64_t i = 1; i < n; ++i) CHECK(keys[i - 1] <= keys[i], "vm keys out of order");
+                        CHECK(st.mov_push + st.mov_merge + st.mov_copy <= st.merge_cost + 3 * n, "vm moves");
+                    }
             }
             if (n < 2) continue;
             const int32_t ell = orc_minrun(n);

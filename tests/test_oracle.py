@@ -435,3 +435,100 @@ def test_desc_runs_theorem_bound_and_counters(orc):
         assert s1["mov_push"] + s1["mov_merge"] <= s1["merge_cost"] + n
         assert s1["runs"] <= s0["runs"]
         assert s1["mov_rev"] > 0
+
+
+# --- Virtual-Memory Powersort (Section 4) ---------------------------------
+
+def test_vm_golden_pages(orc):
+    """Hand-derived page traces (fixture header): output, copy moves, extra
+    pages, live buffers and metadata entries."""
+    for (page,), (ell,), keys, (extra,), (copies,), (bufs,), (meta,) in read_golden("vm_pages.txt"):
+        x = np.array(keys, dtype=np.uint64)
+        k, v, st, vs, log = orc.vm_powersort(x, np.arange(x.size, dtype=np.uint32), page=page, ell=ell,
+                                             log_merges=True)
+        n = x.size
+        assert np.array_equal(v, np.argsort(x, kind="stable")) and np.array_equal(k, np.sort(x))
+        assert log.tolist() == [[0, 2, n]]
+        assert (vs["extra_pages"], st["mov_copy"], vs["max_buffers"], vs["meta_words"]) == (extra, copies, bufs, meta)
+        assert st["mov_push"] == n and st["mov_merge"] == n and vs["input_pages"] == (n + page - 1) // page
+
+
+@pytest.mark.parametrize("desc", [False, True])
+def test_vm_bruteforce_small_pages(orc, desc):
+    """Every permutation of n <= 7 and every {0,1,2}^n word of n <= 8 sorts
+    stably with pages of 1, 2 and 3 elements (a partial last page whenever
+    the page does not divide n)."""
+    cases = []
+    for n in range(0, 8):
+        cases += [np.array(p, dtype=np.uint64) for p in itertools.permutations(range(n))]
+    for n in range(1, 9):
+        cases += [np.array(w, dtype=np.uint64) for w in itertools.product(range(3), repeat=n)]
+    for x in cases:
+        order = np.argsort(x, kind="stable")
+        for page in (1, 2, 3):
+            k, v, _, _, _ = orc.vm_powersort(x, np.arange(x.size, dtype=np.uint32), page=page, ell=2, desc=desc)
+            assert np.array_equal(v, order), (x, page)
+
+
+def test_vm_page_rule(orc):
+    """P: the largest power of two <= sqrt(n / (T log2 n)) (Section 4 and its
+    footnote on powers of two), worked by hand: 2^20 keys give
+    sqrt(2^20/20) = 228.9 -> 128; key-value records (T = 2) sqrt(2^20/40) =
+    161.9 -> 128; 2^28 keys sqrt(2^28/28) = 3096.3 -> 2048; 2^28 records
+    2189.4 -> 2048; 10 keys sqrt(10/4) = 1.58 -> 1; 4096 keys sqrt(4096/12)
+    = 18.5 -> 16."""
+    for n, t, p in ((1 << 20, 1, 128), (1 << 20, 2, 128), (1 << 28, 1, 2048), (1 << 28, 2, 2048),
+                    (10, 1, 1), (4096, 1, 16), (1, 1, 1)):
+        assert orc.vm_page(n, t) == p, (n, t)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "presorted", "dup16", "desc"])
+def test_vm_same_merges_and_move_bound(orc, kind):
+    """The paged buffers change where elements live, not what Algorithm 1
+    does: the merge log and merge comparisons equal Pingpong's.  Moves:
+    n into pages, M by the merges, at most 2n by the final Copy, so at most
+    M + 3n (the bound stated at the start of Section 4)."""
+    for n in (2, 3, 100, 1000, 4097, 1 << 15):
+        x = {"uniform": lambda: workloads.uniform(n, 64, n),
+             "presorted": lambda: workloads.presorted(n, n, mean_run=300),
+             "dup16": lambda: workloads.dup16(n, n),
+             "desc": lambda: np.arange(n, 0, -1, dtype=np.uint64)}[kind]()
+        for page in (0, 1, 5, 64):
+            for desc in (False, True):
+                k, v, st, vs, log = orc.vm_powersort(x, np.arange(n, dtype=np.uint32), page=page, desc=desc,
+                                                     log_merges=True)
+                k2, v2, st2, log2 = orc.powersort(x, np.arange(n, dtype=np.uint32),
+                                                  variant=orc.PINGPONG | (orc.DESC_RUNS if desc else 0),
+                                                  log_merges=True)
+                assert np.array_equal(v, v2) and np.array_equal(k, k2)
+                assert np.array_equal(log, log2)
+                assert st["cmp_merge"] == st2["cmp_merge"] and st["merge_cost"] == st2["merge_cost"]
+                assert st["mov_push"] == n and st["mov_merge"] == st["merge_cost"]
+                assert st["mov_copy"] <= 2 * n
+                assert st["mov_push"] + st["mov_merge"] + st["mov_copy"] <= st["merge_cost"] + 3 * n
+
+
+def test_vm_pages_and_memory(orc):
+    """Pages in use: each live buffer holds all its elements in full pages
+    but for a partial page at each end, so pages in use stay below n/P +
+    buffers + 3; a fresh page is made only when none is free, so the extra
+    pages stay at most buffers + 4.  Buffers: the run stack (at most
+    ceil(log2 n) + 1 runs, the powers on it strictly increase) plus work,
+    curr, next and a merge result.  Metadata: one entry per page in a list,
+    at most every page.  With the page rule the extra words grow like
+    sqrt(n T log n) (Section 4's memory bound)."""
+    for n in (1000, 1 << 14, 1 << 17, 1 << 20):
+        for kind in ("uniform", "presorted", "dup16"):
+            x = {"uniform": workloads.uniform, "dup16": workloads.dup16}.get(kind)
+            x = workloads.presorted(n, 5, mean_run=300) if x is None else (
+                x(n, 64, 5) if kind == "uniform" else x(n, 5))
+            for vals in (None, np.arange(n, dtype=np.uint32)):
+                t = 1 if vals is None else 2
+                _, _, st, vs, _ = orc.vm_powersort(x, vals)
+                P = vs["page"]
+                assert P == orc.vm_page(n, t)
+                assert vs["max_buffers"] <= math.ceil(math.log2(n)) + 1 + 4
+                assert vs["extra_pages"] <= vs["max_buffers"] + 4
+                assert vs["meta_words"] <= vs["input_pages"] + vs["extra_pages"]
+                extra_words = vs["extra_pages"] * P * t + vs["meta_words"]
+                assert extra_words <= 4 * math.sqrt(n * t * math.log2(n)), (n, kind, t, extra_words)

@@ -920,8 +920,11 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     if (len == 0) return;
     if (len > TCAP) {
         // a single natural run longer than the tile: already sorted, or
-        // (with desc) strictly decreasing, which its first two keys tell
-        if (desc && keysA[a] > keysA[a + 1]) {
+        // (with desc) strictly decreasing, which its first two keys tell;
+        // every thread reads them before any thread swaps in place
+        const bool rev = desc && keysA[a] > keysA[a + 1];
+        __syncthreads();
+        if (rev) {
             // reversed: position i takes element len - 1 - i (in place, or
             // into B); values follow, iota values are the source positions
             const uint32_t half = sg.dst == 1 ? len : len / 2;

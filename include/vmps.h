@@ -105,6 +105,49 @@ vmps_status vmps_sort_noalloc(void* keys, uint32_t* values, int64_t n, vmps_dtyp
                               void* stream);
 size_t vmps_noalloc_scratch_bytes(void);
 
+/* ---- Virtual-Memory Powersort (Section 4) ----------------------------
+ * The same stable sort as vmps_sort without the second Pingpong buffer:
+ * the merge levels write into pages (P elements, the merge output tile:
+ * 4096, or 2048 for 64-bit keys with values) taken from a pool of
+ * window + 9 extra pages and from input pages whose elements have all been
+ * consumed (the paper's free list); a page table maps the array's pages to
+ * where they are, and a final Copy permutes the pages into place.  A level
+ * runs in rounds of `window` pages.  Memory beyond keys and values: the
+ * pool, one page per 64 for the Copy, a few words per page, and the merge
+ * schedule (as vmps_sort's).
+ *   window_pages : pages per round (0: N/16, at least 64, N = ceil(n/P));
+ *                  larger windows mean fewer launches and a larger pool. */
+typedef struct {
+    int64_t page_elems;    /* P */
+    int64_t pages;         /* N = ceil(n / P) */
+    int64_t window_pages;  /* W, after the default and the clamp to N */
+    int64_t pool_pages;    /* W + 9 */
+    int64_t copy_pages;    /* ceil(N / 64) pages saved by the Copy */
+    size_t  buffer_bytes;  /* pool + copy pages, keys and values */
+    size_t  workspace_bytes; /* all of ws, the merge schedule included */
+} vmps_vm_layout;
+vmps_status vmps_sort_vm_layout(int64_t n, vmps_dtype kt, int has_values, int64_t window_pages,
+                                vmps_vm_layout* out);
+
+/* Statistics of a vmps_sort_vm call (device array of 8 counts, written at
+ * the end of the call when `stats` is not NULL):
+ *   [0] schedule faults: 0 on every correct run (a fresh page handed out
+ *       before its release, or a broken page permutation)
+ *   [1] elements carried (copied into a fresh page without merging)
+ *   [2] elements moved by the final Copy
+ *   [3] elements written by the page merges
+ *   [4] merge levels that touched pages, [5] page writes of those levels. */
+#define VMPS_VM_STATS 8
+
+/* Stable sort of keys[0,n) in place with paged merge levels.
+ *   keys, values, flags : as vmps_sort (VMPS_VALUES_IOTA, VMPS_DESCENDING_RUNS).
+ *   window_pages        : see above (>= 0).
+ *   ws                  : vmps_sort_vm_layout().workspace_bytes, 256-byte aligned.
+ *   stats               : NULL or a device array of VMPS_VM_STATS uint64.
+ * Asynchronous on `stream`; n in {0,1} is a no-op.  Errors as vmps_sort. */
+vmps_status vmps_sort_vm(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                         int64_t window_pages, void* ws, size_t ws_bytes, uint64_t* stats, void* stream);
+
 /* Workspace of vmps_merge. */
 vmps_status vmps_merge_workspace_size(int64_t na, int64_t nb, vmps_dtype kt, size_t* bytes);
 

@@ -27,6 +27,7 @@ OK, INVALID_ARG, WORKSPACE_TOO_SMALL, UNSUPPORTED, DEVICE = range(5)
 U32, U64 = 0, 1
 VALUES_IOTA = 1
 DESCENDING_RUNS = 2
+VM_STATS = 8  # vmps_sort_vm statistics: faults, carried, copied, merged, levels, page writes
 CDF_KEEP_TRAINED = 1
 
 
@@ -53,6 +54,12 @@ class CdfModel(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
                 ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32)]
+
+
+class VmLayout(ctypes.Structure):
+    _fields_ = [("page_elems", ctypes.c_int64), ("pages", ctypes.c_int64), ("window_pages", ctypes.c_int64),
+                ("pool_pages", ctypes.c_int64), ("copy_pages", ctypes.c_int64), ("buffer_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t)]
 
 
 class LearnedStats(ctypes.Structure):
@@ -119,6 +126,8 @@ def load_library():
                                          ctypes.POINTER(vp)]),
         "vmps_graph_launch": (st, [vp, vp]),
         "vmps_graph_destroy": (st, [vp]),
+        "vmps_sort_vm_layout": (st, [i64, st, st, i64, ctypes.POINTER(VmLayout)]),
+        "vmps_sort_vm": (st, [vp, vp, i64, st, u32, i64, vp, sz, vp, vp]),
         "vmps_trace_enable": (st, [st]),
         "vmps_trace_collect": (st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]),
     }
@@ -268,6 +277,33 @@ def sort_noalloc_(keys, values=None, *, iota: bool = False):
     flags = VALUES_IOTA if iota else 0
     _check(lib.vmps_sort_noalloc(_ptr(keys), _ptr(values), keys.numel(), kt, flags, _stream(keys.device)),
            "vmps_sort_noalloc")
+    return keys
+
+
+def vm_layout(n: int, dtype_code: int, has_values: bool, window_pages: int = 0) -> dict:
+    """Page length, page counts and bytes of the paged sort (vmps_sort_vm)."""
+    out = VmLayout()
+    _check(load_library().vmps_sort_vm_layout(n, dtype_code, int(bool(has_values)), window_pages,
+                                              ctypes.byref(out)), "vmps_sort_vm_layout")
+    return {name: getattr(out, name) for name, _ in VmLayout._fields_}
+
+
+def sort_vm_(keys, values=None, *, iota: bool = False, desc: bool = False, window_pages: int = 0, workspace=None,
+             stats=None):
+    """Stable in-place sort with paged merge levels (Virtual-Memory
+    Powersort): no second array, a pool of window_pages + 9 pages.  stats:
+    None or an int64 GPU tensor of VM_STATS entries (see vmps_sort_vm)."""
+    lib = load_library()
+    _require_cuda(keys, values, stats)
+    kt = _dtype_code(keys)
+    n = keys.numel()
+    lay = vm_layout(n, kt, values is not None, window_pages)
+    ws = workspace if workspace is not None else _workspace(lay["workspace_bytes"], keys.device)
+    if stats is not None and stats.numel() < VM_STATS:
+        raise ValueError(f"stats needs {VM_STATS} entries")
+    flags = (VALUES_IOTA if iota else 0) | (DESCENDING_RUNS if desc else 0)
+    _check(lib.vmps_sort_vm(_ptr(keys), _ptr(values), n, kt, flags, window_pages, _ptr(ws), ws.numel(), _ptr(stats),
+                            _stream(keys.device)), "vmps_sort_vm")
     return keys
 
 

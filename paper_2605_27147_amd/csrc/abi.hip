@@ -196,6 +196,46 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
     return sort_in_workspace(keys, values, n, kt, flags, ws, ws_bytes, (hipStream_t)stream, true);
 }
 
+vmps_status vmps_sort_vm_layout(int64_t n, vmps_dtype kt, int has_values, int64_t window_pages,
+                                vmps_vm_layout* out)
+{
+    if (!out || n < 0 || (uint64_t)n >= (1ull << 32) || window_pages < 0) return VMPS_ERR_INVALID_ARG;
+    if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
+    const int kb = key_bits_of(kt), hv = has_values ? 1 : 0;
+    const uint64_t P = vm_page_elems(kb, hv);
+    out->page_elems = (int64_t)P;
+    out->pages = (int64_t)ceil_div(n > 0 ? (uint64_t)n : 1, P);
+    out->window_pages = (int64_t)vm_window_pages((uint64_t)n, kb, hv, (uint64_t)window_pages);
+    out->pool_pages = out->window_pages + 9;
+    out->copy_pages = (int64_t)ceil_div((uint64_t)out->pages, 64);
+    out->buffer_bytes = vm_buffer_bytes((uint64_t)n, kb, hv, (uint64_t)window_pages);
+    out->workspace_bytes = vm_workspace_bytes((uint64_t)n, kb, hv, (uint64_t)window_pages);
+    return VMPS_OK;
+}
+
+vmps_status vmps_sort_vm(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
+                         int64_t window_pages, void* ws, size_t ws_bytes, uint64_t* stats, void* stream)
+{
+    const vmps_status st = check_sort_args(keys, values, n, kt, flags);
+    if (st != VMPS_OK) return st;
+    if (window_pages < 0 || (stats && ((uintptr_t)stats & 7))) return VMPS_ERR_INVALID_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    if (n <= 1) {
+        if (n == 1 && (flags & VMPS_VALUES_IOTA))
+            return guarded([&] { k_write_zero_u32<<<1, 1, 0, s>>>(values); return hipGetLastError(); });
+        return VMPS_OK;
+    }
+    const int kb = key_bits_of(kt), hv = values ? 1 : 0;
+    if (!ws || ws_bytes < vm_workspace_bytes((uint64_t)n, kb, hv, (uint64_t)window_pages))
+        return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    const int vmode = values ? ((flags & VMPS_VALUES_IOTA) ? 2 : 1) : 0;
+    return guarded([&] {
+        return vm_sort_enqueue(keys, values, (uint64_t)n, kb, vmode, (flags & VMPS_DESCENDING_RUNS) ? 1u : 0u,
+                               (uint64_t)window_pages, ws, (unsigned long long*)stats, s);
+    });
+}
+
 }  // extern "C"
 
 namespace vmps {

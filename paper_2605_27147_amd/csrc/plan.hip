@@ -1108,6 +1108,73 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     return hipGetLastError();
 }
 
+// ------------------------------------------- position-ordered levels --
+// The level table above reserves each node's pair slots with an atomic, so
+// the nodes of a level appear in any order.  The paged merge levels need
+// them in position order (a round takes consecutive pages).  Nodes q are in
+// position order already, so the slot of node q is: the level's offset,
+// plus the tiles of the same-level nodes before q.  Per block of
+// ORDER_BLOCK nodes: the tiles of each level (level-major, so one flat scan
+// gives level offset + earlier blocks), then the rank inside the block.
+constexpr uint32_t ORDER_BLOCK = 256;
+
+__global__ void k_order_sums(const uint32_t* __restrict__ hbm_list, const uint8_t* __restrict__ power,
+                             const uint32_t* __restrict__ tiles, const uint32_t* counters, uint32_t nblocks,
+                             uint32_t* __restrict__ bsum)
+{
+    __shared__ uint32_t lv[MAX_LEVEL];
+    const uint32_t h = counters[CNT_NHBM], b = blockIdx.x;
+    if (threadIdx.x < MAX_LEVEL) lv[threadIdx.x] = 0;
+    __syncthreads();
+    const uint32_t q = b * ORDER_BLOCK + threadIdx.x;
+    if (q < h) {
+        const uint32_t p = power[hbm_list[q]];
+        if (p < MAX_LEVEL) atomicAdd(&lv[p], tiles[q]);
+    }
+    __syncthreads();
+    if (threadIdx.x < MAX_LEVEL) bsum[(uint64_t)threadIdx.x * nblocks + b] = lv[threadIdx.x];
+}
+
+__global__ void k_order_apply(const uint32_t* __restrict__ hbm_list, const uint8_t* __restrict__ power,
+                              const uint32_t* __restrict__ tiles, const uint32_t* counters, uint32_t nblocks,
+                              const uint32_t* __restrict__ boff, uint32_t* __restrict__ node_base)
+{
+    __shared__ uint32_t lp[ORDER_BLOCK], lt[ORDER_BLOCK];
+    const uint32_t h = counters[CNT_NHBM], b = blockIdx.x;
+    const uint32_t q = b * ORDER_BLOCK + threadIdx.x;
+    uint32_t p = MAX_LEVEL, t = 0;
+    if (q < h) {
+        p = power[hbm_list[q]];
+        t = tiles[q];
+    }
+    lp[threadIdx.x] = p;
+    lt[threadIdx.x] = t;
+    __syncthreads();
+    if (q >= h) return;
+    if (p >= MAX_LEVEL) {
+        node_base[q] = NONE;
+        return;
+    }
+    uint32_t before = 0;
+    for (uint32_t j = 0; j < threadIdx.x; ++j) before += lp[j] == p ? lt[j] : 0u;
+    node_base[q] = boff[(uint64_t)p * nblocks + b] + before;
+}
+
+uint64_t plan_order_blocks(const Plan& P) { return ceil_div(P.run_cap, ORDER_BLOCK); }
+
+hipError_t plan_order_levels(Plan& P, uint32_t* bsum, uint32_t* boff, uint32_t* tmp, hipStream_t s)
+{
+    const uint64_t nb = plan_order_blocks(P);
+    uint32_t* C = P.counters;
+    k_order_sums<<<(unsigned)nb, ORDER_BLOCK, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, (uint32_t)nb, bsum);
+    VMPS_HIP(scan_exclusive_u32(bsum, boff, (uint64_t)MAX_LEVEL * nb, nullptr, nullptr, tmp, s));
+    k_order_apply<<<(unsigned)nb, ORDER_BLOCK, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, (uint32_t)nb, boff,
+                                                       P.node_base);
+    k_level_fill<<<stride_grid(P.pair_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
+                                                           P.node_base, P.T_out, C, P.level, P.pairs);
+    return hipGetLastError();
+}
+
 hipError_t plan_enqueue(Plan& P, const void* keys, int key_bits, uint32_t ell_override, hipStream_t s)
 {
     TraceScope tr(VMPS_TRACE_PLAN, s);

@@ -195,6 +195,12 @@ size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
 // Carve Plan arrays from ws; returns bytes used.
 size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
 
+// Re-lay every level's pairs in position order (nodes left to right, each
+// node's tiles in order).  bsum, boff: MAX_LEVEL * plan_order_blocks(P)
+// words each; tmp: scan_tmp_words of that count.
+uint64_t plan_order_blocks(const Plan& P);
+hipError_t plan_order_levels(Plan& P, uint32_t* bsum, uint32_t* boff, uint32_t* tmp, hipStream_t s);
+
 // Enqueue run detection + powers + tree + placement for the instances.
 // key_bits: 32 or 64. ell_override: 0 = minrun rule.
 hipError_t plan_enqueue(Plan& P, const void* keys, int key_bits, uint32_t ell_override,
@@ -273,6 +279,15 @@ constexpr uint32_t JUDGE_GRID = 256;
 hipError_t learned_stats_enqueue(const int64_t* off, uint32_t B, uint32_t T, const vmps_cdf_model* model,
                                  const void* sample, uint64_t m, int key_bits, uint64_t* part,
                                  vmps_learned_stats* st, hipStream_t s);
+
+// Paged merge levels (vm.hip): workspace bytes, pool + copy page bytes,
+// page length, and the sort (n > 1, arguments checked).
+size_t vm_workspace_bytes(uint64_t n, int key_bits, int has_values, uint64_t window_pages);
+size_t vm_buffer_bytes(uint64_t n, int key_bits, int has_values, uint64_t window_pages);
+uint32_t vm_page_elems(int key_bits, int has_values);
+uint64_t vm_window_pages(uint64_t n, int key_bits, int has_values, uint64_t window_pages);
+hipError_t vm_sort_enqueue(void* keys, uint32_t* values, uint64_t n, int key_bits, int vmode, uint32_t desc,
+                           uint64_t window_pages, void* ws, unsigned long long* stats, hipStream_t s);
 
 // The whole stable sort of one array with a caller-provided workspace
 // (vmps_sort's body after its argument checks; allow_host_wait = false never

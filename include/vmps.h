@@ -95,8 +95,9 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
  * host (the host_wait tuning is ignored) and is asynchronous on `stream`.
  *   - The array holds vmps_noalloc_scratch_bytes() bytes (96 MiB) on every
  *     GPU the library runs on, from its first use there until the process
- *     ends.  A sort whose vmps_sort_workspace_size exceeds it (n above 2^22
- *     for some key types) -> WORKSPACE_TOO_SMALL, with nothing enqueued.
+ *     ends.  A sort whose vmps_sort_workspace_size exceeds it (n above about
+ *     6.9 million for 64-bit keys with values, 16.5 million for 32-bit keys
+ *     alone) -> WORKSPACE_TOO_SMALL, with nothing enqueued.
  *   - All calls on one GPU share that GPU's array: calls that overlap in
  *     time on one GPU (two streams, two host threads) race and give wrong
  *     results; order them on one stream.  Each call overwrites what the last

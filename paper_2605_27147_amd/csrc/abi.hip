@@ -64,7 +64,11 @@ struct SortLayout {
     size_t keys_b, vals_b, plan, total;
 };
 
-SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values)
+// One-array sorts with the minrun rule: every run but the last is at least
+// minrun_of(n) long, which sizes the planner's run arrays.
+static uint32_t rule_min_len(uint64_t n) { return n > 0 ? minrun_of(n) : 1u; }
+
+SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values, uint32_t min_len)
 {
     const int kb = key_bits_of(kt);
     SortLayout L;
@@ -73,7 +77,7 @@ SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values)
     L.plan = L.vals_b + (has_values ? align256(4 * n) : 0);
     const uint32_t T = tilesort_capacity(kb, has_values);
     const uint32_t TO = merge_tile_out(kb, has_values);
-    L.total = L.plan + plan_workspace_bytes(n, k, T, TO);
+    L.total = L.plan + plan_workspace_bytes(n, k, T, TO, min_len);
     return L;
 }
 
@@ -184,7 +188,7 @@ vmps_status vmps_sort_workspace_size(int64_t n, vmps_dtype kt, int has_values, s
 {
     if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32)) return VMPS_ERR_INVALID_ARG;
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    *bytes = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0).total;
+    *bytes = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0, rule_min_len((uint64_t)n)).total;
     return VMPS_OK;
 }
 
@@ -260,7 +264,7 @@ vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         return VMPS_OK;
     }
     const int has_values = values ? 1 : 0;
-    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values);
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values, rule_min_len((uint64_t)n));
     if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
     if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
     const int kb = key_bits_of(kt);
@@ -270,7 +274,7 @@ vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtyp
     uint32_t* valsB = has_values ? (uint32_t*)(w + L.vals_b) : nullptr;
     Plan P;
     const uint32_t T = tilesort_capacity(kb, has_values);
-    plan_carve(P, w + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values));
+    plan_carve(P, w + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values), rule_min_len((uint64_t)n));
     P.big_min = T;
     P.desc = (flags & VMPS_DESCENDING_RUNS) ? 1u : 0u;
     return guarded([&]() -> hipError_t {
@@ -348,7 +352,9 @@ static vmps_status extract_runs_impl(const void* keys, int64_t n, vmps_dtype kt,
     if (!run_bounds || !num_runs) return VMPS_ERR_INVALID_ARG;
     const uint32_t ell = minrun > 0 ? (uint32_t)minrun : (n > 0 ? minrun_of((uint64_t)n) : 1u);
     if (minrun > 0 && (int64_t)ell < (n < 16 ? n : 16)) return VMPS_ERR_INVALID_ARG;
-    const SortLayout L = sort_layout((uint64_t)n, 1, kt, 0);
+    // the documented workspace is vmps_sort's; the run chain needs no second
+    // array, so its plan (sized for runs of ell) starts at the front
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, 0, rule_min_len((uint64_t)n));
     if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
     if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
     hipStream_t s = (hipStream_t)stream;
@@ -361,7 +367,9 @@ static vmps_status extract_runs_impl(const void* keys, int64_t n, vmps_dtype kt,
     }
     const int kb = key_bits_of(kt);
     Plan P;
-    plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, tilesort_capacity(kb, 0), merge_tile_out(kb, 0));
+    if (plan_workspace_bytes((uint64_t)n, 1, tilesort_capacity(kb, 0), merge_tile_out(kb, 0), ell) > ws_bytes)
+        return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    plan_carve(P, ws, (uint64_t)n, 1, tilesort_capacity(kb, 0), merge_tile_out(kb, 0), ell);
     P.big_min = 0;
     P.desc = desc ? 1u : 0u;
     return guarded([&]() -> hipError_t {
@@ -397,14 +405,15 @@ vmps_status vmps_sort_schedule(const void* keys, int64_t n, vmps_dtype kt, int h
     if (n < 1 || !node_l || !node_m || !node_r || !node_level || !node_buf || !seg_start || !seg_end || !seg_buf ||
         !counts || !tile)
         return VMPS_ERR_INVALID_ARG;
-    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0);
+    const SortLayout L = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0, rule_min_len((uint64_t)n));
     if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
     if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
     const int kb = key_bits_of(kt);
     const uint32_t T = tilesort_capacity(kb, has_values ? 1 : 0);
     *tile = (int32_t)T;
     Plan P;
-    plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values ? 1 : 0));
+    plan_carve(P, (uint8_t*)ws + L.plan, (uint64_t)n, 1, T, merge_tile_out(kb, has_values ? 1 : 0),
+               rule_min_len((uint64_t)n));
     P.big_min = 0;
     hipStream_t s = (hipStream_t)stream;
     return guarded([&]() -> hipError_t {
@@ -423,7 +432,7 @@ vmps_status vmps_segmented_sort_workspace_size(int64_t total, int64_t nseg, vmps
     if (!bytes || total < 0 || (uint64_t)total >= (1ull << 32) || nseg < 0 || (uint64_t)nseg >= (1ull << 31))
         return VMPS_ERR_INVALID_ARG;
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    *bytes = sort_layout((uint64_t)total, (uint64_t)(nseg > 0 ? nseg : 1), kt, has_values ? 1 : 0).total;
+    *bytes = sort_layout((uint64_t)total, (uint64_t)(nseg > 0 ? nseg : 1), kt, has_values ? 1 : 0, 16).total;
     return VMPS_OK;
 }
 
@@ -439,7 +448,7 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
         return VMPS_ERR_INVALID_ARG;
     if (nseg == 0 || total <= 1) return VMPS_OK;
     const int has_values = values ? 1 : 0;
-    const SortLayout L = sort_layout((uint64_t)total, (uint64_t)nseg, kt, has_values);
+    const SortLayout L = sort_layout((uint64_t)total, (uint64_t)nseg, kt, has_values, 16);
     if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
     if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
     const int kb = key_bits_of(kt);
@@ -508,7 +517,7 @@ LearnedLayout learned_layout(uint64_t n, vmps_dtype kt, int has_values, const vm
     L.keys_b = off; off += align256(key_bytes(kt) * n);
     L.vals_b = off; off += has_values ? align256(4 * n) : 0;
     L.sample = off; off += align256(key_bytes(kt) * L.m);
-    L.sample_ws = off; off += align256(sort_layout(L.m, 1, kt, 0).total);
+    L.sample_ws = off; off += align256(sort_layout(L.m, 1, kt, 0, rule_min_len(L.m)).total);
     L.u = off; off += align256(4 * L.m);
     L.tb = off; off += align256(4 * train_buf_floats());
     L.model = off; off += align256(sizeof(vmps_cdf_model));
@@ -554,7 +563,7 @@ vmps_status vmps_learned_workspace_size(int64_t n, vmps_dtype kt, int has_values
     if (cfg) c = *cfg; else vmps_learned_default_config(n, kt, &c);
     if (n < 2) { *bytes = 256; return VMPS_OK; }
     if (check_config(c, n) != VMPS_OK) return VMPS_ERR_INVALID_ARG;
-    const size_t plain = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0).total;
+    const size_t plain = sort_layout((uint64_t)n, 1, kt, has_values ? 1 : 0, rule_min_len((uint64_t)n)).total;
     const size_t lrn = learned_layout((uint64_t)n, kt, has_values ? 1 : 0, c).total;
     *bytes = plain > lrn ? plain : lrn;
     return VMPS_OK;
@@ -595,7 +604,7 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
             TraceScope tr(VMPS_TRACE_SAMPLE, s);
             VMPS_HIP(sample_enqueue(keys, (uint64_t)n, kb, L.m, c.seed, w + L.sample, s));
             if (vmps_sort(w + L.sample, nullptr, (int64_t)L.m, kt, 0, w + L.sample_ws,
-                          sort_layout(L.m, 1, kt, 0).total, stream) != VMPS_OK)
+                          sort_layout(L.m, 1, kt, 0, rule_min_len(L.m)).total, stream) != VMPS_OK)
                 return hipErrorLaunchFailure;
         }
         {

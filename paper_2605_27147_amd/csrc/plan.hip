@@ -702,14 +702,15 @@ __global__ void k_boundaries(const uint32_t* __restrict__ run_start, const uint3
 
 // --------------------------------------------------------- HBM nodes --
 __global__ void k_hbm_emit(const uint32_t* __restrict__ hbm_flag, const uint32_t* __restrict__ hbm_rank,
-                           const uint32_t* counters, uint32_t* __restrict__ hbm_list,
+                           const uint32_t* counters, uint32_t h_cap, uint32_t* __restrict__ hbm_list,
                            uint32_t* __restrict__ hbm_idx)
 {
     const uint32_t nr = counters[CNT_NRUNS];
     for (uint32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nr; t += gridDim.x * blockDim.x) {
         if (hbm_flag[t]) {
-            hbm_list[hbm_rank[t]] = t;
-            hbm_idx[t] = hbm_rank[t];
+            const uint32_t r = hbm_rank[t];
+            if (r < h_cap) hbm_list[r] = t;  // more only from an inconsistent plan
+            hbm_idx[t] = r;
         }
     }
 }
@@ -729,7 +730,7 @@ __global__ void k_depth_init(const uint32_t* __restrict__ hbm_list, const uint32
         if (l == NONE) parent = r;
         else if (r == NONE) parent = l;
         else parent = power[l] > power[r] ? l : r;
-        const bool ok = parent != NONE && hbm_flag[parent];
+        const bool ok = parent != NONE && hbm_flag[parent] && hbm_idx[parent] < h;
         par[q] = ok ? hbm_idx[parent] : q;
         val[q] = ok ? 1u : 0u;
     }
@@ -906,7 +907,7 @@ struct Carver {
 inline unsigned grid_for(uint64_t threads, unsigned block) { return (unsigned)ceil_div(threads ? threads : 1, block); }
 }  // namespace
 
-size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out)
+size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out, uint32_t min_len)
 {
     Carver c{(uint8_t*)ws, 0};
     P.n = (uint32_t)n;
@@ -915,14 +916,21 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.big_min = T;
     P.T_out = T_out;
     P.n_tiles_out = (uint32_t)ceil_div(n ? n : 1, T_out);
-    // runs are at least 16 long (explicit minrun >= 16, rule >= 32) except
-    // the last of each instance
-    // long runs are >= 16 long; an increasing and a decreasing one share at
-    // most one element
-    P.lr_cap = (uint32_t)(n / 15 + 3);
-    P.run_cap = (uint32_t)(n / 16 + k + 2);
+    // runs are at least min_len >= 16 long (explicit minrun >= 16, rule >=
+    // 32) except the last of each instance
+    // long runs are >= min_len long; an increasing and a decreasing one
+    // share at most one element
+    const uint64_t ml = min_len < 16 ? 16 : min_len;
+    P.lr_cap = (uint32_t)(n / (ml - 1) + 3);
+    P.run_cap = (uint32_t)(n / ml + k + 2);
     P.ent_cap = P.lr_cap + (uint32_t)k + 1;
-    P.seg_cap = P.run_cap + (uint32_t)k + 1;
+    // nodes longer than T: those of one power level are disjoint, so fewer
+    // than n / T + 1 per level
+    {
+        const uint64_t hc = (uint64_t)MAX_LEVEL * (n / (T ? T : 1) + 1) + 1;
+        P.h_cap = (uint32_t)(hc < P.run_cap ? hc : P.run_cap);
+    }
+    P.seg_cap = P.h_cap + (uint32_t)k + 1;
     P.chain_blocks = (uint32_t)ceil_div(P.lr_cap, CHAIN_BLOCK);
     P.bm_tiles = (uint32_t)ceil_div(n / 64 + 2, 64);
     P.bm_words = P.bm_tiles * 64;
@@ -963,13 +971,13 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.hbm_flag = c.take<uint32_t>(P.run_cap);
     P.hbm_rank = c.take<uint32_t>(P.run_cap);
     P.hbm_idx = c.take<uint32_t>(P.run_cap);
-    P.hbm_list = c.take<uint32_t>(P.run_cap);
-    P.hbm_par[0] = c.take<uint32_t>(P.run_cap);
-    P.hbm_par[1] = c.take<uint32_t>(P.run_cap);
-    P.hbm_val[0] = c.take<uint32_t>(P.run_cap);
-    P.hbm_val[1] = c.take<uint32_t>(P.run_cap);
-    P.hbm_tiles = c.take<uint32_t>(P.run_cap + 1);
-    P.hbm_tile_off = c.take<uint32_t>(P.run_cap + 1);
+    P.hbm_list = c.take<uint32_t>(P.h_cap);
+    P.hbm_par[0] = c.take<uint32_t>(P.h_cap);
+    P.hbm_par[1] = c.take<uint32_t>(P.h_cap);
+    P.hbm_val[0] = c.take<uint32_t>(P.h_cap);
+    P.hbm_val[1] = c.take<uint32_t>(P.h_cap);
+    P.hbm_tiles = c.take<uint32_t>(P.h_cap + 1);
+    P.hbm_tile_off = c.take<uint32_t>(P.h_cap + 1);
     P.segs = c.take<Seg>(P.seg_cap);
     // output tiles of all HBM nodes: per level at most n_tiles_out plus two
     // per node, and a level holds fewer than n / T + 1 nodes longer than T
@@ -979,7 +987,7 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
         P.pair_cap = (uint32_t)(cap < 0xffffffffull ? cap : 0xffffffffull);
     }
     P.level = c.take<uint32_t>(3 * MAX_LEVEL);
-    P.node_base = c.take<uint32_t>(P.run_cap);
+    P.node_base = c.take<uint32_t>(P.h_cap);
     P.pairs = c.take<uint32_t>(2 * (uint64_t)P.pair_cap);
     P.splits = c.take<uint32_t>(2 * (uint64_t)P.pair_cap);
     P.counters = c.take<uint32_t>(CNT_COUNT);
@@ -997,10 +1005,10 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     return c.off + 256;
 }
 
-size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out)
+size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out, uint32_t min_len)
 {
     Plan P;
-    return plan_carve(P, nullptr, n, k, T, T_out);
+    return plan_carve(P, nullptr, n, k, T, T_out, min_len);
 }
 
 // Counts are clamped to the capacities the arrays were carved for, so a
@@ -1078,30 +1086,31 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
                                        P.hbm_flag, P.stats);
     // 6. nodes longer than T and their depths
     VMPS_HIP(scan_exclusive_u32(P.hbm_flag, P.hbm_rank, P.run_cap, C + CNT_NRUNS, C + CNT_NHBM, P.scan_tmp, s));
-    k_hbm_emit<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.hbm_list, P.hbm_idx);
-    k_depth_init<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.hbm_idx, P.bnd_l, P.bnd_r, P.power,
+    k_clamp<<<1, 64, 0, s>>>(C, CNT_NHBM, P.h_cap);
+    k_hbm_emit<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_flag, P.hbm_rank, C, P.h_cap, P.hbm_list, P.hbm_idx);
+    k_depth_init<<<stride_grid(P.h_cap), 256, 0, s>>>(P.hbm_list, P.hbm_idx, P.bnd_l, P.bnd_r, P.power,
                                                           P.hbm_flag, C,
                                                           P.hbm_par[0], P.hbm_val[0]);
     int cur = 0;
     for (int round = 0; round < 6; ++round) {
-        k_depth_jump<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_par[cur], P.hbm_val[cur], C,
+        k_depth_jump<<<stride_grid(P.h_cap), 256, 0, s>>>(P.hbm_par[cur], P.hbm_val[cur], C,
                                                               P.hbm_par[cur ^ 1], P.hbm_val[cur ^ 1]);
         cur ^= 1;
     }
     P.hbm_depth = P.hbm_val[cur];
     // 7. LDS segments and the level table
-    k_segs_hbm<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
+    k_segs_hbm<<<stride_grid(P.h_cap), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.power,
                                                         P.hbm_depth, P.inst_start, C, P.segs);
     k_segs_inst<<<grid_for(k, 256), 256, 0, s>>>(P.hbm_list, P.run_start, P.run_inst, P.hbm_depth,
                                                  P.inst_start, P.inst_big, P.inst_bigrank, k, P.k_dev, C, P.segs);
     VMPS_HIP(fill_u32(P.level, 0, 3 * MAX_LEVEL, s));
-    k_level_count<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
+    k_level_count<<<stride_grid(P.h_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.bnd_rpos, P.power, P.T_out,
                                                            C, P.hbm_tiles, P.level);
-    VMPS_HIP(scan_exclusive_u32(P.hbm_tiles, P.hbm_tile_off, P.run_cap, C + CNT_NHBM, C + CNT_NPAIRS,
+    VMPS_HIP(scan_exclusive_u32(P.hbm_tiles, P.hbm_tile_off, P.h_cap, C + CNT_NHBM, C + CNT_NPAIRS,
                                 P.scan_tmp, s));
     k_clamp<<<1, 64, 0, s>>>(C, CNT_NPAIRS, P.pair_cap);
     k_level_offsets<<<1, 64, 0, s>>>(P.level, P.pair_cap);
-    k_level_reserve<<<stride_grid(P.run_cap), 256, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, P.level,
+    k_level_reserve<<<stride_grid(P.h_cap), 256, 0, s>>>(P.hbm_list, P.power, P.hbm_tiles, C, P.level,
                                                              P.node_base);
     k_level_fill<<<stride_grid(P.pair_cap), 256, 0, s>>>(P.hbm_list, P.bnd_lpos, P.power, P.hbm_tile_off,
                                                            P.node_base, P.T_out, C, P.level, P.pairs);
@@ -1160,7 +1169,7 @@ __global__ void k_order_apply(const uint32_t* __restrict__ hbm_list, const uint8
     node_base[q] = boff[(uint64_t)p * nblocks + b] + before;
 }
 
-uint64_t plan_order_blocks(const Plan& P) { return ceil_div(P.run_cap, ORDER_BLOCK); }
+uint64_t plan_order_blocks(const Plan& P) { return ceil_div(P.h_cap, ORDER_BLOCK); }
 
 hipError_t plan_order_levels(Plan& P, uint32_t* bsum, uint32_t* boff, uint32_t* tmp, hipStream_t s)
 {

@@ -101,6 +101,28 @@ struct Pages {
     __device__ K key(const uint32_t* pt, uint32_t x) const { return kp(pt[x >> logp])[x & ((1u << logp) - 1)]; }
 };
 
+// ctr[key] += 1 for every lane that calls it, one atomic per distinct key
+// in the wave (neighbouring pages mostly share a release round, and one
+// atomic per page on a handful of counters serialises); returns the lane's
+// slot among those counted for its key.
+__device__ inline uint32_t wave_count(uint32_t* ctr, uint32_t key)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint64_t todo = __ballot(1);
+    uint32_t slot = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t k0 = __shfl(key, leader, WAVE);
+        const uint64_t same = __ballot(key == k0) & todo;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctr[k0], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, WAVE);
+        if ((same >> lane) & 1) slot = base + (uint32_t)__popcll(same & ((1ull << lane) - 1));
+        todo &= ~same;
+    }
+    return slot;
+}
+
 template <typename K>
 __device__ inline Pages<K> pages_of(const VmArgs& A)
 {
@@ -293,7 +315,7 @@ __global__ void k_vm_release(VmArgs A, uint32_t lvl)
         } else {
             const uint32_t r = last / A.W;
             A.rel[u] = r;
-            atomicAdd(&A.bins[r], 1u);
+            wave_count(A.bins, r);
         }
     }
 }
@@ -327,7 +349,7 @@ __global__ void k_vm_fill(VmArgs A)
         if (u < E) A.S[u] = A.pool[u];
         if (u < U && A.rel[u] != NONE) {
             const uint32_t r = A.rel[u];
-            const uint32_t idx = E + A.boff[r] + atomicAdd(&A.cursor[r], 1u);
+            const uint32_t idx = E + A.boff[r] + wave_count(A.cursor, r);
             A.S[idx] = A.oldp[u];
             if (idx < U && r >= idx / A.W) atomicAdd(&A.vs[VS_BAD], 1ull);
         }
@@ -531,6 +553,12 @@ __global__ __launch_bounds__(VM_NT) void k_vm_copy_heads(VmArgs A, const uint32_
     }
 }
 
+// Every head walks its segment: page x takes the contents of page pt[x],
+// then x = pt[x], until the source is a pool page, a saved head or the
+// segment's own head.  The next page's contents are loaded before the
+// current one is stored (the next source is never the page being stored:
+// that would close a two-page cycle, which a walk from its head does not
+// run into), so each step's load latency overlaps the previous store.
 template <typename K, bool VAL, int PER>
 __global__ __launch_bounds__(VM_NT) void k_vm_copy_move(VmArgs A, const uint32_t* __restrict__ inv,
                                                         const uint8_t* __restrict__ head, const K* __restrict__ tk,
@@ -543,8 +571,43 @@ __global__ __launch_bounds__(VM_NT) void k_vm_copy_move(VmArgs A, const uint32_t
     for (uint32_t v = blockIdx.x; v < A.N; v += gridDim.x) {
         const uint32_t type = head[v];
         if (type == 0) continue;
-        K rk[PER];
-        uint32_t rv[PER];
+        K hk[PER], ck[PER], nk[PER];
+        uint32_t hv[PER], cv[PER], nv[PER];
+        // contents destined for page x, from page s (or its saved copy)
+        auto fetch = [&](uint32_t s, uint32_t x, K* rk, uint32_t* rv) {
+            const uint32_t len = x == A.N - 1 ? A.n - (x << A.logp) : P;
+            if (s == v && type == 3) {
+#pragma unroll
+                for (int j = 0; j < PER; ++j) {
+                    rk[j] = hk[j];
+                    if (VAL) rv[j] = hv[j];
+                }
+                return;
+            }
+            const bool saved = s < A.nin && head[s] == 1;
+            const K* sk = saved ? tk + (uint64_t)(s / VM_HEAD) * P : pg.kp(s);
+            const uint32_t* sv = VAL ? (saved ? tv + (uint64_t)(s / VM_HEAD) * P : pg.vp(s)) : nullptr;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const uint32_t i = tid + (uint32_t)j * VM_NT;
+                rk[j] = i < len ? sk[i] : K(0);
+                if (VAL) rv[j] = i < len ? sv[i] : 0u;
+            }
+        };
+        auto put = [&](uint32_t x, const K* rk, const uint32_t* rv) {
+            const uint32_t len = x == A.N - 1 ? A.n - (x << A.logp) : P;
+            K* dk = pg.kp(x);
+            uint32_t* dv = VAL ? pg.vp(x) : nullptr;
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                const uint32_t i = tid + (uint32_t)j * VM_NT;
+                if (i < len) {
+                    dk[i] = rk[j];
+                    if (VAL) dv[i] = rv[j];
+                }
+            }
+            moved += len;
+        };
         if (type == 3) {
             // page v holds the page that ends this cycle: keep it in
             // registers (every thread its columns)
@@ -553,37 +616,28 @@ __global__ __launch_bounds__(VM_NT) void k_vm_copy_move(VmArgs A, const uint32_t
 #pragma unroll
             for (int j = 0; j < PER; ++j) {
                 const uint32_t i = tid + (uint32_t)j * VM_NT;
-                rk[j] = i < wl ? pg.kp(v)[i] : K(0);
-                if (VAL) rv[j] = i < wl ? pg.vp(v)[i] : 0u;
+                hk[j] = i < wl ? pg.kp(v)[i] : K(0);
+                if (VAL) hv[j] = i < wl ? pg.vp(v)[i] : 0u;
             }
         }
-        uint32_t x = v, steps = 0;
+        uint32_t x = v, s = A.pt[v], steps = 0;
+        fetch(s, x, ck, cv);
         while (++steps <= A.N + 1) {
-            const uint32_t s = A.pt[x];
-            const uint32_t len = x == A.N - 1 ? A.n - (x << A.logp) : P;
-            K* dk = pg.kp(x);
-            uint32_t* dv = VAL ? pg.vp(x) : nullptr;
-            moved += len;
-            if (s == v && type == 3) {
-#pragma unroll
-                for (int j = 0; j < PER; ++j) {
-                    const uint32_t i = tid + (uint32_t)j * VM_NT;
-                    if (i < len) {
-                        dk[i] = rk[j];
-                        if (VAL) dv[i] = rv[j];
-                    }
-                }
+            const bool end = s >= A.nin || s == v || head[s] == 1;
+            if (end) {
+                put(x, ck, cv);
                 break;
             }
-            const bool saved = s < A.nin && head[s] == 1;
-            const K* sk = saved ? tk + (uint64_t)(s / VM_HEAD) * P : pg.kp(s);
-            const uint32_t* sv = VAL ? (saved ? tv + (uint64_t)(s / VM_HEAD) * P : pg.vp(s)) : nullptr;
-            for (uint32_t i = tid; i < len; i += VM_NT) {
-                dk[i] = sk[i];
-                if (VAL) dv[i] = sv[i];
+            const uint32_t s2 = A.pt[s];
+            fetch(s2, s, nk, nv);
+            put(x, ck, cv);
+#pragma unroll
+            for (int j = 0; j < PER; ++j) {
+                ck[j] = nk[j];
+                if (VAL) cv[j] = nv[j];
             }
-            if (saved || s >= A.nin) break;
             x = s;
+            s = s2;
         }
     }
     if (tid == 0 && moved) atomicAdd(&A.vs[VS_COPY], (unsigned long long)moved);
@@ -627,8 +681,9 @@ static VmLayout vm_layout(uint64_t n, int kb, int has_values, uint64_t window_pa
     L.rmax = (uint32_t)ceil_div(L.N, L.W) + 1;
     const size_t kbytes = kb / 8;
     Plan probe;
-    const size_t plan_bytes = plan_workspace_bytes(n, 1, T, L.P);
-    plan_carve(probe, nullptr, n, 1, T, L.P);
+    const uint32_t ml = n > 0 ? minrun_of(n) : 1u;
+    const size_t plan_bytes = plan_workspace_bytes(n, 1, T, L.P, ml);
+    plan_carve(probe, nullptr, n, 1, T, L.P, ml);
     L.pair_cap = probe.pair_cap;
     L.order_blocks = plan_order_blocks(probe);
     size_t o = 0;
@@ -747,7 +802,7 @@ static hipError_t vm_sort_t(void* keys, uint32_t* values, uint64_t n, int vmode,
     const VmLayout L = vm_layout(n, kb, VAL ? 1 : 0, window_pages);
     Plan P;
     const uint32_t T = tilesort_capacity(kb, VAL ? 1 : 0);
-    plan_carve(P, w + L.plan, n, 1, T, L.P);
+    plan_carve(P, w + L.plan, n, 1, T, L.P, minrun_of(n));
     P.big_min = T;
     P.desc = desc;
     VmArgs A{};

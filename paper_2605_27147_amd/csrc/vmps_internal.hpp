@@ -87,6 +87,7 @@ struct Plan {
     uint32_t T_out;                // merge output tile length
     uint32_t n_tiles_out;          // ceil(n / T_out)
     uint32_t lr_cap, run_cap, ent_cap, seg_cap, chain_blocks, bm_tiles, bm_words;
+    uint32_t h_cap;                // nodes longer than T (HBM nodes)
     // instances
     const int64_t* inst_off64;     // caller offsets (k+1), may be null for k = 1
     bool off_trusted;              // offsets built by the library: valid by construction
@@ -132,8 +133,8 @@ struct Plan {
     uint32_t* hbm_flag;            // run_cap
     uint32_t* hbm_rank;            // run_cap
     uint32_t* hbm_idx;             // run_cap: boundary -> HBM list index
-    uint32_t* hbm_list;            // run_cap
-    uint32_t* hbm_par[2];          // run_cap each
+    uint32_t* hbm_list;            // h_cap
+    uint32_t* hbm_par[2];          // h_cap each
     uint32_t* hbm_val[2];
     uint32_t* hbm_depth;           // points at the final hbm_val buffer
     uint32_t* hbm_tiles;           // run_cap + 1 : output tiles per HBM node, scanned
@@ -143,7 +144,7 @@ struct Plan {
     // merge levels: (HBM node, output tile) pairs grouped by power level
     uint32_t pair_cap;
     uint32_t* level;               // 3 * MAX_LEVEL: pairs per level, first pair, fill position
-    uint32_t* node_base;           // run_cap: first pair of every HBM node
+    uint32_t* node_base;           // h_cap: first pair of every HBM node
     uint32_t* pairs;               // 2 * pair_cap
     uint32_t* splits;              // 2 * pair_cap: merge-path split at both ends of every pair
     // counters (device scalars)
@@ -191,9 +192,12 @@ bool trace_suspend();
 void trace_resume(bool was_on);
 
 // ------------------------------------------------------------ host API --
-size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
+// min_len: a lower bound on every run's length but each instance's last
+// (16 for explicit minruns and several instances; a one-instance sort with
+// the minrun rule passes minrun_of(n)), which sizes the run arrays.
+size_t plan_workspace_bytes(uint64_t n, uint64_t k, uint32_t T, uint32_t T_out, uint32_t min_len = 16);
 // Carve Plan arrays from ws; returns bytes used.
-size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out);
+size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_t T_out, uint32_t min_len = 16);
 
 // Re-lay every level's pairs in position order (nodes left to right, each
 // node's tiles in order).  bsum, boff: MAX_LEVEL * plan_order_blocks(P)

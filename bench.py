@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--path", default="learned", choices=["learned", "plain"])
     ap.add_argument("--log2n", type=int, default=28)
     ap.add_argument("--compare-steps", type=int, default=3, help="steps of the other path (0: skip)")
+    ap.add_argument("--vm-steps", type=int, default=3,
+                    help="steps of the paged (virtual-memory) sort at two window sizes (0: skip)")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -172,6 +174,45 @@ def main():
     if args.compare_steps > 0:
         log(f"{other}: timed {args.compare_steps}")
         other_ms, _ = run_path(vm, other, keys, pristine, args.compare_steps, 1)
+
+    vm_out = None
+    if args.vm_steps > 0:
+        # Virtual-Memory Powersort (Section 4): the same input through the
+        # paged merge levels, no second array; extra memory against the
+        # Pingpong buffer and time against the plain path
+        plain_ms = ms if args.path == "plain" else other_ms
+        nvm = vm.vm_layout(n, vm.U64, False)["pages"]
+        vm_out = {"pingpong_buffer_bytes": 8 * n, "plain_workspace_bytes": vm.sort_workspace_size(n, vm.U64, False),
+                  "plain_ms_per_step": round(plain_ms, 4) if plain_ms else None, "windows": []}
+        for wreq in (0, nvm // 4):
+            lay = vm.vm_layout(n, vm.U64, False, wreq)
+            vws = torch.empty(lay["workspace_bytes"], dtype=torch.uint8, device=dev)
+            vst = torch.zeros(vm.VM_STATS, dtype=torch.int64, device=dev)
+            log(f"paged sort, window {lay['window_pages']} pages: timed {args.vm_steps}")
+            tms = []
+            for i in range(args.vm_steps + 1):
+                keys.copy_(pristine)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                vm.sort_vm_(keys, window_pages=wreq, workspace=vws, stats=vst)
+                e1.record()
+                torch.cuda.synchronize()
+                if i:
+                    tms.append(e0.elapsed_time(e1))
+            assert is_sorted_u64(keys) and int(keys.sum().item()) == checksum, "paged sort: wrong output"
+            s = vst.cpu().tolist()
+            assert s[0] == 0, "paged sort: schedule fault"
+            vms = float(np.mean(tms))
+            vm_out["windows"].append({
+                "window_pages": lay["window_pages"], "page_elems": lay["page_elems"], "pages": lay["pages"],
+                "ms_per_step": round(vms, 4), "value": round(n / (vms / 1e3) / 1e9, 4), "unit": "Gkeys/s",
+                "page_buffer_bytes": lay["buffer_bytes"], "workspace_bytes": lay["workspace_bytes"],
+                "page_buffer_vs_pingpong": round(lay["buffer_bytes"] / (8 * n), 4),
+                "workspace_vs_plain": round(lay["workspace_bytes"] / vm_out["plain_workspace_bytes"], 4),
+                "slowdown_vs_plain": round(vms / plain_ms, 3) if plain_ms else None,
+                "carried": s[1], "copy_moves": s[2], "merged": s[3], "levels": s[4], "page_writes": s[5]})
+            del vws
+        torch.cuda.empty_cache()
 
     value = n / (ms / 1e3) / 1e9
     kinds = {k: v for k, v in trace.items() if v[1] > 0}
@@ -237,6 +278,11 @@ def main():
                           "frac": round(path_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)},
         "breakdown": breakdown,
     }
+    # the goal set for this path: the whole path at 60% of HBM peak
+    out["target"] = {"hbm_frac_goal": 0.6, "path_frac": out["path_roofline"]["frac"],
+                     "dominant_kernel_frac": roofline["frac"], "met": out["path_roofline"]["frac"] >= 0.6}
+    if vm_out is not None:
+        out["vm"] = vm_out
     if other_ms is not None:
         out["compare"] = {"path": other, "ms_per_step": round(other_ms, 4),
                           "value": round(n / (other_ms / 1e3) / 1e9, 4), "unit": "Gkeys/s"}

@@ -191,3 +191,29 @@ def test_full_uniform_2p16_u32_matches_oracle(vm, orc):
     torch.cuda.synchronize()
     assert np.array_equal(keys.cpu().numpy().view(np.uint32), want.astype(np.uint32))
     assert np.array_equal(vals.cpu().numpy().view(np.uint32), wantv)
+
+
+def test_full_vm_lognormal_2p28(vm):
+    """The paged sort (Virtual-Memory Powersort, Section 4) on the
+    benchmark's input (n = 2^28 lognormal u64, seed 5) at the default window
+    with index values, checked by the properties; its key-only run (the
+    benchmark's launch) must equal it, with no schedule fault."""
+    import torch
+    n = 1 << 28
+    _say("full vm: generating", n)
+    x = workloads.lognormal(n, 5)
+    x_dev = torch.from_numpy(x.view(np.int64)).cuda()
+    del x
+    keys = x_dev.clone()
+    vals = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.zeros(vm.VM_STATS, dtype=torch.int64, device="cuda")
+    _say("full vm: sort with iota values")
+    vm.sort_vm_(keys, vals, iota=True, stats=st)
+    assert int(st[0].item()) == 0
+    _check_stable_sort(x_dev, keys, vals)
+    del vals
+    _say("full vm: key-only sort")
+    k2 = x_dev.clone()
+    vm.sort_vm_(k2, stats=st)
+    assert int(st[0].item()) == 0
+    assert bool((k2 == keys).all().item())

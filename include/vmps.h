@@ -113,7 +113,10 @@ size_t vmps_noalloc_scratch_bytes(void);
  * window + 9 extra pages and from input pages whose elements have all been
  * consumed (the paper's free list); a page table maps the array's pages to
  * where they are, and a final Copy permutes the pages into place.  A level
- * runs in rounds of `window` pages.  Memory beyond keys and values: the
+ * runs in rounds of `window` pages.  A page whose merge output is exactly
+ * its own contents (a prefix of the left run below the right run, a suffix
+ * of the right run above the left run) keeps its physical page: no fresh
+ * page and no data movement (the remark on skipping whole pages in Sec. 2).  Memory beyond keys and values: the
  * pool, one page per 64 for the Copy, a few words per page, and the merge
  * schedule (as vmps_sort's).
  *   window_pages : pages per round (0: N/16, at least 64, N = ceil(n/P));
@@ -137,7 +140,11 @@ vmps_status vmps_sort_vm_layout(int64_t n, vmps_dtype kt, int has_values, int64_
  *   [1] elements carried (copied into a fresh page without merging)
  *   [2] elements moved by the final Copy
  *   [3] elements written by the page merges
- *   [4] merge levels that touched pages, [5] page writes of those levels. */
+ *   [4] merge levels that touched pages, [5] fresh pages written by them
+ *   [6] elements of pages a merge left in place (the page-skipping merge:
+ *       the page's output tile is exactly its own contents, so it keeps
+ *       its physical page; [3] + [6] is the merge cost of the nodes longer
+ *       than the LDS tile). */
 #define VMPS_VM_STATS 8
 
 /* Stable sort of keys[0,n) in place with paged merge levels.

@@ -27,7 +27,7 @@ OK, INVALID_ARG, WORKSPACE_TOO_SMALL, UNSUPPORTED, DEVICE = range(5)
 U32, U64 = 0, 1
 VALUES_IOTA = 1
 DESCENDING_RUNS = 2
-VM_STATS = 8  # vmps_sort_vm statistics: faults, carried, copied, merged, levels, page writes
+VM_STATS = 8  # vmps_sort_vm statistics: faults, carried, copied, merged, levels, page writes, kept in place
 CDF_KEEP_TRAINED = 1
 
 

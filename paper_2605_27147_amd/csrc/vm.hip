@@ -45,9 +45,11 @@ enum {
     VC_PARKED,    // pages of this level not released (the input's partial page)
     VC_U,         // pages the level touches
     VC_ROUNDS,    // rounds of the level
+    VC_F,         // touched pages that need a fresh page (not kept in place)
     VC_COUNT = 8
 };
-enum { VS_BAD = 0, VS_CARRY, VS_COPY, VS_MERGED, VS_LEVELS, VS_PAGE_WRITES, VS_COUNT = 8 };
+enum { VS_BAD = 0, VS_CARRY, VS_COPY, VS_MERGED, VS_LEVELS, VS_PAGE_WRITES, VS_KEPT, VS_COUNT = 8 };
+constexpr uint32_t KEPT = 0xFFFFFFFEu;  // release round of a page kept in place
 
 struct VmArgs {
     // level table (position-ordered pairs)
@@ -69,7 +71,9 @@ struct VmArgs {
     uint32_t* pt;           // N: virtual page -> physical page
     uint32_t* S;            // N + emax: free sequence of the level
     uint32_t* pool;         // emax: pool pages
-    uint32_t* rel;          // N: release round of each touched page (NONE: kept)
+    uint32_t* rel;          // N: release round of each touched page (NONE: parked, KEPT: kept in place)
+    uint32_t* need;         // N: 1 when the touched page needs a fresh page
+    uint32_t* fidx;         // N: its index among those (exclusive scan of need)
     uint32_t* oldp;         // N: its physical page before the level
     uint32_t* bins;         // rmax + 2: released pages per round, then (boff) their offsets
     uint32_t* boff;
@@ -208,6 +212,7 @@ __global__ void k_vm_partition(VmArgs A, uint32_t lvl)
             A.vc[VC_U] = 0;
             A.vc[VC_ROUNDS] = 0;
             A.vc[VC_PARKED] = 0;
+            A.vc[VC_F] = 0;
         }
     }
     const uint32_t cnt = A.level[lvl], off = A.level[MAX_LEVEL + lvl];
@@ -255,14 +260,20 @@ __device__ inline uint32_t dest_pair_b(const VmArgs& A, uint32_t base, uint32_t 
     return lo;
 }
 
-// For every touched page: the round after which its old contents are no
-// longer read (the latest round of a pair that takes one of its elements:
-// the last element of each run part in the page decides, since a merge
-// consumes each run in order), and the carry marks of the level's nodes.
-__global__ void k_vm_release(VmArgs A, uint32_t lvl)
+// Pages a merge leaves where they are (the page-skipping merge of the
+// remark on galloping in Sec. 2): a page where every output tile of the
+// level takes exactly the elements at its own positions — a prefix of a
+// left run that precedes every element of the right run, or a suffix of a
+// right run that follows every element of the left run — and the rest is
+// carried (stays anyway).  Every element of such a page stays, so nothing
+// else reads it: it keeps its physical page and is neither written nor
+// released.  Also the carry marks of the level's nodes and the number of
+// touched pages.
+__global__ void k_vm_keep(VmArgs A, uint32_t lvl)
 {
     const uint32_t cnt = A.level[lvl], off = A.level[MAX_LEVEL + lvl];
     const uint32_t P = 1u << A.logp;
+    uint32_t kept = 0;  // merge outputs left in place
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += gridDim.x * blockDim.x) {
         const uint32_t i = off + x;
         const uint32_t q = A.pairs[2 * (uint64_t)i], v = A.pairs[2 * (uint64_t)i + 1];
@@ -271,9 +282,43 @@ __global__ void k_vm_release(VmArgs A, uint32_t lvl)
         if (v == (L >> A.logp) && (L & (P - 1))) A.mark_start[v] = ((uint64_t)lvl << 32) | L;
         if (v == ((R - 1) >> A.logp) && (R & (P - 1))) A.mark_end[v] = ((uint64_t)lvl << 32) | R;
         const uint32_t u = A.upage[i];
+        if (x == cnt - 1) A.vc[VC_U] = min(u + 1, A.N);
+        if (x > 0 && A.pairs[2 * (uint64_t)(i - 1) + 1] == v) continue;  // not the page's first pair
+        if (u >= A.N) continue;  // only from a level table out of position order (counted below)
+        const uint32_t vlo = v << A.logp;
+        bool keep = true;
+        uint32_t covered = 0;
+        for (uint32_t j = i; j < off + cnt && j <= i + 1; ++j) {
+            if (A.pairs[2 * (uint64_t)j + 1] != v) break;
+            const uint32_t tj = A.hbm_list[A.pairs[2 * (uint64_t)j]];
+            const uint32_t Lj = A.lpos[tj], Mj = A.run_start[tj + 1], Rj = A.rpos[tj];
+            const uint32_t o0 = Lj > vlo ? Lj : vlo, o1 = Rj < vlo + P ? Rj : vlo + P;
+            const uint32_t i0 = A.splits[2 * (uint64_t)j], i1 = A.splits[2 * (uint64_t)j + 1];
+            const uint32_t j0 = (o0 - Lj) - i0, j1 = (o1 - Lj) - i1;
+            keep = keep && ((j0 == 0 && j1 == 0) || (i0 == Mj - Lj && i1 == Mj - Lj));
+            covered += o1 - o0;
+        }
+        A.need[u] = keep ? 0u : 1u;
+        if (keep) kept += covered;
+    }
+    if (kept) atomicAdd(&A.vs[VS_KEPT], (unsigned long long)kept);
+}
+
+// For every touched page that is not kept: the round after which its old
+// contents are no longer read (the latest round of a pair that takes one of
+// its elements: the last element of each run part in the page decides,
+// since a merge consumes each run in order).  Rounds count fresh pages.
+__global__ void k_vm_release(VmArgs A, uint32_t lvl)
+{
+    const uint32_t cnt = A.level[lvl], off = A.level[MAX_LEVEL + lvl];
+    const uint32_t P = 1u << A.logp;
+    const uint32_t F = A.vc[VC_F];
+    for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < cnt; x += gridDim.x * blockDim.x) {
+        const uint32_t i = off + x;
+        const uint32_t v = A.pairs[2 * (uint64_t)i + 1];
+        const uint32_t u = A.upage[i];
         if (x == cnt - 1) {
-            const uint32_t U = u + 1, rounds = (U + A.W - 1) / A.W;
-            A.vc[VC_U] = U;
+            const uint32_t rounds = (F + A.W - 1) / A.W;
             A.vc[VC_ROUNDS] = rounds;
             A.rfirst[rounds] = off + cnt;
         }
@@ -282,7 +327,12 @@ __global__ void k_vm_release(VmArgs A, uint32_t lvl)
             atomicAdd(&A.vs[VS_BAD], 1ull);
             continue;
         }
-        if (u % A.W == 0) A.rfirst[u / A.W] = i;
+        if (!A.need[u]) {
+            A.rel[u] = KEPT;
+            continue;
+        }
+        const uint32_t f = A.fidx[u];
+        if (f % A.W == 0) A.rfirst[f / A.W] = i;
         // the page's own round reads it only when part of it is carried
         // (covered by no node of the level)
         uint32_t last = 0, covered = 0;
@@ -295,18 +345,20 @@ __global__ void k_vm_release(VmArgs A, uint32_t lvl)
             const uint32_t lo = Lj > vlo ? Lj : vlo, hi = Rj < vhi ? Rj : vhi;
             covered += hi - lo;
             const uint32_t base = A.node_base[qj], nt = A.tiles[qj];
+            // an element's destination page is never a kept one (a kept
+            // page's elements are its own)
             if (lo < Mj) {  // part of the left run: its last element
                 const uint32_t ea = (hi < Mj ? hi : Mj) - 1;
                 const uint32_t d = dest_pair_a(A, base, nt, ea - Lj);
-                last = max(last, A.upage[d]);
+                last = max(last, A.fidx[A.upage[d]]);
             }
             if (hi > Mj) {  // part of the right run
                 const uint32_t d = dest_pair_b(A, base, nt, Lj, hi - 1 - Mj);
-                last = max(last, A.upage[d]);
+                last = max(last, A.fidx[A.upage[d]]);
             }
         }
         const uint32_t vlen = min(P, A.n - (v << A.logp));
-        if (covered < vlen) last = max(last, u);
+        if (covered < vlen) last = max(last, f);
         const uint32_t old = A.pt[v];
         A.oldp[u] = old;
         if (old == A.nin - 1 && (A.n & (P - 1))) {
@@ -339,19 +391,19 @@ __global__ void k_vm_bins(VmArgs A)
 }
 
 // The free sequence S: the pool, then the released pages by round.  Entry
-// u < U is the fresh page of touched page u, written in round u / W: a
-// released page there must have been released in an earlier round.
+// f < F is the fresh page of the f-th page that needs one, written in round
+// f / W: a released page there must have been released in an earlier round.
 __global__ void k_vm_fill(VmArgs A)
 {
-    const uint32_t E = A.vc[VC_E], U = min(A.vc[VC_U], A.N);
+    const uint32_t E = A.vc[VC_E], U = min(A.vc[VC_U], A.N), F = A.vc[VC_F];
     const uint32_t m = E > U ? E : U;
     for (uint32_t u = blockIdx.x * blockDim.x + threadIdx.x; u < m; u += gridDim.x * blockDim.x) {
         if (u < E) A.S[u] = A.pool[u];
-        if (u < U && A.rel[u] != NONE) {
+        if (u < U && A.rel[u] < KEPT) {
             const uint32_t r = A.rel[u];
             const uint32_t idx = E + A.boff[r] + wave_count(A.cursor, r);
             A.S[idx] = A.oldp[u];
-            if (idx < U && r >= idx / A.W) atomicAdd(&A.vs[VS_BAD], 1ull);
+            if (idx < F && r >= idx / A.W) atomicAdd(&A.vs[VS_BAD], 1ull);
         }
     }
 }
@@ -381,8 +433,8 @@ __global__ __launch_bounds__(NT) void k_vm_round(VmArgs A, uint32_t lvl, uint32_
         const uint32_t i0 = A.splits[2 * (uint64_t)j], i1 = A.splits[2 * (uint64_t)j + 1];
         const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
         const uint32_t up = A.upage[j];
-        if (up >= A.N) continue;  // counted by k_vm_release
-        const uint32_t np = A.S[up];
+        if (up >= A.N || !A.need[up]) continue;  // kept in place (or counted by k_vm_release)
+        const uint32_t np = A.S[A.fidx[up]];
         K* dk = pg.kp(np) + (o0 - vlo);
         uint32_t* dv = VAL ? pg.vp(np) + (o0 - vlo) : nullptr;
         // a range of at most P elements spans at most two pages
@@ -465,20 +517,21 @@ __global__ __launch_bounds__(NT) void k_vm_round(VmArgs A, uint32_t lvl, uint32_
 __global__ void k_vm_level_end(VmArgs A, uint32_t lvl)
 {
     const uint32_t cnt = A.level[lvl], off = A.level[MAX_LEVEL + lvl];
-    const uint32_t U = A.vc[VC_U], En = A.vc[VC_E_NEXT];
+    const uint32_t F = A.vc[VC_F], En = A.vc[VC_E_NEXT];
     const uint32_t m = cnt > En ? cnt : En;
     for (uint32_t x = blockIdx.x * blockDim.x + threadIdx.x; x < m; x += gridDim.x * blockDim.x) {
         if (x < cnt) {
             const uint32_t i = off + x;
             const uint32_t v = A.pairs[2 * (uint64_t)i + 1];
             const uint32_t up = A.upage[i];
-            if ((x == 0 || A.pairs[2 * (uint64_t)(i - 1) + 1] != v) && up < A.N) A.pt[v] = A.S[up];
+            if ((x == 0 || A.pairs[2 * (uint64_t)(i - 1) + 1] != v) && up < A.N && A.need[up])
+                A.pt[v] = A.S[A.fidx[up]];
         }
-        if (x < En && U <= A.N) A.pool[x] = A.S[U + x];
+        if (x < En && F <= A.N) A.pool[x] = A.S[F + x];
     }
     if (blockIdx.x == 0 && threadIdx.x == 0 && cnt) {
         atomicAdd(&A.vs[VS_LEVELS], 1ull);
-        atomicAdd(&A.vs[VS_PAGE_WRITES], (unsigned long long)U);
+        atomicAdd(&A.vs[VS_PAGE_WRITES], (unsigned long long)F);
     }
 }
 
@@ -657,7 +710,8 @@ __global__ void k_vm_stats_out(const VmArgs A, unsigned long long* out)
 struct VmLayout {
     uint32_t P, logp, N, nin, W, emax, ntmp, rmax;
     uint64_t order_blocks, pair_cap;
-    size_t plan, kpool, vpool, ktmp, vtmp, pt, inv, S, pool, rel, oldp, bins, boff, cursor, rfirst, mstart, mend,
+    size_t plan, kpool, vpool, ktmp, vtmp, pt, inv, S, pool, rel, need, fidx, oldp, bins, boff, cursor, rfirst, mstart,
+        mend,
         head, bsum, bscan, pflag, gpage, upage, scan, vc, vs, total;
 };
 
@@ -698,6 +752,8 @@ static VmLayout vm_layout(uint64_t n, int kb, int has_values, uint64_t window_pa
     L.S = take(4ull * (L.N + L.emax));
     L.pool = take(4ull * L.emax);
     L.rel = take(4ull * L.N);
+    L.need = take(4ull * L.N);
+    L.fidx = take(4ull * L.N);
     L.oldp = take(4ull * L.N);
     L.bins = take(4ull * (L.rmax + 2));
     L.boff = take(4ull * (L.rmax + 2));
@@ -740,7 +796,7 @@ uint64_t vm_window_pages(uint64_t n, int key_bits, int has_values, uint64_t wind
 
 // ------------------------------------------------------------ driver --
 template <typename K, bool VAL, int NT, int KI>
-static hipError_t vm_levels(const Plan& P, const VmArgs& A, hipStream_t s)
+static hipError_t vm_levels(const Plan& P, const VmArgs& A, uint32_t* scan, hipStream_t s)
 {
     constexpr uint32_t TO = NT * KI;
     constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
@@ -760,6 +816,8 @@ static hipError_t vm_levels(const Plan& P, const VmArgs& A, hipStream_t s)
     const unsigned rgrid = (unsigned)(2ull * A.W < 4096 ? 2ull * A.W : 4096);
     for (int lvl = (int)top; lvl >= 1; --lvl) {
         k_vm_partition<K><<<pgrid, 256, 0, s>>>(A, (uint32_t)lvl);
+        k_vm_keep<<<lgrid, 256, 0, s>>>(A, (uint32_t)lvl);
+        VMPS_HIP(scan_exclusive_u32(A.need, A.fidx, A.N, A.vc + VC_U, A.vc + VC_F, scan, s));
         k_vm_release<<<lgrid, 256, 0, s>>>(A, (uint32_t)lvl);
         k_vm_bins<<<1, 1024, 0, s>>>(A);
         k_vm_fill<<<lgrid, 256, 0, s>>>(A);
@@ -842,6 +900,8 @@ static hipError_t vm_sort_t(void* keys, uint32_t* values, uint64_t n, int vmode,
     A.S = (uint32_t*)(w + L.S);
     A.pool = (uint32_t*)(w + L.pool);
     A.rel = (uint32_t*)(w + L.rel);
+    A.need = (uint32_t*)(w + L.need);
+    A.fidx = (uint32_t*)(w + L.fidx);
     A.oldp = (uint32_t*)(w + L.oldp);
     A.bins = (uint32_t*)(w + L.bins);
     A.boff = (uint32_t*)(w + L.boff);
@@ -866,7 +926,7 @@ static hipError_t vm_sort_t(void* keys, uint32_t* values, uint64_t n, int vmode,
                                   (uint32_t*)(w + L.upage));
     A.emax = L.emax;
     k_vm_init<<<(unsigned)(ceil_div(L.N, 256) < 2048 ? ceil_div(L.N, 256) : 2048), 256, 0, s>>>(A, L.emax);
-    VMPS_HIP((vm_levels<K, VAL, NT, KI>(P, A, s)));
+    VMPS_HIP((vm_levels<K, VAL, NT, KI>(P, A, scan, s)));
     VMPS_HIP((vm_copy<K, VAL>(A, (uint32_t*)(w + L.inv), w + L.head, w + L.ktmp,
                                VAL ? (uint32_t*)(w + L.vtmp) : nullptr, s)));
     if (stats) k_vm_stats_out<<<1, 64, 0, s>>>(A, stats);

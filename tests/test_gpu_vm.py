@@ -87,11 +87,12 @@ def _check(vm, orc, x, values, window, desc, bits):
     if vals is not None:
         assert np.array_equal(_np(vals, np.uint32), wantv)
     assert s[0] == 0, "a page was handed out before it was free"
-    # the page merges write each node longer than a tile once
+    # the page merges write each node longer than a tile once, but for the
+    # pages a merge leaves in place
     T = _tile(bits, values != "none")
     b = orc.extract_runs(x, desc=desc)
     _, _, _, _, m_hbm = orc.plan(b, n, orc.run_powers(b, n), T)
-    assert s[3] == m_hbm
+    assert s[3] + s[6] == m_hbm
     assert 0 <= s[2] <= n and s[1] >= 0
     return s
 
@@ -163,3 +164,26 @@ def test_vm_workspace_reuse(vm, orc):
         keys = _t(x)
         vm.sort_vm_(keys, window_pages=5, workspace=ws)
         assert np.array_equal(_np(keys, np.uint32), np.sort(x)), n
+
+
+def test_vm_pages_kept_in_place(vm, orc):
+    """The page-skipping merge: when runs of a sorted sequence overlap only
+    where they meet, almost every merge output stays where it is (kept
+    pages, no fresh page, no Copy for them); the output and the merge cost
+    are unchanged."""
+    for bits in (32, 64):
+        dt = np.uint32 if bits == 32 else np.uint64
+        # a sorted sequence with a small step back every 5000 keys: runs of
+        # 5000 whose merges interleave two keys each
+        x = np.arange(1 << 19, dtype=np.int64) + 10
+        x[::5000] -= 2
+        s = _check(vm, orc, x.astype(dt), "iota", 0, False, bits)
+        _say("steps", bits, s.tolist())
+        assert s[6] > 0.75 * (s[3] + s[6])
+        # blocks of a sorted sequence in shuffled order: a merge of a lower
+        # block with a higher one keeps its pages, the reverse moves them all
+        x = np.arange(1 << 19, dtype=np.int64).reshape(64, -1)
+        x = x[np.random.default_rng(bits).permutation(64)].reshape(-1).astype(dt)
+        s = _check(vm, orc, x, "input", 0, False, bits)
+        _say("blocks", bits, s.tolist())
+        assert s[6] > 0 and s[3] > 0

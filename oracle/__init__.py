@@ -216,6 +216,20 @@ def vm_powersort(keys, vals=None, page: int = 0, ell: int = 0, desc: bool = Fals
     return out, v, st.as_dict(), vst.as_dict(), merges
 
 
+def records_sort(records, key_offset: int, key_bytes: int, desc: bool = False):
+    """Stable sort of records (an (n, record_bytes) uint8 array) by the
+    little-endian unsigned key field of key_bytes bytes at key_offset: the
+    record types of Sec. 5 sorted as whole elements.  The order is Algorithm
+    1's on the keys (indices as values, so equal keys keep input order);
+    the records are then taken in that order."""
+    rec = np.ascontiguousarray(records, dtype=np.uint8)
+    n = rec.shape[0]
+    field = rec[:, key_offset:key_offset + key_bytes].copy()
+    keys = field.view(np.uint32 if key_bytes == 4 else np.uint64).reshape(n)
+    _, perm, _, _ = powersort(keys, np.arange(n, dtype=np.uint32), variant=PINGPONG | (DESC_RUNS if desc else 0))
+    return rec[perm.astype(np.int64)]
+
+
 def segmented_powersort(keys, offsets, vals=None, variant: int = PINGPONG, ell: int = 0):
     """Every segment [offsets[s], offsets[s+1]) sorted as its own instance
     (ell <= 0: the minrun rule for the segment's length)."""

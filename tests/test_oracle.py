@@ -532,3 +532,36 @@ def test_vm_pages_and_memory(orc):
                 assert vs["meta_words"] <= vs["input_pages"] + vs["extra_pages"]
                 extra_words = vs["extra_pages"] * P * t + vs["meta_words"]
                 assert extra_words <= 4 * math.sqrt(n * t * math.log2(n)), (n, kind, t, extra_words)
+
+
+# --- large records (Sec. 5 record types) ------------------------------------
+
+def test_records_golden(orc):
+    for (off,), words, want in read_golden("records.txt"):
+        rec = np.array(words, dtype=np.uint32).reshape(-1, 2).view(np.uint8)
+        got = orc.records_sort(rec, off, 4).view(np.uint32).reshape(-1)
+        assert got.tolist() == want
+
+
+def test_records_bruteforce_and_stability(orc):
+    """Every permutation of n <= 6 keys with repeats (keys in {0,1,2}),
+    30-word records whose payload words record the input position: the
+    output keys are non-decreasing, each record is intact, and equal keys
+    keep input order (the definition of a stable sort, checked directly);
+    with u64 keys at a word offset inside the record as well."""
+    for n in range(0, 7):
+        for w in itertools.product(range(3), repeat=n):
+            rec = np.zeros((n, 30), dtype=np.uint32)
+            rec[:, 5] = np.array(w, dtype=np.uint32)
+            rec[:, 0] = np.arange(n)
+            rec[:, 29] = np.arange(n) * 7 + 1
+            out = orc.records_sort(rec.view(np.uint8), 20, 4).view(np.uint32).reshape(n, 30)
+            k, pos = out[:, 5].astype(np.int64), out[:, 0].astype(np.int64)
+            assert np.all(np.diff(k) >= 0)
+            assert np.array_equal(out, rec[pos])
+            assert np.all((np.diff(k) > 0) | (np.diff(pos) > 0))
+            rec64 = np.zeros((n, 16), dtype=np.uint64)
+            rec64[:, 3] = np.array(w, dtype=np.uint64) << np.uint64(40)
+            rec64[:, 0] = np.arange(n)
+            out64 = orc.records_sort(rec64.view(np.uint8), 24, 8).view(np.uint64).reshape(n, 16)
+            assert np.array_equal(out64, rec64[np.argsort(rec64[:, 3], kind="stable")])

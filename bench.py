@@ -126,6 +126,8 @@ def main():
     ap.add_argument("--compare-steps", type=int, default=3, help="steps of the other path (0: skip)")
     ap.add_argument("--vm-steps", type=int, default=3,
                     help="steps of the paged (virtual-memory) sort at two window sizes (0: skip)")
+    ap.add_argument("--records-log2", type=int, default=24,
+                    help="records of 120 bytes sorted by a u64 key field (0: skip)")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -214,6 +216,51 @@ def main():
             del vws
         torch.cuda.empty_cache()
 
+    rec_out = None
+    if args.records_log2 > 0:
+        # large records (the 30-word element types of Sec. 5, hypothesis H4):
+        # 120-byte records of random 32-bit words sorted by the u64 in words
+        # 2-3, as (key, index) pairs and one gather, against the bytes a
+        # record-moving Pingpong sort would need
+        nr = 1 << args.records_log2
+        g = torch.Generator(device=dev)
+        g.manual_seed(7)
+        rec = torch.randint(100, 10**9, (nr, 30), dtype=torch.int32, device=dev, generator=g)
+        rec[:, 0] = torch.arange(nr, dtype=torch.int32, device=dev)
+        out_rec = torch.empty_like(rec)
+        rws = torch.empty(vm.records_workspace_size(nr, vm.U64), dtype=torch.uint8, device=dev)
+        log(f"records: 2^{args.records_log2} x 120 bytes")
+        tms = []
+        for i in range(4):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vm.sort_records(rec, 8, vm.U64, out=out_rec, workspace=rws)
+            e1.record()
+            torch.cuda.synchronize()
+            if i:
+                tms.append(e0.elapsed_time(e1))
+        keys_r = out_rec[:, 2:4].contiguous().view(torch.int64).reshape(-1)
+        assert is_sorted_u64(keys_r), "records: keys out of order"
+        idx = out_rec[:, 0].to(torch.int64)
+        assert bool((rec[idx] == out_rec).all().item()), "records: a record changed"
+        sch_r = vm.sort_schedule(rec[:, 2:4].contiguous().view(torch.int64).reshape(-1), has_values=True)
+        m_r = int((sch_r["node_r"].astype(np.int64) - sch_r["node_l"].astype(np.int64)).sum())
+        rms = float(np.mean(tms))
+        # algorithmic bytes: key extraction (8 B read per record), the (key,
+        # index) sort (bitmap 8, tile pass 8 + 12, levels 2 * 12 per element
+        # per merge beyond the tile), the gather (120 read + 120 written)
+        pairs_then_gather = nr * (8 + 8 + 8 + 12 + 240) + 2 * 12 * m_r
+        # the same sort moving whole records: bitmap on the keys, tile pass
+        # reading and writing records, every merge beyond the tile moving them
+        record_merging = nr * (8 + 240) + 2 * 120 * m_r
+        rec_out = {"records": nr, "record_bytes": 120, "key": "u64 in words 2-3", "ms_per_step": round(rms, 4),
+                   "Mrecords_per_s": round(nr / (rms / 1e3) / 1e6, 1),
+                   "record_GB_per_s": round(nr * 240 / (rms / 1e3) / 1e9, 1), "merge_cost_hbm": m_r,
+                   "bytes_pairs_then_gather": pairs_then_gather, "bytes_record_merging": record_merging,
+                   "byte_ratio": round(record_merging / pairs_then_gather, 2)}
+        del rec, out_rec, rws
+        torch.cuda.empty_cache()
+
     value = n / (ms / 1e3) / 1e9
     kinds = {k: v for k, v in trace.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
@@ -283,6 +330,8 @@ def main():
                      "dominant_kernel_frac": roofline["frac"], "met": out["path_roofline"]["frac"] >= 0.6}
     if vm_out is not None:
         out["vm"] = vm_out
+    if rec_out is not None:
+        out["records"] = rec_out
     if other_ms is not None:
         out["compare"] = {"path": other, "ms_per_step": round(other_ms, 4),
                           "value": round(n / (other_ms / 1e3) / 1e9, 4), "unit": "Gkeys/s"}

@@ -156,6 +156,27 @@ vmps_status vmps_sort_vm_layout(int64_t n, vmps_dtype kt, int has_values, int64_
 vmps_status vmps_sort_vm(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags,
                          int64_t window_pages, void* ws, size_t ws_bytes, uint64_t* stats, void* stream);
 
+/* ---- Large records (the 30-word record types of Sec. 5; hypothesis H4) --
+ * Stable sort of n records of record_bytes bytes by a key field (u32 or
+ * u64, kt) at byte key_offset: the (key, index) pairs are sorted with
+ * vmps_sort's path (runs, powers, Pingpong merges), then every record is
+ * gathered once into `out`.  Each record is read and written once instead
+ * of once per merge level it passes through.
+ *   records, out : device, n * record_bytes bytes each, 4-byte aligned, not
+ *                  overlapping (8-byte aligned with record_bytes % 8 == 0
+ *                  moves 8-byte words).
+ *   record_bytes : multiple of 4 (of 8, and records 8-byte aligned, with
+ *                  u64 keys), at least the key size; key_offset a multiple
+ *                  of the key size with key_offset + key size <=
+ *                  record_bytes.
+ *   flags        : 0 or VMPS_DESCENDING_RUNS.
+ *   ws           : vmps_sort_records_workspace_size() bytes, 256-aligned.
+ * Asynchronous on `stream`.  Errors: INVALID_ARG, WORKSPACE_TOO_SMALL,
+ * DEVICE. */
+vmps_status vmps_sort_records_workspace_size(int64_t n, vmps_dtype kt, size_t* bytes);
+vmps_status vmps_sort_records(const void* records, void* out, int64_t n, int32_t record_bytes, int32_t key_offset,
+                              vmps_dtype kt, uint32_t flags, void* ws, size_t ws_bytes, void* stream);
+
 /* Workspace of vmps_merge. */
 vmps_status vmps_merge_workspace_size(int64_t na, int64_t nb, vmps_dtype kt, size_t* bytes);
 

@@ -127,6 +127,8 @@ def load_library():
         "vmps_graph_launch": (st, [vp, vp]),
         "vmps_graph_destroy": (st, [vp]),
         "vmps_sort_vm_layout": (st, [i64, st, st, i64, ctypes.POINTER(VmLayout)]),
+        "vmps_sort_records_workspace_size": (st, [i64, st, ctypes.POINTER(sz)]),
+        "vmps_sort_records": (st, [vp, vp, i64, i32, i32, st, u32, vp, sz, vp]),
         "vmps_sort_vm": (st, [vp, vp, i64, st, u32, i64, vp, sz, vp, vp]),
         "vmps_trace_enable": (st, [st]),
         "vmps_trace_collect": (st, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64), i32]),
@@ -305,6 +307,31 @@ def sort_vm_(keys, values=None, *, iota: bool = False, desc: bool = False, windo
     _check(lib.vmps_sort_vm(_ptr(keys), _ptr(values), n, kt, flags, window_pages, _ptr(ws), ws.numel(), _ptr(stats),
                             _stream(keys.device)), "vmps_sort_vm")
     return keys
+
+
+def records_workspace_size(n: int, key_dtype_code: int) -> int:
+    sz = ctypes.c_size_t(0)
+    _check(load_library().vmps_sort_records_workspace_size(n, key_dtype_code, ctypes.byref(sz)),
+           "vmps_sort_records_workspace_size")
+    return sz.value
+
+
+def sort_records(records, key_offset: int, key_dtype_code: int, *, out=None, desc: bool = False, workspace=None):
+    """Stable sort of records (a contiguous GPU tensor whose last dimension
+    holds one record's bytes or words) by the u32/u64 key field at byte
+    key_offset; returns `out` (a new tensor of the same shape unless given)."""
+    lib = load_library()
+    _require_cuda(records, out)
+    n = records.shape[0] if records.dim() > 0 else 0
+    rb = records.numel() * records.element_size() // max(n, 1)
+    if out is None:
+        out = _torch().empty_like(records)
+    ws = workspace if workspace is not None else _workspace(records_workspace_size(n, key_dtype_code),
+                                                            records.device)
+    _check(lib.vmps_sort_records(_ptr(records), _ptr(out), n, rb, key_offset, key_dtype_code,
+                                 DESCENDING_RUNS if desc else 0, _ptr(ws), ws.numel(), _stream(records.device)),
+           "vmps_sort_records")
+    return out
 
 
 def noalloc_scratch_bytes() -> int:

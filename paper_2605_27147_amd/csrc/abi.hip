@@ -200,6 +200,42 @@ vmps_status vmps_sort(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, ui
     return sort_in_workspace(keys, values, n, kt, flags, ws, ws_bytes, (hipStream_t)stream, true);
 }
 
+vmps_status vmps_sort_records_workspace_size(int64_t n, vmps_dtype kt, size_t* bytes)
+{
+    if (!bytes || n < 0 || (uint64_t)n >= (1ull << 32) || (kt != VMPS_U32 && kt != VMPS_U64))
+        return VMPS_ERR_INVALID_ARG;
+    *bytes = records_workspace_bytes((uint64_t)n, key_bits_of(kt)) +
+             sort_layout((uint64_t)n, 1, kt, 1, rule_min_len((uint64_t)n)).total;
+    return VMPS_OK;
+}
+
+vmps_status vmps_sort_records(const void* records, void* out, int64_t n, int32_t record_bytes, int32_t key_offset,
+                              vmps_dtype kt, uint32_t flags, void* ws, size_t ws_bytes, void* stream)
+{
+    if (n < 0 || (uint64_t)n >= (1ull << 32) || (kt != VMPS_U32 && kt != VMPS_U64)) return VMPS_ERR_INVALID_ARG;
+    if (flags & ~VMPS_DESCENDING_RUNS) return VMPS_ERR_INVALID_ARG;
+    const int32_t kbytes = (int32_t)key_bytes(kt);
+    if (record_bytes < kbytes || record_bytes % 4 || key_offset < 0 || key_offset % kbytes ||
+        key_offset + kbytes > record_bytes)
+        return VMPS_ERR_INVALID_ARG;
+    if (n == 0) return VMPS_OK;
+    if (!records || !out || ((uintptr_t)records & 3) || ((uintptr_t)out & 3)) return VMPS_ERR_INVALID_ARG;
+    if (kbytes == 8 && (record_bytes % 8 || ((uintptr_t)records & 7))) return VMPS_ERR_INVALID_ARG;
+    const size_t total = (size_t)n * (size_t)record_bytes;
+    if (ranges_overlap(records, total, out, total)) return VMPS_ERR_INVALID_ARG;
+    size_t need = 0;
+    vmps_sort_records_workspace_size(n, kt, &need);
+    if (!ws || ws_bytes < need) return VMPS_ERR_WORKSPACE_TOO_SMALL;
+    if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
+    const int kb = key_bits_of(kt);
+    vmps_status st = VMPS_OK;
+    const vmps_status g = guarded([&] {
+        return records_enqueue(records, out, (uint64_t)n, (uint32_t)record_bytes, (uint32_t)key_offset, kb, flags, ws,
+                               need - records_workspace_bytes((uint64_t)n, kb), (hipStream_t)stream, &st);
+    });
+    return g != VMPS_OK ? g : st;
+}
+
 vmps_status vmps_sort_vm_layout(int64_t n, vmps_dtype kt, int has_values, int64_t window_pages,
                                 vmps_vm_layout* out)
 {

@@ -293,6 +293,12 @@ uint64_t vm_window_pages(uint64_t n, int key_bits, int has_values, uint64_t wind
 hipError_t vm_sort_enqueue(void* keys, uint32_t* values, uint64_t n, int key_bits, int vmode, uint32_t desc,
                            uint64_t window_pages, void* ws, unsigned long long* stats, hipStream_t s);
 
+// Large records (records.hip): key extraction, (key, index) sort in the
+// workspace after the keys and indices, gather.  *st gets the sort's status.
+size_t records_workspace_bytes(uint64_t n, int key_bits);
+hipError_t records_enqueue(const void* in, void* out, uint64_t n, uint32_t rb, uint32_t off, int key_bits,
+                           uint32_t flags, void* ws, size_t sort_ws_bytes, hipStream_t s, vmps_status* st);
+
 // The whole stable sort of one array with a caller-provided workspace
 // (vmps_sort's body after its argument checks; allow_host_wait = false never
 // waits on the host and allocates nothing, whatever the tuning says).

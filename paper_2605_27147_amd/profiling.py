@@ -2,7 +2,7 @@
 
     python -m paper_2605_27147_amd.profiling stats   DIR OUT.txt --title T --command C
     python -m paper_2605_27147_amd.profiling traffic FETCH_DIR WRITE_DIR OUT.json --kind K --copy-bytes N
-        [--command C ...]
+        [--command C ...] [--calibrate FETCH_DIR2 WRITE_DIR2]
 
 `stats` turns a `rocprofv3 --kernel-trace --stats --output-format csv` output
 directory into a short text table (kernel, calls, total ms, average us, %).
@@ -40,6 +40,9 @@ KINDS = {
     "scatter": (r"k_part_scatter[12]<", ["learned.hip", "vmps_internal.hpp"]),
     "histogram": (r"k_part_hist1<", ["learned.hip", "vmps_internal.hpp"]),
     "train": (r"k_cdf_step<", ["learned.hip", "vmps_internal.hpp"]),
+    "vm_round": (r"k_vm_round<", ["vm.hip", "merge_tile.hpp", "vmps_internal.hpp"]),
+    "vm_copy": (r"k_vm_copy_move<", ["vm.hip", "vmps_internal.hpp"]),
+    "rec_gather": (r"k_rec_gather<", ["records.hip", "vmps_internal.hpp"]),
 }
 COPY_PATTERN = r"copyBuffer"
 
@@ -131,10 +134,15 @@ def _largest_copies(recs: list) -> list:
     return [r for r in copies if r["grid"] == g]
 
 
-def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int, commands: list) -> dict:
+def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int, commands: list,
+            calibrate: list = None) -> dict:
+    """calibrate: (fetch_dir, write_dir) of another run whose largest copies
+    are all of copy_bytes (when this run's copies differ in size)."""
     pat = re.compile(KINDS[kind][0])
     fetch = _counters(fetch_dir, "FETCH_SIZE")
     write = _counters(write_dir, "WRITE_SIZE")
+    cal_f = _counters(calibrate[0], "FETCH_SIZE") if calibrate else fetch
+    cal_w = _counters(calibrate[1], "WRITE_SIZE") if calibrate else write
 
     def avg(recs, p):
         v = [r["kib"] * 1024.0 for r in recs if p.search(r["name"])]
@@ -143,8 +151,8 @@ def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int
         return sum(v) / len(v), len(v)
 
     anything = re.compile(".")
-    cf, _ = avg(_largest_copies(fetch), anything)
-    cw, _ = avg(_largest_copies(write), anything)
+    cf, _ = avg(_largest_copies(cal_f), anything)
+    cw, _ = avg(_largest_copies(cal_w), anything)
     sf, sw = copy_bytes / cf, copy_bytes / cw
     f, nf = avg(fetch, pat)
     w, nw = avg(write, pat)
@@ -157,7 +165,8 @@ def traffic(fetch_dir: str, write_dir: str, out: str, kind: str, copy_bytes: int
         "traffic_bytes_per_launch": f * sf + w * sw,
         "scale_fetch": sf,
         "scale_write": sw,
-        "calibration": f"device copy of {copy_bytes} bytes: FETCH_SIZE x{sf:.3f}, WRITE_SIZE x{sw:.3f}",
+        "calibration": f"device copy of {copy_bytes} bytes: FETCH_SIZE x{sf:.3f}, WRITE_SIZE x{sw:.3f}"
+                       + (f" (copies of the runs in {calibrate[0]}, {calibrate[1]})" if calibrate else ""),
         "sources": source_hashes(kind),
         "commands": commands,
     }
@@ -206,6 +215,7 @@ def main(argv=None) -> int:
     t.add_argument("--kind", required=True, choices=sorted(KINDS))
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--command", action="append", default=[])
+    t.add_argument("--calibrate", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"), default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         stats(a.dir, a.out, a.title, a.command)
@@ -213,7 +223,7 @@ def main(argv=None) -> int:
         r = counters(a.dirs, a.out, a.kind, a.command)
         print(json.dumps(r["per_launch"]))
     else:
-        r = traffic(a.fetch_dir, a.write_dir, a.out, a.kind, a.copy_bytes, a.command)
+        r = traffic(a.fetch_dir, a.write_dir, a.out, a.kind, a.copy_bytes, a.command, a.calibrate)
         print(json.dumps({k: r[k] for k in ("kind", "traffic_bytes_per_launch", "calibration")}))
     return 0
 

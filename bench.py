@@ -19,6 +19,7 @@ CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
 import sys
@@ -128,6 +129,8 @@ def main():
                     help="steps of the paged (virtual-memory) sort at two window sizes (0: skip)")
     ap.add_argument("--records-log2", type=int, default=24,
                     help="records of 120 bytes sorted by a u64 key field (0: skip)")
+    ap.add_argument("--batch-nseg", type=int, default=4096,
+                    help="arrays of the batched u32 workload sorted in one segmented call (0: skip)")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -293,6 +296,53 @@ def main():
         del rec, out_rec, rws
         torch.cuda.empty_cache()
 
+    batch_out = None
+    if args.batch_nseg > 0:
+        # the batched workload: arrays of 2^6..2^20 u32 keys (log-uniform
+        # lengths; even arrays uniform, odd ones Zipf), one segmented call
+        log(f"batch: generating {args.batch_nseg} arrays")
+        bk, boff = workloads.batch32(args.batch_nseg, 1)
+        nb = int(bk.size)
+        src_b = torch.from_numpy(bk.view(np.int32)).to(dev)
+        off_b = torch.from_numpy(boff).to(dev)
+        kb_ = torch.empty_like(src_b)
+        need = ctypes.c_size_t(0)
+        vm.load_library().vmps_segmented_sort_workspace_size(nb, args.batch_nseg, vm.U32, 0, ctypes.byref(need))
+        bws = torch.empty(need.value, dtype=torch.uint8, device=dev)
+        tms = []
+        for i in range(4):
+            kb_.copy_(src_b)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            vm.segmented_sort_(kb_, off_b, workspace=bws)
+            e1.record()
+            torch.cuda.synchronize()
+            if i:
+                tms.append(e0.elapsed_time(e1))
+        bms = float(np.mean(tms))
+        # algorithmic bytes: the tile pass reads and writes every key; arrays
+        # longer than the LDS tile (16384 u32 keys) also have the descent
+        # bitmap read and their merges beyond the tile (M_HBM) read and write
+        T32 = 16384
+        m_b, big = 0, 0
+        for s in range(args.batch_nseg):
+            a, b = int(boff[s]), int(boff[s + 1])
+            if b - a > T32:
+                big += b - a
+                sch_b = vm.sort_schedule(src_b[a:b].contiguous())
+                m_b += int((sch_b["node_r"].astype(np.int64) - sch_b["node_l"].astype(np.int64)).sum())
+        b_alg = 4 * big + 8 * nb + 8 * m_b
+        out_b = kb_.cpu().numpy().view(np.uint32)
+        for s in range(0, args.batch_nseg, 97):
+            a, b = int(boff[s]), int(boff[s + 1])
+            assert np.array_equal(out_b[a:b], np.sort(bk[a:b])), "batch: segment not sorted"
+        batch_out = {"arrays": args.batch_nseg, "keys": nb, "key_bits": 32, "ms_per_step": round(bms, 4),
+                     "value": round(nb / (bms / 1e3) / 1e9, 4), "unit": "Gkeys/s", "merge_cost_hbm": m_b,
+                     "bytes_alg": b_alg, "achieved_GBs": round(b_alg / (bms / 1e3) / 1e9, 1),
+                     "frac": round(b_alg / (bms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del src_b, off_b, kb_, bws
+        torch.cuda.empty_cache()
+
     value = n / (ms / 1e3) / 1e9
     kinds = {k: v for k, v in trace.items() if v[1] > 0}
     dom = max(kinds, key=lambda k: kinds[k][0])
@@ -364,6 +414,8 @@ def main():
         out["vm"] = vm_out
     if rec_out is not None:
         out["records"] = rec_out
+    if batch_out is not None:
+        out["batch"] = batch_out
     if other_ms is not None:
         out["compare"] = {"path": other, "ms_per_step": round(other_ms, 4),
                           "value": round(n / (other_ms / 1e3) / 1e9, 4), "unit": "Gkeys/s"}

@@ -437,7 +437,7 @@ def trace_collect() -> dict:
     return {name: (ms[i], cnt[i]) for i, name in enumerate(TRACE_KINDS)}
 
 
-def segmented_sort_(keys, offsets, values=None):
+def segmented_sort_(keys, offsets, values=None, workspace=None):
     """Independent stable sorts of keys[offsets[s]:offsets[s+1]] (offsets: int64 on the GPU)."""
     lib = load_library()
     _require_cuda(keys, values, offsets)
@@ -447,7 +447,9 @@ def segmented_sort_(keys, offsets, values=None):
     need = ctypes.c_size_t(0)
     _check(lib.vmps_segmented_sort_workspace_size(total, max(nseg, 0), kt, int(values is not None),
                                                   ctypes.byref(need)), "vmps_segmented_sort_workspace_size")
-    ws = _workspace(need.value, keys.device)
+    if workspace is not None and workspace.numel() < need.value:
+        raise ValueError("workspace too small")
+    ws = workspace if workspace is not None else _workspace(need.value, keys.device)
     _check(lib.vmps_segmented_sort(_ptr(keys), _ptr(values), _ptr(offsets), nseg, total, kt, _ptr(ws),
                                    ws.numel(), _stream(keys.device)), "vmps_segmented_sort")
     return keys

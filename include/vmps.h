@@ -414,10 +414,14 @@ typedef struct {
                                the non-empty levels; 0 (default): fully
                                asynchronous, every level launched (empty
                                ones return at once); 0 or 1 only */
+    int32_t merge_ki;       /* outputs per thread of an HBM merge-level tile
+                               (256 threads): 8 or 16 (0: 16, or 8 for 64-bit
+                               keys with values); the workspace sizes allow
+                               either.  The paged sort keeps the default. */
 } vmps_tuning;
 
-/* t == NULL restores the defaults.  Negative fields, bucket_div > 64 or
- * host_wait outside {0, 1} -> INVALID_ARG. */
+/* t == NULL restores the defaults.  Negative fields, bucket_div > 64,
+ * host_wait outside {0, 1} or merge_ki outside {0, 8, 16} -> INVALID_ARG. */
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t);
 vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t);
 

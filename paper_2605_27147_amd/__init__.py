@@ -53,7 +53,7 @@ class CdfModel(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
-                ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32)]
+                ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32), ("merge_ki", ctypes.c_int32)]
 
 
 class VmLayout(ctypes.Structure):
@@ -157,7 +157,10 @@ def _apply_autotune(lib, path: str = AUTOTUNE_PATH):
     if arch is None or table.get("arch") != arch:
         return
     for e in table.get("entries", []):
-        t = Tuning(int(e.get("tile_wg_per_cu", 0)), int(e.get("merge_grid", 0)), int(e.get("bucket_div", 0)), 0)
+        if e.get("merge_ki", 0) not in (0, 8, 16):
+            continue
+        t = Tuning(int(e.get("tile_wg_per_cu", 0)), int(e.get("merge_grid", 0)), int(e.get("bucket_div", 0)), 0,
+                   int(e.get("merge_ki", 0)))
         kt = U64 if e["dtype"] == "u64" else U32
         lib.vmps_set_tuning(kt, int(bool(e["values"])), ctypes.byref(t))
 
@@ -173,8 +176,8 @@ def _gpu_arch():
 
 
 def set_tuning(dtype_code: int, has_values: bool, tile_wg_per_cu: int = 0, merge_grid: int = 0,
-               bucket_div: int = 0, host_wait: int = 0):
-    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, host_wait)
+               bucket_div: int = 0, host_wait: int = 0, merge_ki: int = 0):
+    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, host_wait, merge_ki)
     _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_set_tuning")
 
 
@@ -186,7 +189,7 @@ def get_tuning(dtype_code: int, has_values: bool) -> dict:
     t = Tuning()
     _check(load_library().vmps_get_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_get_tuning")
     return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div,
-            "host_wait": t.host_wait}
+            "host_wait": t.host_wait, "merge_ki": t.merge_ki}
 
 
 def status_string(s: int) -> str:

@@ -10,6 +10,12 @@ fastest into the JSON table the binding loads with the library
 
   u64 keys (learned path): lognormal keys, n = 2^log2n
   u32 keys (segmented path): `batch` arrays of log-uniform length in [2^6, 2^20]
+  u64 keys with values, u32 keys with values (plain path): (key, index)
+      pairs of n = 2^(log2n - 2) lognormal / uniform keys
+
+The candidates cover the persistent tile pass's workgroups per CU, the
+merge-level grid, the merge tile's outputs per thread (merge_ki 8 or 16:
+tiles of 2048 or 4096 elements) and, for the learned path, the bucket size.
 """
 from __future__ import annotations
 
@@ -89,14 +95,14 @@ def main(argv=None):
     keys = torch.empty_like(pristine)
     cfg = vm.learned_default_config(n, vm.U64)
     ws = torch.empty(vm.learned_workspace_size(n, vm.U64, False, cfg) + (1 << 20), dtype=torch.uint8, device=dev)
-    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": b}
-             for t, m, b in itertools.product([0, 1], [1024, 2048, 4096], [2, 3])]
+    fields = ("tile_wg_per_cu", "merge_grid", "bucket_div", "merge_ki")
+    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": b, "merge_ki": k}
+             for t, m, b, k in itertools.product([0, 1], [1024, 2048], [0, 4], [0, 8])]
     best, res = tune(space,
                      lambda c: vm.set_tuning(vm.U64, False, **c), lambda: vm.reset_tuning(vm.U64, False),
                      lambda: vm.sort_learned_(keys, workspace=ws, read_stats=False),
                      lambda: keys.copy_(pristine), lambda: keys, a.steps)
-    entries.append({"dtype": "u64", "values": False, **{k: best[k] for k in ("tile_wg_per_cu", "merge_grid",
-                                                                          "bucket_div")},
+    entries.append({"dtype": "u64", "values": False, **{k: best[k] for k in fields},
                     "workload": f"learned sort, lognormal n=2^{a.log2n}", "ms": best["ms"], "candidates": res})
     del pristine, keys, ws
     torch.cuda.empty_cache()
@@ -106,15 +112,38 @@ def main(argv=None):
     pristine = torch.from_numpy(kb.view(np.int32)).to(dev)
     offs = torch.from_numpy(off).to(dev)
     keys = torch.empty_like(pristine)
-    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0}
-             for t, m in itertools.product([0, 1], [1024, 2048, 4096])]
+    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k}
+             for t, m, k in itertools.product([0, 1], [1024, 2048, 4096], [0, 8])]
     best, res = tune(space,
                      lambda c: vm.set_tuning(vm.U32, False, **c), lambda: vm.reset_tuning(vm.U32, False),
                      lambda: vm.segmented_sort_(keys, offs), lambda: keys.copy_(pristine), lambda: keys, a.steps)
-    entries.append({"dtype": "u32", "values": False, **{k: best[k] for k in ("tile_wg_per_cu", "merge_grid",
-                                                                          "bucket_div")},
+    entries.append({"dtype": "u32", "values": False, **{k: best[k] for k in fields},
                     "workload": f"segmented sort, {a.batch} arrays, {kb.size} keys", "ms": best["ms"],
                     "candidates": res})
+    del pristine, offs, keys
+    torch.cuda.empty_cache()
+
+    # (key, index) pairs, plain path: u64 and u32 keys
+    npairs = 1 << (a.log2n - 2)
+    for dtype, code, gen, ki_alt in (("u64", vm.U64, lambda: workloads.lognormal(npairs, 8), 16),
+                                     ("u32", vm.U32, lambda: workloads.uniform(npairs, 32, 9), 8)):
+        xk = gen()
+        pristine = torch.from_numpy(xk.view(np.int64 if dtype == "u64" else np.int32)).to(dev)
+        keys = torch.empty_like(pristine)
+        vals = torch.empty(npairs, dtype=torch.int32, device=dev)
+        pws = torch.empty(vm.sort_workspace_size(npairs, code, True), dtype=torch.uint8, device=dev)
+        space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k}
+                 for t, m, k in itertools.product([0, 1], [1024, 2048, 4096], [0, ki_alt])]
+        best, res = tune(space,
+                         lambda c, code=code: vm.set_tuning(code, True, **c),
+                         lambda code=code: vm.reset_tuning(code, True),
+                         lambda: vm.sort_(keys, vals, iota=True, workspace=pws),
+                         lambda: keys.copy_(pristine), lambda: vals, a.steps)
+        entries.append({"dtype": dtype, "values": True, **{k: best[k] for k in fields},
+                        "workload": f"plain sort of (key, index) pairs, n=2^{a.log2n - 2}", "ms": best["ms"],
+                        "candidates": res})
+        del pristine, keys, vals, pws
+        torch.cuda.empty_cache()
 
     table = {"arch": arch, "cus": props.multi_processor_count,
              "generated": time.strftime("%Y-%m-%d %H:%M:%S"), "entries": entries}

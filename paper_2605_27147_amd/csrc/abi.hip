@@ -785,12 +785,12 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t)
 {
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    Tuning v{0, 0, 0, 0};
+    Tuning v{0, 0, 0, 0, 0};
     if (t) {
         if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 ||
-            (t->host_wait != 0 && t->host_wait != 1))
+            (t->host_wait != 0 && t->host_wait != 1) || (t->merge_ki != 0 && t->merge_ki != 8 && t->merge_ki != 16))
             return VMPS_ERR_INVALID_ARG;
-        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->host_wait};
+        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->host_wait, t->merge_ki};
     }
     tuning_table()[kt == VMPS_U64][has_values ? 1 : 0] = v;
     return VMPS_OK;
@@ -804,6 +804,7 @@ vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t)
     t->merge_grid = v.merge_grid;
     t->bucket_div = v.bucket_div;
     t->host_wait = v.host_wait;
+    t->merge_ki = v.merge_ki;
     return VMPS_OK;
 }
 

@@ -172,21 +172,37 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     return hipGetLastError();
 }
 
-uint32_t merge_tile_out(int key_bits, int has_values)
+uint32_t merge_tile_default(int key_bits, int has_values)
 {
     if (key_bits == 64 && has_values) return 256 * 8;
     return 256 * 16;
 }
 
+uint32_t merge_tile_out(int key_bits, int has_values)
+{
+    const int ki = tuning_for(key_bits, has_values != 0).merge_ki;
+    return ki ? 256u * (uint32_t)ki : merge_tile_default(key_bits, has_values);
+}
+
+// The level tiles are those the plan was made with (P.T_out).
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
                                 int key_bits, int has_values, hipStream_t s)
 {
+    const bool k16 = P.T_out == 256 * 16;
     if (key_bits == 32) {
-        if (has_values) return launch_levels<uint32_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
-        return launch_levels<uint32_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+        if (has_values) {
+            if (k16) return launch_levels<uint32_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+            return launch_levels<uint32_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+        }
+        if (k16) return launch_levels<uint32_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+        return launch_levels<uint32_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s);
     }
-    if (has_values) return launch_levels<uint64_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
-    return launch_levels<uint64_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+    if (has_values) {
+        if (k16) return launch_levels<uint64_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+        return launch_levels<uint64_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+    }
+    if (k16) return launch_levels<uint64_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
+    return launch_levels<uint64_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s);
 }
 
 // ------------------------------------------------- merge of two arrays --

@@ -980,9 +980,10 @@ size_t plan_carve(Plan& P, void* ws, uint64_t n, uint64_t k, uint32_t T, uint32_
     P.hbm_tile_off = c.take<uint32_t>(P.h_cap + 1);
     P.segs = c.take<Seg>(P.seg_cap);
     // output tiles of all HBM nodes: per level at most n_tiles_out plus two
-    // per node, and a level holds fewer than n / T + 1 nodes longer than T
+    // per node, and a level holds fewer than n / T + 1 nodes longer than T;
+    // sized for the smallest merge tile, so the tuning may pick any
     {
-        const uint64_t per_level = (uint64_t)P.n_tiles_out + 2 * (n / (T ? T : 1) + 1);
+        const uint64_t per_level = ceil_div(n ? n : 1, MERGE_TILE_MIN) + 2 * (n / (T ? T : 1) + 1);
         const uint64_t cap = (uint64_t)MAX_LEVEL * per_level;
         P.pair_cap = (uint32_t)(cap < 0xffffffffull ? cap : 0xffffffffull);
     }

@@ -721,7 +721,7 @@ static VmLayout vm_layout(uint64_t n, int kb, int has_values, uint64_t window_pa
 {
     VmLayout L{};
     const uint32_t T = tilesort_capacity(kb, has_values);
-    L.P = merge_tile_out(kb, has_values);
+    L.P = merge_tile_default(kb, has_values);
     L.logp = 0;
     while ((1u << L.logp) < L.P) ++L.logp;
     L.N = (uint32_t)ceil_div(n ? n : 1, L.P);
@@ -787,7 +787,7 @@ size_t vm_buffer_bytes(uint64_t n, int key_bits, int has_values, uint64_t window
     return L.pt - L.kpool;  // pool and copy pages (keys and values)
 }
 
-uint32_t vm_page_elems(int key_bits, int has_values) { return merge_tile_out(key_bits, has_values); }
+uint32_t vm_page_elems(int key_bits, int has_values) { return merge_tile_default(key_bits, has_values); }
 
 uint64_t vm_window_pages(uint64_t n, int key_bits, int has_values, uint64_t window_pages)
 {

@@ -184,6 +184,7 @@ struct Tuning {
     int merge_grid;      // workgroups of a merge level (0: 2048)
     int bucket_div;      // learned buckets target the tile length / bucket_div (0: 2)
     int host_wait;       // 1: wait on the host for the level counts, launch the non-empty levels only
+    int merge_ki;        // outputs per thread of a merge-level tile (0: default)
 };
 const Tuning& tuning_for(int key_bits, bool has_values);
 
@@ -242,7 +243,11 @@ hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipS
                                bool allowed = true);
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                                 uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
+// Merge-level output tile with the tuning's merge_ki; the built-in default
+// (the paged sort's page); the smallest choice, which sizes workspaces.
 uint32_t merge_tile_out(int key_bits, int has_values);
+uint32_t merge_tile_default(int key_bits, int has_values);
+constexpr uint32_t MERGE_TILE_MIN = 256 * 8;
 
 // Standalone stable merge of two sorted arrays.
 hipError_t merge_two_enqueue(const void* a, const uint32_t* va, uint32_t na, const void* b,

@@ -55,8 +55,8 @@ def test_tuning_table_host_side():
     lib = vm.load_library()
     vm.set_tuning(vm.U64, False, tile_wg_per_cu=1, merge_grid=1024, bucket_div=3)
     assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 1, "merge_grid": 1024, "bucket_div": 3,
-                                            "host_wait": 0}
-    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0}
+                                            "host_wait": 0, "merge_ki": 0}
+    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0, "merge_ki": 0}
     vm.set_tuning(vm.U32, True, host_wait=1)
     assert vm.get_tuning(vm.U32, True)["host_wait"] == 1
     vm.reset_tuning(vm.U32, True)
@@ -66,9 +66,14 @@ def test_tuning_table_host_side():
     assert lib.vmps_set_tuning(vm.U64, 0, ctypes.byref(bad)) == 1
     bad = vm.Tuning(0, 0, 0, 2)
     assert lib.vmps_set_tuning(vm.U32, 1, ctypes.byref(bad)) == 1
+    bad = vm.Tuning(0, 0, 0, 0, 12)
+    assert lib.vmps_set_tuning(vm.U32, 1, ctypes.byref(bad)) == 1
+    vm.set_tuning(vm.U32, False, merge_ki=8)
+    assert vm.get_tuning(vm.U32, False)["merge_ki"] == 8
+    vm.reset_tuning(vm.U32, False)
     assert lib.vmps_set_tuning(5, 0, None) == 1
     vm.reset_tuning(vm.U64, False)
-    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0}
+    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0, "merge_ki": 0}
 
 
 def test_graph_capture_rejects_bad_arguments_without_gpu_work():

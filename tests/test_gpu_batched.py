@@ -91,25 +91,36 @@ def test_learned_graph_replays_match_oracle(vm, orc):
     g.close()
 
 
-@pytest.mark.parametrize("tile_wg, merge_grid, bucket_div, host_wait", [(1, 256, 2, 1), (2, 4096, 4, 0), (0, 0, 3, 0)])
-def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, host_wait):
+@pytest.mark.parametrize("tile_wg, merge_grid, bucket_div, host_wait, merge_ki",
+                         [(1, 256, 2, 1, 8), (2, 4096, 4, 0, 16), (0, 0, 3, 0, 0), (0, 0, 0, 0, 8)])
+def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, host_wait, merge_ki):
     import torch
     keys_np, off = workloads.batch32(128, 45, lengths=workloads.batch_lengths(128, 45, hi_log2=17))
     want, _ = orc.segmented_powersort(keys_np, off)
     x = workloads.lognormal(1 << 19, 46)
     wantx, _, _, _ = orc.powersort(x)
     try:
-        vm.set_tuning(vm.U32, False, tile_wg, merge_grid, bucket_div, host_wait)
-        vm.set_tuning(vm.U64, False, tile_wg, merge_grid, bucket_div, host_wait)
+        for hv in (False, True):
+            vm.set_tuning(vm.U32, hv, tile_wg, merge_grid, bucket_div, host_wait, merge_ki)
+            vm.set_tuning(vm.U64, hv, tile_wg, merge_grid, bucket_div, host_wait, merge_ki)
         keys = _t(keys_np)
         vm.segmented_sort_(keys, torch.from_numpy(off).cuda())
         assert np.array_equal(_np(keys, np.uint32), want.astype(np.uint32))
         k2 = _t(x)
         vm.sort_learned_(k2)
         assert np.array_equal(_np(k2, np.uint64), wantx)
+        # plain sorts of (key, index) pairs at both merge tile sizes
+        for bits in (32, 64):
+            xp = workloads.uniform(300007, bits, 47)
+            kp = _t(xp)
+            vp = torch.empty(xp.size, dtype=torch.int32, device="cuda")
+            vm.sort_(kp, vp, iota=True)
+            _, wantv, _, _ = orc.powersort(xp, np.arange(xp.size, dtype=np.uint32))
+            assert np.array_equal(_np(vp, np.uint32), wantv), bits
     finally:
-        vm.reset_tuning(vm.U32, False)
-        vm.reset_tuning(vm.U64, False)
+        for hv in (False, True):
+            vm.reset_tuning(vm.U32, hv)
+            vm.reset_tuning(vm.U64, hv)
 
 
 def _brute_force_segments():

@@ -17,6 +17,8 @@
 // outputs [i*KI, (i+1)*KI), computes them into registers, and writes them
 // back into the single LDS buffer after a barrier.  The segment is written
 // once, to the buffer the planner chose (Pingpong).
+#include <type_traits>
+
 #include "merge_tile.hpp"
 
 namespace vmps {
@@ -38,6 +40,51 @@ __device__ __forceinline__ uint32_t pxp(uint32_t i) { return LAY == 1 ? px(i) : 
 // Length of the blocks the spare slots separate (elements).
 template <int LAY>
 constexpr uint32_t lay_block() { return LAY == 2 ? 16u : 32u; }
+
+// S[pxp<LAY>(i)] read with its byte offset formed as (i + i / block) scaled
+// by the key size: one shift and one v_add_lshl_u32 (plain VGPR arithmetic),
+// with the buffer's base left to the LDS instruction's offset field.  Left
+// to itself the compiler splits the scaled sum into two scaled terms, two
+// more instructions on every merge step.
+template <int LAY, typename K>
+__device__ __forceinline__ K lds_get(const K* __restrict__ S, uint32_t i)
+{
+    if constexpr (LAY == 0) {
+        return S[i];
+    } else {
+        const uint32_t q = i >> (LAY == 1 ? 5 : 4);
+        uint32_t off;
+        if constexpr (sizeof(K) == 8)
+            asm("v_add_lshl_u32 %0, %1, %2, 3" : "=v"(off) : "v"(i), "v"(q));
+        else
+            asm("v_add_lshl_u32 %0, %1, %2, 2" : "=v"(off) : "v"(i), "v"(q));
+        return *(const K*)((const uint8_t*)S + off);
+    }
+}
+
+// f(integral_constant<int, I>) for I = 0 .. N-1, unrolled at compile time
+// (the step number is a constant expression inside f).
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
+// The B cursor of a merge step from the A cursor: inside one node every
+// output advances exactly one cursor, so before output j the cursors sum to
+// s0 + j, and jb = (s0 - ia) + j with s0 >= ia.  One v_sad_u32 (|a - b| + c,
+// plain VGPR arithmetic) instead of advancing jb by the complement of the
+// comparison's lane mask (a select and an add).
+template <int J>
+__device__ __forceinline__ uint32_t b_cursor(uint32_t s0, uint32_t ia)
+{
+    uint32_t jb;
+    asm("v_sad_u32 %0, %1, %2, %3" : "=v"(jb) : "v"(s0), "v"(ia), "i"(J));
+    return jb;
+}
 
 template <int TCAP>
 struct TileMeta {
@@ -107,21 +154,26 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             // Every lane's outputs lie in its first node: no node changes.
             // Indices stay <= max(R, p0 + KI) <= TCAP.  Wave-uniform, so a
             // wave runs one of the three loops only.
-#pragma unroll
-            for (int j = 0; j < KI; ++j) {
+            const uint32_t s0 = ia + jb;
+            static_for<KI>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
                 const bool takeA = ia < M && (jb >= R || ha <= hb);
-                const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
-                if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
-                const uint32_t nx = cur + 1;
-                ia = takeA ? nx : ia;
-                jb = takeA ? jb : nx;
-                if (j + 1 < KI) {
-                    const K nv = S[pxp<LAY>(nx)];
+                if (VMODE) rv[j] = SV[pxp<LAY>(takeA ? ia : jb)];
+                // the A cursor advances by the comparison's bit, the B
+                // cursor follows from the sum
+                ia += takeA ? 1u : 0u;
+                // kept opaque, so that the compiler does not re-associate
+                // the chain of increments (it would rebuild each step's
+                // bit as a 0/1 value: one more instruction per step)
+                asm("" : "+v"(ia));
+                if constexpr (j + 1 < KI) {
+                    jb = b_cursor<j + 1>(s0, ia);
+                    const K nv = lds_get<LAY>(S, takeA ? ia : jb);
                     ha = takeA ? nv : ha;
                     hb = takeA ? hb : nv;
                 }
-            }
+            });
         } else if (__all(pe <= R2)) {
             // At most one node change per lane, at output R (nodes at least
             // KI long, the usual case): the second node's state is set up
@@ -131,30 +183,37 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             // the change happens at step R - p0 (> 0): compared with the
             // unrolled step number, no per-step position is kept live
             const uint32_t jsw = R - p0;
-#pragma unroll
-            for (int j = 0; j < KI; ++j) {
-                if (j > 0) {
+            // cursor sums: s0 + j in the first node, s1 + j in the second
+            // (both cursors of the first node end exactly at M and R)
+            uint32_t s0 = ia + jb;
+            const uint32_t s1 = R + M2 - jsw;
+            static_for<KI>([&](auto jc) {
+                constexpr int j = decltype(jc)::value;
+                if constexpr (j > 0) {
                     const bool sw = jsw == (uint32_t)j;
                     ia = sw ? R : ia;
                     jb = sw ? M2 : jb;
+                    s0 = sw ? s1 : s0;
                     Mc = sw ? M2 : Mc;
                     Rc = sw ? R2 : Rc;
                     ha = sw ? ha2 : ha;
                     hb = sw ? hb2 : hb;
                 }
                 const bool takeA = ia < Mc && (jb >= Rc || ha <= hb);
-                const uint32_t cur = takeA ? ia : jb;
                 rk[j] = takeA ? ha : hb;
-                if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
-                const uint32_t nx = cur + 1;
-                ia = takeA ? nx : ia;
-                jb = takeA ? jb : nx;
-                if (j + 1 < KI) {
-                    const K nv = S[pxp<LAY>(nx)];
+                if (VMODE) rv[j] = SV[pxp<LAY>(takeA ? ia : jb)];
+                ia += takeA ? 1u : 0u;
+                // kept opaque, so that the compiler does not re-associate
+                // the chain of increments (it would rebuild each step's
+                // bit as a 0/1 value: one more instruction per step)
+                asm("" : "+v"(ia));
+                if constexpr (j + 1 < KI) {
+                    jb = b_cursor<j + 1>(s0, ia);
+                    const K nv = lds_get<LAY>(S, takeA ? ia : jb);
                     ha = takeA ? nv : ha;
                     hb = takeA ? hb : nv;
                 }
-            }
+            });
         } else {
 #pragma unroll
         for (int j = 0; j < KI; ++j) {
@@ -168,13 +227,12 @@ __device__ __forceinline__ void merge_pass(K* __restrict__ S, uint32_t* __restri
             }
             // StandardMerge: the left run wins ties; a copy node only has a left run
             const bool takeA = ia < M && (jb >= R || ha <= hb);
-            const uint32_t cur = takeA ? ia : jb;
             rk[j] = takeA ? ha : hb;
-            if (VMODE) rv[j] = SV[pxp<LAY>(cur)];
-            const uint32_t nx = cur + 1;
-            ia = takeA ? nx : ia;
-            jb = takeA ? jb : nx;
-            const K nv = S[pxp<LAY>(nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP)];
+            if (VMODE) rv[j] = SV[pxp<LAY>(takeA ? ia : jb)];
+            ia += takeA ? 1u : 0u;
+            jb += takeA ? 0u : 1u;
+            const uint32_t nx = takeA ? ia : jb;
+            const K nv = lds_get<LAY>(S, nx < (uint32_t)TCAP ? nx : (uint32_t)TCAP);
             ha = takeA ? nv : ha;
             hb = takeA ? hb : nv;
         }
@@ -1014,8 +1072,11 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     // segments of length in (len_lo, len_hi] only, so that two launches of
     // different workgroup sizes can share one segment list (each with its
     // own ticket counter)
-    extern __shared__ __align__(16) uint8_t smem[];
-    __shared__ uint32_t s_next;
+    // static LDS of the configuration's size: its address is a compile-time
+    // constant, so an element's LDS offset needs no base register added
+    // (the ticket word follows the tile's sections)
+    __shared__ __align__(16) uint8_t smem[tile_lds_bytes<K, NT, TCAP, VMODE>() + 16];
+    uint32_t& s_next = *(uint32_t*)(smem + tile_lds_bytes<K, NT, TCAP, VMODE>());
     const uint32_t nseg = counters[CNT_NSEG];
     // a ticket claims sb consecutive segments: every claim is an atomic on
     // one counter shared by the whole grid, so claims are kept to about 16
@@ -1044,10 +1105,9 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
                                   int wg_per_cu, hipStream_t s, uint32_t len_lo = 0, uint32_t len_hi = 0xffffffffu,
                                   int ticket = CNT_TICKET)
 {
-    constexpr size_t lds = tile_lds_bytes<K, NT, TCAP, VMODE>();
     auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW, NARROW>;
-    // the LDS limit and the occupancy, once per device (set before any
-    // launch on it; concurrent first calls only repeat the same setting)
+    // the occupancy, once per device (the kernel's LDS is static: no
+    // dynamic LDS at launch)
     static bool attr_set[16] = {};
     static int resident[16] = {};
     static int cus[16] = {};
@@ -1055,8 +1115,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     VMPS_HIP(hipGetDevice(&dev));
     const int d = dev & 15;
     if (!attr_set[d]) {
-        VMPS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[d], (const void*)kern, NT, lds));
+        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[d], (const void*)kern, NT, 0));
         VMPS_HIP(hipDeviceGetAttribute(&cus[d], hipDeviceAttributeMultiprocessorCount, dev));
         attr_set[d] = true;
     }
@@ -1065,7 +1124,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     uint64_t grid = (uint64_t)per_cu * (uint64_t)(cus[d] > 0 ? cus[d] : 1);
     if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
-    kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
+    kern<<<(unsigned)(grid ? grid : 1), NT, 0, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
                                                      P.inst_start, len_lo, len_hi, ticket, (int)P.desc);
     return hipGetLastError();
 }
@@ -1084,8 +1143,8 @@ uint32_t tilesort_capacity(int key_bits, int has_values)
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 {
     if (key_bits == 32)
-        return has_values ? tile_lds_bytes<uint32_t, 512, 8192, 1>() : tile_lds_bytes<uint32_t, 512, 16384, 0>();
-    return has_values ? tile_lds_bytes<uint64_t, 256, 4096, 1>() : tile_lds_bytes<uint64_t, 512, 8192, 0>();
+        return 16 + (has_values ? tile_lds_bytes<uint32_t, 512, 8192, 1>() : tile_lds_bytes<uint32_t, 512, 16384, 0>());
+    return 16 + (has_values ? tile_lds_bytes<uint64_t, 256, 4096, 1>() : tile_lds_bytes<uint64_t, 512, 8192, 0>());
 }
 
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,

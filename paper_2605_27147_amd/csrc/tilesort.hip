@@ -575,6 +575,27 @@ __device__ __forceinline__ void tile_store(const KT* __restrict__ S, const uint3
     }
 }
 
+// One load per 128-byte line of the keys (and values) of the workgroup's
+// next segment, issued before the current segment's store: the lines come
+// into the XCD's L2 while the store runs, and the next segment's own loads
+// then find them there.  The loaded words are folded into one register
+// that the next segment consumes as a dependence only (a single register
+// carried around the loop, where the keys themselves would be 16).
+template <typename K, int NT, int TCAP, int VMODE>
+__device__ __forceinline__ uint32_t tile_touch(const K* __restrict__ src, const uint32_t* __restrict__ vsrc,
+                                               const Seg nx, bool nok, uint32_t tid)
+{
+    constexpr uint32_t KL = 128 / sizeof(K);  // keys per line
+    uint32_t t = 0;
+    if (nok) {
+        const uint32_t n = nx.end - nx.start;
+        for (uint32_t i = tid * KL; i < n; i += NT * KL) t |= (uint32_t)src[nx.start + i];
+        if (VMODE == 1)
+            for (uint32_t i = tid * 32; i < n; i += NT * 32) t |= vsrc[nx.start + i];
+    }
+    return t;
+}
+
 // HBM -> LDS for 64-bit keys: all CH keys of a thread in registers, the
 // segment's minimum and maximum by a block reduction (red: 4 * NT/64 words
 // of LDS), then either 32-bit offsets from the minimum (returns true, kmin
@@ -937,10 +958,14 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
 // smem: tile_lds_bytes<K, NT, TCAP, VMODE>() bytes of LDS.  NARROW (64-bit
 // keys without values): segments whose keys span less than 2^32 run on
 // 32-bit offsets.
+//   touch: the folded words of this segment's lines, loaded ahead by the
+// previous segment (consumed at the start); before this segment's store the
+// lines of the next segment nx are loaded ahead when nok is set.
 template <typename K, int NT, int TCAP, int VMODE, bool NARROW>
 __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keysA, K* __restrict__ keysB,
                                              uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB,
-                                             const Seg sg, const uint32_t* __restrict__ inst_start, bool desc)
+                                             const Seg sg, const uint32_t* __restrict__ inst_start, bool desc,
+                                             uint32_t& touch, const Seg nx, bool nok)
 {
     using MT = TileMeta<TCAP>;
     constexpr int NW = NT / 64;
@@ -1015,6 +1040,9 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
         }
         return;
     }
+    // the lines loaded ahead have arrived (a dependence only; the value
+    // is not used)
+    asm volatile("" ::"v"(touch));
     const uint32_t ib = inst_start[sg.inst];
     const uint32_t il = inst_start[sg.inst + 1] - ib;
     const uint32_t ell = minrun_of(il);
@@ -1041,6 +1069,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
         if (narrow) {
             tile_body<uint32_t, NT, TCAP, VMODE, 2>((uint32_t*)S, SV, T, len, ell, g, il, tid, desc);
             asm volatile("" : "+v"(tid_st));
+            touch = tile_touch<K, NT, TCAP, VMODE>(keysA, valsA, nx, nok, tid_st);
             tile_store<uint32_t, K, NT, TCAP, VMODE, 2>((const uint32_t*)S, SV, sg.dst ? keysB : keysA,
                                                     sg.dst ? valsB : valsA, a, len, tid_st, kmin);
             __syncthreads();
@@ -1049,6 +1078,7 @@ __device__ __forceinline__ void tile_segment(uint8_t* smem, K* __restrict__ keys
     }
     tile_body<K, NT, TCAP, VMODE, 1>(S, SV, T, len, ell, g, il, tid, desc);
     asm volatile("" : "+v"(tid_st));
+    touch = tile_touch<K, NT, TCAP, VMODE>(keysA, valsA, nx, nok, tid_st);
     tile_store<K, K, NT, TCAP, VMODE, 1>(S, SV, sg.dst ? keysB : keysA, sg.dst ? valsB : valsA, a, len, tid_st, K(0));
     __syncthreads();
 }
@@ -1078,6 +1108,7 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     __shared__ __align__(16) uint8_t smem[tile_lds_bytes<K, NT, TCAP, VMODE>() + 16];
     uint32_t& s_next = *(uint32_t*)(smem + tile_lds_bytes<K, NT, TCAP, VMODE>());
     const uint32_t nseg = counters[CNT_NSEG];
+    uint32_t touch = 0;
     // a ticket claims sb consecutive segments: every claim is an atomic on
     // one counter shared by the whole grid, so claims are kept to about 16
     // per workgroup (at most 16 segments each) when segments are many
@@ -1094,7 +1125,17 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
             const Seg sg = segs[si];
             const uint32_t len = sg.end - sg.start;
             if (len <= len_lo || len > len_hi) continue;
-            tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start, desc != 0);
+            // the next segment of the batch, when this launch sorts it in
+            // LDS: its lines are loaded ahead
+            Seg nx = sg;
+            bool nok = false;
+            if (si + 1 < b1) {
+                nx = segs[si + 1];
+                const uint32_t nl = nx.end - nx.start;
+                nok = nl > len_lo && nl <= len_hi && nl > 0 && nl <= (uint32_t)TCAP;
+            }
+            tile_segment<K, NT, TCAP, VMODE, NARROW>(smem, keysA, keysB, valsA, valsB, sg, inst_start, desc != 0,
+                                                     touch, nx, nok);
         }
     }
 }

@@ -596,6 +596,39 @@ __device__ __forceinline__ uint32_t tile_touch(const K* __restrict__ src, const 
     return t;
 }
 
+// One step of a wave reduction of 64-bit values by DPP: each lane combines
+// its value with the one CTRL names (lanes without a source, or in rows
+// outside RM, combine with the identity).
+template <bool MAX, int CTRL, int RM>
+__device__ __forceinline__ uint64_t dpp_minmax_step(uint64_t v)
+{
+    constexpr uint64_t id = MAX ? 0ull : ~0ull;
+    const uint32_t l = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)id, (int)(uint32_t)v, CTRL, RM, 0xf, false);
+    const uint32_t h =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(id >> 32), (int)(uint32_t)(v >> 32), CTRL, RM, 0xf, false);
+    const uint64_t t = ((uint64_t)h << 32) | l;
+    return MAX ? (t > v ? t : v) : (t < v ? t : v);
+}
+
+// Minimum (or maximum) of a 64-bit value over the 64 lanes of a wave (all
+// active), in scalar registers: prefix steps inside each row of 16 lanes
+// (shifts 1, 2, 4, 8), then row 0's last lane into row 1 and row 2's into
+// row 3, then lane 31 into rows 2 and 3; lane 63 holds the result.  No LDS
+// traffic, where lane shuffles would take six LDS permute rounds per half.
+template <bool MAX>
+__device__ __forceinline__ uint64_t wave_minmax_u64(uint64_t v)
+{
+    v = dpp_minmax_step<MAX, 0x111, 0xf>(v);  // row_shr:1
+    v = dpp_minmax_step<MAX, 0x112, 0xf>(v);  // row_shr:2
+    v = dpp_minmax_step<MAX, 0x114, 0xf>(v);  // row_shr:4
+    v = dpp_minmax_step<MAX, 0x118, 0xf>(v);  // row_shr:8
+    v = dpp_minmax_step<MAX, 0x142, 0xa>(v);  // row_bcast:15 into rows 1, 3
+    v = dpp_minmax_step<MAX, 0x143, 0xc>(v);  // row_bcast:31 into rows 2, 3
+    const uint32_t l = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 63);
+    return ((uint64_t)h << 32) | l;
+}
+
 // HBM -> LDS for 64-bit keys: all CH keys of a thread in registers, the
 // segment's minimum and maximum by a block reduction (red: 4 * NT/64 words
 // of LDS), then either 32-bit offsets from the minimum (returns true, kmin
@@ -629,12 +662,8 @@ __device__ __forceinline__ bool tile_load_narrow(uint64_t* __restrict__ S, uint3
             hi = r[c] > hi ? r[c] : hi;
         }
     }
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t ol = __shfl_xor(lo, off, 64), oh = __shfl_xor(hi, off, 64);
-        lo = ol < lo ? ol : lo;
-        hi = oh > hi ? oh : hi;
-    }
+    lo = wave_minmax_u64<false>(lo);
+    hi = wave_minmax_u64<true>(hi);
     const uint32_t wave = tid >> 6;
     if ((tid & 63) == 0) {
         red[4 * wave + 0] = (uint32_t)lo;

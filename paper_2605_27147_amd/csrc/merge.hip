@@ -135,8 +135,7 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     A.depth = P.hbm_depth;
     A.splits = P.splits;
     A.T_out = TO;
-    uint32_t top = 1;
-    while (top < 32 && (1ull << top) < P.n) ++top;  // powers never exceed ceil(log2 n)
+    const uint32_t top = hbm_top_level(P.n, P.T);  // higher levels hold no merge longer than T
     const uint64_t most = (uint64_t)P.n_tiles_out + 2 * ((uint64_t)P.n / (P.T ? P.T : 1) + 1);  // pairs of one level
     const unsigned pgrid = (unsigned)(ceil_div(2 * most, 256) < 256 ? ceil_div(2 * most, 256) : 256);
     const int tg = tuning_for(sizeof(K) * 8, VAL).merge_grid;

@@ -808,8 +808,8 @@ static hipError_t vm_levels(const Plan& P, const VmArgs& A, uint32_t* scan, hipS
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set[dev & 15] = true;
     }
-    uint32_t top = 1;
-    while (top < 32 && (1ull << top) < P.n) ++top;
+    // higher levels hold no merge longer than T: no pair, no page touched
+    const uint32_t top = hbm_top_level(P.n, P.T);
     const uint64_t most = (uint64_t)P.n_tiles_out + 2 * ((uint64_t)P.n / (P.T ? P.T : 1) + 1);
     const unsigned pgrid = (unsigned)(ceil_div(2 * most, 256) < 256 ? ceil_div(2 * most, 256) : 256);
     const unsigned lgrid = (unsigned)(ceil_div(most + A.emax, 256) < 1024 ? ceil_div(most + A.emax, 256) : 1024);

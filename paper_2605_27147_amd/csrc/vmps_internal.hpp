@@ -34,6 +34,24 @@ __host__ __device__ inline uint32_t minrun_of(uint64_t n)
 
 __host__ __device__ inline uint64_t ceil_div(uint64_t a, uint64_t b) { return (a + b - 1) / b; }
 
+// Highest power a merge longer than T elements can have, in Powersort
+// instances of at most n elements (the powers of Section 2, from 32-bit
+// midpoint expansions).  Every boundary inside a node of power p has power
+// at least p, so the runs on its two sides sum to less than il 2^(2-p) (plus
+// one unit of the midpoints' rounding), and the node's run midpoints lie in
+// a window of width il 2^(1-p): the node is shorter than 3 il 2^(1-p) plus
+// rounding, under 4.5 il 2^(1-p).  So a node longer than T has 2^p < 9 n / T,
+// and the levels above that power hold no merge in HBM.  Capped at
+// ceil(log2 n), above which no power occurs.
+inline uint32_t hbm_top_level(uint64_t n, uint32_t T)
+{
+    uint32_t top = 1;
+    while (top < 32 && (1ull << top) < n) ++top;
+    uint32_t p = 1;
+    while (p < top && ((uint64_t)2 * T << p) < 9 * n) ++p;
+    return p;
+}
+
 // Inclusive scan across the 64 lanes of a wave.
 __device__ inline uint32_t wave_incl_scan(uint32_t v)
 {

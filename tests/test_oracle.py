@@ -291,6 +291,56 @@ def test_plan_executes_to_sorted_result(orc):
             assert Mh == int(sum(R - L for L, _, R, _ in nodes if R - L > T))
 
 
+def _hbm_top_level(n, T):
+    """Largest power p with 2^p < 9 n / T, at most ceil(log2 n): the highest
+    merge level the GPU launches for nodes longer than T."""
+    top = 1
+    while top < 32 and (1 << top) < n:
+        top += 1
+    p = 1
+    while p < top and ((2 * T) << p) < 9 * n:
+        p += 1
+    return p
+
+
+def test_long_merges_power_bound(orc):
+    """A node of power p has its run midpoints in a window of width n 2^(1-p)
+    and each of its runs borders a boundary of power >= p, so it is shorter
+    than about 3 n 2^(1-p): every merge of Algorithm 1 longer than T has
+    2^p < 9 n / T, and the merge levels above that power are empty.  Checked
+    on the merges Algorithm 1 performs, for random, presorted, block-shuffled
+    and long-next-to-tiny run structures; the bound comes within one level
+    of the largest power seen (it is not vacuous)."""
+    closest = -99
+    for seed in range(4):
+        rng = np.random.default_rng(100 + seed)
+        for n in (1000, 4097, 30000, 1 << 17):
+            inputs = [workloads.uniform(n, 64, seed),
+                      workloads.presorted(n, seed, mean_run=int(rng.integers(2, 5000))).astype(np.uint64)]
+            parts, tot = [], 0
+            while tot < n:  # long runs next to runs of one to three keys
+                L = min(int(rng.choice([1, 2, 3, int(rng.integers(1, n // 2 + 2))])), n - tot)
+                parts.append(np.sort(rng.integers(0, 1 << 40, L)))
+                tot += L
+            inputs.append(np.concatenate(parts).astype(np.uint64))
+            cut = np.sort(rng.choice(np.arange(1, n), size=int(rng.integers(2, 64)), replace=False))
+            inputs.append(np.concatenate(np.split(np.arange(n, dtype=np.uint64), cut)[::-1]))
+            for x in inputs:
+                for ell in (0, 16):
+                    b = orc.extract_runs(x, ell or None)
+                    pw = orc.run_powers(b, n)
+                    _, _, _, log = orc.powersort(x, ell=ell, log_merges=True)
+                    where = {int(v): i for i, v in enumerate(b)}
+                    for T in (32, 100, 1024, 8192):
+                        top = _hbm_top_level(n, T)
+                        for L, M, R in log:
+                            if R - L > T:
+                                p = int(pw[where[int(M)] - 1])
+                                assert p <= top, (n, T, int(L), int(M), int(R), p, top)
+                                closest = max(closest, p - top)
+    assert closest >= -1, closest
+
+
 def test_plan_depth_perfect_tree(orc):
     # perfect tree: depth = power - 1, so the buffer is (power - 1) mod 2
     n = 32 << 8

@@ -93,6 +93,10 @@ struct TileMeta {
     static constexpr uint32_t SP = TCAP + TCAP / 32 + 1;  // padded element slots
 };
 
+// Whether a tile configuration declares its LDS statically (see k_tilesort).
+template <typename K, int VMODE>
+constexpr bool tile_lds_static() { return !(sizeof(K) == 4 && VMODE != 0); }
+
 template <typename K, int NT, int TCAP, int VMODE>
 constexpr size_t tile_lds_bytes()
 {
@@ -1133,8 +1137,13 @@ __global__ __launch_bounds__(NT, MINW) void k_tilesort(K* __restrict__ keysA, K*
     // own ticket counter)
     // static LDS of the configuration's size: its address is a compile-time
     // constant, so an element's LDS offset needs no base register added
-    // (the ticket word follows the tile's sections)
-    __shared__ __align__(16) uint8_t smem[tile_lds_bytes<K, NT, TCAP, VMODE>() + 16];
+    // (the ticket word follows the tile's sections).  32-bit keys with values
+    // take it as dynamic LDS instead: at their register limit the static
+    // form spills more registers.
+    constexpr bool STATIC_LDS = tile_lds_static<K, VMODE>();
+    __shared__ __align__(16) uint8_t smem_s[STATIC_LDS ? tile_lds_bytes<K, NT, TCAP, VMODE>() + 16 : 16];
+    extern __shared__ __align__(16) uint8_t smem_d[];
+    uint8_t* smem = STATIC_LDS ? smem_s : smem_d;
     uint32_t& s_next = *(uint32_t*)(smem + tile_lds_bytes<K, NT, TCAP, VMODE>());
     const uint32_t nseg = counters[CNT_NSEG];
     uint32_t touch = 0;
@@ -1176,8 +1185,9 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
                                   int ticket = CNT_TICKET)
 {
     auto kern = k_tilesort<K, NT, TCAP, VMODE, MINW, NARROW>;
-    // the occupancy, once per device (the kernel's LDS is static: no
-    // dynamic LDS at launch)
+    // dynamic LDS bytes at launch: none when the kernel declares its LDS
+    constexpr size_t lds = tile_lds_static<K, VMODE>() ? 0 : tile_lds_bytes<K, NT, TCAP, VMODE>() + 16;
+    // the LDS limit and the occupancy, once per device
     static bool attr_set[16] = {};
     static int resident[16] = {};
     static int cus[16] = {};
@@ -1185,7 +1195,8 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     VMPS_HIP(hipGetDevice(&dev));
     const int d = dev & 15;
     if (!attr_set[d]) {
-        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[d], (const void*)kern, NT, 0));
+        if (lds) VMPS_HIP(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        VMPS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident[d], (const void*)kern, NT, lds));
         VMPS_HIP(hipDeviceGetAttribute(&cus[d], hipDeviceAttributeMultiprocessorCount, dev));
         attr_set[d] = true;
     }
@@ -1194,7 +1205,7 @@ static hipError_t launch_tilesort(const Plan& P, void* keysA, void* keysB, uint3
     uint64_t grid = (uint64_t)per_cu * (uint64_t)(cus[d] > 0 ? cus[d] : 1);
     if (grid > P.seg_cap) grid = P.seg_cap;
     TraceScope tr(VMPS_TRACE_TILESORT, s);
-    kern<<<(unsigned)(grid ? grid : 1), NT, 0, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
+    kern<<<(unsigned)(grid ? grid : 1), NT, lds, s>>>((K*)keysA, (K*)keysB, valsA, valsB, P.segs, P.counters,
                                                      P.inst_start, len_lo, len_hi, ticket, (int)P.desc);
     return hipGetLastError();
 }

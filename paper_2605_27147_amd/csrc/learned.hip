@@ -645,40 +645,64 @@ __device__ inline PartModel part_model(const vmps_cdf_model* model, uint32_t B, 
     return P;
 }
 
-// Level-2 histogram of one tile from the 16-bit ids (the bucket's level-2
-// digit) the level-1 scatter moved with the keys.  Counting only, so the
-// order is free: 16-byte chunks of 8 ids from the aligned position below
-// s0 (the id arrays are padded to a multiple of 128), ids outside [s0, s1)
-// skipped.  Per-wave counters keep LDS atomics on popular digits apart.
+// The per-tile counts of a histogram level go to a digit-major table (digit
+// d of tile t at d * tiles + t, the order the offsets scan needs), one word
+// per digit and tile.  Written tile by tile, every word is a partial write
+// of its own 32-byte sector, from whichever XCD ran the tile (0.54 GB of
+// sector traffic per level for 68 MB of counts at n = 2^28).  So a
+// workgroup takes HIST_CHUNK consecutive tiles, keeps their counts in LDS
+// (16 bits each: a tile holds at most 8192 keys) and then writes each
+// digit's counts of those tiles together: consecutive words, from one XCD.
+constexpr int HIST_CHUNK = 8;
+
+// Level-2 histogram of HIST_CHUNK consecutive tiles from the 16-bit ids (the
+// bucket's level-2 digit) the level-1 scatter moved with the keys.  Counting
+// only, so the order is free: 16-byte chunks of 8 ids from the aligned
+// position below s0 (the id arrays are padded to a multiple of 128), ids
+// outside [s0, s1) skipped.  Per-wave counters keep LDS atomics on popular
+// digits apart.
 __global__ __launch_bounds__(PART_NT) void k_part_hist2(const uint16_t* __restrict__ ids_in, PartLevel L)
 {
     __shared__ uint32_t hist[PART_NW][PART_DMAX];
-    const uint32_t tile = blockIdx.x;
-    if (tile >= L.tbase[L.P]) return;
-    uint32_t c, tl, nt, s0, s1;
-    part_tile(L, tile, c, tl, nt, s0, s1);
+    __shared__ uint16_t cbuf[HIST_CHUNK][PART_DMAX];
+    __shared__ uint32_t cbase[HIST_CHUNK], cnt_t[HIST_CHUNK];
+    const uint32_t ntiles = L.tbase[L.P];
+    const uint32_t t0 = blockIdx.x * HIST_CHUNK;
+    if (t0 >= ntiles) return;
+    const uint32_t nc = ntiles - t0 < (uint32_t)HIST_CHUNK ? ntiles - t0 : (uint32_t)HIST_CHUNK;
     const int tid = threadIdx.x, wave = tid >> 6;
-    for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
-    __syncthreads();
-    const uint32_t a0 = s0 & ~7u;
-    const uint32_t chunks = (s1 - a0 + 7) / 8;
-    for (uint32_t q = tid; q < chunks; q += PART_NT) {
-        const uint4 w = *(const uint4*)(ids_in + a0 + 8 * q);
-        const uint32_t word[4] = {w.x, w.y, w.z, w.w};
+    for (uint32_t j = 0; j < nc; ++j) {
+        uint32_t c, tl, nt, s0, s1;
+        part_tile(L, t0 + j, c, tl, nt, s0, s1);
+        for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
+        __syncthreads();
+        const uint32_t a0 = s0 & ~7u;
+        const uint32_t chunks = (s1 - a0 + 7) / 8;
+        for (uint32_t q = tid; q < chunks; q += PART_NT) {
+            const uint4 w = *(const uint4*)(ids_in + a0 + 8 * q);
+            const uint32_t word[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const uint32_t idx = a0 + 8 * q + e;
-            const uint32_t id = (word[e >> 1] >> (16 * (e & 1))) & 0xffffu;
-            if (idx >= s0 && idx < s1) atomicAdd(&hist[wave][(id >> L.shift) & L.mask], 1u);
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t idx = a0 + 8 * q + e;
+                const uint32_t id = (word[e >> 1] >> (16 * (e & 1))) & 0xffffu;
+                if (idx >= s0 && idx < s1) atomicAdd(&hist[wave][(id >> L.shift) & L.mask], 1u);
+            }
         }
-    }
-    __syncthreads();
-    for (uint32_t d = tid; d < L.F; d += PART_NT) {
-        uint32_t t = 0;
+        __syncthreads();
+        for (uint32_t d = tid; d < L.F; d += PART_NT) {
+            uint32_t t = 0;
 #pragma unroll
-        for (int w = 0; w < PART_NW; ++w) t += hist[w][d];
-        L.counts[(uint64_t)L.tbase[c] * L.F + (uint64_t)d * nt + tl] = t;
+            for (int w = 0; w < PART_NW; ++w) t += hist[w][d];
+            cbuf[j][d] = (uint16_t)t;
+        }
+        if (tid == 0) {
+            cbase[j] = L.tbase[c] * L.F + tl;
+            cnt_t[j] = nt;
+        }
+        __syncthreads();
     }
+    for (uint32_t d = tid; d < L.F; d += PART_NT)
+        for (uint32_t j = 0; j < nc; ++j) L.counts[(uint64_t)cbase[j] + (uint64_t)d * cnt_t[j]] = cbuf[j][d];
 }
 
 // Level-1 histogram with the model: the level's tiles are the aligned
@@ -700,76 +724,86 @@ __global__ __launch_bounds__(PART_NT) void k_part_hist1(const K* __restrict__ ke
     __shared__ uint32_t tab[VMPS_CDF_MAX_KNOTS + 1];
     __shared__ uint32_t hist[PART_NW][PART_DMAX];
     __shared__ __align__(16) uint32_t stage[PART_TILE];  // bucket ids in tile order
+    __shared__ uint16_t cbuf[HIST_CHUNK][PART_DMAX];      // counts of the chunk's tiles
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const PartModel PM = part_model(model, B, tab);
     const bool hi = B > 65536;
-    for (uint32_t tile = blockIdx.x; tile < nt1; tile += gridDim.x) {
-        for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
-        __syncthreads();
-        const uint32_t s0 = tile * PART_TILE;
-        const uint32_t len = n - s0 < PART_TILE ? n - s0 : PART_TILE;
-        KPair kp[RP];
+    const uint32_t nch = (nt1 + HIST_CHUNK - 1) / HIST_CHUNK;
+    for (uint32_t ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+        const uint32_t tc0 = ch * HIST_CHUNK;
+        const uint32_t nc = nt1 - tc0 < (uint32_t)HIST_CHUNK ? nt1 - tc0 : (uint32_t)HIST_CHUNK;
+        for (uint32_t jt = 0; jt < nc; ++jt) {
+            const uint32_t tile = tc0 + jt;
+            for (int i = tid; i < PART_NW * PART_DMAX; i += PART_NT) (&hist[0][0])[i] = 0;
+            __syncthreads();
+            const uint32_t s0 = tile * PART_TILE;
+            const uint32_t len = n - s0 < PART_TILE ? n - s0 : PART_TILE;
+            KPair kp[RP];
 #pragma unroll
-        for (int r = 0; r < RP; ++r) {
-            const uint32_t q = 2 * (r * PART_NT + tid);
-            if (q + 1 < len) {
-                kp[r] = *(const KPair*)(keys + s0 + q);
-            } else {
-                kp[r].a = q < len ? keys[s0 + q] : K(0);
-                kp[r].b = K(0);
+            for (int r = 0; r < RP; ++r) {
+                const uint32_t q = 2 * (r * PART_NT + tid);
+                if (q + 1 < len) {
+                    kp[r] = *(const KPair*)(keys + s0 + q);
+                } else {
+                    kp[r].a = q < len ? keys[s0 + q] : K(0);
+                    kp[r].b = K(0);
+                }
             }
+#pragma unroll
+            for (int r = 0; r < RP; ++r) {
+                const uint32_t q = 2 * (r * PART_NT + tid);
+                if (q < len) {
+                    const uint32_t b0 = PM.bucket((uint64_t)kp[r].a);
+                    atomicAdd(&hist[wave][(b0 >> shift) & mask], 1u);
+                    stage[q] = b0;
+                }
+                if (q + 1 < len) {
+                    const uint32_t b1 = PM.bucket((uint64_t)kp[r].b);
+                    atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
+                    stage[q + 1] = b1;
+                }
+            }
+            __syncthreads();
+            if ((uint32_t)tid < F) {
+                uint32_t t = 0;
+#pragma unroll
+                for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
+                cbuf[jt][tid] = (uint16_t)t;  // each thread keeps its own digit's column
+            }
+            // ids out: lane t of the workgroup holds keys [8t, 8t + 8) of the
+            // tile per round (PART_TILE / 8 / PART_NT rounds)
+#pragma unroll
+            for (int r = 0; r < (int)(PART_TILE / 8 / PART_NT); ++r) {
+                const uint32_t e = 8 * (r * PART_NT + tid);
+                const uint4 lo4 = *(const uint4*)&stage[e], hi4 = *(const uint4*)&stage[e + 4];
+                const uint32_t bs[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
+                uint32_t w[4] = {0u, 0u, 0u, 0u}, hb = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint32_t b = e + j < len ? bs[j] : 0u;
+                    w[j >> 1] |= (b & 0xffffu) << (16 * (j & 1));
+                    hb |= ((b >> 16) & 3u) << (2 * j);
+                }
+                if (e + 8 <= len) {
+                    *(uint4*)(ids_out + s0 + e) = make_uint4(w[0], w[1], w[2], w[3]);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        if (e + j < len) ids_out[s0 + e + j] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
+                }
+                if (hi) {
+                    // two lanes make one 16-key word (the tile start is a
+                    // multiple of 16); lanes past the end contribute zeros
+                    uint32_t word = hb << (16 * (lane & 1));
+                    word |= __shfl_xor(word, 1, 64);
+                    if ((lane & 1) == 0 && e < len) hibits[(s0 + e) >> 4] = word;
+                }
+            }
+            __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < RP; ++r) {
-            const uint32_t q = 2 * (r * PART_NT + tid);
-            if (q < len) {
-                const uint32_t b0 = PM.bucket((uint64_t)kp[r].a);
-                atomicAdd(&hist[wave][(b0 >> shift) & mask], 1u);
-                stage[q] = b0;
-            }
-            if (q + 1 < len) {
-                const uint32_t b1 = PM.bucket((uint64_t)kp[r].b);
-                atomicAdd(&hist[wave][(b1 >> shift) & mask], 1u);
-                stage[q + 1] = b1;
-            }
-        }
-        __syncthreads();
-        if ((uint32_t)tid < F) {
-            uint32_t t = 0;
-#pragma unroll
-            for (int w = 0; w < PART_NW; ++w) t += hist[w][tid];
-            counts[(uint64_t)tid * nt1 + tile] = t;
-        }
-        // ids out: lane t of the workgroup holds keys [8t, 8t + 8) of the
-        // tile per round (PART_TILE / 8 / PART_NT rounds)
-#pragma unroll
-        for (int r = 0; r < (int)(PART_TILE / 8 / PART_NT); ++r) {
-            const uint32_t e = 8 * (r * PART_NT + tid);
-            const uint4 lo4 = *(const uint4*)&stage[e], hi4 = *(const uint4*)&stage[e + 4];
-            const uint32_t bs[8] = {lo4.x, lo4.y, lo4.z, lo4.w, hi4.x, hi4.y, hi4.z, hi4.w};
-            uint32_t w[4] = {0u, 0u, 0u, 0u}, hb = 0;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const uint32_t b = e + j < len ? bs[j] : 0u;
-                w[j >> 1] |= (b & 0xffffu) << (16 * (j & 1));
-                hb |= ((b >> 16) & 3u) << (2 * j);
-            }
-            if (e + 8 <= len) {
-                *(uint4*)(ids_out + s0 + e) = make_uint4(w[0], w[1], w[2], w[3]);
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j)
-                    if (e + j < len) ids_out[s0 + e + j] = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
-            }
-            if (hi) {
-                // two lanes make one 16-key word (the tile start is a
-                // multiple of 16); lanes past the end contribute zeros
-                uint32_t word = hb << (16 * (lane & 1));
-                word |= __shfl_xor(word, 1, 64);
-                if ((lane & 1) == 0 && e < len) hibits[(s0 + e) >> 4] = word;
-            }
-        }
-        __syncthreads();
+        // the chunk's counts, digit by digit: nc consecutive words per digit
+        if ((uint32_t)tid < F)
+            for (uint32_t jt = 0; jt < nc; ++jt) counts[(uint64_t)tid * nt1 + tc0 + jt] = cbuf[jt][tid];
     }
 }
 
@@ -1217,7 +1251,8 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
     {
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_init<<<1, 1, 0, s>>>(n, p1, t1, cnt_total, F1);
-        const unsigned g1 = nt1 < occ_h1[d] ? nt1 : occ_h1[d];
+        const uint32_t nch1 = (uint32_t)ceil_div(nt1, HIST_CHUNK);
+        const unsigned g1 = nch1 < occ_h1[d] ? nch1 : occ_h1[d];
         k_part_hist1<K><<<g1, PART_NT, 0, s>>>(kin, id1, hib, n, nt1, F1, lo_bits, F1 - 1, c1, Mdev, B);
         VMPS_HIP(scan_exclusive_u32(c1, o1, (uint64_t)nt1 * F1, cnt_total, tot, stmp, s));
     }
@@ -1233,7 +1268,7 @@ hipError_t partition_t(const K* kin, const uint32_t* vin, K* ktmp, uint32_t* vtm
         TraceScope tr(VMPS_TRACE_HISTOGRAM, s);
         k_part_level2<<<1, PART_DMAX, 0, s>>>(o1, nt1, F1, n, F2, p2, t2, cnt_total + 1);
         PartLevel L2{p2, t2, F1, F2, 0, F2 - 1, dbits2, c2, o2};
-        k_part_hist2<<<nt2cap, PART_NT, 0, s>>>(id2, L2);
+        k_part_hist2<<<(unsigned)ceil_div(nt2cap, HIST_CHUNK), PART_NT, 0, s>>>(id2, L2);
         VMPS_HIP(scan_exclusive_u32(c2, o2, (uint64_t)nt2cap * F2, cnt_total + 1, tot + 1, stmp, s));
     }
     {

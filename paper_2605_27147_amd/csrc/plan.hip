@@ -813,18 +813,56 @@ __global__ void k_segs_inst(const uint32_t* __restrict__ hbm_list, const uint32_
 // power level.  level[0, MAX_LEVEL): tiles of each level; level[MAX_LEVEL,
 // 2*MAX_LEVEL): their start in the level-ordered pair list; level[2*MAX_LEVEL,
 // 3*MAX_LEVEL): fill positions.
+// The counters of a level take one atomic per wave and power present in the
+// wave (the lanes of one power summed first): one atomic per node put tens
+// of thousands of updates on a handful of addresses.  p = MAX_LEVEL marks a
+// lane without a node.  Returns, for the lane's power, the sum of v over the
+// lanes of that power before it, and the value the level's counter held
+// before the wave's atomic.
+__device__ inline uint32_t wave_level_add(uint32_t p, uint32_t v, uint32_t* __restrict__ ctr, uint32_t& before)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint64_t todo = __ballot(p < MAX_LEVEL);
+    uint32_t old = 0;
+    before = 0;
+    while (todo) {
+        const int leader = __ffsll((unsigned long long)todo) - 1;
+        const uint32_t pl = (uint32_t)__shfl((int)p, leader, WAVE);
+        const bool mine = p == pl;
+        const uint32_t inc = wave_incl_scan(mine ? v : 0u);
+        const uint32_t tot = (uint32_t)__shfl((int)inc, WAVE - 1, WAVE);
+        uint32_t o = 0;
+        if (lane == leader) o = atomicAdd(&ctr[pl], tot);
+        o = (uint32_t)__shfl((int)o, leader, WAVE);
+        if (mine) {
+            before = inc - v;
+            old = o;
+        }
+        todo &= ~__ballot(mine);
+    }
+    return old;
+}
+
 __global__ void k_level_count(const uint32_t* __restrict__ hbm_list, const uint32_t* __restrict__ bnd_lpos,
                               const uint32_t* __restrict__ bnd_rpos, const uint8_t* __restrict__ power,
                               uint32_t T_out, const uint32_t* counters, uint32_t* __restrict__ tiles,
                               uint32_t* __restrict__ level)
 {
     const uint32_t h = counters[CNT_NHBM];
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
-        const uint32_t t = hbm_list[q];
-        const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
-        const uint32_t nt = (R - 1) / T_out - L / T_out + 1;
-        tiles[q] = nt;
-        if (power[t] < MAX_LEVEL) atomicAdd(&level[power[t]], nt);
+    // whole workgroups step together, so that every lane of a wave takes
+    // part in the wave's sums
+    for (uint32_t b = blockIdx.x * blockDim.x; b < h; b += gridDim.x * blockDim.x) {
+        const uint32_t q = b + threadIdx.x;
+        uint32_t p = MAX_LEVEL, nt = 0;
+        if (q < h) {
+            const uint32_t t = hbm_list[q];
+            const uint32_t L = bnd_lpos[t], R = bnd_rpos[t];
+            nt = (R - 1) / T_out - L / T_out + 1;
+            tiles[q] = nt;
+            p = power[t] < MAX_LEVEL ? power[t] : MAX_LEVEL;
+        }
+        uint32_t before;
+        wave_level_add(p, nt, level, before);
     }
 }
 
@@ -843,17 +881,23 @@ __global__ void k_level_offsets(uint32_t* __restrict__ level, uint32_t pair_cap)
     }
 }
 
-// Every HBM node reserves the slots of its output tiles in its level (one
-// atomic per node, not per tile: a level's counter sees as many updates as
-// the level has nodes).
+// Every HBM node reserves the slots of its output tiles in its level: the
+// nodes of one power in a wave take consecutive slots from one atomic.
 __global__ void k_level_reserve(const uint32_t* __restrict__ hbm_list, const uint8_t* __restrict__ power,
                                 const uint32_t* __restrict__ tiles, const uint32_t* counters,
                                 uint32_t* __restrict__ level, uint32_t* __restrict__ node_base)
 {
     const uint32_t h = counters[CNT_NHBM];
-    for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < h; q += gridDim.x * blockDim.x) {
-        const uint32_t p = power[hbm_list[q]];
-        node_base[q] = p < MAX_LEVEL ? level[MAX_LEVEL + p] + atomicAdd(&level[2 * MAX_LEVEL + p], tiles[q]) : NONE;
+    for (uint32_t b = blockIdx.x * blockDim.x; b < h; b += gridDim.x * blockDim.x) {
+        const uint32_t q = b + threadIdx.x;
+        uint32_t p = MAX_LEVEL, nt = 0;
+        if (q < h) {
+            p = power[hbm_list[q]];
+            if (p < MAX_LEVEL) nt = tiles[q]; else p = MAX_LEVEL;
+        }
+        uint32_t before;
+        const uint32_t old = wave_level_add(p, nt, level + 2 * MAX_LEVEL, before);
+        if (q < h) node_base[q] = p < MAX_LEVEL ? level[MAX_LEVEL + p] + old + before : NONE;
     }
 }
 

@@ -203,6 +203,45 @@ def test_sort_repeatable_with_poisoned_workspace(vm, orc):
         assert np.array_equal(_np(keys, np.uint64), want)
 
 
+def _long_next_to_tiny(n, seed, bits):
+    """Sorted runs of one to three keys next to sorted runs of up to half the
+    input: the run structure whose long merges reach the highest power a
+    merge longer than the tile can have, where the launched merge levels
+    stop (2^p < 9 n / T)."""
+    rng = np.random.default_rng(seed)
+    parts, tot = [], 0
+    while tot < n:
+        L = min(int(rng.choice([1, 2, 3, int(rng.integers(1, n // 2 + 2))])), n - tot)
+        parts.append(np.sort(rng.integers(0, 1 << (bits - 8), L)))
+        tot += L
+    return np.concatenate(parts).astype(np.uint32 if bits == 32 else np.uint64)
+
+
+@pytest.mark.parametrize("bits", [32, 64])
+def test_sort_long_runs_next_to_tiny_runs(vm, orc, bits):
+    """Plain sort (keys, and the stable argsort) and paged sort on long runs
+    next to tiny ones, against the oracle: no merge level the sorts skip
+    holds a merge."""
+    import torch
+    dt = np.uint32 if bits == 32 else np.uint64
+    for seed in range(3):
+        for n in ((1 << 20) + 77, 3 << 19):
+            x = _long_next_to_tiny(n, seed, bits)
+            _say("long next to tiny", bits, seed, n)
+            want, wantv, _, _ = orc.powersort(x, np.arange(n, dtype=np.uint32))
+            keys = _t(x)
+            vm.sort_(keys)
+            assert np.array_equal(_np(keys, dt), want.astype(dt)), (seed, n)
+            keys = _t(x)
+            vals = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            vm.argsort_(keys, vals)
+            assert np.array_equal(_np(keys, dt), want.astype(dt)), (seed, n)
+            assert np.array_equal(_np(vals, np.uint32), wantv), (seed, n)
+            keys = _t(x)
+            vm.sort_vm_(keys, window_pages=3)
+            assert np.array_equal(_np(keys, dt), want.astype(dt)), (seed, n)
+
+
 # ------------------------------------------------------------- segmented --
 @pytest.mark.parametrize("bits", [32, 64])
 def test_segmented_sort_matches_oracle(vm, orc, bits):

@@ -386,26 +386,33 @@ struct BatcherNet {
     }
 };
 
-// Sort of S[s, s+cnt), cnt <= 32, keys without values: equal keys cannot be
-// told apart, so the result of any sorting network is the stable sort (the
-// result of the insertion sort).  Min/max comparators on the registers;
-// unused slots hold the largest key and stay last.
-template <typename K, int LAY>
-__device__ __forceinline__ void chunk_sort32(K* __restrict__ S, uint32_t s, uint32_t cnt)
+// Sort of S[s, s+cnt), cnt <= N (32 or 64), keys without values: equal keys
+// cannot be told apart, so the result of any sorting network is the stable
+// sort (the result of the insertion sort).  Min/max comparators on the
+// registers; unused slots hold the largest key and stay last.  With N = 64
+// a whole forced run (minrun is below 64) is sorted by one lane, and no
+// bottom-up merge pass over the tile is needed to join two 32-key halves.
+template <int N>
+constexpr BatcherNet<N> batcher_net{};
+
+template <int N, typename K, int LAY>
+__device__ __forceinline__ void chunk_sort_net(K* __restrict__ S, uint32_t s, uint32_t cnt)
 {
-    constexpr BatcherNet<32> net{};
-    K x[32];
+    K x[N];
 #pragma unroll
-    for (int j = 0; j < 32; ++j) x[j] = (uint32_t)j < cnt ? S[pxp<LAY>(s + j)] : ~K(0);
+    for (int j = 0; j < N; ++j) x[j] = (uint32_t)j < cnt ? S[pxp<LAY>(s + j)] : ~K(0);
+    // every comparator's register indices are compile-time constants (a
+    // loop the compiler does not unroll fully would put x in scratch memory)
+    static_for<BatcherNet<N>::count()>([&](auto cc) {
+        constexpr int c = decltype(cc)::value;
+        constexpr int ia = batcher_net<N>.a[c], ib = batcher_net<N>.b[c];
+        const K u = x[ia], v = x[ib];
+        x[ia] = u < v ? u : v;
+        x[ib] = u < v ? v : u;
+    });
+    asm volatile("" : "+v"(s));  // recompute the addresses rather than keep N of them live
 #pragma unroll
-    for (int c = 0; c < BatcherNet<32>::count(); ++c) {
-        const K u = x[net.a[c]], v = x[net.b[c]];
-        x[net.a[c]] = u < v ? u : v;
-        x[net.b[c]] = u < v ? v : u;
-    }
-    asm volatile("" : "+v"(s));  // recompute the addresses rather than keep 32 of them live
-#pragma unroll
-    for (int j = 0; j < 32; ++j)
+    for (int j = 0; j < N; ++j)
         if ((uint32_t)j < cnt) S[pxp<LAY>(s + j)] = x[j];
 }
 
@@ -958,20 +965,30 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     // 7a. the first bottom-up levels of every forced run: chunks of 2^CWL
     // elements from the run start, sorted in registers (unsorted runs are
     // forced runs, shorter than 64).  32-bit keys without values: 32-element
-    // chunks by a sorting network (five levels); otherwise 16-element chunks
-    // by the stable transposition network (four levels).
+    // chunks by a sorting network, and in the 32-bit key kernels (plain
+    // layout, registers to spare) whole forced runs of up to 64 keys when
+    // some forced run is longer than 32 (the narrow kernels, at 128
+    // registers, spilled inside the 64-key network and ran 10% slower);
+    // otherwise 16-element chunks by the stable transposition network.
     constexpr bool NET32 = sizeof(KT) == 4 && VMODE == 0;
-    constexpr uint32_t CWL = NET32 ? 5u : 4u;
+    constexpr bool NET64 = NET32 && LAY == 1;
+    const uint32_t CWL = NET32 ? ((NET64 && maxf > 32) ? 6u : 5u) : 4u;
     if (maxf > 1) {
         const uint32_t cpr = (maxf + (1u << CWL) - 1) >> CWL;
         for (uint32_t x = tid; x < cpr * kr; x += NT) {
             const uint32_t r = x / cpr, c = x - r * cpr;
             const uint32_t cs = RS[r] + (c << CWL), ce = RS[r + 1];
             if (!SR[r] && cs + 1 < ce) {
-                if constexpr (NET32)
-                    chunk_sort32<KT, LAY>(S, cs, min(32u, ce - cs));
-                else
+                if constexpr (NET64) {
+                    if (CWL == 6)
+                        chunk_sort_net<64, KT, LAY>(S, cs, min(64u, ce - cs));
+                    else
+                        chunk_sort_net<32, KT, LAY>(S, cs, min(32u, ce - cs));
+                } else if constexpr (NET32) {
+                    chunk_sort_net<32, KT, LAY>(S, cs, min(32u, ce - cs));
+                } else {
                     chunk_sort16<KT, VMODE, LAY>(S, SV, cs, min(16u, ce - cs));
+                }
             }
         }
         __syncthreads();

@@ -964,13 +964,16 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
     const uint32_t maxf = scal[3], mask = scal[2];
     // 7a. the first bottom-up levels of every forced run: chunks of 2^CWL
     // elements from the run start, sorted in registers (unsorted runs are
-    // forced runs, shorter than 64).  32-bit keys without values: 32-element
-    // chunks by a sorting network, and in the 32-bit key kernels (plain
-    // layout, registers to spare) whole forced runs of up to 64 keys when
-    // some forced run is longer than 32 (the narrow kernels, at 128
-    // registers, spilled inside the 64-key network and ran 10% slower);
-    // otherwise 16-element chunks by the stable transposition network.
-    constexpr bool NET32 = sizeof(KT) == 4 && VMODE == 0;
+    // forced runs, shorter than 64).  Keys without values: 32-element chunks
+    // by a sorting network, and in the 32-bit key kernels (plain layout,
+    // registers to spare) whole forced runs of up to 64 keys when some
+    // forced run is longer than 32 (the narrow kernels, at 128 registers,
+    // spilled inside the 64-key network and ran 10% slower).  64-bit keys
+    // without values: 16-element chunks by a sorting network (32 of them
+    // spilled).  With values: 16-element chunks by the stable transposition
+    // network.
+    constexpr bool NET = VMODE == 0;  // keys without values: any network gives the stable sort
+    constexpr bool NET32 = NET && sizeof(KT) == 4;
     constexpr bool NET64 = NET32 && LAY == 1;
     const uint32_t CWL = NET32 ? ((NET64 && maxf > 32) ? 6u : 5u) : 4u;
     if (maxf > 1) {
@@ -986,6 +989,8 @@ __device__ __forceinline__ void tile_body(KT* __restrict__ S, uint32_t* __restri
                         chunk_sort_net<32, KT, LAY>(S, cs, min(32u, ce - cs));
                 } else if constexpr (NET32) {
                     chunk_sort_net<32, KT, LAY>(S, cs, min(32u, ce - cs));
+                } else if constexpr (NET) {
+                    chunk_sort_net<16, KT, LAY>(S, cs, min(16u, ce - cs));
                 } else {
                     chunk_sort16<KT, VMODE, LAY>(S, SV, cs, min(16u, ce - cs));
                 }

@@ -112,6 +112,129 @@ def run_path(vm, path, keys, pristine, steps, warmup, traced_steps=None):
     return float(np.mean(ms)), trace
 
 
+def _timed(fn, restore, steps):
+    """Mean ms of `steps` calls after one warm-up call, HIP events around
+    each call, input restored before each (outside the events)."""
+    import numpy as np
+    import torch
+    ts = []
+    for i in range(steps + 1):
+        restore()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        if i:
+            ts.append(e0.elapsed_time(e1))
+    return float(np.mean(ts))
+
+
+def _m_hbm(vm, keys, has_values=False):
+    import numpy as np
+    sch = vm.sort_schedule(keys, has_values=has_values)
+    return int((sch["node_r"].astype(np.int64) - sch["node_l"].astype(np.int64)).sum()), int(sch["tile"])
+
+
+def bench_configs(vm, dev, steps):
+    """The other workload configurations, each timed on its own input:
+    algorithmic bytes of the plain path = bitmap read (kb per key), tile pass
+    (kb in, kb + vb out; index values are generated, not read), merges
+    beyond the LDS tile (2 (kb + vb) per element of M_HBM)."""
+    import numpy as np
+    import torch
+
+    import workloads
+    out = {}
+
+    def entry(name, n, ms, b_alg=None, **kw):
+        e = {"workload": name, "n": n, "ms_per_step": round(ms, 4), "value": round(n / (ms / 1e3) / 1e9, 4),
+             "unit": "Gkeys/s"}
+        if b_alg is not None:
+            e.update({"bytes_alg": b_alg, "achieved_GBs": round(b_alg / (ms / 1e3) / 1e9, 1),
+                      "frac": round(b_alg / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)})
+        e.update(kw)
+        return e
+
+    # 2^16 uint32 keys, uniform, plain path (launch-bound at this size)
+    n1 = 1 << 16
+    x1 = workloads.uniform(n1, 32, 1)
+    src1 = torch.from_numpy(x1.view(np.int32)).to(dev)
+    k1 = torch.empty_like(src1)
+    ws1 = torch.empty(vm.sort_workspace_size(n1, vm.U32, False), dtype=torch.uint8, device=dev)
+    log(f"config uniform32 2^16: timed {steps * 10}")
+    ms1 = _timed(lambda: vm.sort_(k1, workspace=ws1), lambda: k1.copy_(src1), steps * 10)
+    assert np.array_equal(k1.cpu().numpy().view(np.uint32), np.sort(x1)), "uniform32: wrong output"
+    m1, _ = _m_hbm(vm, src1)
+    out["uniform32_2p16"] = entry("n=2^16 uint32 uniform keys, plain path", n1, ms1, 4 * n1 + 8 * n1 + 8 * m1,
+                                  merge_cost_hbm=m1)
+
+    # 2^24 uint64 keys with presortedness (geometric runs of mean 2^10, 10%
+    # reversed, 1% random swaps), plain path, with and without the reversal
+    # of strictly decreasing runs
+    n2 = 1 << 24
+    x2 = workloads.presorted(n2, 33, mean_run=1024, bits=64)
+    src2 = torch.from_numpy(x2.view(np.int64)).to(dev)
+    k2 = torch.empty_like(src2)
+    ws2 = torch.empty(vm.sort_workspace_size(n2, vm.U64, False), dtype=torch.uint8, device=dev)
+    log(f"config presorted64 2^24: timed {steps * 3}")
+    ms2 = _timed(lambda: vm.sort_(k2, workspace=ws2), lambda: k2.copy_(src2), steps * 3)
+    ref2 = np.sort(x2)
+    assert np.array_equal(k2.cpu().numpy().view(np.uint64), ref2), "presorted64: wrong output"
+    ms2d = _timed(lambda: vm.sort_(k2, workspace=ws2, desc=True), lambda: k2.copy_(src2), steps * 3)
+    assert np.array_equal(k2.cpu().numpy().view(np.uint64), ref2), "presorted64 (descending runs): wrong output"
+    m2, _ = _m_hbm(vm, src2)
+    out["presorted64_2p24"] = entry("n=2^24 uint64 keys, geometric runs (mean 2^10), 10% reversed, 1% swaps, "
+                                    "plain path", n2, ms2, 8 * n2 + 16 * n2 + 16 * m2, merge_cost_hbm=m2,
+                                    descending_runs_ms=round(ms2d, 4),
+                                    descending_runs_value=round(n2 / (ms2d / 1e3) / 1e9, 4))
+    del src2, k2, ws2
+
+    # 2^28 uint64 keys, mixture (50% uniform, 30% Zipf 1.1 over 2^20
+    # values, 20% normal around 64 centres), stable sort of (key, u32 index)
+    # pairs: plain and learned paths
+    n3 = 1 << 28
+    log("config mixture64 pairs 2^28: generating")
+    x3 = workloads.mixture(n3, 36)
+    src3 = torch.from_numpy(x3.view(np.int64)).to(dev)
+    del x3
+    k3 = torch.empty_like(src3)
+    v3 = torch.empty(n3, dtype=torch.int32, device=dev)
+    ws3 = torch.empty(vm.sort_workspace_size(n3, vm.U64, True), dtype=torch.uint8, device=dev)
+
+    def check3(what):
+        s = k3 ^ torch.iinfo(torch.int64).min
+        assert bool((s[1:] >= s[:-1]).all().item()), f"{what}: keys out of order"
+        idx = v3.to(torch.int64)
+        assert bool((src3[idx] == k3).all().item()), f"{what}: a value does not index its key"
+        hit = torch.zeros(n3, dtype=torch.bool, device=dev)
+        hit[idx] = True
+        assert bool(hit.all().item()), f"{what}: values are not a permutation"
+        del idx, hit
+        eq = s[1:] == s[:-1]
+        assert bool(((v3[1:] > v3[:-1]) | ~eq).all().item()), f"{what}: equal keys out of input order"
+
+    log(f"config mixture64 pairs 2^28, plain: timed {steps}")
+    ms3 = _timed(lambda: vm.sort_(k3, v3, iota=True, workspace=ws3), lambda: k3.copy_(src3), steps)
+    check3("mixture64 pairs, plain")
+    del ws3
+    torch.cuda.empty_cache()
+    lcfg = vm.learned_default_config(n3, vm.U64)
+    lws = torch.empty(vm.learned_workspace_size(n3, vm.U64, True, lcfg), dtype=torch.uint8, device=dev)
+    log(f"config mixture64 pairs 2^28, learned: timed {steps}")
+    ms3l = _timed(lambda: vm.sort_learned_(k3, v3, iota=True, workspace=lws, read_stats=False),
+                  lambda: k3.copy_(src3), steps)
+    check3("mixture64 pairs, learned")
+    m3, _ = _m_hbm(vm, src3, has_values=True)
+    out["mixture64_pairs_2p28"] = entry("n=2^28 uint64 mixture keys, stable sort of (key, u32 index) pairs, "
+                                        "plain path", n3, ms3, 8 * n3 + 20 * n3 + 24 * m3, merge_cost_hbm=m3,
+                                        learned_ms=round(ms3l, 4),
+                                        learned_value=round(n3 / (ms3l / 1e3) / 1e9, 4))
+    del src3, k3, v3, lws
+    torch.cuda.empty_cache()
+    return out
+
+
 WS = [None]
 MEDIAN = {}
 TRACED = 3  # extra sorts run with per-kernel tracing for the breakdown
@@ -131,6 +254,9 @@ def main():
                     help="records of 120 bytes sorted by a u64 key field (0: skip)")
     ap.add_argument("--batch-nseg", type=int, default=4096,
                     help="arrays of the batched u32 workload sorted in one segmented call (0: skip)")
+    ap.add_argument("--configs-steps", type=int, default=3,
+                    help="steps of the other workload configurations: 2^16 u32 uniform, 2^24 u64 presorted, "
+                         "2^28 u64 mixture (key, index) pairs (0: skip)")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -296,6 +422,10 @@ def main():
         del rec, out_rec, rws
         torch.cuda.empty_cache()
 
+    cfg_out = None
+    if args.configs_steps > 0:
+        cfg_out = bench_configs(vm, dev, args.configs_steps)
+
     batch_out = None
     if args.batch_nseg > 0:
         # the batched workload: arrays of 2^6..2^20 u32 keys (log-uniform
@@ -416,6 +546,8 @@ def main():
         out["records"] = rec_out
     if batch_out is not None:
         out["batch"] = batch_out
+    if cfg_out is not None:
+        out["configs"] = cfg_out
     if other_ms is not None:
         out["compare"] = {"path": other, "ms_per_step": round(other_ms, 4),
                           "value": round(n / (other_ms / 1e3) / 1e9, 4), "unit": "Gkeys/s"}

@@ -451,8 +451,10 @@ def main():
                 tms.append(e0.elapsed_time(e1))
         bms = float(np.mean(tms))
         # algorithmic bytes: the tile pass reads and writes every key; arrays
-        # longer than the LDS tile (16384 u32 keys) also have the descent
-        # bitmap read and their merges beyond the tile (M_HBM) read and write
+        # longer than the LDS tile also have the descent bitmap read and
+        # their merges beyond the tile (M_HBM) read and write.  Counted with
+        # the 16384-key tile's schedule, the fewest bytes of the compiled
+        # tiles (the tuned 8192-key tile sends more merges to HBM)
         T32 = 16384
         m_b, big = 0, 0
         for s in range(args.batch_nseg):
@@ -466,7 +468,9 @@ def main():
         for s in range(0, args.batch_nseg, 97):
             a, b = int(boff[s]), int(boff[s + 1])
             assert np.array_equal(out_b[a:b], np.sort(bk[a:b])), "batch: segment not sorted"
+        tu = vm.get_tuning(vm.U32, False)
         batch_out = {"arrays": args.batch_nseg, "keys": nb, "key_bits": 32, "ms_per_step": round(bms, 4),
+                     "lds_tile": tu["tile_elems"] or T32, "tile_threads": tu["tile_threads"] or 512,
                      "value": round(nb / (bms / 1e3) / 1e9, 4), "unit": "Gkeys/s", "merge_cost_hbm": m_b,
                      "bytes_alg": b_alg, "achieved_GBs": round(b_alg / (bms / 1e3) / 1e9, 1),
                      "frac": round(b_alg / (bms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}

@@ -418,10 +418,20 @@ typedef struct {
                                (256 threads): 8 or 16 (0: 16, or 8 for 64-bit
                                keys with values); the workspace sizes allow
                                either.  The paged sort keeps the default. */
+    int32_t tile_elems;     /* segmented sort (vmps_segmented_sort and its
+                               graph), 32-bit keys without values only: the
+                               LDS tile T, 16384 or 8192 elements (0: 16384);
+                               other configurations accept 0 only.  The
+                               segmented workspace size allows either. */
+    int32_t tile_threads;   /* threads of a tile-pass workgroup with
+                               tile_elems = 8192: 512 (16 keys per thread) or
+                               256 (32 per thread); 0 keeps 512.  Must be 0
+                               or 512 when tile_elems is 0 or 16384. */
 } vmps_tuning;
 
 /* t == NULL restores the defaults.  Negative fields, bucket_div > 64,
- * host_wait outside {0, 1} or merge_ki outside {0, 8, 16} -> INVALID_ARG. */
+ * host_wait outside {0, 1}, merge_ki outside {0, 8, 16}, or a tile_elems /
+ * tile_threads pair other than those listed above -> INVALID_ARG. */
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t);
 vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t);
 

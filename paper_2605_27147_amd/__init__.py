@@ -53,7 +53,8 @@ class CdfModel(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("tile_wg_per_cu", ctypes.c_int32), ("merge_grid", ctypes.c_int32),
-                ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32), ("merge_ki", ctypes.c_int32)]
+                ("bucket_div", ctypes.c_int32), ("host_wait", ctypes.c_int32), ("merge_ki", ctypes.c_int32),
+                ("tile_elems", ctypes.c_int32), ("tile_threads", ctypes.c_int32)]
 
 
 class VmLayout(ctypes.Structure):
@@ -160,8 +161,9 @@ def _apply_autotune(lib, path: str = AUTOTUNE_PATH):
         if e.get("merge_ki", 0) not in (0, 8, 16):
             continue
         t = Tuning(int(e.get("tile_wg_per_cu", 0)), int(e.get("merge_grid", 0)), int(e.get("bucket_div", 0)), 0,
-                   int(e.get("merge_ki", 0)))
+                   int(e.get("merge_ki", 0)), int(e.get("tile_elems", 0)), int(e.get("tile_threads", 0)))
         kt = U64 if e["dtype"] == "u64" else U32
+        # an entry the library rejects (INVALID_ARG) leaves the defaults
         lib.vmps_set_tuning(kt, int(bool(e["values"])), ctypes.byref(t))
 
 
@@ -176,8 +178,9 @@ def _gpu_arch():
 
 
 def set_tuning(dtype_code: int, has_values: bool, tile_wg_per_cu: int = 0, merge_grid: int = 0,
-               bucket_div: int = 0, host_wait: int = 0, merge_ki: int = 0):
-    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, host_wait, merge_ki)
+               bucket_div: int = 0, host_wait: int = 0, merge_ki: int = 0, tile_elems: int = 0,
+               tile_threads: int = 0):
+    t = Tuning(tile_wg_per_cu, merge_grid, bucket_div, host_wait, merge_ki, tile_elems, tile_threads)
     _check(load_library().vmps_set_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_set_tuning")
 
 
@@ -189,7 +192,8 @@ def get_tuning(dtype_code: int, has_values: bool) -> dict:
     t = Tuning()
     _check(load_library().vmps_get_tuning(dtype_code, int(bool(has_values)), ctypes.byref(t)), "vmps_get_tuning")
     return {"tile_wg_per_cu": t.tile_wg_per_cu, "merge_grid": t.merge_grid, "bucket_div": t.bucket_div,
-            "host_wait": t.host_wait, "merge_ki": t.merge_ki}
+            "host_wait": t.host_wait, "merge_ki": t.merge_ki, "tile_elems": t.tile_elems,
+            "tile_threads": t.tile_threads}
 
 
 def status_string(s: int) -> str:

@@ -15,7 +15,9 @@ fastest into the JSON table the binding loads with the library
 
 The candidates cover the persistent tile pass's workgroups per CU, the
 merge-level grid, the merge tile's outputs per thread (merge_ki 8 or 16:
-tiles of 2048 or 4096 elements) and, for the learned path, the bucket size.
+tiles of 2048 or 4096 elements), for the learned path the bucket size, and
+for the segmented sort of u32 keys the LDS tile and its workgroup size
+(512 threads x 16384 keys, 512 x 8192 or 256 x 8192).
 """
 from __future__ import annotations
 
@@ -95,12 +97,13 @@ def main(argv=None):
     keys = torch.empty_like(pristine)
     cfg = vm.learned_default_config(n, vm.U64)
     ws = torch.empty(vm.learned_workspace_size(n, vm.U64, False, cfg) + (1 << 20), dtype=torch.uint8, device=dev)
-    fields = ("tile_wg_per_cu", "merge_grid", "bucket_div", "merge_ki")
+    fields = ("tile_wg_per_cu", "merge_grid", "bucket_div", "merge_ki", "tile_elems", "tile_threads")
     # merge_ki stays at its default here: this entry (u64 keys, no values)
     # also serves the plain sort of u64 keys, whose merge levels need the
     # 4096-element tiles (2048 measured 7% slower there), while the learned
     # sort's few merges cannot tell the two apart
-    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": b, "merge_ki": 0}
+    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": b, "merge_ki": 0, "tile_elems": 0,
+              "tile_threads": 0}
              for t, m, b in itertools.product([0, 1], [1024, 2048], [0, 4])]
     best, res = tune(space,
                      lambda c: vm.set_tuning(vm.U64, False, **c), lambda: vm.reset_tuning(vm.U64, False),
@@ -116,8 +119,12 @@ def main(argv=None):
     pristine = torch.from_numpy(kb.view(np.int32)).to(dev)
     offs = torch.from_numpy(off).to(dev)
     keys = torch.empty_like(pristine)
-    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k}
-             for t, m, k in itertools.product([0, 1], [1024, 2048, 4096], [0, 8])]
+    # the LDS tile and the workgroup size of its pass: 512 x 16384 (32 keys
+    # per thread), 512 x 8192 (16) and 256 x 8192 (32)
+    space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k, "tile_elems": te,
+              "tile_threads": tt}
+             for t, m, k, (te, tt) in itertools.product([0, 1], [1024, 2048, 4096], [0, 8],
+                                                        [(0, 0), (8192, 512), (8192, 256)])]
     best, res = tune(space,
                      lambda c: vm.set_tuning(vm.U32, False, **c), lambda: vm.reset_tuning(vm.U32, False),
                      lambda: vm.segmented_sort_(keys, offs), lambda: keys.copy_(pristine), lambda: keys, a.steps)
@@ -136,7 +143,8 @@ def main(argv=None):
         keys = torch.empty_like(pristine)
         vals = torch.empty(npairs, dtype=torch.int32, device=dev)
         pws = torch.empty(vm.sort_workspace_size(npairs, code, True), dtype=torch.uint8, device=dev)
-        space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k}
+        space = [{"tile_wg_per_cu": t, "merge_grid": m, "bucket_div": 0, "merge_ki": k, "tile_elems": 0,
+                  "tile_threads": 0}
                  for t, m, k in itertools.product([0, 1], [1024, 2048, 4096], [0, ki_alt])]
         best, res = tune(space,
                          lambda c, code=code: vm.set_tuning(code, True, **c),

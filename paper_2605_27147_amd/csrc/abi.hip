@@ -68,14 +68,14 @@ struct SortLayout {
 // minrun_of(n) long, which sizes the planner's run arrays.
 static uint32_t rule_min_len(uint64_t n) { return n > 0 ? minrun_of(n) : 1u; }
 
-SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values, uint32_t min_len)
+SortLayout sort_layout(uint64_t n, uint64_t k, vmps_dtype kt, int has_values, uint32_t min_len, uint32_t T = 0)
 {
     const int kb = key_bits_of(kt);
     SortLayout L;
     L.keys_b = 0;
     L.vals_b = align256(key_bytes(kt) * n);
     L.plan = L.vals_b + (has_values ? align256(4 * n) : 0);
-    const uint32_t T = tilesort_capacity(kb, has_values);
+    if (!T) T = tilesort_capacity(kb, has_values);
     const uint32_t TO = merge_tile_out(kb, has_values);
     L.total = L.plan + plan_workspace_bytes(n, k, T, TO, min_len);
     return L;
@@ -468,7 +468,14 @@ vmps_status vmps_segmented_sort_workspace_size(int64_t total, int64_t nseg, vmps
     if (!bytes || total < 0 || (uint64_t)total >= (1ull << 32) || nseg < 0 || (uint64_t)nseg >= (1ull << 31))
         return VMPS_ERR_INVALID_ARG;
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    *bytes = sort_layout((uint64_t)total, (uint64_t)(nseg > 0 ? nseg : 1), kt, has_values ? 1 : 0, 16).total;
+    const uint64_t k = (uint64_t)(nseg > 0 ? nseg : 1);
+    size_t b = sort_layout((uint64_t)total, k, kt, has_values ? 1 : 0, 16).total;
+    // 32-bit keys without values may run on the tuned 8192-element tile
+    if (kt == VMPS_U32 && !has_values) {
+        const size_t b2 = sort_layout((uint64_t)total, k, kt, 0, 16, 8192).total;
+        if (b2 > b) b = b2;
+    }
+    *bytes = b;
     return VMPS_OK;
 }
 
@@ -484,15 +491,17 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
         return VMPS_ERR_INVALID_ARG;
     if (nseg == 0 || total <= 1) return VMPS_OK;
     const int has_values = values ? 1 : 0;
-    const SortLayout L = sort_layout((uint64_t)total, (uint64_t)nseg, kt, has_values, 16);
+    const int kb = key_bits_of(kt);
+    // the tile length (and workgroup size) tuned for this configuration
+    const Tuning& tu = tuning_for(kb, has_values != 0);
+    const uint32_t T = tu.tile_elems ? (uint32_t)tu.tile_elems : tilesort_capacity(kb, has_values);
+    const SortLayout L = sort_layout((uint64_t)total, (uint64_t)nseg, kt, has_values, 16, T);
     if (!ws || ws_bytes < L.total) return VMPS_ERR_WORKSPACE_TOO_SMALL;
     if ((uintptr_t)ws & 255) return VMPS_ERR_INVALID_ARG;
-    const int kb = key_bits_of(kt);
     uint8_t* w = (uint8_t*)ws;
     void* keysB = w + L.keys_b;
     uint32_t* valsB = has_values ? (uint32_t*)(w + L.vals_b) : nullptr;
     Plan P;
-    const uint32_t T = tilesort_capacity(kb, has_values);
     plan_carve(P, w + L.plan, (uint64_t)total, (uint64_t)nseg, T, merge_tile_out(kb, has_values));
     P.inst_off64 = seg_offsets;
     P.big_min = T;
@@ -500,7 +509,7 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
     return guarded([&]() -> hipError_t {
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
-        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s));
+        VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s, tu.tile_threads));
         return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
     });
 }
@@ -785,12 +794,22 @@ vmps_status vmps_partition(const void* keys_in, const uint32_t* vals_in, int64_t
 vmps_status vmps_set_tuning(vmps_dtype kt, int has_values, const vmps_tuning* t)
 {
     if (kt != VMPS_U32 && kt != VMPS_U64) return VMPS_ERR_INVALID_ARG;
-    Tuning v{0, 0, 0, 0, 0};
+    Tuning v{0, 0, 0, 0, 0, 0, 0};
     if (t) {
         if (t->tile_wg_per_cu < 0 || t->merge_grid < 0 || t->bucket_div < 0 || t->bucket_div > 64 ||
             (t->host_wait != 0 && t->host_wait != 1) || (t->merge_ki != 0 && t->merge_ki != 8 && t->merge_ki != 16))
             return VMPS_ERR_INVALID_ARG;
-        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->host_wait, t->merge_ki};
+        // tile variants compiled for the segmented sort: 32-bit keys without
+        // values, 512 x 16384 (default), 512 x 8192, 256 x 8192
+        const bool seg32 = kt == VMPS_U32 && !has_values;
+        const bool big = t->tile_elems == 0 || t->tile_elems == 16384;
+        if (big ? (t->tile_threads != 0 && t->tile_threads != 512)
+                : (!seg32 || t->tile_elems != 8192 ||
+                   (t->tile_threads != 0 && t->tile_threads != 256 && t->tile_threads != 512)))
+            return VMPS_ERR_INVALID_ARG;
+        if (!seg32 && t->tile_elems != 0) return VMPS_ERR_INVALID_ARG;
+        v = Tuning{t->tile_wg_per_cu, t->merge_grid, t->bucket_div, t->host_wait, t->merge_ki,
+                   big ? 0 : 8192, big ? 0 : (t->tile_threads == 256 ? 256 : 0)};
     }
     tuning_table()[kt == VMPS_U64][has_values ? 1 : 0] = v;
     return VMPS_OK;
@@ -805,6 +824,8 @@ vmps_status vmps_get_tuning(vmps_dtype kt, int has_values, vmps_tuning* t)
     t->bucket_div = v.bucket_div;
     t->host_wait = v.host_wait;
     t->merge_ki = v.merge_ki;
+    t->tile_elems = v.tile_elems;
+    t->tile_threads = v.tile_threads;
     return VMPS_OK;
 }
 

@@ -1251,11 +1251,21 @@ size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t)
 }
 
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                            int key_bits, int vmode, uint32_t narrow, hipStream_t s)
+                            int key_bits, int vmode, uint32_t narrow, hipStream_t s, int threads)
 {
     const int w = tuning_for(key_bits, vmode != 0).tile_wg_per_cu;
     if (key_bits == 32) {
-        if (vmode == 0) return launch_tilesort<uint32_t, 512, 16384, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+        if (vmode == 0) {
+            // the plan's segments are at most P.T long: the kernel's tile
+            // must hold them
+            if (P.T == 8192) {
+                if (threads == 256)
+                    return launch_tilesort<uint32_t, 256, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+                return launch_tilesort<uint32_t, 512, 8192, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+            }
+            if (P.T != 16384) return hipErrorInvalidValue;
+            return launch_tilesort<uint32_t, 512, 16384, 0, 4>(P, keysA, keysB, valsA, valsB, w, s);
+        }
         if (vmode == 1) return launch_tilesort<uint32_t, 512, 8192, 1, 4>(P, keysA, keysB, valsA, valsB, w, s);
         return launch_tilesort<uint32_t, 512, 8192, 2, 4>(P, keysA, keysB, valsA, valsB, w, s);
     }

@@ -203,6 +203,8 @@ struct Tuning {
     int bucket_div;      // learned buckets target the tile length / bucket_div (0: 2)
     int host_wait;       // 1: wait on the host for the level counts, launch the non-empty levels only
     int merge_ki;        // outputs per thread of a merge-level tile (0: default)
+    int tile_elems;      // segmented sort, 32-bit keys without values: LDS tile (0: default)
+    int tile_threads;    // workgroup size of that tile pass (0: 512)
 };
 const Tuning& tuning_for(int key_bits, bool has_values);
 
@@ -243,10 +245,13 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t count, hipStream_t s);
 // segments whose keys span less than 2^32 on 32-bit offsets, with segments
 // of up to 4096 keys in a launch of 256-thread workgroups (four per CU) and
 // the longer ones in the 512-thread launch; worth it where most segments
-// are short and narrow (the learned buckets).
+// are short and narrow (the learned buckets).  32-bit keys without values
+// also run plans made with T = 8192 (the segmented sort's tuned tile), in
+// 512-thread or, with threads = 256, 256-thread workgroups; any other T
+// for that configuration is an error.
 hipError_t tilesort_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
                             uint32_t* valsB, int key_bits, int vmode, uint32_t narrow,
-                            hipStream_t s);
+                            hipStream_t s, int threads = 0);
 uint32_t tilesort_capacity(int key_bits, int has_values);
 size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
 

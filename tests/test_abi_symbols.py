@@ -54,9 +54,10 @@ def test_tuning_table_host_side():
     import paper_2605_27147_amd as vm
     lib = vm.load_library()
     vm.set_tuning(vm.U64, False, tile_wg_per_cu=1, merge_grid=1024, bucket_div=3)
-    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 1, "merge_grid": 1024, "bucket_div": 3,
-                                            "host_wait": 0, "merge_ki": 0}
-    assert vm.get_tuning(vm.U64, True) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0, "merge_ki": 0}
+    zero = {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0, "merge_ki": 0, "tile_elems": 0,
+            "tile_threads": 0}
+    assert vm.get_tuning(vm.U64, False) == {**zero, "tile_wg_per_cu": 1, "merge_grid": 1024, "bucket_div": 3}
+    assert vm.get_tuning(vm.U64, True) == zero
     vm.set_tuning(vm.U32, True, host_wait=1)
     assert vm.get_tuning(vm.U32, True)["host_wait"] == 1
     vm.reset_tuning(vm.U32, True)
@@ -70,10 +71,22 @@ def test_tuning_table_host_side():
     assert lib.vmps_set_tuning(vm.U32, 1, ctypes.byref(bad)) == 1
     vm.set_tuning(vm.U32, False, merge_ki=8)
     assert vm.get_tuning(vm.U32, False)["merge_ki"] == 8
+    # the tuned LDS tile: u32 keys without values only, 8192 with 512 or 256
+    # threads; 16384 is the default and reads back as 0
+    vm.set_tuning(vm.U32, False, tile_elems=8192, tile_threads=256)
+    assert vm.get_tuning(vm.U32, False) == {**zero, "tile_elems": 8192, "tile_threads": 256}
+    vm.set_tuning(vm.U32, False, tile_elems=8192, tile_threads=512)
+    assert vm.get_tuning(vm.U32, False) == {**zero, "tile_elems": 8192}
+    vm.set_tuning(vm.U32, False, tile_elems=16384, tile_threads=512)
+    assert vm.get_tuning(vm.U32, False) == zero
+    for kt, hv, te, tt in ((vm.U32, 0, 4096, 0), (vm.U32, 0, 8192, 128), (vm.U32, 0, 16384, 256),
+                           (vm.U32, 0, 0, 256), (vm.U32, 1, 8192, 0), (vm.U64, 0, 8192, 0), (vm.U64, 1, 16384, 0)):
+        bad = vm.Tuning(0, 0, 0, 0, 0, te, tt)
+        assert lib.vmps_set_tuning(kt, hv, ctypes.byref(bad)) == 1, (kt, hv, te, tt)
     vm.reset_tuning(vm.U32, False)
     assert lib.vmps_set_tuning(5, 0, None) == 1
     vm.reset_tuning(vm.U64, False)
-    assert vm.get_tuning(vm.U64, False) == {"tile_wg_per_cu": 0, "merge_grid": 0, "bucket_div": 0, "host_wait": 0, "merge_ki": 0}
+    assert vm.get_tuning(vm.U64, False) == zero
 
 
 def test_graph_capture_rejects_bad_arguments_without_gpu_work():

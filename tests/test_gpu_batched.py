@@ -123,6 +123,53 @@ def test_tuning_never_changes_results(vm, orc, tile_wg, merge_grid, bucket_div, 
             vm.reset_tuning(vm.U64, hv)
 
 
+
+@pytest.mark.parametrize("tile_threads, extra", [(512, {}), (256, {}),
+                                                 (256, {"tile_wg_per_cu": 1, "merge_ki": 8, "merge_grid": 1024})])
+def test_segmented_tuned_tile_8192(vm, orc, tile_threads, extra):
+    """The segmented sort on the 8192-element LDS tile (u32 keys without
+    values, 512 or 256 threads a workgroup): eager and graph replays against
+    the oracle, with segment lengths around both tile sizes, single natural
+    runs longer than the tile, duplicates, and empty segments."""
+    import torch
+    g0 = np.random.default_rng(48)
+    keys_np, off = workloads.batch32(96, 48, lengths=workloads.batch_lengths(96, 48, hi_log2=17))
+    parts, lens = [keys_np], list(np.diff(off))
+    for ln in (0, 1, 2, 31, 32, 33, 4095, 4096, 4097, 8191, 8192, 8193, 12000, 16383, 16384, 16385, 40000, 0):
+        parts.append(g0.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32))
+        lens.append(ln)
+    for ln in (8193, 20000):
+        parts.append(np.sort(g0.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32)))        # one run
+        parts.append(np.sort(g0.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32))[::-1].copy())
+        parts.append(g0.integers(0, 16, ln, dtype=np.uint64).astype(np.uint32))                   # duplicates
+        lens += [ln, ln, ln]
+    kn = np.concatenate(parts).astype(np.uint32)
+    offs_np = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    _say("tuned tile 8192 x", tile_threads, "keys", kn.size, "segments", offs_np.size - 1)
+    want, _ = orc.segmented_powersort(kn, offs_np)
+    want = want.astype(np.uint32)
+    pristine = _t(kn)
+    offs = torch.from_numpy(offs_np).cuda()
+    try:
+        vm.set_tuning(vm.U32, False, tile_elems=8192, tile_threads=tile_threads, **extra)
+        keys = pristine.clone()
+        vm.segmented_sort_(keys, offs)
+        assert np.array_equal(_np(keys, np.uint32), want)
+        g = vm.segmented_sort_graph(keys, offs)
+        for rep in range(3):
+            keys.copy_(pristine)
+            torch.cuda.synchronize()
+            g.replay()
+            assert np.array_equal(_np(keys, np.uint32), want), rep
+            (pristine.float() * 2).sum().item()
+        g.close()
+    finally:
+        vm.reset_tuning(vm.U32, False)
+    # back on the default tile, the same workspace size query still fits
+    keys = pristine.clone()
+    vm.segmented_sort_(keys, offs)
+    assert np.array_equal(_np(keys, np.uint32), want)
+
 def _brute_force_segments():
     """Every permutation of 0..n-1 for n <= 9 and every word over {0,1,2} of
     length n <= 12, each as one segment (u32 keys), in one array."""

@@ -410,48 +410,129 @@ __global__ __launch_bounds__(64) void k_long_runs(const uint64_t* __restrict__ b
 }
 
 // ------------------------------------------------------------- chain --
-// Smallest x >= u with x == r (mod l), written from u's residue.
-__device__ inline uint32_t chain_land(uint32_t u, uint32_t ph, uint32_t ell)
+// x mod d and x / d for 32-bit x and a divisor d >= 1 from one 64-bit
+// constant c = floor((2^64 - 1) / d) + 1, after Lemire, Kaser and Kurz,
+// "Faster remainder by direct computation" (2019): x mod d is the high
+// word of ((c x) mod 2^64) d, x / d the high word of c x.  c wraps to 0 for
+// d = 1 (remainder 0, quotient x).  The chain walks below are sequential
+// per lane, and a division by a variable costs several times more.
+struct DivBy {
+    uint64_t c;
+    uint32_t d;
+};
+__device__ inline DivBy div_by(uint32_t d) { return DivBy{~0ull / d + 1, d}; }
+__device__ inline uint32_t mod_by(uint32_t x, const DivBy& v) { return (uint32_t)__umul64hi(v.c * x, v.d); }
+__device__ inline uint32_t quot_by(uint32_t x, const DivBy& v)
 {
-    return u + (ph + ell - u % ell) % ell;
+    return v.d == 1 ? x : (uint32_t)__umul64hi(v.c, x);
+}
+
+// Smallest x >= u with x == ph (mod l), ph < l, written from u's residue.
+__device__ inline uint32_t chain_land(uint32_t u, uint32_t ph, const DivBy& l)
+{
+    uint32_t t = ph + l.d - mod_by(u, l);  // in [1, 2l - 1]
+    if (t >= l.d) t -= l.d;
+    return u + t;
+}
+
+// A block of long runs is walked as CHAIN_SUBS sub-blocks of CHAIN_SUB runs
+// in parallel (one wave each, lane phi following the chain that enters the
+// sub-block at phase phi), and the sub-block maps are then composed in
+// order; the walks stay short although the blocks are long.
+constexpr uint32_t CHAIN_SUBS = 16;
+constexpr uint32_t CHAIN_SUB = CHAIN_BLOCK / CHAIN_SUBS;
+constexpr uint32_t CHAIN_NT = 64 * CHAIN_SUBS;
+
+struct ChainLds {
+    uint32_t u[CHAIN_BLOCK], e[CHAIN_BLOCK], inst[CHAIN_BLOCK];
+    uint32_t val[CHAIN_SUBS][64];
+    uint64_t known[CHAIN_SUBS];
+    uint32_t rin[CHAIN_SUBS];
+};
+
+// Instance of long run j (of block [j0, j1) staged in S), NONE before 0.
+__device__ inline uint32_t chain_inst_at(const ChainLds& S, const uint32_t* __restrict__ lr_inst, uint32_t j0,
+                                         uint32_t j)
+{
+    if (j + 1 == 0) return NONE;
+    return j >= j0 ? S.inst[j - j0] : lr_inst[j];
+}
+
+// Stages the block's runs and computes the map of every sub-block: after
+// the walk, lane phi of wave w holds the last jump target of the chain that
+// enters sub-block w at phase phi, or 0 with its known bit clear (no jump
+// and no instance change: the chain passes unchanged).
+__device__ void chain_sub_maps(ChainLds& S, const uint32_t* __restrict__ lr_u, const uint32_t* __restrict__ lr_e,
+                               const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
+                               uint32_t ell_ovr, uint32_t j0, uint32_t j1)
+{
+    const uint32_t tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    for (uint32_t j = j0 + tid; j < j1; j += CHAIN_NT) {
+        S.u[j - j0] = lr_u[j]; S.e[j - j0] = lr_e[j]; S.inst[j - j0] = lr_inst[j];
+    }
+    __syncthreads();
+    const uint32_t s0 = j0 + w * CHAIN_SUB, s1 = min(j1, s0 + CHAIN_SUB);
+    bool known = false;
+    uint32_t r = 0;
+    if (s0 < j1) {
+        uint32_t prev = chain_inst_at(S, lr_inst, j0, s0 - 1), ib = 0;
+        DivBy ell = div_by(1);
+        if (prev != NONE) { ell = div_by(inst_ell(inst_start, prev, ell_ovr)); ib = inst_start[prev]; }
+        for (uint32_t j = s0; j < s1; ++j) {
+            const uint32_t inst = S.inst[j - j0];
+            if (inst != prev) {
+                known = true; r = 0; prev = inst;
+                ell = div_by(inst_ell(inst_start, inst, ell_ovr));
+                ib = inst_start[inst];
+            }
+            const uint32_t u = S.u[j - j0] - ib, e = S.e[j - j0] - ib;
+            const uint32_t ph = mod_by(known ? r : lane, ell);
+            const uint32_t sf = chain_land(u, ph, ell);
+            if (e - sf >= ell.d) { known = true; r = e; }
+        }
+    }
+    S.val[w][lane] = r;
+    const uint64_t m = __ballot(known);
+    if (lane == 0) S.known[w] = m;
+    __syncthreads();
 }
 
 // Map of a block of long runs: lane phi follows the chain entering the
 // block at phase phi; afterwards it holds the last jump target (known) or
 // is still the identity.
-__global__ __launch_bounds__(64) void k_chain_blocks(const uint32_t* __restrict__ lr_u,
-                                                     const uint32_t* __restrict__ lr_e,
-                                                     const uint32_t* __restrict__ lr_inst,
-                                                     const uint32_t* __restrict__ inst_start,
-                                                     uint32_t ell_ovr, const uint32_t* counters,
-                                                     uint32_t* __restrict__ chain_val,
-                                                     uint64_t* __restrict__ chain_known)
+__global__ __launch_bounds__(CHAIN_NT) void k_chain_blocks(const uint32_t* __restrict__ lr_u,
+                                                           const uint32_t* __restrict__ lr_e,
+                                                           const uint32_t* __restrict__ lr_inst,
+                                                           const uint32_t* __restrict__ inst_start,
+                                                           uint32_t ell_ovr, const uint32_t* counters,
+                                                           uint32_t* __restrict__ chain_val,
+                                                           uint64_t* __restrict__ chain_known)
 {
+    __shared__ ChainLds S;
     const uint32_t nl = counters[CNT_NLONG];
-    const uint32_t b = blockIdx.x;
-    const uint32_t j0 = b * CHAIN_BLOCK;
-    if (j0 >= nl) return;
-    const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
-    const uint32_t lane = threadIdx.x;
-    uint32_t prev = j0 ? lr_inst[j0 - 1] : NONE;
-    bool known = false;
-    uint32_t r = 0, ell = 1, ib = 0;
-    if (prev != NONE) { ell = inst_ell(inst_start, prev, ell_ovr); ib = inst_start[prev]; }
-    for (uint32_t j = j0; j < j1; ++j) {
-        const uint32_t inst = lr_inst[j];
-        if (inst != prev) {
-            known = true; r = 0; prev = inst;
-            ell = inst_ell(inst_start, inst, ell_ovr);
-            ib = inst_start[inst];
+    // a capped grid loops over the blocks (most of the capacity is unused)
+    for (uint32_t b = blockIdx.x; (uint64_t)b * CHAIN_BLOCK < nl; b += gridDim.x) {
+        const uint32_t j0 = b * CHAIN_BLOCK;
+        const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
+        chain_sub_maps(S, lr_u, lr_e, lr_inst, inst_start, ell_ovr, j0, j1);
+        if (threadIdx.x < 64) {
+            // compose the sub-block maps: lane phi enters the block at phase phi
+            const uint32_t lane = threadIdx.x;
+            bool known = false;
+            uint32_t r = 0;
+            for (uint32_t v = 0; v < CHAIN_SUBS; ++v) {
+                const uint32_t t0 = j0 + v * CHAIN_SUB;
+                if (t0 >= j1) break;
+                // known only after a first sub-block (v > 0): t0 - 1 is in the block
+                const uint32_t ph = known ? r % inst_ell(inst_start, S.inst[t0 - 1 - j0], ell_ovr) : lane;
+                if ((S.known[v] >> ph) & 1ull) { known = true; r = S.val[v][ph]; }
+            }
+            chain_val[(uint64_t)b * 64 + lane] = r;
+            const uint64_t m = __ballot(known);
+            if (lane == 0) chain_known[b] = m;
         }
-        const uint32_t u = lr_u[j] - ib, e = lr_e[j] - ib;
-        const uint32_t ph = known ? r % ell : lane % ell;
-        const uint32_t sf = chain_land(u, ph, ell);
-        if (e - sf >= ell) { known = true; r = e; }
+        __syncthreads();  // LDS is staged again for the next block
     }
-    chain_val[(uint64_t)b * 64 + lane] = r;
-    const uint64_t m = __ballot(known);
-    if (lane == 0) chain_known[b] = m;
 }
 
 // Sequential composition over blocks: incoming chain state of every block.
@@ -475,52 +556,84 @@ __global__ void k_chain_scan(const uint32_t* __restrict__ lr_inst, const uint32_
     }
 }
 
-// Apply: walk each block with its real incoming state, recording for every
-// long run where the chain jumps (run count of the progression it closes).
-__global__ __launch_bounds__(64) void k_chain_apply(const uint32_t* __restrict__ lr_u,
-                                                    const uint32_t* __restrict__ lr_e,
-                                                    const uint32_t* __restrict__ lr_inst,
-                                                    const uint32_t* __restrict__ inst_start,
-                                                    uint32_t ell_ovr, const uint32_t* counters,
-                                                    const uint32_t* __restrict__ chain_rin,
-                                                    uint32_t* __restrict__ lr_cnt,
-                                                    uint32_t* __restrict__ lr_base,
-                                                    uint32_t* __restrict__ inst_rfinal)
+// One block of k_chain_apply, by the whole workgroup.
+__device__ void chain_apply_block(ChainLds& S, const uint32_t* __restrict__ lr_u, const uint32_t* __restrict__ lr_e,
+                                  const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
+                                  uint32_t ell_ovr, uint32_t nl, uint32_t b, uint32_t j0, uint32_t j1,
+                                  const uint32_t* __restrict__ chain_rin, uint32_t* __restrict__ lr_cnt,
+                                  uint32_t* __restrict__ lr_base, uint32_t* __restrict__ inst_rfinal)
 {
-    __shared__ uint32_t su[CHAIN_BLOCK], se[CHAIN_BLOCK], si[CHAIN_BLOCK];
-    const uint32_t nl = counters[CNT_NLONG];
-    const uint32_t b = blockIdx.x;
-    const uint32_t j0 = b * CHAIN_BLOCK;
-    if (j0 >= nl) return;
-    const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
-    for (uint32_t j = j0 + threadIdx.x; j < j1; j += 64) {
-        su[j - j0] = lr_u[j]; se[j - j0] = lr_e[j]; si[j - j0] = lr_inst[j];
+    chain_sub_maps(S, lr_u, lr_e, lr_inst, inst_start, ell_ovr, j0, j1);
+    if (threadIdx.x == 0) {
+        // state entering every sub-block (before its first run's instance
+        // check, as in one sequential walk)
+        uint32_t r = chain_rin[b];
+        for (uint32_t v = 0; v < CHAIN_SUBS; ++v) {
+            const uint32_t t0 = j0 + v * CHAIN_SUB;
+            if (t0 >= j1) break;
+            S.rin[v] = r;
+            const uint32_t pi = chain_inst_at(S, lr_inst, j0, t0 - 1);
+            // a sub-block that opens an instance restarts from 0: its map is
+            // known at every phase
+            const uint32_t ph = (pi == NONE || S.inst[t0 - j0] != pi) ? 0u : r % inst_ell(inst_start, pi, ell_ovr);
+            if ((S.known[v] >> ph) & 1ull) r = S.val[v][ph];
+        }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
-    uint32_t prev = j0 ? lr_inst[j0 - 1] : NONE;
-    uint32_t r = chain_rin[b], ell = 1, ib = 0;
-    if (prev != NONE) { ell = inst_ell(inst_start, prev, ell_ovr); ib = inst_start[prev]; }
-    const uint32_t next_inst = j1 < nl ? lr_inst[j1] : NONE;
-    for (uint32_t j = j0; j < j1; ++j) {
-        const uint32_t inst = si[j - j0];
+    const uint32_t w = threadIdx.x >> 6;
+    const uint32_t s0 = j0 + w * CHAIN_SUB;
+    if ((threadIdx.x & 63) != 0 || s0 >= j1) return;
+    const uint32_t s1 = min(j1, s0 + CHAIN_SUB);
+    uint32_t prev = chain_inst_at(S, lr_inst, j0, s0 - 1);
+    uint32_t r = S.rin[w], ib = 0;
+    DivBy ell = div_by(1);
+    if (prev != NONE) { ell = div_by(inst_ell(inst_start, prev, ell_ovr)); ib = inst_start[prev]; }
+    const uint32_t next_inst = s1 < j1 ? S.inst[s1 - j0] : (j1 < nl ? lr_inst[j1] : NONE);
+    for (uint32_t j = s0; j < s1; ++j) {
+        const uint32_t inst = S.inst[j - j0];
         if (inst != prev) {
             r = 0; prev = inst;
-            ell = inst_ell(inst_start, inst, ell_ovr);
+            ell = div_by(inst_ell(inst_start, inst, ell_ovr));
             ib = inst_start[inst];
         }
-        const uint32_t u = su[j - j0] - ib, e = se[j - j0] - ib;
-        const uint32_t sf = chain_land(u, r % ell, ell);
-        if (e - sf >= ell) {
-            lr_cnt[j] = (sf - r) / ell + 1;
+        const uint32_t u = S.u[j - j0] - ib, e = S.e[j - j0] - ib;
+        const uint32_t sf = chain_land(u, mod_by(r, ell), ell);
+        if (e - sf >= ell.d) {
+            lr_cnt[j] = quot_by(sf - r, ell) + 1;
             lr_base[j] = r;
             r = e;
         } else {
             lr_cnt[j] = 0;
             lr_base[j] = 0;
         }
-        const uint32_t nxt = (j + 1 < j1) ? si[j + 1 - j0] : next_inst;
+        const uint32_t nxt = (j + 1 < s1) ? S.inst[j + 1 - j0] : next_inst;
         if (nxt != inst) inst_rfinal[inst] = r;
+    }
+}
+
+// Apply: walk each block with its real incoming state, recording for every
+// long run where the chain jumps (run count of the progression it closes).
+// The sub-block maps give each sub-block's incoming state, and the
+// sub-blocks are then walked in parallel, one lane each.
+__global__ __launch_bounds__(CHAIN_NT) void k_chain_apply(const uint32_t* __restrict__ lr_u,
+                                                          const uint32_t* __restrict__ lr_e,
+                                                          const uint32_t* __restrict__ lr_inst,
+                                                          const uint32_t* __restrict__ inst_start,
+                                                          uint32_t ell_ovr, const uint32_t* counters,
+                                                          const uint32_t* __restrict__ chain_rin,
+                                                          uint32_t* __restrict__ lr_cnt,
+                                                          uint32_t* __restrict__ lr_base,
+                                                          uint32_t* __restrict__ inst_rfinal)
+{
+    __shared__ ChainLds S;
+    const uint32_t nl = counters[CNT_NLONG];
+    // a capped grid loops over the blocks (most of the capacity is unused)
+    for (uint32_t b = blockIdx.x; (uint64_t)b * CHAIN_BLOCK < nl; b += gridDim.x) {
+        const uint32_t j0 = b * CHAIN_BLOCK;
+        const uint32_t j1 = min(nl, j0 + CHAIN_BLOCK);
+        chain_apply_block(S, lr_u, lr_e, lr_inst, inst_start, ell_ovr, nl, b, j0, j1, chain_rin, lr_cnt, lr_base,
+                          inst_rfinal);
+        __syncthreads();  // LDS is staged again for the next block
     }
 }
 
@@ -1108,10 +1221,11 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
                                                 P.inst_start, P.inst_big, k, ell_ovr, cand_min, P.lr_cap, nullptr,
                                                 P.tile_off, P.lr_u, P.lr_e, P.lr_inst);
     // 3. chain of run starts
-    k_chain_blocks<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C,
+    const unsigned chain_grid = P.chain_blocks < 512u ? P.chain_blocks : 512u;  // two workgroups per CU
+    k_chain_blocks<<<chain_grid ? chain_grid : 1, CHAIN_NT, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C,
                                                  P.chain_val, P.chain_known);
     k_chain_scan<<<1, 64, 0, s>>>(P.lr_inst, P.inst_start, ell_ovr, C, P.chain_val, P.chain_known, P.chain_rin);
-    k_chain_apply<<<P.chain_blocks, 64, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C, P.chain_rin,
+    k_chain_apply<<<chain_grid ? chain_grid : 1, CHAIN_NT, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C, P.chain_rin,
                                                 P.lr_cnt, P.lr_base, P.inst_rfinal);
     k_entries_lr<<<stride_grid(P.lr_cap), 256, 0, s>>>(P.lr_inst, P.lr_cnt, P.lr_base, P.inst_bigrank, C,
                                                          P.ent_cnt, P.ent_base, P.ent_inst);

@@ -170,6 +170,43 @@ def test_segmented_tuned_tile_8192(vm, orc, tile_threads, extra):
     vm.segmented_sort_(keys, offs)
     assert np.array_equal(_np(keys, np.uint32), want)
 
+
+def test_segmented_long_runs_across_instances(vm, orc):
+    """Segments longer than the tile made of natural runs of 33 to 70 keys
+    (thousands of long runs, so the planner's run-start chain spans several
+    blocks and sub-blocks, with instances opening inside them), next to
+    short random segments; each segment against the oracle."""
+    import torch
+    rng = np.random.default_rng(49)
+    parts, lens = [], []
+    for sidx in range(40):
+        if sidx % 3 == 2:
+            ln = int(rng.integers(0, 3000))
+            parts.append(rng.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32))
+        else:
+            ln = int(rng.integers(17000, 90000))
+            x = rng.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32)
+            pos = 0
+            while pos < ln:
+                L = int(rng.integers(33, 71))
+                x[pos:pos + L] = np.sort(x[pos:pos + L])
+                pos += L + int(rng.integers(0, 2))
+            parts.append(x)
+        lens.append(ln)
+    kn = np.concatenate(parts).astype(np.uint32)
+    offs_np = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    _say("long-run segments", kn.size, len(lens))
+    want, _ = orc.segmented_powersort(kn, offs_np)
+    keys = _t(kn)
+    vals = torch.arange(kn.size, dtype=torch.int32, device="cuda")
+    vm.segmented_sort_(keys, torch.from_numpy(offs_np).cuda(), vals)
+    got = _np(keys, np.uint32)
+    assert np.array_equal(got, want.astype(np.uint32))
+    # the index payload is the stable permutation of every segment
+    gv = _np(vals, np.uint32).astype(np.int64)
+    for a, b in zip(offs_np[:-1], offs_np[1:]):
+        assert np.array_equal(gv[a:b], a + np.argsort(kn[a:b], kind="stable"))
+
 def _brute_force_segments():
     """Every permutation of 0..n-1 for n <= 9 and every word over {0,1,2} of
     length n <= 12, each as one segment (u32 keys), in one array."""

@@ -536,23 +536,47 @@ __global__ __launch_bounds__(CHAIN_NT) void k_chain_blocks(const uint32_t* __res
 }
 
 // Sequential composition over blocks: incoming chain state of every block.
-__global__ void k_chain_scan(const uint32_t* __restrict__ lr_inst, const uint32_t* __restrict__ inst_start,
-                             uint32_t ell_ovr, const uint32_t* counters,
-                             const uint32_t* __restrict__ chain_val,
-                             const uint64_t* __restrict__ chain_known, uint32_t* __restrict__ chain_rin)
+// The block maps, instances and divisors are staged in LDS by the
+// workgroup, SCAN_CHUNK blocks at a time, so that the sequential walk of
+// thread 0 reads only LDS.
+constexpr uint32_t SCAN_CHUNK = 64;
+
+__global__ __launch_bounds__(256) void k_chain_scan(const uint32_t* __restrict__ lr_inst,
+                                                    const uint32_t* __restrict__ inst_start, uint32_t ell_ovr,
+                                                    const uint32_t* counters, const uint32_t* __restrict__ chain_val,
+                                                    const uint64_t* __restrict__ chain_known,
+                                                    uint32_t* __restrict__ chain_rin)
 {
-    if (threadIdx.x != 0) return;
+    __shared__ uint32_t sval[SCAN_CHUNK][64];
+    __shared__ uint64_t sknown[SCAN_CHUNK];
+    __shared__ uint32_t sfirst[SCAN_CHUNK], slast[SCAN_CHUNK];
+    __shared__ DivBy sell[SCAN_CHUNK];
     const uint32_t nl = counters[CNT_NLONG];
     const uint32_t nb = (uint32_t)ceil_div(nl, CHAIN_BLOCK);
-    uint32_t r = 0, prev_last = NONE;
-    for (uint32_t b = 0; b < nb; ++b) {
-        const uint32_t j0 = b * CHAIN_BLOCK;
-        const uint32_t first = lr_inst[j0];
-        if (first != prev_last) r = 0;
-        chain_rin[b] = r;
-        const uint32_t ph = r % inst_ell(inst_start, first, ell_ovr);
-        if ((chain_known[b] >> ph) & 1ull) r = chain_val[(uint64_t)b * 64 + ph];
-        prev_last = lr_inst[min(nl, j0 + CHAIN_BLOCK) - 1];
+    uint32_t r = 0, prev_last = NONE;  // thread 0's chain state
+    for (uint32_t c0 = 0; c0 < nb; c0 += SCAN_CHUNK) {
+        const uint32_t cn = min(SCAN_CHUNK, nb - c0);
+        for (uint32_t x = threadIdx.x; x < cn * 64; x += blockDim.x)
+            sval[x >> 6][x & 63] = chain_val[(uint64_t)(c0 + (x >> 6)) * 64 + (x & 63)];
+        for (uint32_t x = threadIdx.x; x < cn; x += blockDim.x) {
+            const uint32_t j0 = (c0 + x) * CHAIN_BLOCK;
+            const uint32_t first = lr_inst[j0];
+            sknown[x] = chain_known[c0 + x];
+            sfirst[x] = first;
+            slast[x] = lr_inst[min(nl, j0 + CHAIN_BLOCK) - 1];
+            sell[x] = div_by(inst_ell(inst_start, first, ell_ovr));
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (uint32_t x = 0; x < cn; ++x) {
+                if (sfirst[x] != prev_last) r = 0;
+                chain_rin[c0 + x] = r;
+                const uint32_t ph = mod_by(r, sell[x]);
+                if ((sknown[x] >> ph) & 1ull) r = sval[x][ph];
+                prev_last = slast[x];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1224,7 +1248,7 @@ static hipError_t plan_enqueue_t(Plan& P, const K* keys, uint32_t ell_ovr, hipSt
     const unsigned chain_grid = P.chain_blocks < 512u ? P.chain_blocks : 512u;  // two workgroups per CU
     k_chain_blocks<<<chain_grid ? chain_grid : 1, CHAIN_NT, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C,
                                                  P.chain_val, P.chain_known);
-    k_chain_scan<<<1, 64, 0, s>>>(P.lr_inst, P.inst_start, ell_ovr, C, P.chain_val, P.chain_known, P.chain_rin);
+    k_chain_scan<<<1, 256, 0, s>>>(P.lr_inst, P.inst_start, ell_ovr, C, P.chain_val, P.chain_known, P.chain_rin);
     k_chain_apply<<<chain_grid ? chain_grid : 1, CHAIN_NT, 0, s>>>(P.lr_u, P.lr_e, P.lr_inst, P.inst_start, ell_ovr, C, P.chain_rin,
                                                 P.lr_cnt, P.lr_base, P.inst_rfinal);
     k_entries_lr<<<stride_grid(P.lr_cap), 256, 0, s>>>(P.lr_inst, P.lr_cnt, P.lr_base, P.inst_bigrank, C,

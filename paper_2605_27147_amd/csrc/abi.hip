@@ -672,7 +672,8 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 1, s));
-        VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s));
+        // only buckets longer than the tile reach the levels: mostly empty
+        VMPS_HIP(merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s, true));
         if (stats)
             VMPS_HIP(learned_stats_enqueue(boff, L.B, T, M, w + L.sample, L.m, kb, (uint64_t*)(w + L.judge), stats,
                                            s));

@@ -43,11 +43,16 @@ __global__ void k_level_partition(LevelArgs A, const K* __restrict__ keysA, cons
     }
 }
 
-// One output tile per workgroup iteration, over the level's pairs.
-template <typename K, bool VAL, int NT, int KI>
+// One output tile per workgroup iteration, over the level's pairs.  FUSED:
+// the tile's two cuts are searched here (two threads, before the merge)
+// instead of read from k_level_partition's table, so a level is one launch;
+// for levels that are mostly empty (the learned path, where only buckets
+// longer than the tile reach them) that halves the launches.
+template <typename K, bool VAL, int NT, int KI, bool FUSED>
 __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__ keysA, K* __restrict__ keysB,
                                                     uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB)
 {
+    __shared__ uint32_t s_cut[FUSED ? 2 : 1];
     constexpr uint32_t TO = NT * KI;
     constexpr uint32_t SP = MergeLds<TO>::SP;
     extern __shared__ __align__(16) uint8_t smem[];
@@ -67,7 +72,19 @@ __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__
         const uint64_t t0 = (uint64_t)tt * TO;
         const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
         const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
-        const uint32_t i0 = A.splits[2 * (uint64_t)i], i1 = A.splits[2 * (uint64_t)i + 1];
+        uint32_t i0, i1;
+        if constexpr (FUSED) {
+            if (threadIdx.x < 2)
+                s_cut[threadIdx.x] =
+                    merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, (threadIdx.x ? o1 : o0) - L);
+            __syncthreads();
+            i0 = s_cut[0];
+            i1 = s_cut[1];
+            __syncthreads();  // every thread has its cuts before the next tile's are written
+        } else {
+            i0 = A.splits[2 * (uint64_t)i];
+            i1 = A.splits[2 * (uint64_t)i + 1];
+        }
         const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
         merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid, VAL ? vsrc + Mid : nullptr,
                                    j0, j1, dst + o0, VAL ? vdst + o0 : nullptr, S, SV);
@@ -113,7 +130,7 @@ hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipS
 
 template <typename K, bool VAL, int NT, int KI>
 static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                                hipStream_t s)
+                                hipStream_t s, bool fused)
 {
     constexpr uint32_t TO = NT * KI;
     constexpr size_t lds = (sizeof(K) + (VAL ? sizeof(uint32_t) : 0)) * MergeLds<TO>::SP;
@@ -121,7 +138,9 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
     int dev = 0;
     VMPS_HIP(hipGetDevice(&dev));
     if (!attr_set[dev & 15]) {
-        VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI>,
+        VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI, false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        VMPS_HIP(hipFuncSetAttribute((const void*)k_level_merge<K, VAL, NT, KI, true>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set[dev & 15] = true;
     }
@@ -159,13 +178,18 @@ static hipError_t launch_levels(const Plan& P, void* keysA, void* keysB, uint32_
             pg = (unsigned)(ceil_div(2 * c, 256) < pgrid ? ceil_div(2 * c, 256) : pgrid);
             mg = (unsigned)(c < mgrid ? c : mgrid);
         }
+        if (fused) {
+            TraceScope tr(VMPS_TRACE_LEVEL_MERGE, s);
+            k_level_merge<K, VAL, NT, KI, true><<<mg, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+            continue;
+        }
         {
             TraceScope tr(VMPS_TRACE_LEVEL_PARTITION, s);
             k_level_partition<K><<<pg, 256, 0, s>>>(A, (const K*)keysA, (const K*)keysB);
         }
         {
             TraceScope tr(VMPS_TRACE_LEVEL_MERGE, s);
-            k_level_merge<K, VAL, NT, KI><<<mg, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
+            k_level_merge<K, VAL, NT, KI, false><<<mg, NT, lds, s>>>(A, (K*)keysA, (K*)keysB, valsA, valsB);
         }
     }
     return hipGetLastError();
@@ -185,23 +209,23 @@ uint32_t merge_tile_out(int key_bits, int has_values)
 
 // The level tiles are those the plan was made with (P.T_out).
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA, uint32_t* valsB,
-                                int key_bits, int has_values, hipStream_t s)
+                                int key_bits, int has_values, hipStream_t s, bool fused)
 {
     const bool k16 = P.T_out == 256 * 16;
     if (key_bits == 32) {
         if (has_values) {
-            if (k16) return launch_levels<uint32_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
-            return launch_levels<uint32_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+            if (k16) return launch_levels<uint32_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s, fused);
+            return launch_levels<uint32_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s, fused);
         }
-        if (k16) return launch_levels<uint32_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
-        return launch_levels<uint32_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+        if (k16) return launch_levels<uint32_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s, fused);
+        return launch_levels<uint32_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s, fused);
     }
     if (has_values) {
-        if (k16) return launch_levels<uint64_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s);
-        return launch_levels<uint64_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+        if (k16) return launch_levels<uint64_t, true, 256, 16>(P, keysA, keysB, valsA, valsB, s, fused);
+        return launch_levels<uint64_t, true, 256, 8>(P, keysA, keysB, valsA, valsB, s, fused);
     }
-    if (k16) return launch_levels<uint64_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s);
-    return launch_levels<uint64_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s);
+    if (k16) return launch_levels<uint64_t, false, 256, 16>(P, keysA, keysB, valsA, valsB, s, fused);
+    return launch_levels<uint64_t, false, 256, 8>(P, keysA, keysB, valsA, valsB, s, fused);
 }
 
 // ------------------------------------------------- merge of two arrays --

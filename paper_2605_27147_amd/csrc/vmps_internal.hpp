@@ -264,8 +264,11 @@ size_t tilesort_lds_bytes(int key_bits, int has_values, uint32_t T);
 // disarms any earlier probe and every level is launched.
 hipError_t level_probe_enqueue(const Plan& P, int key_bits, int has_values, hipStream_t s,
                                bool allowed = true);
+// fused: every level is one launch whose workgroups search their own tile
+// cuts (for plans whose levels are mostly empty).
 hipError_t merge_levels_enqueue(const Plan& P, void* keysA, void* keysB, uint32_t* valsA,
-                                uint32_t* valsB, int key_bits, int has_values, hipStream_t s);
+                                uint32_t* valsB, int key_bits, int has_values, hipStream_t s,
+                                bool fused = false);
 // Merge-level output tile with the tuning's merge_ki; the built-in default
 // (the paged sort's page); the smallest choice, which sizes workspaces.
 uint32_t merge_tile_out(int key_bits, int has_values);

@@ -44,50 +44,65 @@ __global__ void k_level_partition(LevelArgs A, const K* __restrict__ keysA, cons
 }
 
 // One output tile per workgroup iteration, over the level's pairs.  FUSED:
-// the tile's two cuts are searched here (two threads, before the merge)
-// instead of read from k_level_partition's table, so a level is one launch;
-// for levels that are mostly empty (the learned path, where only buckets
-// longer than the tile reach them) that halves the launches.
+// the tile cuts are searched here instead of read from k_level_partition's
+// table, so a level is one launch (for levels that are mostly empty, as in
+// the learned path, where only buckets longer than the tile reach them,
+// that halves the launches).  The workgroup takes its tiles in chunks of
+// up to NT / 2: all their cuts are searched at once, one thread each, then
+// the chunk's tiles are merged in turn, so one search latency is spent per
+// chunk rather than per tile.
 template <typename K, bool VAL, int NT, int KI, bool FUSED>
 __global__ __launch_bounds__(NT) void k_level_merge(LevelArgs A, K* __restrict__ keysA, K* __restrict__ keysB,
                                                     uint32_t* __restrict__ valsA, uint32_t* __restrict__ valsB)
 {
-    __shared__ uint32_t s_cut[FUSED ? 2 : 1];
     constexpr uint32_t TO = NT * KI;
     constexpr uint32_t SP = MergeLds<TO>::SP;
+    constexpr uint32_t CH = FUSED ? NT / 2 : 1;  // tiles per chunk
+    __shared__ uint32_t s_cut[2 * CH];
     extern __shared__ __align__(16) uint8_t smem[];
     K* S = (K*)smem;
     uint32_t* SV = (uint32_t*)(S + SP);
     const uint32_t cnt = A.level[A.lvl], off = A.level[MAX_LEVEL + A.lvl];
-    for (uint32_t j = blockIdx.x; j < cnt; j += gridDim.x) {
-        const uint32_t i = off + j;
-        const uint32_t q = A.pairs[2 * (uint64_t)i], tt = A.pairs[2 * (uint64_t)i + 1];
-        const uint32_t t = A.hbm_list[q];
-        const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
-        const bool dstB = (A.depth[q] & 1u) != 0;
-        K* src = dstB ? keysA : keysB;
-        K* dst = dstB ? keysB : keysA;
-        uint32_t* vsrc = dstB ? valsA : valsB;
-        uint32_t* vdst = dstB ? valsB : valsA;
-        const uint64_t t0 = (uint64_t)tt * TO;
-        const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
-        const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
-        uint32_t i0, i1;
+    for (uint64_t jb = blockIdx.x; jb < cnt; jb += (uint64_t)gridDim.x * CH) {
         if constexpr (FUSED) {
-            if (threadIdx.x < 2)
-                s_cut[threadIdx.x] =
-                    merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, (threadIdx.x ? o1 : o0) - L);
+            // cut x: tile k = x / 2 of the chunk, its start (even x) or end
+            const uint32_t x = threadIdx.x;
+            const uint64_t j = jb + (uint64_t)(x >> 1) * gridDim.x;
+            if (x < 2 * CH && j < cnt) {
+                const uint32_t i = off + (uint32_t)j;
+                const uint32_t q = A.pairs[2 * (uint64_t)i], tt = A.pairs[2 * (uint64_t)i + 1];
+                const uint32_t t = A.hbm_list[q];
+                const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+                const K* src = (A.depth[q] & 1u) ? keysA : keysB;
+                const uint64_t t0 = (uint64_t)tt * TO;
+                const uint32_t o = (x & 1) ? (uint32_t)(R < t0 + TO ? R : t0 + TO) : (uint32_t)(L > t0 ? L : t0);
+                s_cut[x] = merge_path<K>(src + L, Mid - L, src + Mid, R - Mid, o - L);
+            }
             __syncthreads();
-            i0 = s_cut[0];
-            i1 = s_cut[1];
-            __syncthreads();  // every thread has its cuts before the next tile's are written
-        } else {
-            i0 = A.splits[2 * (uint64_t)i];
-            i1 = A.splits[2 * (uint64_t)i + 1];
         }
-        const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
-        merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid, VAL ? vsrc + Mid : nullptr,
-                                   j0, j1, dst + o0, VAL ? vdst + o0 : nullptr, S, SV);
+        for (uint32_t k = 0; k < CH; ++k) {
+            const uint64_t jj = jb + (uint64_t)k * gridDim.x;
+            if (jj >= cnt) break;
+            const uint32_t i = off + (uint32_t)jj;
+            const uint32_t q = A.pairs[2 * (uint64_t)i], tt = A.pairs[2 * (uint64_t)i + 1];
+            const uint32_t t = A.hbm_list[q];
+            const uint32_t L = A.lpos[t], Mid = A.run_start[t + 1], R = A.rpos[t];
+            const bool dstB = (A.depth[q] & 1u) != 0;
+            K* src = dstB ? keysA : keysB;
+            K* dst = dstB ? keysB : keysA;
+            uint32_t* vsrc = dstB ? valsA : valsB;
+            uint32_t* vdst = dstB ? valsB : valsA;
+            const uint64_t t0 = (uint64_t)tt * TO;
+            const uint32_t o0 = (uint32_t)(L > t0 ? L : t0);
+            const uint32_t o1 = (uint32_t)(R < t0 + TO ? R : t0 + TO);
+            const uint32_t i0 = FUSED ? s_cut[2 * k] : A.splits[2 * (uint64_t)i];
+            const uint32_t i1 = FUSED ? s_cut[2 * k + 1] : A.splits[2 * (uint64_t)i + 1];
+            const uint32_t j0 = (o0 - L) - i0, j1 = (o1 - L) - i1;
+            merge_tile<K, VAL, NT, KI>(src + L, VAL ? vsrc + L : nullptr, i0, i1, src + Mid,
+                                       VAL ? vsrc + Mid : nullptr, j0, j1, dst + o0, VAL ? vdst + o0 : nullptr, S,
+                                       SV);
+        }
+        if constexpr (FUSED) __syncthreads();  // every cut read before the next chunk's are written
     }
 }
 

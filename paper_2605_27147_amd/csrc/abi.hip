@@ -292,7 +292,7 @@ vmps_status check_sort_args(void* keys, uint32_t* values, int64_t n, vmps_dtype 
 }
 
 vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
-                              size_t ws_bytes, hipStream_t s, bool allow_host_wait)
+                              size_t ws_bytes, hipStream_t s, bool allow_host_wait, bool fused_levels)
 {
     if (n <= 1) {
         if (n == 1 && (flags & VMPS_VALUES_IOTA))
@@ -321,7 +321,7 @@ vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s, allow_host_wait));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
-        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
+        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s, fused_levels);
     });
 }
 
@@ -648,8 +648,10 @@ vmps_status vmps_sort_learned(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         {
             TraceScope tr(VMPS_TRACE_SAMPLE, s);
             VMPS_HIP(sample_enqueue(keys, (uint64_t)n, kb, L.m, c.seed, w + L.sample, s));
-            if (vmps_sort(w + L.sample, nullptr, (int64_t)L.m, kt, 0, w + L.sample_ws,
-                          sort_layout(L.m, 1, kt, 0, rule_min_len(L.m)).total, stream) != VMPS_OK)
+            // the sample's levels as one launch each (a tile or two per
+            // workgroup: searching the cuts in the merge costs no more)
+            if (sort_in_workspace(w + L.sample, nullptr, (int64_t)L.m, kt, 0, w + L.sample_ws,
+                                  sort_layout(L.m, 1, kt, 0, rule_min_len(L.m)).total, s, false, true) != VMPS_OK)
                 return hipErrorLaunchFailure;
         }
         {

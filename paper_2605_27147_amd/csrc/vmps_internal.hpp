@@ -332,9 +332,10 @@ hipError_t records_enqueue(const void* in, void* out, uint64_t n, uint32_t rb, u
 
 // The whole stable sort of one array with a caller-provided workspace
 // (vmps_sort's body after its argument checks; allow_host_wait = false never
-// waits on the host and allocates nothing, whatever the tuning says).
+// waits on the host and allocates nothing, whatever the tuning says;
+// fused_levels: one launch per merge level, as merge_levels_enqueue's).
 vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags, void* ws,
-                              size_t ws_bytes, hipStream_t s, bool allow_host_wait);
+                              size_t ws_bytes, hipStream_t s, bool allow_host_wait, bool fused_levels = false);
 vmps_status check_sort_args(void* keys, uint32_t* values, int64_t n, vmps_dtype kt, uint32_t flags);
 
 }  // namespace vmps

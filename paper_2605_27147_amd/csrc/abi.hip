@@ -321,7 +321,11 @@ vmps_status sort_in_workspace(void* keys, uint32_t* values, int64_t n, vmps_dtyp
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s, allow_host_wait));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, vmode, 0, s));
-        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s, fused_levels);
+        // up to 2^20 elements a level holds at most a few hundred tiles,
+        // about one per workgroup: the fused levels save the partition
+        // launches at no cost
+        const bool fused = fused_levels || (uint64_t)n <= (1ull << 20);
+        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s, fused);
     });
 }
 

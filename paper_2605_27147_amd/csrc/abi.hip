@@ -514,7 +514,8 @@ vmps_status vmps_segmented_sort(void* keys, uint32_t* values, const int64_t* seg
         VMPS_HIP(plan_enqueue(P, keys, kb, 0, s));
         VMPS_HIP(level_probe_enqueue(P, kb, has_values, s));
         VMPS_HIP(tilesort_enqueue(P, keys, keysB, values, valsB, kb, values ? 1 : 0, 0, s, tu.tile_threads));
-        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s);
+        // levels above the longest array's powers are empty: one launch each
+        return merge_levels_enqueue(P, keys, keysB, values, valsB, kb, has_values, s, true);
     });
 }
 
